@@ -1,0 +1,60 @@
+"""Pins of the oracle gradient (complex-step VJP of the stamped A, b with respect
+to per-device W, L, VTH0): against central finite differences of the local device
+outputs, and against directional finite differences of the assembled
+J = <Abar, A> + <bbar, b>, which also pins the mapping of cotangents to slots."""
+import numpy as np
+import pytest
+
+from paper_2604_03079_amd import netgen as G
+
+NC, PC = G.default_card(1), G.default_card(-1)
+
+
+def test_local_sensitivities_match_central_differences(orc):
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        pol = 1 if rng.random() < 0.5 else -1
+        W, L = rng.uniform(0.2e-6, 20e-6), rng.uniform(45e-9, 500e-9)
+        VTH0 = pol * (0.4 + 0.02 * rng.standard_normal())
+        V = rng.uniform(0.0, 1.2, 4)
+        card = NC if pol > 0 else PC
+        theta = [W, L, VTH0]
+        for which in range(3):
+            dY, dbl = orc.device_dparam(card, pol, W, L, VTH0, V, 1e12, None, which)
+            h = 1e-6 * abs(theta[which])
+            tp = list(theta); tp[which] += h
+            tm = list(theta); tm[which] -= h
+            Y0, b0, _, _ = orc.device_eval(card, pol, *theta, V, 1e12)
+            Yp, bp, _, _ = orc.device_eval(card, pol, *tp, V, 1e12)
+            Ym, bm, _, _ = orc.device_eval(card, pol, *tm, V, 1e12)
+            fY = (Yp - Ym) / (2 * h)
+            fb = (bp - bm) / (2 * h)
+            # truncation O(h^2) relative, plus the rounding floor of a central
+            # difference, ~eps*|value|/h (dominant for cut-off devices, where the
+            # VTH0 sensitivity is far below the overlap-capacitance entries)
+            floorY = 64 * 2.2e-16 * np.abs(Y0).max() / h
+            floorb = 64 * 2.2e-16 * np.abs(b0).max() / h
+            assert np.abs(fY - dY).max() <= 1e-6 * np.abs(dY).max() + floorY
+            assert np.abs(fb - dbl).max() <= 1e-6 * np.abs(dbl).max() + floorb
+
+
+@pytest.mark.parametrize("make", [lambda: G.workload(0), lambda: G.draw_params(
+    G.opamp2(13), np.random.default_rng(5), G.W_OPAMP, G.L_OPAMP), lambda: G.sram_case(3, 3, 2)],
+    ids=["chain50", "opamp13", "sram3x3"])
+def test_vjp_matches_directional_difference_of_assembly(orc, make):
+    circ = make()
+    rp, ci = orc.pattern(circ)
+    Ab, bb = G.cotangents(len(ci), circ.n_rows, seed=50)
+    gW, gL, gV = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb)
+    rng = np.random.default_rng(7)
+    for name, base, g in (("W", circ.W, gW), ("L", circ.L, gL), ("VTH0", circ.VTH0, gV)):
+        d = rng.standard_normal(circ.n_dev) * np.abs(base)
+        eps = 1e-6
+        kw_p = {name: base + eps * d}
+        kw_m = {name: base - eps * d}
+        Ap, bp = orc.assemble(circ, rp, ci, NC, PC, 1e12, **kw_p)
+        Am, bm = orc.assemble(circ, rp, ci, NC, PC, 1e12, **kw_m)
+        fd = ((Ab @ Ap + bb @ bp) - (Ab @ Am + bb @ bm)) / (2 * eps)
+        an = float(g @ d)
+        scale = float(np.abs(g * d).sum())
+        assert abs(fd - an) <= 1e-6 * scale, (name, fd, an)

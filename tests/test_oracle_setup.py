@@ -1,0 +1,160 @@
+"""Pins of the oracle's setup: conflict graph, greedy colouring and CSR pattern.
+
+Conflict graph and colouring (Introduction and Methodology): one vertex per FET,
+an edge when two FETs share a non-ground node; greedy colouring gives each vertex,
+in visiting order, the smallest colour not used by its already coloured
+neighbours.  Pins: validity, the exact greedy property, brute-force chromatic
+numbers of tiny graphs, clique lower bounds, the empty-graph case of Table I's
+R89 row (C = 1), and closed-form colour and nonzero counts of the generators."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2604_03079_amd import netgen as G
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def conflict_sets(circ, exclude):
+    sets = []
+    for t in circ.term:
+        s = {int(n) for n in t if n != 0 and not (exclude and circ.exclude[n])}
+        sets.append(s)
+    return sets
+
+
+def adjacency(circ, exclude):
+    sets = conflict_sets(circ, exclude)
+    by_node = {}
+    for v, s in enumerate(sets):
+        for n in s:
+            by_node.setdefault(n, []).append(v)
+    adj = [set() for _ in sets]
+    for devs in by_node.values():
+        for a in devs:
+            adj[a].update(devs)
+    for v in range(len(adj)):
+        adj[v].discard(v)
+    return adj
+
+
+def check_greedy(col, adj):
+    for v, nb in enumerate(adj):
+        lower = {col[u] for u in nb if u < v}
+        assert all(col[u] != col[v] for u in nb), "invalid colouring"
+        assert col[v] not in lower and all(c in lower for c in range(col[v])), "not greedy"
+
+
+def chromatic_number(adj):
+    n = len(adj)
+    for k in range(1, n + 1):
+        for assign in itertools.product(range(k), repeat=n):
+            if assign[0] != 0:
+                continue
+            if all(assign[a] != assign[b] for a in range(n) for b in adj[a] if b > a):
+                return k
+    return n
+
+
+SMALL = [G.inverter_chain(1), G.inverter_chain(4), G.inverter_chain(50), G.ota5t(),
+         G.opamp2(8), G.opamp2(14), G.ring_oscillator(11), G.sram6t(6, 5),
+         G.parallel_chain(7, 3), G.no_shared_nets(9)]
+
+
+@pytest.mark.parametrize("circ", SMALL, ids=lambda c: c.name)
+@pytest.mark.parametrize("exclude", [False, True])
+def test_colouring_is_valid_and_greedy(orc, circ, exclude):
+    col, C, E = orc.colour(circ, exclude)
+    adj = adjacency(circ, exclude)
+    check_greedy(col, adj)
+    assert C == col.max() + 1
+    assert E == sum(len(a) for a in adj) // 2
+
+
+@pytest.mark.parametrize("circ,exclude,chi", [
+    (G.inverter_chain(1), False, 2), (G.inverter_chain(1), True, 2),
+    (G.ota5t(), False, 3), (G.ota5t(), True, 3),
+    (G.inverter_chain(4), True, 4),
+], ids=lambda x: getattr(x, "name", str(x)))
+def test_greedy_reaches_brute_force_chromatic_number(orc, circ, exclude, chi):
+    col, C, _ = orc.colour(circ, exclude)
+    assert chromatic_number(adjacency(circ, exclude)) == chi
+    assert C == chi
+
+
+def test_no_shared_nets_gives_one_colour(orc):
+    # Table I, R89 row: once every net is split, one colour holds every FET.
+    col, C, E = orc.colour(G.no_shared_nets(1000), False)
+    assert C == 1 and E == 0 and not col.any()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 50, 1000])
+def test_chain_counts(orc, n):
+    c = G.inverter_chain_fast(n) if n > 3 else G.inverter_chain(n)
+    _, C_excl, _ = orc.colour(c, True)
+    _, C_strict, _ = orc.colour(c, False)
+    if n >= 2:
+        assert C_excl == 4
+    # strict rule, by hand: N=1 is a 2-clique, N=2 a 4-clique on out1, N=3 needs 5;
+    # from N=4 on each new PMOS (vdd clique) takes one new colour: N+1
+    assert C_strict == {1: 2, 2: 4, 3: 5}.get(n, n + 1)
+    assert C_strict >= int((c.pol < 0).sum())        # all PMOS bodies on vdd: a clique
+    rp, ci = orc.pattern(c)
+    assert len(rp) - 1 == n + 3 and len(ci) == 5 * n + 6
+
+
+@pytest.mark.parametrize("n", [3, 11, 501])
+def test_odd_ring_colours(orc, n):
+    _, C, _ = orc.colour(G.ring_oscillator(n), True)
+    assert C == 6
+
+
+@pytest.mark.parametrize("g", [1, 2, 4, 8])
+def test_parallel_chain_colours(orc, g):
+    _, C, _ = orc.colour(G.parallel_chain(20, g), True)
+    assert C == 4 * g
+
+
+def test_chain1_pattern_matches_hand_derivation(orc):
+    gold = json.load(open(os.path.join(GOLD, "chain1_pattern.json")))
+    rp, ci = orc.pattern(G.inverter_chain(1))
+    assert rp.tolist() == gold["row_ptr"] and ci.tolist() == gold["col_idx"]
+
+
+def test_sram_full_size_counts(orc):
+    c = G.sram6t(256, 256)
+    col, C, E = orc.colour(c, True)
+    assert C >= 512            # each wordline gates 512 access transistors: a clique
+    assert C == 516
+    rp, ci = orc.pattern(c)
+    assert len(rp) - 1 == 131_842 and len(ci) == 1_311_491
+
+
+def test_stamp_map_flags(orc):
+    for circ in (G.workload(0), G.ota5t(), G.opamp2(12), G.sram6t(4, 4)):
+        for exclude in (False, True):
+            col, _, _ = orc.colour(circ, exclude)
+            rp, ci = orc.pattern(circ)
+            slot, sflag, brow, bflag = orc.stamp_map(circ, rp, ci, col, exclude)
+            # one store per written non-hub entry; hubs exactly where both nodes are excluded
+            stores = np.bincount(slot[sflag == 1], minlength=len(ci))
+            written = np.bincount(slot[(sflag == 0) | (sflag == 1)], minlength=len(ci))
+            assert np.all(stores[written > 0] == 1)
+            for v in range(circ.n_dev):
+                nodes = []
+                for n in circ.term[v]:
+                    if n != 0 and n not in nodes:
+                        nodes.append(int(n))
+                k = len(nodes)
+                for a in range(k):
+                    for b in range(k):
+                        j = a * k + b
+                        r, cc = nodes[a] - 1, nodes[b] - 1
+                        assert ci[slot[v, j]] == cc and rp[r] <= slot[v, j] < rp[r + 1]
+                        hub = exclude and circ.exclude[nodes[a]] and circ.exclude[nodes[b]]
+                        assert (sflag[v, j] == 2) == bool(hub)
+                    assert brow[v, a] == nodes[a] - 1
+                assert np.all(slot[v, k * k:] == -1) and np.all(brow[v, k:] == -1)
