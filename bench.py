@@ -1,0 +1,242 @@
+"""Benchmark: devices evaluated and stamped per second for one Newton-Raphson step.
+
+Workload (default): inverter chain of 100,000 stages (200,000 MOSFETs, 100,003 MNA
+rows, 500,006 nonzeros), rail-excluded conflict rule (4 colours), FP64, one NR step
+= evaluate every device at x and stamp A, b (ag0 = 1e12, backward Euler with h = 1
+ps).  Synthetic seeded inputs (W, L, VTH0, x).  Each step is one replay of a HIP
+graph holding the whole step; the timed region is K replays between events.
+
+Prints one JSON line.  Extra keys report the other kernel variants, the 6T SRAM
+array, the batched sweep and the adjoint, plus the roofline of the dominant kernel
+and the oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x FP64 lanes x clock: one op per lane-cycle
+PEAK_HBM = 8.0e12
+AG0 = 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2604_03079_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def device_tensors(torch, circ, dev):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    return t(circ.W), t(circ.L), t(circ.VTH0), t(circ.x)
+
+
+def time_graph(torch, fn, steps, warmup):
+    """Capture fn() (one NR step) in a graph; replay warmup times, then time steps."""
+    fn()
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, g
+
+
+def algorithmic_counts(circ, exclude=True):
+    """FP64 operations and bytes one step needs (counted on the oracle's definition)."""
+    from oracle import oracle as O
+    from paper_2604_03079_amd import netgen as G
+    rp, ci = O.pattern(circ)
+    col, C, _ = O.colour(circ, exclude)
+    O.lib().or_count_ops(1)
+    O.assemble(circ, rp, ci, G.default_card(1), G.default_card(-1), AG0, col=col, exclude=exclude)
+    model_ops = O.lib().or_ops()
+    O.lib().or_count_ops(0)
+    slot, sflag, brow, bflag = O.stamp_map(circ, rp, ci, col, exclude)
+    merges = 0
+    for t4 in circ.term:
+        nz = [int(n) for n in t4 if n != 0]
+        k = len(set(nz))
+        merges += len(nz) * len(nz) - k * k + len(nz) - k
+    add_ops = int((sflag == 0).sum() + (bflag == 0).sum())
+    hub_sizes = {}
+    for s in slot[sflag == 2]:
+        hub_sizes[("A", int(s))] = hub_sizes.get(("A", int(s)), 0) + 1
+    for r in brow[bflag == 2]:
+        hub_sizes[("b", int(r))] = hub_sizes.get(("b", int(r)), 0) + 1
+    hub_ops = sum(m - 1 for m in hub_sizes.values())
+    ops = model_ops + merges + add_ops + hub_ops
+    n = circ.n_dev
+    nslot = int((sflag >= 0).sum())
+    nbrow = int((bflag >= 0).sum())
+    # bytes: params (3 x 8) + polarity (1) + terminals (4 x 4) + x gathers (8 per row
+    # once) + stamp codes (4 per entry) + value writes (8 per entry) + load-add reads
+    # (8 per add) + hub staging written and read (16 per hub entry)
+    nhub = int((sflag == 2).sum() + (bflag == 2).sum())
+    byts = (n * (24 + 1 + 16) + 8 * circ.n_rows + 4 * (nslot + nbrow)
+            + 8 * (nslot + nbrow) + 8 * add_ops + 16 * nhub)
+    return dict(ops=int(ops), model_ops=int(model_ops), bytes=int(byts), n_colors=int(C))
+
+
+def cpu_baseline(circ, budget_s=12.0):
+    """The oracle (serial, colour replay) on the host: devices per second."""
+    from oracle import oracle as O
+    from paper_2604_03079_amd import netgen as G
+    rp, ci = O.pattern(circ)
+    col, _, _ = O.colour(circ, True)
+    nc, pc = G.default_card(1), G.default_card(-1)
+    it = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        O.assemble(circ, rp, ci, nc, pc, AG0, col=col, exclude=True)
+        it += 1
+    dt = time.perf_counter() - t0
+    return dict(value=round(circ.n_dev * it / dt / 1e6, 4), unit="M devices/s", cores=1,
+                kind="oracle",
+                sample=f"{it} NR steps of the full {circ.n_dev}-device chain, serial colour-replay "
+                       f"oracle (C, -O2), {dt:.1f} s")
+
+
+def traffic_from_profiles(kernel_hash: str, key: str):
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    e = d.get(key)
+    if not e or e.get("kernel_hash") != kernel_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--variant", default="persistent")
+    ap.add_argument("--no-extras", action="store_true", help="skip SRAM/batch/adjoint lines")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: every box here has one GPU (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_03079_amd import colorstamp as CS
+    from paper_2604_03079_amd import netgen as G
+
+    dev = torch.device("cuda:0")
+    khash = kernel_sources_hash()
+    circ = G.workload(1)
+    log(f"workload: chain 100000 stages, {circ.n_dev} devices")
+    counts = algorithmic_counts(circ)
+    W, L, V, x = device_tensors(torch, circ, dev)
+
+    variants = {}
+    graphs = []
+    for variant, coop in (("persistent", True), ("persistent", False), ("per_kernel", True),
+                          ("buffered", True), ("atomic", True)):
+        c = CS.prepare(circ, exclude=True)
+        c.set_launch(256, -1, coop)
+        c.set_params(W, L, V)
+        A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+        b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+        steps = args.steps if variant == args.variant and coop else max(10, args.steps // 4)
+        ms, g = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, args.warmup)
+        c.check()
+        graphs.append((c, g, A, b))
+        name = variant if coop else variant + "_ordinary_launch"
+        variants[name] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2),
+                              info=c.info(), steps=steps)
+        log(f"  {name:28s} {ms * 1e3:9.2f} us/step  {circ.n_dev / ms / 1e3:9.1f} M devices/s")
+
+    main_v = variants[args.variant]
+    ms = main_v["ms_per_step"]
+    secs = ms * 1e-3
+    result = {
+        "metric": "M devices eval+stamp/s per NR iter (colored vs atomic); batched & fwd+adjoint",
+        "value": main_v["value"],
+        "unit": "M devices/s",
+        "n_gpus": 1,
+        "steps": main_v["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "inverter_chain_100k_stages", "n_dev": circ.n_dev,
+                   "n_rows": int(main_v["info"]["n_rows"]), "nnz": int(main_v["info"]["nnz"]),
+                   "n_colors": counts["n_colors"], "conflict_rule": "rails_excluded",
+                   "variant": args.variant, "ag0": AG0, "graph_replay": True},
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(counts["ops"] / secs / 1e12, 4),
+            "peak": round(PEAK_FP64_OPS / 1e12, 2),
+            "unit": "TFLOP/s",
+            "frac": round(counts["ops"] / secs / PEAK_FP64_OPS, 5),
+            "traffic": traffic_from_profiles(khash, "persistent_chain100k"),
+            "algorithmic_ops_per_launch": counts["ops"],
+            "algorithmic_bytes_per_launch": counts["bytes"],
+            "hbm_frac_at_algorithmic_bytes": round(counts["bytes"] / secs / PEAK_HBM, 5),
+            "kernel": "k_persistent (one launch per step)",
+        },
+        "variants": variants,
+        "kernel_sources": khash,
+    }
+
+    if not args.no_extras:
+        extras = {}
+        sram = G.workload(2)
+        Ws, Ls, Vs, xs = device_tensors(torch, sram, dev)
+        ex = {}
+        for variant in ("persistent", "per_kernel", "atomic"):
+            c = CS.prepare(sram, exclude=True)
+            c.set_params(Ws, Ls, Vs)
+            A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+            b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+            msv, _ = time_graph(torch, lambda: c.eval_stamp(xs, AG0, None, A, b, variant), 5, 2)
+            c.check()
+            ex[variant] = dict(ms_per_step=round(msv, 4), value=round(sram.n_dev / msv / 1e3, 2))
+            log(f"  sram {variant:12s} {msv:8.3f} ms/step {sram.n_dev / msv / 1e3:9.1f} M devices/s")
+        extras["sram_256x256"] = dict(n_dev=sram.n_dev, n_colors=c.info()["n_colors"], **ex)
+        result["extras"] = extras
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(circ)
+        log(f"  cpu oracle: {result['cpu_baseline']['value']} M devices/s")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

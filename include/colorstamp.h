@@ -1,0 +1,189 @@
+/* colorstamp: coloured, conflict-free MOSFET evaluate-and-stamp on MI355X (gfx950).
+ *
+ * The operation (paper "EEspice: A Modular Circuit Simulation Platform with Parallel
+ * Device Model Evaluation via Graph Coloring"):
+ *   - Introduction / Methodology: each Newton-Raphson iteration evaluates every
+ *     device model at the present operating point (compute phase: equivalent
+ *     conductances and current/charge terms) and stamps the contributions into the
+ *     shared MNA matrix A and right-hand side b (stamp phase);
+ *   - Methodology: the FET conflict graph (one vertex per FET, an edge when two FETs
+ *     share a non-ground node) is built at circuit setup and coloured greedily; the
+ *     NR loop processes colours sequentially and evaluates and stamps all devices of
+ *     a colour in parallel, without locks;
+ *   - Table "Summary of BSIM4 evaluation-kernel variants": kernels are
+ *     interchangeable without changing the simulation loop (cs_variant below).
+ *
+ * Conventions
+ *   - Nodes: 0 is ground.  MNA rows: non-ground node n -> row n-1, then one branch row
+ *     per voltage source, in source order.  A is CSR with sorted, unique columns:
+ *     every ordered pair of a device's non-ground terminal nodes, every node-row
+ *     diagonal, and (pos, br), (br, pos) (and neg likewise) per voltage source.
+ *   - Device terminals are (d, g, s, b); pol = +1 NMOS, -1 PMOS.
+ *   - Ownership: create copies every host input; the library owns its setup buffers
+ *     (host and device).  x, A, b, W, L, VTH0, hist, cotangents and gradients are
+ *     caller-owned DEVICE memory (FP64).  Streams are hipStream_t passed as void*.
+ *   - Calls are stream-ordered and asynchronous.  Argument and state errors are
+ *     detected on the host before any launch; a failed launch returns CS_EHIP.
+ *     No exceptions cross the ABI.  cs_last_error() describes the last failure of
+ *     the calling thread.  A handle is used by one stream at a time.
+ *   - cs_eval_stamp overwrites every entry of A_val and b (no zero-fill contract).
+ */
+#ifndef COLORSTAMP_H
+#define COLORSTAMP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cs_circuit cs_circuit;
+typedef struct cs_batch cs_batch;
+
+typedef enum {
+    CS_OK = 0,
+    CS_EINVAL = -1,   /* bad argument: null pointer, node id, polarity or size */
+    CS_ENOMEM = -2,   /* host or device allocation failed */
+    CS_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+    CS_ESTATE = -4,   /* calls out of order (e.g. evaluate before the stamp map) */
+    CS_ENOTSUP = -5,  /* size or configuration beyond what the library supports */
+    CS_EDOMAIN = -6   /* a kernel reported a failed bounded wait (see cs_check) */
+} cs_status;
+
+/* Kernel variants (paper, Table "Summary of BSIM4 evaluation-kernel variants"). */
+typedef enum {
+    CS_COLOR_PERSISTENT = 0,  /* ColorFused: one persistent kernel; colours in sequence,
+                                 grid-wide barrier between colours; plain stores and
+                                 load-adds only */
+    CS_COLOR_PER_KERNEL = 1,  /* ColorFused with one kernel launch per colour (the
+                                 per-colour parallel-for of the paper's OpenMP form) */
+    CS_ATOMIC = 2,            /* comparison: no colouring, FP64 atomic adds (the
+                                 paper's lock-based foil, Introduction) */
+    CS_COLOR_BUFFERED = 3     /* Color: evaluate every device into a buffer, then
+                                 stamp colour by colour from the buffer */
+} cs_variant;
+
+/* Model card of the BSIM4-core subset (SI units).  One card per polarity. */
+typedef struct {
+    uint32_t size;  /* = sizeof(cs_model_card) */
+    double tnom, toxe, ndep, phis, vbi, k1, k2, k3, w0, dvt0, dvt1, dsub, eta0, nfactor,
+        cdsc, voff, u0, ua, ub, uc, vsat, a0, xj, delta, delta1, lambda_l, cgdo, lint, wint;
+} cs_model_card;
+
+/* Create a circuit.  term: n_dev*4 node ids (d, g, s, b), 0 <= id < n_nodes;
+ * pol: n_dev entries of +1/-1; vsrc: n_vsrc*2 (pos, neg) node ids; vsrc_volts:
+ * n_vsrc values.  All host pointers, copied.  *out receives the handle. */
+cs_status cs_circuit_create(int32_t n_nodes, int32_t n_dev, const int32_t *term,
+                            const int8_t *pol, int32_t n_vsrc, const int32_t *vsrc,
+                            const double *vsrc_volts, cs_circuit **out);
+void cs_circuit_destroy(cs_circuit *c);
+
+/* Conflict graph and greedy colouring (Methodology; Introduction for the greedy
+ * rule).  exclude: n_nodes host flags of nodes that do not create conflicts (NULL:
+ * only ground, the paper's rule).  Devices are visited in ascending index and take
+ * the smallest colour unused by an already coloured neighbour.  Entries whose row
+ * and column nodes are both excluded (and b rows of excluded nodes) become hub
+ * entries, summed by a fixed-shape reduction.  Outputs (each may be NULL): number
+ * of colours, colour per device (host, n_dev), number of conflict edges. */
+cs_status cs_build_coloring(cs_circuit *c, const uint8_t *exclude, int32_t *n_colors,
+                            int32_t *colour_out, int64_t *n_edges);
+
+/* CSR pattern and the device-to-slot stamp map (Methodology: stamps touch common
+ * MNA rows/columns).  Requires cs_build_coloring.  Uploads topology and map to the
+ * current HIP device.  Outputs: number of rows and nonzeros. */
+cs_status cs_build_stamp_map(cs_circuit *c, int32_t *n_rows, int64_t *nnz);
+
+/* Host copies of the pattern: row_ptr[n_rows+1], col_idx[nnz]. */
+cs_status cs_get_pattern(const cs_circuit *c, int32_t *row_ptr, int32_t *col_idx);
+
+/* Host copy of the stamp map in original device order: slot[16*v + j] for
+ * j < k*k (k = distinct non-ground nodes of device v, in first-appearance order over
+ * d, g, s, b; entry j = a*k + b is node pair (a, b)), -1 beyond; sflag: 0 load-add,
+ * 1 plain store (first writer in colour order), 2 hub; brow[4*v + a] = row of node a,
+ * -1 beyond; bflag likewise.  Any pointer may be NULL. */
+cs_status cs_get_stamp_map(const cs_circuit *c, int32_t *slot, int8_t *sflag, int32_t *brow,
+                           int8_t *bflag);
+
+/* Model cards (host pointers, copied; size field checked). */
+cs_status cs_set_models(cs_circuit *c, const cs_model_card *nmos, const cs_model_card *pmos);
+
+/* Per-device parameters in original device order (device pointers, n_dev each).
+ * Copied into the library's colour-major layout on `stream`. */
+cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const double *VTH0,
+                        void *stream);
+
+/* Evaluate every device at x (device, n_rows) and stamp A_val (device, nnz) and b
+ * (device, n_rows).  ag0: charge-to-current coefficient of the integration formula
+ * (0 for a DC stamp); hist: device, n_dev*4 history terms in original device order,
+ * or NULL.  Per device the local conductance matrix Y = dI/dV + ag0*dQ/dV and
+ * right-hand side Y*(V - Vs) - I - ag0*Q (+ hist) are merged onto its node pairs and
+ * accumulated: colour by colour, first writer stores, later writers add. */
+cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
+                        const double *hist, double *A_val, double *b, void *stream);
+
+/* Vector-Jacobian product of the stamped (A, b) with respect to W, L, VTH0:
+ * W_bar[k] = sum_j A_bar[slot] * dA_contrib/dW_k + sum_r b_bar[r] * db_contrib/dW_k,
+ * likewise L and VTH0.  All pointers are device memory in original device order;
+ * model intermediates are recomputed, not stored. */
+cs_status cs_vjp(cs_circuit *c, const double *x, double ag0, const double *hist,
+                 const double *A_bar, const double *b_bar, double *W_bar, double *L_bar,
+                 double *VTH0_bar, void *stream);
+
+/* Launch configuration.  block: threads per block (64, 128, 192 or 256; 0 =
+ * default 256); eval_ahead: 1 = the persistent kernel evaluates every device before
+ * the colour phases and keeps the results in registers (requires the resident grid
+ * to hold one device per thread), 0 = evaluate inside each colour phase, -1 =
+ * choose; cooperative: 1 = hipLaunchCooperativeKernel (the runtime guarantees that
+ * every block is resident), 0 = an ordinary launch of a grid that the occupancy
+ * query says fits the device at once (lower launch cost; the caller must not run
+ * other work on the device concurrently - a block that cannot become resident makes
+ * the bounded barrier waits expire, reported by cs_check as CS_EDOMAIN). */
+cs_status cs_set_launch(cs_circuit *c, int32_t block, int32_t eval_ahead, int32_t cooperative);
+
+/* Sizes and launch facts: n_dev, n_rows, nnz, n_colors, grid (persistent kernel
+ * blocks), block, eval_ahead in use, number of hub entries.  Any pointer may be NULL. */
+cs_status cs_get_info(const cs_circuit *c, int64_t *n_dev, int32_t *n_rows, int64_t *nnz,
+                      int32_t *n_colors, int32_t *grid, int32_t *block, int32_t *eval_ahead,
+                      int32_t *n_hub);
+
+/* Read and clear the device error word of the last bounded waits (synchronises the
+ * stream).  Returns CS_EDOMAIN if a barrier wait ran out of its spin budget. */
+cs_status cs_check(cs_circuit *c, void *stream);
+
+/* Spin budget of the persistent kernel's barrier waits (iterations; 0 = default). */
+cs_status cs_set_spin_limit(cs_circuit *c, int64_t spins);
+
+/* ---- batches: many independent circuits stamped in one launch ------------------
+ * The batch packs its circuits (each already coloured and mapped, models set) into
+ * one instance table.  Packed layouts concatenate per-circuit arrays in batch order:
+ * x and b by rows, A by nonzeros, W/L/VTH0 and gradients by devices, hist by 4*devices.
+ * Offsets come from cs_batch_layout. */
+cs_status cs_batch_create(int32_t n, cs_circuit *const *circuits, cs_batch **out);
+void cs_batch_destroy(cs_batch *b);
+/* Offsets (host arrays of n+1 entries each; any may be NULL). */
+cs_status cs_batch_layout(const cs_batch *b, int64_t *dev_off, int64_t *row_off,
+                          int64_t *nnz_off);
+cs_status cs_batch_set_params(cs_batch *b, const double *W, const double *L,
+                              const double *VTH0, void *stream);
+/* Launch configuration of the batched persistent kernel (see cs_set_launch) and the
+ * size up to which a circuit is stamped inside one workgroup with workgroup
+ * barriers (colour-phase fusion; 0 = off). */
+cs_status cs_batch_set_launch(cs_batch *b, int32_t block, int32_t eval_ahead,
+                              int32_t local_max_dev);
+cs_status cs_batch_get_info(const cs_batch *b, int64_t *n_dev, int64_t *n_rows, int64_t *nnz,
+                            int32_t *max_colors, int32_t *grid, int32_t *block,
+                            int32_t *eval_ahead, int32_t *n_local);
+/* One launch over every circuit of the batch. */
+cs_status cs_batch_eval_stamp(cs_batch *b, const double *x, double ag0, const double *hist,
+                              double *A, double *b_vec, void *stream);
+cs_status cs_batch_vjp(cs_batch *b, const double *x, double ag0, const double *hist,
+                       const double *A_bar, const double *b_bar, double *W_bar, double *L_bar,
+                       double *VTH0_bar, void *stream);
+cs_status cs_batch_check(cs_batch *b, void *stream);
+
+/* Message for the last non-OK status returned to the calling thread. */
+const char *cs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

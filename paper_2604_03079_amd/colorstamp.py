@@ -1,0 +1,238 @@
+"""Python binding of libcolorstamp (ctypes; argument marshalling only).
+
+Every step of the evaluate-and-stamp path runs in the HIP library; torch supplies
+device memory and the current stream.  If the library is not built the import of
+``lib()`` raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libcolorstamp.so")
+
+VARIANTS = {"persistent": 0, "per_kernel": 1, "atomic": 2, "buffered": 3}
+STATUS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EHIP", -4: "CS_ESTATE",
+          -5: "CS_ENOTSUP", -6: "CS_EDOMAIN"}
+CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "dvt0", "dvt1",
+               "dsub", "eta0", "nfactor", "cdsc", "voff", "u0", "ua", "ub", "uc", "vsat", "a0",
+               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint")
+
+# Every entry point of include/colorstamp.h.
+EXPORTS = (
+    "cs_circuit_create", "cs_circuit_destroy", "cs_build_coloring", "cs_build_stamp_map",
+    "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
+    "cs_vjp", "cs_set_launch", "cs_get_info", "cs_check", "cs_set_spin_limit",
+    "cs_batch_create", "cs_batch_destroy", "cs_batch_layout", "cs_batch_set_params",
+    "cs_batch_set_launch", "cs_batch_get_info", "cs_batch_eval_stamp", "cs_batch_vjp",
+    "cs_batch_check", "cs_last_error",
+)
+
+
+class CsError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ModelCard(C.Structure):
+    _fields_ = [("size", C.c_uint32)] + [(f, C.c_double) for f in CARD_FIELDS]
+
+
+def make_card(d: dict) -> ModelCard:
+    c = ModelCard(C.sizeof(ModelCard), *[float(d[f]) for f in CARD_FIELDS])
+    return c
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libcolorstamp.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        i32, i64, d, p = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+        sig = {
+            "cs_circuit_create": [i32, i32, p, p, i32, p, p, p],
+            "cs_build_coloring": [p, p, p, p, p],
+            "cs_build_stamp_map": [p, p, p],
+            "cs_get_pattern": [p, p, p],
+            "cs_get_stamp_map": [p, p, p, p, p],
+            "cs_set_models": [p, p, p],
+            "cs_set_params": [p, p, p, p, p],
+            "cs_eval_stamp": [p, C.c_int, p, d, p, p, p, p],
+            "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
+            "cs_set_launch": [p, i32, i32, i32],
+            "cs_get_info": [p, p, p, p, p, p, p, p, p],
+            "cs_check": [p, p],
+            "cs_set_spin_limit": [p, i64],
+            "cs_batch_create": [i32, p, p],
+            "cs_batch_layout": [p, p, p, p],
+            "cs_batch_set_params": [p, p, p, p, p],
+            "cs_batch_set_launch": [p, i32, i32, i32],
+            "cs_batch_get_info": [p, p, p, p, p, p, p, p, p],
+            "cs_batch_eval_stamp": [p, p, d, p, p, p, p],
+            "cs_batch_vjp": [p, p, d, p, p, p, p, p, p, p],
+            "cs_batch_check": [p, p],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.cs_circuit_destroy.argtypes = [p]
+        L.cs_circuit_destroy.restype = None
+        L.cs_batch_destroy.argtypes = [p]
+        L.cs_batch_destroy.restype = None
+        L.cs_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise CsError(st, where, lib().cs_last_error().decode())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Circuit:
+    """One circuit behind the C-ABI.  Topology comes from numpy arrays (host)."""
+
+    def __init__(self, n_nodes, term, pol, vsrc, vsrc_volts):
+        term = np.ascontiguousarray(term, dtype=np.int32).reshape(-1, 4)
+        pol = np.ascontiguousarray(pol, dtype=np.int8)
+        vsrc = np.ascontiguousarray(vsrc, dtype=np.int32).reshape(-1, 2)
+        vv = np.ascontiguousarray(vsrc_volts, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().cs_circuit_create(int(n_nodes), term.shape[0], _np_ptr(term), _np_ptr(pol),
+                                       vsrc.shape[0], _np_ptr(vsrc), _np_ptr(vv), C.byref(h)),
+               "cs_circuit_create")
+        self._h = h
+        self.n_nodes = int(n_nodes)
+        self.n_dev = term.shape[0]
+        self.n_rows = None
+        self.nnz = None
+        self.n_colors = None
+
+    @classmethod
+    def from_netlist(cls, circ):
+        return cls(circ.n_nodes, circ.term, circ.pol, circ.vsrc, circ.vsrc_volts)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cs_circuit_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def colour(self, exclude=None):
+        """Greedy colouring; exclude = None (paper rule) or per-node flags."""
+        ex = None if exclude is None else np.ascontiguousarray(exclude, dtype=np.uint8)
+        col = np.zeros(self.n_dev, dtype=np.int32)
+        nc = C.c_int32()
+        ne = C.c_int64()
+        _check(lib().cs_build_coloring(self._h, _np_ptr(ex), C.byref(nc), _np_ptr(col), C.byref(ne)),
+               "cs_build_coloring")
+        self.n_colors = nc.value
+        return col, nc.value, ne.value
+
+    def build_map(self):
+        nr = C.c_int32()
+        nz = C.c_int64()
+        _check(lib().cs_build_stamp_map(self._h, C.byref(nr), C.byref(nz)), "cs_build_stamp_map")
+        self.n_rows, self.nnz = nr.value, nz.value
+        return nr.value, nz.value
+
+    def pattern(self):
+        rp = np.zeros((self.n_rows or 0) + 1, dtype=np.int32)
+        ci = np.zeros(max(self.nnz or 0, 1), dtype=np.int32)
+        _check(lib().cs_get_pattern(self._h, _np_ptr(rp), _np_ptr(ci)), "cs_get_pattern")
+        return rp, ci[:self.nnz]
+
+    def stamp_map(self):
+        n = self.n_dev
+        slot = np.zeros(16 * n, np.int32); sflag = np.zeros(16 * n, np.int8)
+        brow = np.zeros(4 * n, np.int32); bflag = np.zeros(4 * n, np.int8)
+        _check(lib().cs_get_stamp_map(self._h, _np_ptr(slot), _np_ptr(sflag), _np_ptr(brow),
+                                      _np_ptr(bflag)), "cs_get_stamp_map")
+        return slot.reshape(n, 16), sflag.reshape(n, 16), brow.reshape(n, 4), bflag.reshape(n, 4)
+
+    def set_models(self, nmos: dict, pmos: dict):
+        cn, cp = make_card(nmos), make_card(pmos)
+        _check(lib().cs_set_models(self._h, C.byref(cn), C.byref(cp)), "cs_set_models")
+
+    def set_params(self, W, L, VTH0, stream=None):
+        _check(lib().cs_set_params(self._h, _dev_ptr(W), _dev_ptr(L), _dev_ptr(VTH0), _stream(stream)),
+               "cs_set_params")
+
+    def set_launch(self, block: int = 0, eval_ahead: int = -1, cooperative: bool = True):
+        _check(lib().cs_set_launch(self._h, int(block), int(eval_ahead), int(bool(cooperative))),
+               "cs_set_launch")
+
+    def set_spin_limit(self, spins: int):
+        _check(lib().cs_set_spin_limit(self._h, int(spins)), "cs_set_spin_limit")
+
+    def info(self) -> dict:
+        nd, nr, nz = C.c_int64(), C.c_int32(), C.c_int64()
+        nc, g, bl, ea, nh = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().cs_get_info(self._h, C.byref(nd), C.byref(nr), C.byref(nz), C.byref(nc),
+                                 C.byref(g), C.byref(bl), C.byref(ea), C.byref(nh)), "cs_get_info")
+        return dict(n_dev=nd.value, n_rows=nr.value, nnz=nz.value, n_colors=nc.value, grid=g.value,
+                    block=bl.value, eval_ahead=ea.value, n_hub=nh.value)
+
+    def eval_stamp(self, x, ag0: float, hist=None, A=None, b=None, variant="persistent", stream=None):
+        import torch
+        if A is None:
+            A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
+        if b is None:
+            b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
+        _check(lib().cs_eval_stamp(self._h, VARIANTS[variant], _dev_ptr(x), float(ag0), _dev_ptr(hist),
+                                   _dev_ptr(A), _dev_ptr(b), _stream(stream)), "cs_eval_stamp")
+        return A, b
+
+    def vjp(self, x, ag0: float, A_bar, b_bar, hist=None, stream=None):
+        import torch
+        gW = torch.empty(self.n_dev, dtype=torch.float64, device=x.device)
+        gL = torch.empty_like(gW)
+        gV = torch.empty_like(gW)
+        _check(lib().cs_vjp(self._h, _dev_ptr(x), float(ag0), _dev_ptr(hist), _dev_ptr(A_bar),
+                            _dev_ptr(b_bar), _dev_ptr(gW), _dev_ptr(gL), _dev_ptr(gV), _stream(stream)),
+               "cs_vjp")
+        return gW, gL, gV
+
+    def check(self, stream=None):
+        _check(lib().cs_check(self._h, _stream(stream)), "cs_check")
+
+
+def prepare(circ, exclude: bool = True, nmos=None, pmos=None):
+    """Circuit from a generator netlist: coloured (rails excluded or not) and mapped."""
+    from . import netgen
+    c = Circuit.from_netlist(circ)
+    c.colour(circ.exclude if exclude else None)
+    c.build_map()
+    c.set_models(nmos or netgen.default_card(1), pmos or netgen.default_card(-1))
+    return c

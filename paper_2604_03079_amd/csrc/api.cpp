@@ -1,0 +1,420 @@
+// C-ABI of the colorstamp library: argument and state checks, uploads, dispatch of
+// the kernel variants.  No exception crosses the ABI.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "colorstamp.h"
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace cs {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace cs
+
+using namespace cs;
+
+namespace {
+
+cs_status fail(cs_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+cs_status hip_fail(hipError_t e, const char *what) {
+    return fail(CS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CS_CHECK_HIP(expr, what)                     \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+int current_device() {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) return -1;
+    return d;
+}
+
+// Order positions inside each colour by polarity (NMOS first), then device index,
+// so that waves mostly hold one polarity.  Any order inside a colour is valid.
+void order_within_colours(HostCircuit &h) {
+    for (int32_t c = 0; c < h.n_colors; ++c) {
+        auto b = h.perm.begin() + h.colour_ptr[(size_t)c];
+        auto e = h.perm.begin() + h.colour_ptr[(size_t)c + 1];
+        std::stable_sort(b, e, [&](int32_t x, int32_t y) {
+            return (h.pol[(size_t)x] < 0) < (h.pol[(size_t)y] < 0);
+        });
+    }
+}
+
+// Colour-major SoA of the terminals: x index + 1 (0 = ground), offset by row_off.
+std::vector<int32_t> colour_major_terms(const HostCircuit &h, int64_t row_off) {
+    const size_t n = (size_t)h.n_dev;
+    std::vector<int32_t> t(4 * n);
+    for (size_t p = 0; p < n; ++p) {
+        const int32_t v = h.perm[p];
+        for (int j = 0; j < 4; ++j) {
+            const int32_t nd = h.term[4 * (size_t)v + j];
+            t[(size_t)j * n + p] = nd == 0 ? 0 : (int32_t)(row_off + nd);
+        }
+    }
+    return t;
+}
+
+cs_status upload_circuit(cs_circuit *c) {
+    HostCircuit &h = c->h;
+    const size_t n = (size_t)h.n_dev;
+    std::vector<int8_t> pol(n);
+    for (size_t p = 0; p < n; ++p) pol[p] = h.pol[(size_t)h.perm[p]];
+    CS_CHECK_HIP(c->d_term.upload(colour_major_terms(h, 0)), "upload terminals");
+    CS_CHECK_HIP(c->d_pol.upload(pol), "upload polarity");
+    CS_CHECK_HIP(c->d_code.upload(h.code), "upload stamp codes");
+    CS_CHECK_HIP(c->d_acode.upload(h.acode), "upload atomic codes");
+    CS_CHECK_HIP(c->d_perm.upload(h.perm), "upload permutation");
+    CS_CHECK_HIP(c->d_cptr.upload(h.colour_ptr), "upload colour pointers");
+    CS_CHECK_HIP(c->d_fixA_idx.upload(h.fixA_idx), "upload fixed stores");
+    CS_CHECK_HIP(c->d_fixA_val.upload(h.fixA_val), "upload fixed stores");
+    CS_CHECK_HIP(c->d_fixB_idx.upload(h.fixB_idx), "upload fixed stores");
+    CS_CHECK_HIP(c->d_fixB_val.upload(h.fixB_val), "upload fixed stores");
+    CS_CHECK_HIP(c->d_hub_ptr.upload(h.hub_ptr), "upload hub lists");
+    CS_CHECK_HIP(c->d_hub_target.upload(h.hub_target), "upload hub lists");
+    CS_CHECK_HIP(c->d_stage.alloc(h.hub_ptr.empty() ? 0 : (size_t)h.hub_ptr.back()), "alloc staging");
+    CS_CHECK_HIP(c->d_hub_cptr.upload(h.hub_cptr), "upload hub chunks");
+    CS_CHECK_HIP(c->d_hub_of_chunk.upload(h.hub_of_chunk), "upload hub chunks");
+    CS_CHECK_HIP(c->d_hub_part.alloc(h.hub_of_chunk.size()), "alloc hub partials");
+    CS_CHECK_HIP(c->d_hub_count.alloc(h.hub_target.size()), "alloc hub counters");
+    if (!h.hub_target.empty())
+        CS_CHECK_HIP(hipMemset(c->d_hub_count.p, 0, sizeof(uint32_t) * h.hub_target.size()), "clear hub counters");
+    CS_CHECK_HIP(c->d_par.alloc(3 * n), "alloc parameters");
+    int dev_count = 0;
+    CS_CHECK_HIP(hipGetDeviceCount(&dev_count), "device count");
+    hipDeviceProp_t prop;
+    CS_CHECK_HIP(hipGetDeviceProperties(&prop, current_device()), "device properties");
+    const size_t words = 2 + (size_t)prop.multiProcessorCount * 64;
+    CS_CHECK_HIP(c->d_sync.alloc(words), "alloc barrier state");
+    CS_CHECK_HIP(hipMemset(c->d_sync.p, 0, words * sizeof(uint32_t)), "clear barrier state");
+    c->device = current_device();
+    c->grid = 0;
+    c->params_set = false;
+    return CS_OK;
+}
+
+KCirc make_kcirc(cs_circuit *c) {
+    KCirc k{};
+    const HostCircuit &h = c->h;
+    k.n = h.n_dev;
+    k.n_colors = h.n_colors;
+    k.term = c->d_term.p;
+    k.pol = c->d_pol.p;
+    k.par = c->d_par.p;
+    k.code = c->d_code.p;
+    k.acode = c->d_acode.p;
+    k.perm = c->d_perm.p;
+    k.cptr = c->d_cptr.p;
+    k.n_fixA = (int32_t)h.fixA_idx.size();
+    k.n_fixB = (int32_t)h.fixB_idx.size();
+    k.fixA_idx = c->d_fixA_idx.p;
+    k.fixA_val = c->d_fixA_val.p;
+    k.fixB_idx = c->d_fixB_idx.p;
+    k.fixB_val = c->d_fixB_val.p;
+    k.n_hub = (int32_t)h.hub_target.size();
+    k.hub_ptr = c->d_hub_ptr.p;
+    k.hub_target = c->d_hub_target.p;
+    k.stage = c->d_stage.p;
+    k.n_hub_chunks = (int32_t)h.hub_of_chunk.size();
+    k.hub_cptr = c->d_hub_cptr.p;
+    k.hub_of_chunk = c->d_hub_of_chunk.p;
+    k.hub_part = c->d_hub_part.p;
+    k.hub_count = c->d_hub_count.p;
+    k.card[0] = c->card[0];
+    k.card[1] = c->card[1];
+    return k;
+}
+
+// Grid of the persistent kernel for the current configuration.
+cs_status plan_persistent(cs_circuit *c) {
+    if (c->grid > 0) return CS_OK;
+    hipDeviceProp_t prop;
+    CS_CHECK_HIP(hipGetDeviceProperties(&prop, c->device), "device properties");
+    const int block = c->block;
+    int per_cu_ahead = 0, per_cu_phase = 0;
+    CS_CHECK_HIP(persistent_capacity(1, block, &per_cu_ahead), "occupancy");
+    CS_CHECK_HIP(persistent_capacity(0, block, &per_cu_phase), "occupancy");
+    const int64_t cap_ahead = (int64_t)per_cu_ahead * prop.multiProcessorCount;
+    const int64_t cap_phase = (int64_t)per_cu_phase * prop.multiProcessorCount;
+    const int64_t need_ahead = std::max<int64_t>(1, (c->h.n_dev + block - 1) / block);
+    int64_t max_colour = 0;
+    for (int32_t k = 0; k < c->h.n_colors; ++k)
+        max_colour = std::max<int64_t>(max_colour, c->h.colour_ptr[k + 1] - c->h.colour_ptr[k]);
+    const bool fits = need_ahead <= cap_ahead;
+    if (c->eval_ahead_req == 1 && !fits)
+        return fail(CS_ENOTSUP, "evaluate-ahead needs one resident thread per device");
+    c->eval_ahead = c->eval_ahead_req == 0 ? 0 : (fits ? 1 : 0);
+    int64_t grid = c->eval_ahead ? need_ahead
+                                 : std::min<int64_t>(cap_phase, std::max<int64_t>(1, (max_colour + block - 1) / block));
+    if (grid < 1 || cap_phase < 1) return fail(CS_ENOTSUP, "persistent kernel does not fit the device");
+    if ((size_t)grid + 2 > c->d_sync.n) return fail(CS_ENOTSUP, "grid larger than the barrier state");
+    c->grid = (int32_t)grid;
+    return CS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cs_last_error(void) { return g_err.c_str(); }
+
+cs_status cs_circuit_create(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                            int32_t n_vsrc, const int32_t *vsrc, const double *vsrc_volts,
+                            cs_circuit **out) {
+    if (!out) return fail(CS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_nodes < 1 || n_dev < 0 || n_vsrc < 0) return fail(CS_EINVAL, "negative or empty sizes");
+    if ((n_dev > 0 && (!term || !pol)) || (n_vsrc > 0 && (!vsrc || !vsrc_volts)))
+        return fail(CS_EINVAL, "NULL input array");
+    for (int64_t i = 0; i < 4 * (int64_t)n_dev; ++i)
+        if (term[i] < 0 || term[i] >= n_nodes) return fail(CS_EINVAL, "terminal node id out of range");
+    for (int32_t i = 0; i < n_dev; ++i)
+        if (pol[i] != 1 && pol[i] != -1) return fail(CS_EINVAL, "polarity must be +1 or -1");
+    for (int64_t i = 0; i < 2 * (int64_t)n_vsrc; ++i)
+        if (vsrc[i] < 0 || vsrc[i] >= n_nodes) return fail(CS_EINVAL, "source node id out of range");
+    if ((int64_t)n_dev * NCODE >= ((int64_t)1 << 31)) return fail(CS_ENOTSUP, "too many devices");
+    cs_circuit *c = new (std::nothrow) cs_circuit();
+    if (!c) return fail(CS_ENOMEM, "host allocation");
+    try {
+        c->h.n_nodes = n_nodes;
+        c->h.n_dev = n_dev;
+        c->h.n_vsrc = n_vsrc;
+        c->h.term.assign(term, term + 4 * (size_t)n_dev);
+        c->h.pol.assign(pol, pol + (size_t)n_dev);
+        if (n_vsrc) {
+            c->h.vsrc.assign(vsrc, vsrc + 2 * (size_t)n_vsrc);
+            c->h.vsrc_volts.assign(vsrc_volts, vsrc_volts + (size_t)n_vsrc);
+        }
+    } catch (...) {
+        delete c;
+        return fail(CS_ENOMEM, "host allocation");
+    }
+    *out = c;
+    return CS_OK;
+}
+
+void cs_circuit_destroy(cs_circuit *c) { delete c; }
+
+cs_status cs_build_coloring(cs_circuit *c, const uint8_t *exclude, int32_t *n_colors,
+                            int32_t *colour_out, int64_t *n_edges) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    try {
+        Err e = build_colouring(c->h, exclude, n_edges);
+        if (e.st != CS_OK) return fail(e.st, e.msg);
+        order_within_colours(c->h);
+    } catch (const std::bad_alloc &) {
+        return fail(CS_ENOMEM, "host allocation");
+    }
+    c->grid = 0;
+    c->device = -1;
+    if (n_colors) *n_colors = c->h.n_colors;
+    if (colour_out) std::memcpy(colour_out, c->h.colour.data(), sizeof(int32_t) * c->h.n_dev);
+    return CS_OK;
+}
+
+cs_status cs_build_stamp_map(cs_circuit *c, int32_t *n_rows, int64_t *nnz) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->h.coloured) return fail(CS_ESTATE, "cs_build_coloring must come first");
+    try {
+        Err e = build_map(c->h);
+        if (e.st != CS_OK) return fail(e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(CS_ENOMEM, "host allocation");
+    }
+    c->device = -1;
+    c->grid = 0;
+    if (n_rows) *n_rows = c->h.n_rows;
+    if (nnz) *nnz = c->h.nnz;
+    return CS_OK;
+}
+
+cs_status cs_get_pattern(const cs_circuit *c, int32_t *row_ptr, int32_t *col_idx) {
+    if (!c || !row_ptr || !col_idx) return fail(CS_EINVAL, "NULL argument");
+    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    std::memcpy(row_ptr, c->h.row_ptr.data(), sizeof(int32_t) * c->h.row_ptr.size());
+    std::memcpy(col_idx, c->h.col_idx.data(), sizeof(int32_t) * c->h.col_idx.size());
+    return CS_OK;
+}
+
+cs_status cs_get_stamp_map(const cs_circuit *c, int32_t *slot, int8_t *sflag, int32_t *brow,
+                           int8_t *bflag) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    const HostCircuit &h = c->h;
+    if (!h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    const size_t n = (size_t)h.n_dev;
+    for (size_t p = 0; p < n; ++p) {
+        const size_t v = (size_t)h.perm[p];
+        int32_t u[4];
+        int k = 0;
+        for (int t = 0; t < 4; ++t) {
+            const int32_t nd = h.term[4 * v + t];
+            if (nd == 0) continue;
+            bool seen = false;
+            for (int j = 0; j < k; ++j) seen = seen || u[j] == nd;
+            if (!seen) u[k++] = nd;
+        }
+        for (int j = 0; j < 16; ++j) {
+            if (slot) slot[16 * v + j] = -1;
+            if (sflag) sflag[16 * v + j] = -1;
+        }
+        for (int j = 0; j < 4; ++j) {
+            if (brow) brow[4 * v + j] = -1;
+            if (bflag) bflag[4 * v + j] = -1;
+        }
+        for (int j = 0; j < k * k + k; ++j) {
+            const uint32_t cd = (uint32_t)h.code[(size_t)j * n + p];
+            const int8_t tag = (int8_t)(cd >> 30);
+            const int32_t target = h.acode[(size_t)j * n + p];
+            if (j < k * k) {
+                if (slot) slot[16 * v + j] = target;
+                if (sflag) sflag[16 * v + j] = tag;
+            } else {
+                if (brow) brow[4 * v + (j - k * k)] = target;
+                if (bflag) bflag[4 * v + (j - k * k)] = tag;
+            }
+        }
+    }
+    return CS_OK;
+}
+
+cs_status cs_set_models(cs_circuit *c, const cs_model_card *nmos, const cs_model_card *pmos) {
+    if (!c || !nmos || !pmos) return fail(CS_EINVAL, "NULL argument");
+    if (nmos->size != sizeof(cs_model_card) || pmos->size != sizeof(cs_model_card))
+        return fail(CS_EINVAL, "model card size mismatch");
+    c->card[0] = derive_card(*nmos);
+    c->card[1] = derive_card(*pmos);
+    c->models_set = true;
+    return CS_OK;
+}
+
+cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const double *VTH0,
+                        void *stream) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    if (c->device < 0) {
+        cs_status st = upload_circuit(c);
+        if (st != CS_OK) return st;
+    }
+    if (c->h.n_dev > 0 && (!W || !L || !VTH0)) return fail(CS_EINVAL, "NULL parameter array");
+    if (current_device() != c->device) return fail(CS_ESTATE, "circuit uploaded to another device");
+    CS_CHECK_HIP(launch_gather_params(c->h.n_dev, c->d_perm.p, W, L, VTH0, c->d_par.p,
+                                      (hipStream_t)stream), "parameter gather launch");
+    c->params_set = true;
+    return CS_OK;
+}
+
+cs_status cs_set_launch(cs_circuit *c, int32_t block, int32_t eval_ahead, int32_t cooperative) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (cooperative != 0 && cooperative != 1) return fail(CS_EINVAL, "cooperative must be 0 or 1");
+    c->cooperative = cooperative == 1;
+    if (block != 0 && (block < 64 || block > 256 || block % 64 != 0))
+        return fail(CS_EINVAL, "block must be 64, 128, 192 or 256");
+    if (eval_ahead < -1 || eval_ahead > 1) return fail(CS_EINVAL, "eval_ahead must be -1, 0 or 1");
+    c->block = block ? block : 256;
+    c->eval_ahead_req = eval_ahead;
+    c->grid = 0;
+    return CS_OK;
+}
+
+cs_status cs_set_spin_limit(cs_circuit *c, int64_t spins) {
+    if (!c || spins < 0) return fail(CS_EINVAL, "bad argument");
+    c->spin_limit = spins ? spins : (1 << 22);
+    return CS_OK;
+}
+
+cs_status cs_get_info(const cs_circuit *c, int64_t *n_dev, int32_t *n_rows, int64_t *nnz,
+                      int32_t *n_colors, int32_t *grid, int32_t *block, int32_t *eval_ahead,
+                      int32_t *n_hub) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (n_dev) *n_dev = c->h.n_dev;
+    if (n_rows) *n_rows = c->h.n_rows;
+    if (nnz) *nnz = c->h.nnz;
+    if (n_colors) *n_colors = c->h.n_colors;
+    if (grid) *grid = c->grid;
+    if (block) *block = c->block;
+    if (eval_ahead) *eval_ahead = c->eval_ahead;
+    if (n_hub) *n_hub = (int32_t)c->h.hub_target.size();
+    return CS_OK;
+}
+
+cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
+                        const double *hist, double *A_val, double *b, void *stream) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    if (!c->models_set) return fail(CS_ESTATE, "cs_set_models must come first");
+    if (!c->params_set) return fail(CS_ESTATE, "cs_set_params must come first");
+    if (!x || !A_val || !b) return fail(CS_EINVAL, "NULL x, A or b");
+    if (current_device() != c->device) return fail(CS_ESTATE, "circuit uploaded to another device");
+    hipStream_t s = (hipStream_t)stream;
+    const KCirc kc = make_kcirc(c);
+    const KCall call{x, ag0, hist, A_val, b};
+    switch (variant) {
+        case CS_COLOR_PERSISTENT:
+        case CS_COLOR_BUFFERED: {
+            cs_status st = plan_persistent(c);
+            if (st != CS_OK) return st;
+            int mode = c->eval_ahead;
+            int grid = c->grid;
+            if (variant == CS_COLOR_BUFFERED) {
+                if (c->d_buf.n < (size_t)NCODE * c->h.n_dev)
+                    CS_CHECK_HIP(c->d_buf.alloc((size_t)NCODE * c->h.n_dev), "alloc buffer");
+                CS_CHECK_HIP(launch_eval_buffer(kc, call, c->d_buf.p, s), "evaluate launch");
+                mode = 2;
+                if (c->eval_ahead) {
+                    // the stamp-only grid only needs the largest colour
+                    int64_t mc = 0;
+                    for (int32_t k = 0; k < c->h.n_colors; ++k)
+                        mc = std::max<int64_t>(mc, c->h.colour_ptr[k + 1] - c->h.colour_ptr[k]);
+                    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (mc + c->block - 1) / c->block));
+                }
+            }
+            const KSync ks{c->d_sync.p, c->spin_limit};
+            CS_CHECK_HIP(launch_persistent(kc, call, ks, c->d_buf.p, mode, grid, c->block,
+                                           c->cooperative, s), "persistent launch");
+            return CS_OK;
+        }
+        case CS_COLOR_PER_KERNEL: {
+            const HostCircuit &h = c->h;
+            if (h.n_colors == 0) CS_CHECK_HIP(launch_fixed(kc, call, s), "fixed-store launch");
+            for (int32_t k = 0; k < h.n_colors; ++k)
+                CS_CHECK_HIP(launch_colour_phase(kc, call, k, h.colour_ptr[k + 1] - h.colour_ptr[k],
+                                                 k == 0, s), "colour launch");
+            CS_CHECK_HIP(launch_hub(kc, call, s), "hub launch");
+            return CS_OK;
+        }
+        case CS_ATOMIC:
+            CS_CHECK_HIP(launch_atomic(kc, call, c->h.nnz, c->h.n_rows, s), "atomic launch");
+            return CS_OK;
+        default:
+            return fail(CS_EINVAL, "unknown variant");
+    }
+}
+
+cs_status cs_check(cs_circuit *c, void *stream) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (c->device < 0) return CS_OK;
+    CS_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream), "stream synchronise");
+    uint32_t err = 0;
+    CS_CHECK_HIP(hipMemcpy(&err, c->d_sync.p + 1, sizeof(err), hipMemcpyDeviceToHost), "read error word");
+    if (err) {
+        CS_CHECK_HIP(hipMemset(c->d_sync.p + 1, 0, sizeof(uint32_t)), "clear error word");
+        if (c->d_hub_count.n)
+            CS_CHECK_HIP(hipMemset(c->d_hub_count.p, 0, sizeof(uint32_t) * c->d_hub_count.n), "clear hub counters");
+        return fail(CS_EDOMAIN, "a barrier wait exceeded its spin budget");
+    }
+    return CS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal definitions of the colorstamp library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "colorstamp.h"
+#include "kernel_args.hpp"
+
+namespace cs {
+
+// Thread-local error message behind cs_last_error().
+void set_error(const std::string &msg);
+
+// Status carrier for internal helpers.
+struct Err {
+    cs_status st;
+    std::string msg;
+};
+
+// Owned device allocation.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count) {
+        release();
+        n = count;
+        if (count == 0) return hipSuccess;
+        return hipMalloc(reinterpret_cast<void **>(&p), sizeof(T) * count);
+    }
+    hipError_t upload(const std::vector<T> &h) {
+        hipError_t e = alloc(h.size());
+        if (e != hipSuccess || h.empty()) return e;
+        return hipMemcpy(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+    }
+};
+
+// Host-side topology, colouring, pattern and stamp map of one circuit.
+struct HostCircuit {
+    int32_t n_nodes = 0, n_dev = 0, n_vsrc = 0;
+    std::vector<int32_t> term;        // n_dev*4, original order
+    std::vector<int8_t> pol;          // n_dev
+    std::vector<int32_t> vsrc;        // n_vsrc*2
+    std::vector<double> vsrc_volts;   // n_vsrc
+
+    // colouring
+    bool coloured = false;
+    std::vector<uint8_t> excl;        // n_nodes (all zero = paper rule)
+    int32_t n_colors = 0;
+    std::vector<int32_t> colour;      // n_dev
+    std::vector<int32_t> perm;        // position -> device (colour-major, stable)
+    std::vector<int32_t> colour_ptr;  // n_colors+1
+
+    // pattern and map
+    bool mapped = false;
+    int32_t n_rows = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> row_ptr, col_idx;
+    std::vector<int32_t> code;        // NCODE*n_dev, colour-major SoA (tag | index)
+    std::vector<int32_t> acode;       // NCODE*n_dev, plain A/b targets (atomic variant)
+    std::vector<int32_t> fixA_idx, fixB_idx;
+    std::vector<double> fixA_val, fixB_val;
+    std::vector<int32_t> hub_ptr;     // n_hub+1 into the staging array
+    std::vector<int32_t> hub_target;  // A index, or b row | HUB_B_FLAG
+    std::vector<int32_t> hub_cptr;    // n_hub+1: chunk ranges (chunks of HUB_K)
+    std::vector<int32_t> hub_of_chunk;
+    int32_t max_hub_len = 0;
+};
+
+// Build the greedy colouring (ascending device order) and the colour-major order.
+Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges);
+// Build pattern, stamp codes, fixed stores and hub lists.
+Err build_map(HostCircuit &h);
+// Card-derived constants, in the model's operation order.
+DevCard derive_card(const cs_model_card &c);
+
+}  // namespace cs
+
+struct cs_circuit {
+    cs::HostCircuit h;
+    bool models_set = false;
+    bool params_set = false;
+    cs::DevCard card[2];               // 0 NMOS, 1 PMOS
+    int device = -1;                   // HIP device of the uploads
+    // device copies (colour-major)
+    cs::DevBuf<int32_t> d_term, d_code, d_acode, d_perm, d_cptr, d_fixA_idx, d_fixB_idx,
+        d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk;
+    cs::DevBuf<int8_t> d_pol;
+    cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_buf, d_hub_part;
+    cs::DevBuf<uint32_t> d_sync;       // barrier words + per-block arrival flags + error
+    cs::DevBuf<uint32_t> d_hub_count;
+    int32_t block = 256;
+    int32_t eval_ahead_req = -1;
+    bool cooperative = true;
+    int32_t grid = 0;                  // persistent grid
+    int32_t eval_ahead = 0;
+    int64_t spin_limit = 1 << 22;
+};
+
+struct cs_batch {
+    std::vector<cs_circuit *> circ;
+    std::vector<int64_t> dev_off, row_off, nnz_off;
+    cs::HostCircuit h;                 // block-diagonal union, packed indices
+    cs::DevCard card[2];
+    int device = -1;
+    cs::DevBuf<int32_t> d_term, d_code, d_acode, d_perm, d_cptr, d_fixA_idx, d_fixB_idx,
+        d_hub_ptr, d_hub_target, d_local;
+    cs::DevBuf<int8_t> d_pol;
+    cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage;
+    cs::DevBuf<uint32_t> d_sync;
+    int32_t block = 256;
+    int32_t eval_ahead_req = -1;
+    int32_t local_max_dev = 0;
+    int32_t grid = 0;
+    int32_t eval_ahead = 0;
+    int32_t n_local = 0;
+    int64_t spin_limit = 1 << 22;
+};

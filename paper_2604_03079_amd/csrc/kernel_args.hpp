@@ -1,0 +1,76 @@
+// Plain structs passed from the host launchers to the kernels.
+#pragma once
+#include <cstdint>
+
+namespace cs {
+
+// Number of stamp-code rows per device: k*k matrix entries plus k RHS entries for
+// k <= 4 distinct non-ground nodes.
+constexpr int NCODE = 20;
+
+// Stamp codes: bits 30..31 = tag, bits 0..29 = index.
+constexpr uint32_t TAG_ADD = 0u;    // load-add into A (or b)
+constexpr uint32_t TAG_STORE = 1u;  // plain store (first writer in colour order)
+constexpr uint32_t TAG_HUB = 2u;    // store into the hub staging array
+constexpr int32_t INDEX_LIMIT = 1 << 30;
+constexpr uint32_t HUB_B_FLAG = 0x80000000u;  // hub target is a b row
+
+// Fixed-shape hub sum: chunks of HUB_K contributions, folded left, recursively.
+constexpr int HUB_K = 256;
+// Largest hub handled by the one-workgroup reduction (level-1 partials in LDS).
+constexpr int HUB_MAX_CHUNKS = 2048;
+
+// Card-derived constants of the device model, evaluated once on the host in the
+// model's operation order.
+struct DevCard {
+    double VT, COXE, LT, LA, SQPHIS, VBM, CDEP0_SQPHIS, COXE_KS, TWO_VT, FOUR_DELTA,
+        FOUR_DELTA1_VBM, VBI_M_PHIS, K3_TOXE_PHIS, TWO_WINT, TWO_LINT, TWO_VSAT;
+    double phis, k1, k2, eta0, nfactor, cdsc, voff, u0, ua, ub, uc, toxe, delta, delta1,
+        dvt0, dvt1, dsub, w0, lambda_l, a0, cgdo;
+};
+
+// Device view of one (possibly batched) circuit in colour-major position order.
+struct KCirc {
+    int32_t n;               // devices
+    int32_t n_colors;
+    const int32_t *term;     // [4][n]: x index + 1 of d, g, s, b (0 = ground)
+    const int8_t *pol;       // [n]
+    const double *par;       // [3][n]: W, L, VTH0
+    const int32_t *code;     // [NCODE][n]
+    const int32_t *acode;    // [NCODE][n]
+    const int32_t *perm;     // [n] position -> caller's device index
+    const int32_t *cptr;     // [n_colors+1]
+    int32_t n_fixA, n_fixB;
+    const int32_t *fixA_idx;
+    const double *fixA_val;
+    const int32_t *fixB_idx;
+    const double *fixB_val;
+    int32_t n_hub;
+    const int32_t *hub_ptr;      // [n_hub+1] contribution ranges in the staging array
+    const int32_t *hub_target;
+    double *stage;
+    int32_t n_hub_chunks;        // chunks of HUB_K contributions over all hubs
+    const int32_t *hub_cptr;     // [n_hub+1] chunk ranges
+    const int32_t *hub_of_chunk; // [n_hub_chunks]
+    double *hub_part;            // [n_hub_chunks] chunk sums
+    uint32_t *hub_count;         // [n_hub] chunks done (returns to 0 after each call)
+    DevCard card[2];         // 0 NMOS, 1 PMOS
+};
+
+// Per-call operands.
+struct KCall {
+    const double *x;
+    double ag0;
+    const double *hist;      // caller order [n][4] or nullptr
+    double *A;
+    double *b;
+};
+
+// Grid-barrier state: sync[0] = release epoch, sync[1] = error word,
+// sync[2 + blk] = arrival epoch of block blk.
+struct KSync {
+    uint32_t *sync;
+    int64_t spin_limit;
+};
+
+}  // namespace cs

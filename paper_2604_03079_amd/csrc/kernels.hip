@@ -1,0 +1,455 @@
+// HIP kernels for gfx950: coloured fused evaluate-and-stamp (persistent, with
+// grid-wide barriers between colours), one-kernel-per-colour, buffered-colour and
+// atomic variants, the hub reduction, and the adjoint (VJP) kernel.
+//
+// Paper, Methodology: colours are processed sequentially; within a colour every
+// device is evaluated and stamped in parallel, no two of them touching the same
+// entry, so stamping needs neither locks nor atomics.  Table "Summary of BSIM4
+// evaluation-kernel variants" lists the schedules mirrored here.
+#include <hip/hip_runtime.h>
+
+#include "kernel_args.hpp"
+#include "launch.hpp"
+#include "model.hpp"
+#include "stamp.hpp"
+
+namespace cs {
+
+// ---- per-device helpers -----------------------------------------------------------
+
+struct DevIn {
+    int32_t t0, t1, t2, t3;
+    int key;
+};
+
+__device__ __forceinline__ DevIn load_terms(const KCirc &kc, int pos) {
+    DevIn d;
+    d.t0 = kc.term[pos];
+    d.t1 = kc.term[(size_t)kc.n + pos];
+    d.t2 = kc.term[2 * (size_t)kc.n + pos];
+    d.t3 = kc.term[3 * (size_t)kc.n + pos];
+    d.key = pattern_key(d.t0, d.t1, d.t2, d.t3);
+    return d;
+}
+
+__device__ __forceinline__ double volt(const double *x, int32_t t) { return t == 0 ? 0.0 : x[t - 1]; }
+
+// Evaluate the device at position pos; the card is chosen per polarity with a
+// wave-uniform index (one pass per polarity present in the wave).
+__device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, int pos,
+                                           const DevIn &d) {
+    const int isP = kc.pol[pos] < 0 ? 1 : 0;
+    const double W = kc.par[pos];
+    const double L = kc.par[(size_t)kc.n + pos];
+    const double VTH0 = kc.par[2 * (size_t)kc.n + pos];
+    const double Vd = volt(call.x, d.t0), Vg = volt(call.x, d.t1);
+    const double Vs = volt(call.x, d.t2), Vb = volt(call.x, d.t3);
+    const double *hist = call.hist ? call.hist + 4 * (size_t)kc.perm[pos] : nullptr;
+    DevOut o;
+    for (;;) {
+        const int p0 = __builtin_amdgcn_readfirstlane(isP);
+        if (isP == p0) {
+            const DevCard &cd = kc.card[p0];
+            const double p = p0 ? -1.0 : 1.0;
+            const SizeDep sd = size_dep(cd, p, W, L, VTH0);
+            o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist);
+            break;
+        }
+    }
+    return o;
+}
+
+template <bool COHERENT>
+__device__ __forceinline__ void stamp_colour(const KCirc &kc, const KCall &call, int pos,
+                                             const DevIn &d, const DevOut &o) {
+    double Y[16];
+    full_Y(o, Y);
+    const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+    ColourSinkT<COHERENT> sink{kc.code, kc.n, pos, call.A, call.b, kc.stage};
+    emit_merged(d.key, Y, bl, sink);
+}
+
+template <int K, class Sink>
+__device__ __forceinline__ void stamp_k(Sink &sink, const double *buf, int n, int pos) {
+    double m[K * K + K];
+#pragma unroll
+    for (int j = 0; j < K * K + K; ++j) m[j] = buf[(size_t)j * n + pos];
+    sink.template stamp<K * K, K>(m);
+}
+template <class Sink>
+__device__ __forceinline__ void stamp_from_buffer(Sink &sink, const double *buf, int n, int pos, int k) {
+    for (;;) {
+        const int k0 = __builtin_amdgcn_readfirstlane(k);
+        if (k == k0) {
+            switch (k0) {
+                case 1: stamp_k<1>(sink, buf, n, pos); break;
+                case 2: stamp_k<2>(sink, buf, n, pos); break;
+                case 3: stamp_k<3>(sink, buf, n, pos); break;
+                case 4: stamp_k<4>(sink, buf, n, pos); break;
+                default: break;
+            }
+            break;
+        }
+    }
+}
+
+// Voltage-source stamps and entries no device writes (grid-stride).
+__device__ __forceinline__ void fixed_stores(const KCirc &kc, const KCall &call, int tid,
+                                             int nthreads) {
+    for (int i = tid; i < kc.n_fixA; i += nthreads) call.A[kc.fixA_idx[i]] = kc.fixA_val[i];
+    for (int i = tid; i < kc.n_fixB; i += nthreads) call.b[kc.fixB_idx[i]] = kc.fixB_val[i];
+}
+
+__device__ __forceinline__ double ld_coherent(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Left fold of n values in LDS by one thread.
+__device__ __forceinline__ double fold_lds(const double *v, int n) {
+    double s = v[0];
+    for (int i = 1; i < n; ++i) s = s + v[i];
+    return s;
+}
+
+__device__ __forceinline__ void hub_store(const KCirc &kc, const KCall &call, int h, double s) {
+    const uint32_t tgt = (uint32_t)kc.hub_target[h];
+    if (tgt & HUB_B_FLAG) call.b[tgt & ~HUB_B_FLAG] = s;
+    else call.A[tgt] = s;
+}
+
+// Fixed-shape hub sum (contributions in ascending device index; chunks of HUB_K
+// folded left; the chunk sums reduced the same way).  Work item = one chunk per
+// wave: the wave loads the chunk into its LDS slice with coalesced loads, lane 0
+// folds it.  The wave that completes the last chunk of a hub (a coherent counter)
+// folds the chunk sums, so no grid barrier is needed.  Every wave of the block
+// calls this (it contains workgroup barriers).  lds: (blockDim/64)*HUB_K doubles.
+__device__ void hub_chunks(const KCirc &kc, const KCall &call, int wave0, int nwaves, double *lds) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    double *mine = lds + (size_t)wave * HUB_K;
+    const int rounds = (kc.n_hub_chunks + nwaves - 1) / nwaves;
+    for (int r = 0; r < rounds; ++r) {
+        const int q = wave0 + wave + r * nwaves;
+        int h = 0, e = 0, nchunk = 0;
+        if (q < kc.n_hub_chunks) {
+            h = kc.hub_of_chunk[q];
+            const int j = q - kc.hub_cptr[h];
+            nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
+            const int beg = kc.hub_ptr[h];
+            e = min(HUB_K, kc.hub_ptr[h + 1] - beg - j * HUB_K);
+            for (int t = lane; t < e; t += 64) mine[t] = ld_coherent(kc.stage + beg + (size_t)j * HUB_K + t);
+        }
+        __syncthreads();
+        int last = 0;
+        if (q < kc.n_hub_chunks && lane == 0) {
+            const double s = fold_lds(mine, e);
+            if (nchunk == 1) {
+                hub_store(kc, call, h, s);
+            } else {
+                st_coherent(kc.hub_part + q, s);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                const uint32_t done = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                last = done + 1 == (uint32_t)nchunk;
+            }
+        }
+        last = __shfl(last, 0, 64);
+        __syncthreads();
+        if (last) {
+            // level 1 and up, by this wave: chunk sums of HUB_K partials, then the
+            // (at most HUB_MAX_CHUNKS / HUB_K) level-1 sums folded by lane 0
+            const int c0 = kc.hub_cptr[h];
+            double lvl1 = 0.0;
+            const int n1 = (nchunk + HUB_K - 1) / HUB_K;   // <= HUB_MAX_CHUNKS / HUB_K
+            for (int g = 0; g < n1; ++g) {
+                const int ee = min(HUB_K, nchunk - g * HUB_K);
+                for (int t = lane; t < ee; t += 64) mine[t] = ld_coherent(kc.hub_part + c0 + (size_t)g * HUB_K + t);
+                __builtin_amdgcn_s_waitcnt(0);
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    const double f = fold_lds(mine, ee);
+                    lvl1 = g == 0 ? f : lvl1 + f;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (lane == 0) {
+                hub_store(kc, call, h, lvl1);
+                __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
+    (void)wpb;
+}
+
+// ---- grid barrier -----------------------------------------------------------------
+// Every access to data shared between colour phases (A, b, hub staging) is an
+// agent-scope coherent access, so the barrier only has to order them: each wave
+// waits for its outstanding memory operations (s_waitcnt 0) before the workgroup
+// barrier, block i > 0 then publishes its arrival epoch in its own word, block 0
+// polls all arrival words in parallel and releases everyone through one word.
+// Every wait is bounded by spin_limit; on expiry the error word is set and all
+// later waits fall through, so the grid always drains.
+__device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void drain_memory() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ void grid_barrier(const KSync &ks, uint32_t epoch) {
+    uint32_t *rel = ks.sync;
+    uint32_t *err = ks.sync + 1;
+    uint32_t *arr = ks.sync + 2;
+    drain_memory();
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (uint32_t i = threadIdx.x + 1; i < gridDim.x; i += blockDim.x) {
+            int64_t spins = 0;
+            while (ld_flag(arr + i) != epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 63) == 0 && (spins > ks.spin_limit || ld_flag(err) != 0)) {
+                    st_flag(err, 1u);
+                    break;
+                }
+            }
+        }
+        drain_memory();
+        __syncthreads();
+        if (threadIdx.x == 0) st_flag(rel, epoch);
+    } else if (threadIdx.x == 0) {
+        st_flag(arr + blockIdx.x, epoch);
+        int64_t spins = 0;
+        while (ld_flag(rel) != epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 63) == 0 && (spins > ks.spin_limit || ld_flag(err) != 0)) {
+                st_flag(err, 1u);
+                break;
+            }
+        }
+    }
+    drain_memory();
+    __syncthreads();
+}
+
+// ---- kernels ----------------------------------------------------------------------
+
+__global__ void k_gather_params(int32_t n, const int32_t *perm, const double *W, const double *L,
+                                const double *V, double *par) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const int32_t v = perm[p];
+        par[p] = W[v];
+        par[(size_t)n + p] = L[v];
+        par[2 * (size_t)n + p] = V[v];
+    }
+}
+
+// One colour per launch (the per-colour parallel-for schedule).
+__global__ void __launch_bounds__(256) k_colour_phase(KCirc kc, KCall call, int32_t c,
+                                                      int32_t with_fixed) {
+    const int beg = kc.cptr[c], end = kc.cptr[c + 1];
+    for (int pos = beg + blockIdx.x * blockDim.x + threadIdx.x; pos < end;
+         pos += gridDim.x * blockDim.x) {
+        const DevIn d = load_terms(kc, pos);
+        const DevOut o = eval_pos(kc, call, pos, d);
+        stamp_colour<false>(kc, call, pos, d, o);
+    }
+    if (with_fixed) fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ void k_fixed(KCirc kc, KCall call) {
+    fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
+    __shared__ double lds[4 * HUB_K];
+    hub_chunks(kc, call, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
+}
+
+// Persistent coloured kernel.  MODE 0: evaluate inside each colour phase (grid-
+// stride).  MODE 1: every thread evaluates its own device before the first phase
+// and keeps the local values in registers (requires grid*block >= n).  MODE 2:
+// stamp phases only, merged values read from the buffer of k_eval_buffer.
+template <int MODE>
+__device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &call,
+                                                const KSync &ks, const double *buf) {
+    __shared__ double lds[4 * HUB_K];
+    __shared__ uint32_t base_s;
+    if (threadIdx.x == 0) base_s = ld_flag(ks.sync);
+    __syncthreads();
+    const uint32_t base = base_s;
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nthr = gridDim.x * blockDim.x;
+
+    DevIn d{};
+    DevOut o{};
+    if constexpr (MODE == 1) {
+        if (gtid < kc.n) {
+            d = load_terms(kc, gtid);
+            o = eval_pos(kc, call, gtid, d);
+        }
+    }
+    fixed_stores(kc, call, gtid, nthr);
+    uint32_t epoch = base;
+    for (int c = 0; c < kc.n_colors; ++c) {
+        const int beg = kc.cptr[c], end = kc.cptr[c + 1];
+        if constexpr (MODE == 1) {
+            if (gtid >= beg && gtid < end) stamp_colour<true>(kc, call, gtid, d, o);
+        } else {
+            for (int pos = beg + gtid; pos < end; pos += nthr) {
+                const DevIn dd = load_terms(kc, pos);
+                if constexpr (MODE == 0) {
+                    const DevOut oo = eval_pos(kc, call, pos, dd);
+                    stamp_colour<true>(kc, call, pos, dd, oo);
+                } else {
+                    const int k = (dd.t0 != 0) + (dd.t1 != 0 && dd.t1 != dd.t0) +
+                                  (dd.t2 != 0 && dd.t2 != dd.t0 && dd.t2 != dd.t1) +
+                                  (dd.t3 != 0 && dd.t3 != dd.t0 && dd.t3 != dd.t1 && dd.t3 != dd.t2);
+                    ColourSinkT<true> sink{kc.code, kc.n, pos, call.A, call.b, kc.stage};
+                    stamp_from_buffer(sink, buf, kc.n, pos, k);
+                }
+            }
+        }
+        if (c + 1 < kc.n_colors || kc.n_hub > 0) grid_barrier(ks, ++epoch);
+    }
+    hub_chunks(kc, call, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
+}
+
+__global__ void __launch_bounds__(256) k_persistent_phase(KCirc kc, KCall call, KSync ks,
+                                                          const double *buf) {
+    persistent_body<0>(kc, call, ks, buf);
+}
+// Evaluate-ahead holds one device's local values per thread across the colour
+// phases; it needs every device resident at once, hence four waves per SIMD.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_persistent_ahead(KCirc kc, KCall call, KSync ks, const double *buf) {
+    persistent_body<1>(kc, call, ks, buf);
+}
+__global__ void __launch_bounds__(256) k_persistent_stamp(KCirc kc, KCall call, KSync ks,
+                                                          const double *buf) {
+    persistent_body<2>(kc, call, ks, buf);
+}
+
+// Evaluate every device and write its merged values (buffered variant).
+__global__ void __launch_bounds__(256) k_eval_buffer(KCirc kc, KCall call, double *buf) {
+    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < kc.n; pos += gridDim.x * blockDim.x) {
+        const DevIn d = load_terms(kc, pos);
+        const DevOut o = eval_pos(kc, call, pos, d);
+        double Y[16];
+        full_Y(o, Y);
+        const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+        BufferSink sink{buf, kc.n, pos};
+        emit_merged(d.key, Y, bl, sink);
+    }
+}
+
+__global__ void k_fill_zero(double *A, int64_t nA, double *b, int64_t nb) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nA + nb;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nA) A[i] = 0.0; else b[i - nA] = 0.0;
+    }
+}
+
+// Atomic variant: no colouring; every contribution is an FP64 atomic add.
+__global__ void __launch_bounds__(256) k_atomic(KCirc kc, KCall call) {
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
+    for (int pos = gtid; pos < kc.n; pos += nthr) {
+        const DevIn d = load_terms(kc, pos);
+        const DevOut o = eval_pos(kc, call, pos, d);
+        double Y[16];
+        full_Y(o, Y);
+        const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+        AtomicSink sink{kc.acode, kc.n, pos, call.A, call.b};
+        emit_merged(d.key, Y, bl, sink);
+    }
+    fixed_stores(kc, call, gtid, nthr);
+}
+
+// ---- host launchers ----------------------------------------------------------------
+
+static hipError_t occupancy(const void *fn, int block, int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
+}
+
+hipError_t persistent_capacity(int mode, int block, int *blocks_per_cu) {
+    const void *fn = mode == 1 ? (const void *)k_persistent_ahead
+                   : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
+    return occupancy(fn, block, blocks_per_cu);
+}
+
+hipError_t launch_gather_params(int32_t n, const int32_t *perm, const double *W, const double *L,
+                                const double *V, double *par, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_gather_params, dim3(grid), dim3(256), 0, s, n, perm, W, L, V, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_colour_phase(const KCirc &kc, const KCall &call, int c, int count,
+                               int with_fixed, hipStream_t s) {
+    int grid = (count + 255) / 256;
+    if (with_fixed) grid = max(grid, min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
+    grid = max(grid, 1);
+    hipLaunchKernelGGL(k_colour_phase, dim3(grid), dim3(256), 0, s, kc, call, c, with_fixed);
+    return hipGetLastError();
+}
+
+hipError_t launch_fixed(const KCirc &kc, const KCall &call, hipStream_t s) {
+    const int grid = std::max(1, std::min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
+    hipLaunchKernelGGL(k_fixed, dim3(grid), dim3(256), 0, s, kc, call);
+    return hipGetLastError();
+}
+
+hipError_t launch_hub(const KCirc &kc, const KCall &call, hipStream_t s) {
+    if (kc.n_hub == 0) return hipSuccess;
+    const int grid = min((kc.n_hub_chunks + 3) / 4, 4096);
+    hipLaunchKernelGGL(k_hub, dim3(grid), dim3(256), 0, s, kc, call);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks,
+                             const double *buf, int mode, int grid, int block, bool cooperative,
+                             hipStream_t s) {
+    KCirc a = kc;
+    KCall b = call;
+    KSync c = ks;
+    const double *d = buf;
+    void *args[] = {&a, &b, &c, &d};
+    const void *fn = mode == 1 ? (const void *)k_persistent_ahead
+                   : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
+    if (!cooperative) return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, s);
+}
+
+hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s) {
+    if (kc.n == 0) return hipSuccess;
+    const int grid = (kc.n + 255) / 256;
+    hipLaunchKernelGGL(k_eval_buffer, dim3(grid), dim3(256), 0, s, kc, call, buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,
+                         hipStream_t s) {
+    const int64_t tot = nnz + n_rows;
+    const int gz = (int)std::min<int64_t>((tot + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_zero, dim3(std::max(gz, 1)), dim3(256), 0, s, call.A, nnz, call.b, n_rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int grid = (kc.n + 255) / 256;
+    grid = std::max(grid, std::min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
+    hipLaunchKernelGGL(k_atomic, dim3(std::max(grid, 1)), dim3(256), 0, s, kc, call);
+    return hipGetLastError();
+}
+
+}  // namespace cs

@@ -1,0 +1,27 @@
+// Host launchers of the HIP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernel_args.hpp"
+
+namespace cs {
+
+// Resident blocks per CU of the persistent kernel in `mode` (0 phase-evaluate,
+// 1 evaluate-ahead, 2 stamp from buffer) at `block` threads.
+hipError_t persistent_capacity(int mode, int block, int *blocks_per_cu);
+hipError_t launch_gather_params(int32_t n, const int32_t *perm, const double *W, const double *L,
+                                const double *V, double *par, hipStream_t s);
+hipError_t launch_colour_phase(const KCirc &kc, const KCall &call, int c, int count,
+                               int with_fixed, hipStream_t s);
+hipError_t launch_fixed(const KCirc &kc, const KCall &call, hipStream_t s);
+hipError_t launch_hub(const KCirc &kc, const KCall &call, hipStream_t s);
+// cooperative: hipLaunchCooperativeKernel (the runtime checks co-residency);
+// otherwise an ordinary launch of a grid the occupancy query says fits at once.
+hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks,
+                             const double *buf, int mode, int grid, int block, bool cooperative,
+                             hipStream_t s);
+hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s);
+hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,
+                         hipStream_t s);
+
+}  // namespace cs

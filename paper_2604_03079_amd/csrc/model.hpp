@@ -1,0 +1,370 @@
+// Device model M (BSIM4-core subset) for gfx950, FP64, one device per lane.
+//
+// The paper evaluates BSIM 4.82 (Methodology, experimental setup) and prints no
+// model equations; model M is the project's subset of the published BSIM4 equation
+// forms: threshold voltage with body effect, SCE, DIBL and narrow width; unified
+// Vgsteff; vertical-field mobility degradation; velocity-saturation Vdsat and the
+// smoothed Vdseff; channel-length modulation; charge-conserving inversion/depletion
+// charges with a 50/50 partition and overlap charges.
+//
+// Every operation below is a correctly rounded IEEE binary64 +, -, *, /, sqrt (or an
+// exact rint/ldexp/sign change) in a fixed order, with no contraction (the library is
+// built with -ffp-contract=off), so a serial CPU evaluation in the same order gives
+// the same bits.  Partial derivatives w.r.t. the three frame voltages travel with
+// each value ("Dual3"):
+//   a*b -> (ab, a_i b + a b_i);  a/b -> q = a/b, q_i = (a_i - q b_i)/b;
+//   c/b -> q = c/b, q_i = (-(q b_i))/b;  sqrt(a) -> s, s_i = (0.5 a_i)/s;
+//   exp(a) -> e, e_i = e a_i;  softplus(a) -> sp, sp_i = sigma(a) a_i;
+//   c*a and a/c scale all four components; a +- c changes the value only;
+//   c - a negates the partials.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernel_args.hpp"
+
+namespace cs {
+
+// ---- elementary functions -----------------------------------------------------
+// exp: Cody-Waite reduction by ln 2 (k = rint(a/ln 2), ln 2 split into a 32-bit head
+// and a correctly rounded tail), degree-13 Taylor polynomial in Horner form with
+// coefficients RN(1/j!), exact scaling by 2^k.  Valid for |a| <= 40.
+__device__ __forceinline__ double pexp(double a) {
+    constexpr double INV_LN2 = 0x1.71547652b82fep+0;
+    constexpr double LN2_HI = 0x1.62e42feep-1;
+    constexpr double LN2_LO = 0x1.a39ef35793c76p-33;
+    const double k = __builtin_rint(a * INV_LN2);
+    const double r = (a - k * LN2_HI) - k * LN2_LO;
+    double p = 0x1.6124613a86d09p-33;   // 1/13!
+    p = p * r + 0x1.1eed8eff8d898p-29;  // 1/12!
+    p = p * r + 0x1.ae64567f544e4p-26;  // 1/11!
+    p = p * r + 0x1.27e4fb7789f5cp-22;  // 1/10!
+    p = p * r + 0x1.71de3a556c734p-19;  // 1/9!
+    p = p * r + 0x1.a01a01a01a01ap-16;  // 1/8!
+    p = p * r + 0x1.a01a01a01a01ap-13;  // 1/7!
+    p = p * r + 0x1.6c16c16c16c17p-10;  // 1/6!
+    p = p * r + 0x1.1111111111111p-7;   // 1/5!
+    p = p * r + 0x1.5555555555555p-5;   // 1/4!
+    p = p * r + 0x1.5555555555555p-3;   // 1/3!
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return __builtin_ldexp(p, (int)k);
+}
+
+// log1p on [0, 1]: 2*atanh(s), s = y/(2+y), series sum_{j<17} s^(2j)/(2j+1), Horner.
+__device__ __forceinline__ double plog1p(double y) {
+    const double s = y / (2.0 + y);
+    const double z = s * s;
+    double p = 0x1.f07c1f07c1f08p-6;    // 1/33
+    p = p * z + 0x1.0842108421084p-5;   // 1/31
+    p = p * z + 0x1.1a7b9611a7b96p-5;   // 1/29
+    p = p * z + 0x1.2f684bda12f68p-5;   // 1/27
+    p = p * z + 0x1.47ae147ae147bp-5;   // 1/25
+    p = p * z + 0x1.642c8590b2164p-5;   // 1/23
+    p = p * z + 0x1.8618618618618p-5;   // 1/21
+    p = p * z + 0x1.af286bca1af28p-5;   // 1/19
+    p = p * z + 0x1.e1e1e1e1e1e1ep-5;   // 1/17
+    p = p * z + 0x1.1111111111111p-4;   // 1/15
+    p = p * z + 0x1.3b13b13b13b14p-4;   // 1/13
+    p = p * z + 0x1.745d1745d1746p-4;   // 1/11
+    p = p * z + 0x1.c71c71c71c71cp-4;   // 1/9
+    p = p * z + 0x1.2492492492492p-3;   // 1/7
+    p = p * z + 0x1.999999999999ap-3;   // 1/5
+    p = p * z + 0x1.5555555555555p-2;   // 1/3
+    p = p * z + 1.0;
+    return (2.0 * s) * p;
+}
+
+__device__ __forceinline__ double pcosh(double u) {
+    const double e = pexp(u);
+    return 0.5 * (e + 1.0 / e);
+}
+
+// ---- scalar types ------------------------------------------------------------------
+// The model is written once for a scalar type S: plain double (the stamped values,
+// bit-exact) or Tan, a value with one tangent w.r.t. a device parameter (the
+// adjoint's forward-mode sweeps).  Branches are decided on values.
+struct Tan {
+    double v, t;
+    Tan() = default;
+    __device__ __forceinline__ Tan(double x) : v(x), t(0.0) {}
+    __device__ __forceinline__ Tan(double x, double dx) : v(x), t(dx) {}
+};
+__device__ __forceinline__ Tan operator+(Tan a, Tan b) { return {a.v + b.v, a.t + b.t}; }
+__device__ __forceinline__ Tan operator-(Tan a, Tan b) { return {a.v - b.v, a.t - b.t}; }
+__device__ __forceinline__ Tan operator-(Tan a) { return {-a.v, -a.t}; }
+__device__ __forceinline__ Tan operator*(Tan a, Tan b) { return {a.v * b.v, a.t * b.v + a.v * b.t}; }
+__device__ __forceinline__ Tan operator/(Tan a, Tan b) {
+    const double q = a.v / b.v;
+    return {q, (a.t - q * b.t) / b.v};
+}
+__device__ __forceinline__ Tan operator+(Tan a, double b) { return {a.v + b, a.t}; }
+__device__ __forceinline__ Tan operator+(double a, Tan b) { return {a + b.v, b.t}; }
+__device__ __forceinline__ Tan operator-(Tan a, double b) { return {a.v - b, a.t}; }
+__device__ __forceinline__ Tan operator-(double a, Tan b) { return {a - b.v, -b.t}; }
+__device__ __forceinline__ Tan operator*(double a, Tan b) { return {a * b.v, a * b.t}; }
+__device__ __forceinline__ Tan operator*(Tan a, double b) { return {a.v * b, a.t * b}; }
+__device__ __forceinline__ Tan operator/(Tan a, double b) { return {a.v / b, a.t / b}; }
+__device__ __forceinline__ Tan operator/(double a, Tan b) {
+    const double q = a / b.v;
+    return {q, (-(q * b.t)) / b.v};
+}
+
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ double val(const Tan &x) { return x.v; }
+__device__ __forceinline__ double gsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ Tan gsqrt(Tan x) {
+    const double s = __builtin_sqrt(x.v);
+    return {s, (0.5 * x.t) / s};
+}
+__device__ __forceinline__ double gabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ Tan gabs(Tan x) { return x.v >= 0.0 ? x : -x; }
+__device__ __forceinline__ double gexp(double a) { return pexp(a); }
+__device__ __forceinline__ Tan gexp(Tan a) {
+    const double e = pexp(a.v);
+    return {e, e * a.t};
+}
+__device__ __forceinline__ double glog1p(double y) { return plog1p(y); }
+__device__ __forceinline__ Tan glog1p(Tan y) { return {plog1p(y.v), y.t / (1.0 + y.v)}; }
+template <class S>
+__device__ __forceinline__ S gcosh(S u) {
+    const S e = gexp(u);
+    return 0.5 * (e + 1.0 / e);
+}
+
+// ---- values with three partials -------------------------------------------------
+template <class S>
+struct Dual3T {
+    S v, d0, d1, d2;
+};
+
+template <class S>
+__device__ __forceinline__ Dual3T<S> seed(double v, int k) {
+    return {S(v), S(k == 0 ? 1.0 : 0.0), S(k == 1 ? 1.0 : 0.0), S(k == 2 ? 1.0 : 0.0)};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> operator+(Dual3T<S> a, Dual3T<S> b) {
+    return {a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> operator-(Dual3T<S> a, Dual3T<S> b) {
+    return {a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> operator-(Dual3T<S> a) { return {-a.v, -a.d0, -a.d1, -a.d2}; }
+template <class S, class C>
+__device__ __forceinline__ Dual3T<S> plus_c(Dual3T<S> a, C c) { return {a.v + c, a.d0, a.d1, a.d2}; }
+template <class S, class C>
+__device__ __forceinline__ Dual3T<S> minus_c(Dual3T<S> a, C c) { return {a.v - c, a.d0, a.d1, a.d2}; }
+template <class S, class C>
+__device__ __forceinline__ Dual3T<S> c_minus(C c, Dual3T<S> a) { return {c - a.v, -a.d0, -a.d1, -a.d2}; }
+template <class S, class C>
+__device__ __forceinline__ Dual3T<S> scale(C c, Dual3T<S> a) {
+    return {c * a.v, c * a.d0, c * a.d1, c * a.d2};
+}
+template <class S, class C>
+__device__ __forceinline__ Dual3T<S> over_c(Dual3T<S> a, C c) {
+    return {a.v / c, a.d0 / c, a.d1 / c, a.d2 / c};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> operator*(Dual3T<S> a, Dual3T<S> b) {
+    return {a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> operator/(Dual3T<S> a, Dual3T<S> b) {
+    const S q = a.v / b.v;
+    return {q, (a.d0 - q * b.d0) / b.v, (a.d1 - q * b.d1) / b.v, (a.d2 - q * b.d2) / b.v};
+}
+template <class S, class C>
+__device__ __forceinline__ Dual3T<S> c_over(C c, Dual3T<S> b) {
+    const S q = c / b.v;
+    return {q, (-(q * b.d0)) / b.v, (-(q * b.d1)) / b.v, (-(q * b.d2)) / b.v};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> dsqrt(Dual3T<S> a) {
+    const S s = gsqrt(a.v);
+    return {s, (0.5 * a.d0) / s, (0.5 * a.d1) / s, (0.5 * a.d2) / s};
+}
+template <class S>
+__device__ __forceinline__ Dual3T<S> dexp(Dual3T<S> a) {
+    const S e = gexp(a.v);
+    return {e, e * a.d0, e * a.d1, e * a.d2};
+}
+// softplus(t) = max(t, 0) + log1p(e^-|t|); its derivative sigma(t) = 1/(1+e) for
+// t >= 0, e/(1+e) otherwise, e = e^-|t|.
+template <class S>
+__device__ __forceinline__ Dual3T<S> dsoftplus(Dual3T<S> a) {
+    const S t = a.v;
+    const S e = gexp(-gabs(t));
+    const S sp = (val(t) > 0.0 ? t : S(0.0)) + glog1p(e);
+    const S dn = 1.0 + e;
+    const S sg = val(t) >= 0.0 ? 1.0 / dn : e / dn;
+    return {sp, sg * a.d0, sg * a.d1, sg * a.d2};
+}
+
+// Size-dependent constants of one device (depend on W, L, VTH0 only).
+template <class S>
+struct SizeDepT {
+    S Leff, vth_s, theta_dibl, theta_sce, beta0, lambda, AbL, Cg, Cov;
+};
+
+template <class S>
+__device__ __forceinline__ SizeDepT<S> size_dep(const DevCard &cd, double pol, S W, S L, S VTH0) {
+    SizeDepT<S> s;
+    const S Weff = W - cd.TWO_WINT;
+    s.Leff = L - cd.TWO_LINT;
+    const S VTH0i = pol * VTH0;
+    s.theta_sce = 0.5 / (gcosh((cd.dvt1 * s.Leff) / cd.LT) - 1.0);
+    s.theta_dibl = 0.5 / (gcosh((cd.dsub * s.Leff) / cd.LT) - 1.0);
+    s.vth_s = (VTH0i - (cd.dvt0 * s.theta_sce) * cd.VBI_M_PHIS) + cd.K3_TOXE_PHIS / (Weff + cd.w0);
+    s.beta0 = (Weff * cd.COXE) / s.Leff;
+    s.lambda = cd.lambda_l / s.Leff;
+    s.AbL = (cd.a0 * s.Leff) / (s.Leff + cd.LA);
+    s.Cg = (Weff * s.Leff) * cd.COXE;
+    s.Cov = cd.cgdo * Weff;
+    return s;
+}
+
+// Local outputs of one device: the 9 independent entries of Y (rows/cols d, g, b;
+// the s row and column follow from conservation) and the local RHS.
+template <class S>
+struct DevOutT {
+    S Ydd, Ydg, Ydb, Ygd, Ygg, Ygb, Ybd, Ybg, Ybb;
+    S bd, bg, bs, bb;
+};
+
+// Model M at terminal voltages V = (Vd, Vg, Vs, Vb).
+template <class S>
+__device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, const SizeDepT<S> &sd,
+                                                 double Vd, double Vg, double Vs, double Vb,
+                                                 double ag0, const double *hist) {
+    using D = Dual3T<S>;
+    const double vds = p * (Vd - Vs), vgs = p * (Vg - Vs), vbs = p * (Vb - Vs);
+    const bool fwd = vds >= 0.0;
+    const double x1 = fwd ? vds : -vds;
+    const double x2 = fwd ? vgs : vgs - vds;
+    const double x3 = fwd ? vbs : vbs - vds;
+    const D X1 = seed<S>(x1, 0), X2 = seed<S>(x2, 1), X3 = seed<S>(x3, 2);
+
+    // effective body bias and body factor
+    const D T0 = minus_c(c_minus(cd.VBM, X3), cd.delta1);
+    const D sq0 = dsqrt(plus_c(T0 * T0, cd.FOUR_DELTA1_VBM));
+    const D Vbseff = c_minus(cd.VBM, scale(0.5, T0 + sq0));
+    const D sqPs = dsqrt(c_minus(cd.phis, Vbseff));
+    // threshold voltage
+    const D Vth = (plus_c(scale(cd.k1, minus_c(sqPs, cd.SQPHIS)), sd.vth_s) - scale(cd.k2, Vbseff))
+                  - scale(cd.eta0 * sd.theta_dibl, X1);
+    // subthreshold swing factor
+    const D Cdep = c_over(cd.CDEP0_SQPHIS, sqPs);
+    const D n = plus_c(plus_c(over_c(scale(cd.nfactor, Cdep), cd.COXE), 1.0),
+                       (cd.cdsc * sd.theta_sce) / cd.COXE);
+    const D nvt = scale(cd.VT, n);
+    const D Vgst = X2 - Vth;
+    // unified effective gate overdrive
+    const D h = scale(0.5, Vgst);
+    const D num6 = nvt * dsoftplus(h / nvt);
+    const D ex6 = dexp((-minus_c(h, cd.voff)) / nvt);
+    const D den6 = plus_c(scale(cd.COXE_KS, n) * ex6, 0.5);
+    const D Vgsteff = num6 / den6;
+    // mobility
+    const D Ee = over_c(Vgsteff + scale(2.0, Vth), cd.toxe);
+    const D mden = plus_c(plus_c(scale(cd.uc, Vbseff), cd.ua) * Ee, 1.0) + scale(cd.ub, Ee * Ee);
+    const D mu = c_over(cd.u0, mden);
+    // saturation
+    const D EsatL = c_over(cd.TWO_VSAT * sd.Leff, mu);
+    const D Abulk = plus_c(c_over(cd.k1 * sd.AbL, scale(2.0, sqPs)), 1.0);
+    const D V2 = plus_c(Vgsteff, cd.TWO_VT);
+    const D Vdsat = (EsatL * V2) / ((Abulk * EsatL) + V2);
+    const D T1 = minus_c(Vdsat - X1, cd.delta);
+    const D sq1 = dsqrt((T1 * T1) + scale(cd.FOUR_DELTA, Vdsat));
+    const D Vdseff = Vdsat - scale(0.5, T1 + sq1);
+    // drain current with channel-length modulation
+    const D c11 = (scale(sd.beta0, mu) * Vgsteff) * Vdseff;
+    const D f11 = c_minus(1.0, (Abulk * Vdseff) / scale(2.0, V2));
+    const D g11 = plus_c(Vdseff / EsatL, 1.0);
+    const D Ids0 = (c11 * f11) / g11;
+    const D Ids = Ids0 * plus_c(scale(sd.lambda, X1 - Vdseff), 1.0);
+    // charges
+    const D Vdc = Vgsteff / Abulk;
+    const D T2 = minus_c(Vdc - X1, cd.delta);
+    const D sq2 = dsqrt((T2 * T2) + scale(cd.FOUR_DELTA, Vdc));
+    const D Vdcv = Vdc - scale(0.5, T2 + sq2);
+    const D AV = Abulk * Vdcv;
+    const D Tq = Vgsteff - scale(0.5, AV);
+    const D Qinv = scale(-sd.Cg, Tq + (AV * AV) / scale(12.0, Tq));
+    const D Qb = scale(-(sd.Cg * cd.k1), sqPs);
+    const D hQ = scale(0.5, Qinv);
+    const D Qd = hQ - scale(sd.Cov, X2 - X1);
+    const D Qs = hQ - scale(sd.Cov, X2);
+    const D Qg = -((Qd + Qs) + Qb);
+
+    // frame partials -> partials w.r.t. (vds, vgs, vbs); reverse mode swaps d and s
+    auto term = [&](const D &f, S &gd, S &gg, S &gb) {
+        if (fwd) { gd = f.d0; gg = f.d1; gb = f.d2; }
+        else { gd = ((-f.d0) - f.d1) - f.d2; gg = f.d1; gb = f.d2; }
+    };
+    S iD, iG, iB, qdD, qdG, qdB, qsD, qsG, qsB, qgD, qgG, qgB, qbD, qbG, qbB;
+    term(Ids, iD, iG, iB);
+    term(Qd, qdD, qdG, qdB);
+    term(Qs, qsD, qsG, qsB);
+    term(Qg, qgD, qgG, qgB);
+    term(Qb, qbD, qbG, qbB);
+    S Idp, Qdp, Qsp;
+    if (fwd) {
+        Idp = Ids.v; Qdp = Qd.v; Qsp = Qs.v;
+    } else {
+        Idp = -Ids.v; Qdp = Qs.v; Qsp = Qd.v;
+        iD = -iD; iG = -iG; iB = -iB;
+        S t;
+        t = qdD; qdD = qsD; qsD = t;
+        t = qdG; qdG = qsG; qsG = t;
+        t = qdB; qdB = qsB; qsB = t;
+    }
+    (void)qsD; (void)qsG; (void)qsB;
+
+    DevOutT<S> o;
+    o.Ydd = iD + ag0 * qdD; o.Ydg = iG + ag0 * qdG; o.Ydb = iB + ag0 * qdB;
+    o.Ygd = ag0 * qgD;      o.Ygg = ag0 * qgG;      o.Ygb = ag0 * qgB;
+    o.Ybd = ag0 * qbD;      o.Ybg = ag0 * qbG;      o.Ybb = ag0 * qbB;
+    const S Ysd = -((o.Ydd + o.Ygd) + o.Ybd);
+    const S Ysg = -((o.Ydg + o.Ygg) + o.Ybg);
+    const S Ysb = -((o.Ydb + o.Ygb) + o.Ybb);
+
+    // physical terminal currents and charges
+    const S I_d = p * Idp, I_s = p * (-Idp);
+    const S Q_d = p * Qdp, Q_g = p * Qg.v, Q_s = p * Qsp, Q_b = p * Qb.v;
+    const double dvd = Vd - Vs, dvg = Vg - Vs, dvb = Vb - Vs;
+    o.bd = (((o.Ydd * dvd + o.Ydg * dvg) + o.Ydb * dvb) - I_d) - ag0 * Q_d;
+    o.bg = (((o.Ygd * dvd + o.Ygg * dvg) + o.Ygb * dvb) - 0.0) - ag0 * Q_g;
+    o.bs = (((Ysd * dvd + Ysg * dvg) + Ysb * dvb) - I_s) - ag0 * Q_s;
+    o.bb = (((o.Ybd * dvd + o.Ybg * dvg) + o.Ybb * dvb) - 0.0) - ag0 * Q_b;
+    if (hist) {
+        o.bd = o.bd + hist[0];
+        o.bg = o.bg + hist[1];
+        o.bs = o.bs + hist[2];
+        o.bb = o.bb + hist[3];
+    }
+    return o;
+}
+
+// The full local matrix, rows and columns (d, g, s, b), in the same order of
+// operations the conservation rules define.
+template <class S>
+__device__ __forceinline__ void full_Y(const DevOutT<S> &o, S Y[16]) {
+    Y[0] = o.Ydd; Y[1] = o.Ydg; Y[3] = o.Ydb;
+    Y[4] = o.Ygd; Y[5] = o.Ygg; Y[7] = o.Ygb;
+    Y[12] = o.Ybd; Y[13] = o.Ybg; Y[15] = o.Ybb;
+    Y[8] = -((o.Ydd + o.Ygd) + o.Ybd);
+    Y[9] = -((o.Ydg + o.Ygg) + o.Ybg);
+    Y[11] = -((o.Ydb + o.Ygb) + o.Ybb);
+    Y[2] = -((Y[0] + Y[1]) + Y[3]);
+    Y[6] = -((Y[4] + Y[5]) + Y[7]);
+    Y[10] = -((Y[8] + Y[9]) + Y[11]);
+    Y[14] = -((Y[12] + Y[13]) + Y[15]);
+}
+
+using Dual3 = Dual3T<double>;
+using SizeDep = SizeDepT<double>;
+using DevOut = DevOutT<double>;
+
+}  // namespace cs

@@ -1,0 +1,211 @@
+"""GPU parity of the evaluate-and-stamp path (through the C-ABI) against the oracle.
+
+Bars: the coloured variants (persistent, per-colour kernels, buffered) reproduce the
+oracle's colour replay bit for bit; the atomic variant (no colour order) agrees with
+the oracle's serial order within 1e-12 of the per-entry sum of |contributions|
+(the reordering bound).  Cases span several workgroups and ragged tails, both
+conflict rules, history terms, the empty circuit and the full workload sizes."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_03079_amd import colorstamp as CS
+from paper_2604_03079_amd import netgen as G
+
+pytestmark = pytest.mark.gpu
+NC, PC = G.default_card(1), G.default_card(-1)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    CS.lib()
+    return torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_stamp(torch, circ, exclude, variant, ag0=1e12, hist=None, block=0, eval_ahead=-1, cooperative=True,
+              repeat=1):
+    c = CS.prepare(circ, exclude)
+    c.set_launch(block, eval_ahead, cooperative)
+    dev = torch.device("cuda:0")
+    W = torch.from_numpy(circ.W).to(dev)
+    L = torch.from_numpy(circ.L).to(dev)
+    V = torch.from_numpy(circ.VTH0).to(dev)
+    x = torch.from_numpy(circ.x).to(dev)
+    h = None if hist is None else torch.from_numpy(np.ascontiguousarray(hist)).to(dev)
+    c.set_params(W, L, V)
+    A = torch.full((c.nnz,), float("nan"), dtype=torch.float64, device=dev)
+    b = torch.full((c.n_rows,), float("nan"), dtype=torch.float64, device=dev)
+    for _ in range(repeat):
+        c.eval_stamp(x, ag0, h, A, b, variant=variant)
+    torch.cuda.synchronize()
+    c.check()
+    return A.cpu().numpy(), b.cpu().numpy(), c
+
+
+def oracle_replay(orc, circ, exclude, ag0=1e12, hist=None):
+    rp, ci = orc.pattern(circ)
+    col, _, _ = orc.colour(circ, exclude)
+    return orc.assemble(circ, rp, ci, NC, PC, ag0, hist, col=col, exclude=exclude)
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.int64)
+
+
+def assert_bit_exact(got, ref, what):
+    g, r = bits(got), bits(ref)
+    bad = np.nonzero(g != r)[0]
+    assert bad.size == 0, f"{what}: {bad.size} entries differ, first {bad[:5]}: {got[bad[:5]]} vs {ref[bad[:5]]}"
+
+
+def small_cases():
+    rng = np.random.default_rng(77)
+    out = [
+        ("chain50", G.workload(0)),
+        ("chain1", G.chain_case(1, 3)),
+        ("chain333", G.chain_case(333, 4)),
+        ("ota5t", G.draw_params(G.ota5t(), rng, G.W_OPAMP, G.L_OPAMP)),
+        ("ring501", G.draw_params(G.ring_oscillator(501), rng, G.W_CHAIN, G.L_CHAIN)),
+        ("sram16x16", G.sram_case(16, 16, 5)),
+        ("sram3x40", G.sram_case(3, 40, 6)),
+        ("pchain50x6", G.draw_params(G.parallel_chain(50, 6), rng, G.W_CHAIN, G.L_CHAIN)),
+        ("private700", G.draw_params(G.no_shared_nets(700), rng, G.W_CHAIN, G.L_CHAIN)),
+    ]
+    for k in range(8, 15):
+        out.append((f"opamp{k}", G.draw_params(G.opamp2(k, 0.9), rng, G.W_OPAMP, G.L_OPAMP)))
+    return out
+
+
+SMALL = small_cases()
+
+
+@pytest.mark.parametrize("name,circ", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("exclude", [True, False])
+def test_coloured_variants_bit_exact(torch_dev, orc, name, circ, exclude):
+    A0, b0 = oracle_replay(orc, circ, exclude)
+    for variant, block, ea in (("persistent", 256, 0), ("persistent", 64, 1), ("persistent", 128, -1),
+                               ("per_kernel", 0, -1), ("buffered", 0, -1)):
+        say(f"case {name} exclude={exclude} variant={variant} block={block} eval_ahead={ea}")
+        A, b, _ = gpu_stamp(torch_dev, circ, exclude, variant, block=block, eval_ahead=ea)
+        assert_bit_exact(A, A0, f"{name}/{variant}/A")
+        assert_bit_exact(b, b0, f"{name}/{variant}/b")
+
+
+@pytest.mark.parametrize("name,circ", SMALL, ids=[s[0] for s in SMALL])
+def test_atomic_within_reordering_bound(torch_dev, orc, name, circ):
+    rp, ci = orc.pattern(circ)
+    As, bs = orc.assemble(circ, rp, ci, NC, PC, 1e12)
+    mA, mb = orc.assemble_magnitude(circ, rp, ci, NC, PC, 1e12)
+    say(f"case {name} variant=atomic")
+    A, b, _ = gpu_stamp(torch_dev, circ, True, "atomic")
+    assert np.all(np.abs(A - As) <= 1e-12 * mA)
+    assert np.all(np.abs(b - bs) <= 1e-12 * mb)
+
+
+def test_history_and_dc(torch_dev, orc):
+    circ = G.workload(0)
+    rng = np.random.default_rng(3)
+    hist = rng.normal(0.0, 1e-5, (circ.n_dev, 4))
+    for ag0, h in ((1e12, hist), (0.0, None), (3.7e11, hist)):
+        A0, b0 = oracle_replay(orc, circ, True, ag0, h)
+        for variant in ("persistent", "per_kernel"):
+            say(f"case chain50 ag0={ag0} hist={h is not None} variant={variant}")
+            A, b, _ = gpu_stamp(torch_dev, circ, True, variant, ag0=ag0, hist=h)
+            assert_bit_exact(A, A0, "A")
+            assert_bit_exact(b, b0, "b")
+
+
+def test_empty_circuit(torch_dev, orc):
+    circ = G.Circuit("empty", 3, np.zeros((0, 4), np.int32), np.zeros(0, np.int8),
+                     np.array([[1, 0]], np.int32), np.array([1.1]), np.array([0, 1, 0], np.uint8), 1.1,
+                     np.zeros(0), np.zeros(0), np.zeros(0), np.array([1.1, 0.3, 0.0]))
+    for variant in ("persistent", "per_kernel", "atomic", "buffered"):
+        say(f"case empty variant={variant}")
+        A, b, _ = gpu_stamp(torch_dev, circ, True, variant)
+        # rows: vdd, node 2, branch; entries: (vdd,vdd), (vdd,br), (2,2), (br,vdd)
+        assert A.tolist() == [0.0, 1.0, 0.0, 1.0] and b.tolist() == [0.0, 0.0, 1.1]
+
+
+def test_repeated_calls_are_deterministic(torch_dev, orc):
+    circ = G.sram_case(32, 8, 11)
+    A1, b1, _ = gpu_stamp(torch_dev, circ, True, "persistent", repeat=1)
+    A2, b2, _ = gpu_stamp(torch_dev, circ, True, "persistent", repeat=3)
+    assert_bit_exact(A1, A2, "A")
+    assert_bit_exact(b1, b2, "b")
+
+
+@pytest.mark.parametrize("idx", [1, 2])
+def test_full_size_workloads(torch_dev, orc, idx):
+    circ = G.workload(idx)
+    A0, b0 = oracle_replay(orc, circ, True)
+    variants = [("persistent", 256, -1), ("persistent", 256, 0), ("per_kernel", 0, -1),
+                ("buffered", 0, -1)]
+    for variant, block, ea in variants:
+        say(f"case workload{idx} variant={variant} eval_ahead={ea}")
+        A, b, c = gpu_stamp(torch_dev, circ, True, variant, block=block, eval_ahead=ea)
+        say("  info", c.info())
+        assert_bit_exact(A, A0, f"workload{idx}/{variant}/A")
+        assert_bit_exact(b, b0, f"workload{idx}/{variant}/b")
+    rp, ci = orc.pattern(circ)
+    As, bs = orc.assemble(circ, rp, ci, NC, PC, 1e12)
+    mA, mb = orc.assemble_magnitude(circ, rp, ci, NC, PC, 1e12)
+    say(f"case workload{idx} variant=atomic")
+    A, b, _ = gpu_stamp(torch_dev, circ, True, "atomic")
+    assert np.all(np.abs(A - As) <= 1e-12 * mA)
+    assert np.all(np.abs(b - bs) <= 1e-12 * mb)
+
+
+@pytest.mark.parametrize("variant", ["persistent", "per_kernel", "buffered", "atomic"])
+def test_graph_replay_matches_eager(torch_dev, orc, variant):
+    # The NR step captured once and replayed; x changes between replays (eager work
+    # in between); every replay must equal the oracle at that x.
+    torch = torch_dev
+    circ = G.sram_case(12, 20, 21)
+    c = CS.prepare(circ, True)
+    dev = torch.device("cuda:0")
+    c.set_params(*(torch.from_numpy(a).to(dev) for a in (circ.W, circ.L, circ.VTH0)))
+    x = torch.from_numpy(circ.x).to(dev)
+    A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+    b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+    c.eval_stamp(x, 1e12, None, A, b, variant)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        c.eval_stamp(x, 1e12, None, A, b, variant)
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        xs = circ.x.copy()
+        xs[1:circ.n_nodes - 1] = rng.uniform(0.0, circ.vdd, circ.n_nodes - 2)
+        x.copy_(torch.from_numpy(xs))
+        A.fill_(float("nan"))
+        say(f"case graph replay {rep} variant={variant}")
+        g.replay()
+        torch.cuda.synchronize()
+        c.check()
+        rp, ci = orc.pattern(circ)
+        if variant == "atomic":
+            As, bs = orc.assemble(circ, rp, ci, NC, PC, 1e12, x=xs)
+            assert np.allclose(A.cpu().numpy(), As, rtol=1e-12, atol=1e-18)
+            continue
+        col, _, _ = orc.colour(circ, True)
+        A0, b0 = orc.assemble(circ, rp, ci, NC, PC, 1e12, col=col, exclude=True, x=xs)
+        assert_bit_exact(A.cpu().numpy(), A0, f"replay{rep}/A")
+        assert_bit_exact(b.cpu().numpy(), b0, f"replay{rep}/b")
+
+
+def test_ordinary_launch_bit_exact(torch_dev, orc):
+    for idx in (0, 1):
+        circ = G.workload(idx)
+        A0, b0 = oracle_replay(orc, circ, True)
+        for ea in (0, 1):
+            say(f"case workload{idx} ordinary launch eval_ahead={ea}")
+            A, b, _ = gpu_stamp(torch_dev, circ, True, "persistent", eval_ahead=ea, cooperative=False)
+            assert_bit_exact(A, A0, "A")
+            assert_bit_exact(b, b0, "b")

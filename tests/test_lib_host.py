@@ -1,0 +1,111 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point declared in
+include/colorstamp.h, its host setup (colouring, CSR pattern, stamp map) equals the
+oracle's bit for bit, and argument/state errors are reported before any launch."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_03079_amd import colorstamp as CS
+from paper_2604_03079_amd import netgen as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_entry_point():
+    L = CS.lib()
+    header = open(os.path.join(ROOT, "include", "colorstamp.h")).read()
+    declared = set(re.findall(r"\b(cs_[a-z_]+)\s*\(", header))
+    assert declared == set(CS.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+CASES = [
+    ("chain50", lambda: G.workload(0)),
+    ("ota5t", G.ota5t),
+    ("opamp8", lambda: G.opamp2(8)),
+    ("opamp14", lambda: G.opamp2(14)),
+    ("ring11", lambda: G.ring_oscillator(11)),
+    ("sram5x7", lambda: G.sram6t(5, 7)),
+    ("pchain9x4", lambda: G.parallel_chain(9, 4)),
+    ("private13", lambda: G.no_shared_nets(13)),
+    ("chain1", lambda: G.inverter_chain(1)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("exclude", [False, True])
+def test_setup_equals_oracle(orc, name, make, exclude):
+    circ = make()
+    c = CS.Circuit.from_netlist(circ)
+    col, C, E = c.colour(circ.exclude if exclude else None)
+    ocol, oC, oE = orc.colour(circ, exclude)
+    assert np.array_equal(col, ocol) and C == oC and E == oE
+    c.build_map()
+    rp, ci = c.pattern()
+    orp, oci = orc.pattern(circ)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    for a, b in zip(c.stamp_map(), orc.stamp_map(circ, orp, oci, ocol, exclude)):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("idx", [1, 2])
+def test_setup_equals_oracle_full_size(orc, idx):
+    circ = G.workload(idx)
+    c = CS.Circuit.from_netlist(circ)
+    col, C, E = c.colour(circ.exclude)
+    ocol, oC, oE = orc.colour(circ, True)
+    assert np.array_equal(col, ocol) and (C, E) == (oC, oE)
+    c.build_map()
+    rp, ci = c.pattern()
+    orp, oci = orc.pattern(circ)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    for a, b in zip(c.stamp_map(), orc.stamp_map(circ, orp, oci, ocol, True)):
+        assert np.array_equal(a, b)
+
+
+def test_strict_rule_large_chain_is_greedy():
+    # the vdd clique of the paper's rule: C = N + 1 for the chain (N >= 4)
+    circ = G.inverter_chain_fast(20_000)
+    c = CS.Circuit.from_netlist(circ)
+    col, C, _ = c.colour(None)
+    assert C == 20_001
+    assert len(set(col[circ.pol < 0].tolist())) == 20_000
+
+
+def test_error_paths():
+    L = CS.lib()
+    circ = G.workload(0)
+    bad = circ.term.copy()
+    bad[3, 1] = circ.n_nodes
+    with pytest.raises(CS.CsError) as e:
+        CS.Circuit(circ.n_nodes, bad, circ.pol, circ.vsrc, circ.vsrc_volts)
+    assert e.value.status == -1
+    badp = circ.pol.copy()
+    badp[0] = 0
+    with pytest.raises(CS.CsError) as e:
+        CS.Circuit(circ.n_nodes, circ.term, badp, circ.vsrc, circ.vsrc_volts)
+    assert e.value.status == -1
+    c = CS.Circuit.from_netlist(circ)
+    with pytest.raises(CS.CsError) as e:
+        c.build_map()                       # before colouring
+    assert e.value.status == -4
+    c.colour(circ.exclude)
+    with pytest.raises(CS.CsError) as e:
+        c.pattern()                         # before the map
+    assert e.value.status == -4
+    c.build_map()
+    with pytest.raises(CS.CsError) as e:
+        c.set_launch(100, 0)
+    assert e.value.status == -1
+    # evaluate before models/params: state error, no launch
+    import ctypes
+    st = L.cs_eval_stamp(c.handle, 0, ctypes.c_void_p(1), 0.0, None, ctypes.c_void_p(1),
+                         ctypes.c_void_p(1), None)
+    assert st == -4
+    assert L.cs_circuit_create(3, 1, None, None, 0, None, None, ctypes.byref(ctypes.c_void_p())) == -1
+    bad_card = CS.make_card(G.default_card(1))
+    bad_card.size = 3
+    assert L.cs_set_models(c.handle, ctypes.byref(bad_card), ctypes.byref(bad_card)) == -1
