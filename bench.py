@@ -135,6 +135,51 @@ def traffic_from_profiles(kernel_hash: str, key: str):
     return e.get("bytes_per_launch")
 
 
+def bench_batch(torch, CS, G, dev):
+    """512 uneven circuits: autotuned batched kernel vs one launch per circuit."""
+    from paper_2604_03079_amd import autotune
+    t0 = time.perf_counter()
+    circs = G.workload(3)
+    cs = [CS.prepare(c, exclude=True) for c in circs]
+    B = CS.Batch(cs)
+    setup_s = time.perf_counter() - t0
+    cat = lambda a: torch.from_numpy(np.concatenate([getattr(c, a) for c in circs])).to(dev)
+    W, L, V, x = cat("W"), cat("L"), cat("VTH0"), cat("x")
+    A = torch.empty(B.nnz, dtype=torch.float64, device=dev)
+    b = torch.empty(B.n_rows, dtype=torch.float64, device=dev)
+    best = autotune.tune(B, W, L, V, x, AG0, A, b, cache_path=None, reps=5, log=log)
+    ms_b, _ = time_graph(torch, lambda: B.eval_stamp(x, AG0, None, A, b), 20, 3)
+    B.check()
+    B.per_circuit_params(W, L, V)
+    ms_p, _ = time_graph(torch, lambda: B.per_circuit_eval(x, AG0, A, b), 5, 1)
+    log(f"  batch 512: batched {ms_b:.3f} ms ({B.n_dev / ms_b / 1e3:.1f} M dev/s), "
+        f"per-circuit launches {ms_p:.3f} ms ({B.n_dev / ms_p / 1e3:.1f} M dev/s), setup {setup_s:.1f} s")
+    return dict(n_circuits=len(circs), n_dev=B.n_dev, n_rows=B.n_rows, nnz=B.nnz,
+                max_colors=B.info()["max_colors"], tuned=best,
+                batched=dict(ms_per_step=round(ms_b, 4), value=round(B.n_dev / ms_b / 1e3, 2)),
+                per_circuit_launches=dict(ms_per_step=round(ms_p, 4), value=round(B.n_dev / ms_p / 1e3, 2)),
+                speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2))
+
+
+def bench_adjoint(torch, CS, G, dev):
+    """Forward + hand-written adjoint: chain of 10,000 stages, cotangents N(0,1)."""
+    circ = G.workload(4)
+    c = CS.prepare(circ, exclude=True)
+    W, L, V, x = device_tensors(torch, circ, dev)
+    c.set_params(W, L, V)
+    Ab, bb = G.cotangents(c.nnz, c.n_rows, seed=50)
+    Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
+    A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+    b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+    ms_f, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "persistent"), 50, 5)
+    ms_a, _ = time_graph(torch, lambda: c.vjp(x, AG0, Ab, bb), 50, 5)
+    log(f"  adjoint chain10k: forward {ms_f * 1e3:.1f} us, adjoint {ms_a * 1e3:.1f} us, ratio {ms_a / ms_f:.2f}")
+    return dict(workload="inverter_chain_10k_stages", n_dev=circ.n_dev,
+                forward_ms=round(ms_f, 5), adjoint_ms=round(ms_a, 5),
+                adjoint_over_forward=round(ms_a / ms_f, 3),
+                forward_plus_adjoint_value=round(circ.n_dev / (ms_f + ms_a) / 1e3, 2))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +275,8 @@ def main():
             ex[variant] = dict(ms_per_step=round(msv, 4), value=round(sram.n_dev / msv / 1e3, 2))
             log(f"  sram {variant:12s} {msv:8.3f} ms/step {sram.n_dev / msv / 1e3:9.1f} M devices/s")
         extras["sram_256x256"] = dict(n_dev=sram.n_dev, n_colors=c.info()["n_colors"], **ex)
+        extras["batch_512"] = bench_batch(torch, CS, G, dev)
+        extras["adjoint"] = bench_adjoint(torch, CS, G, dev)
         result["extras"] = extras
 
     if not args.no_cpu:

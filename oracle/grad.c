@@ -30,12 +30,12 @@ void or_device_dparam(const or_card *card, int pol, double W, double L, double V
     for (int j = 0; j < 4; ++j) dbl[j] = cimag(bl[j]) / h;
 }
 
-int or_vjp(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
-           const or_card *nmos, const or_card *pmos, const double *W, const double *L,
-           const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
-           const double *x, double ag0, const double *hist, const double *A_bar,
-           const double *b_bar, double *W_bar, double *L_bar, double *VTH0_bar) {
-    (void)n_nodes;
+static int vjp_impl(int32_t n_dev, const int32_t *term, const int8_t *pol,
+                    const or_card *nmos, const or_card *pmos, const double *W, const double *L,
+                    const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+                    const double *x, double ag0, const double *hist, const double *A_bar,
+                    const double *b_bar, double *W_bar, double *L_bar, double *VTH0_bar,
+                    int magnitude) {
     for (int32_t v = 0; v < n_dev; ++v) {
         const int32_t *t4 = term + 4 * (int64_t)v;
         double V[4];
@@ -52,12 +52,34 @@ int or_vjp(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *po
                     if (t4[s] == 0) continue;
                     int64_t sl = or_find_slot(row_ptr, col_idx, t4[t] - 1, t4[s] - 1);
                     if (sl < 0) return -3;
-                    g += A_bar[sl] * dY[t * 4 + s];
+                    g += magnitude ? fabs(A_bar[sl] * dY[t * 4 + s]) : A_bar[sl] * dY[t * 4 + s];
                 }
-                g += b_bar[t4[t] - 1] * dbl[t];
+                g += magnitude ? fabs(b_bar[t4[t] - 1] * dbl[t]) : b_bar[t4[t] - 1] * dbl[t];
             }
             *out[which] = g;
         }
     }
     return 0;
+}
+
+int or_vjp(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+           const or_card *nmos, const or_card *pmos, const double *W, const double *L,
+           const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+           const double *x, double ag0, const double *hist, const double *A_bar,
+           const double *b_bar, double *W_bar, double *L_bar, double *VTH0_bar) {
+    (void)n_nodes;
+    return vjp_impl(n_dev, term, pol, nmos, pmos, W, L, VTH0, row_ptr, col_idx, x, ag0, hist, A_bar,
+                    b_bar, W_bar, L_bar, VTH0_bar, 0);
+}
+
+/* Per device, sum of |cotangent * local sensitivity| over its entries: the scale of
+ * the rounding in a gradient assembled in another order. */
+int or_vjp_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                     const or_card *nmos, const or_card *pmos, const double *W, const double *L,
+                     const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *x, double ag0, const double *hist, const double *A_bar,
+                     const double *b_bar, double *W_mag, double *L_mag, double *VTH0_mag) {
+    (void)n_nodes;
+    return vjp_impl(n_dev, term, pol, nmos, pmos, W, L, VTH0, row_ptr, col_idx, x, ag0, hist, A_bar,
+                    b_bar, W_mag, L_mag, VTH0_mag, 1);
 }

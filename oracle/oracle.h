@@ -100,6 +100,13 @@ int or_vjp(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *po
            const double *x, double ag0, const double *hist, const double *A_bar,
            const double *b_bar, double *W_bar, double *L_bar, double *VTH0_bar);
 
+/* Per device, sum over its entries of |cotangent * d(entry)/d(theta)|. */
+int or_vjp_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                     const or_card *nmos, const or_card *pmos, const double *W, const double *L,
+                     const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *x, double ag0, const double *hist, const double *A_bar,
+                     const double *b_bar, double *W_mag, double *L_mag, double *VTH0_mag);
+
 /* Per-device local sensitivities d(Y, bl)/d(theta) by complex step, theta = 0 (W),
  * 1 (L), 2 (VTH0).  dY[16], dbl[4]. */
 void or_device_dparam(const or_card *card, int pol, double W, double L, double VTH0,

@@ -55,6 +55,7 @@ def lib():
         _lib.or_hubsum.restype = d
         _lib.or_hubsum.argtypes = [p, i64]
         _lib.or_vjp.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
+        _lib.or_vjp_magnitude.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_device_dparam.argtypes = [p, C.c_int, d, d, d, p, d, p, C.c_int, p, p]
         _lib.or_elem_array.argtypes = [C.c_int, p, p, i64]
         _lib.or_assemble_magnitude.argtypes = [i32, i32, p, p, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p]
@@ -229,7 +230,7 @@ def hubsum(c) -> float:
 
 
 def vjp(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, A_bar, b_bar, hist=None,
-        x=None, W=None, L=None, VTH0=None):
+        x=None, W=None, L=None, VTH0=None, magnitude=False):
     term = np.ascontiguousarray(circ.term, dtype=np.int32)
     pol = np.ascontiguousarray(circ.pol, dtype=np.int8)
     xx = np.ascontiguousarray(circ.x if x is None else x, dtype=np.float64)
@@ -241,7 +242,8 @@ def vjp(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, A_bar, b_bar, hist=Non
     bb = np.ascontiguousarray(b_bar, dtype=np.float64)
     gW = np.zeros(circ.n_dev); gL = np.zeros(circ.n_dev); gV = np.zeros(circ.n_dev)
     cn, cp = card(nmos), card(pmos)
-    rc = lib().or_vjp(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), C.byref(cn), C.byref(cp),
+    fn = lib().or_vjp_magnitude if magnitude else lib().or_vjp
+    rc = fn(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), C.byref(cn), C.byref(cp),
                       _ptr(Wa), _ptr(La), _ptr(Va), _ptr(rp), _ptr(ci), _ptr(xx), float(ag0),
                       _ptr(h), _ptr(Ab), _ptr(bb), _ptr(gW), _ptr(gL), _ptr(gV))
     if rc != 0:

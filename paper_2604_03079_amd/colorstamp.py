@@ -236,3 +236,126 @@ def prepare(circ, exclude: bool = True, nmos=None, pmos=None):
     c.build_map()
     c.set_models(nmos or netgen.default_card(1), pmos or netgen.default_card(-1))
     return c
+
+
+class Batch:
+    """Many prepared circuits stamped in one launch (packed layouts, see cs_batch_layout)."""
+
+    def __init__(self, circuits):
+        self.circuits = list(circuits)
+        n = len(self.circuits)
+        arr = (C.c_void_p * n)(*[c.handle for c in self.circuits])
+        h = C.c_void_p()
+        _check(lib().cs_batch_create(n, arr, C.byref(h)), "cs_batch_create")
+        self._h = h
+        self.dev_off = np.zeros(n + 1, np.int64)
+        self.row_off = np.zeros(n + 1, np.int64)
+        self.nnz_off = np.zeros(n + 1, np.int64)
+        _check(lib().cs_batch_layout(h, _np_ptr(self.dev_off), _np_ptr(self.row_off),
+                                     _np_ptr(self.nnz_off)), "cs_batch_layout")
+        self.n_dev = int(self.dev_off[-1])
+        self.n_rows = int(self.row_off[-1])
+        self.nnz = int(self.nnz_off[-1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cs_batch_destroy(h)
+            self._h = None
+
+    def set_launch(self, block: int = 0, eval_ahead: int = -1, local_max_dev: int = 0):
+        _check(lib().cs_batch_set_launch(self._h, int(block), int(eval_ahead), int(local_max_dev)),
+               "cs_batch_set_launch")
+
+    def set_params(self, W, L, VTH0, stream=None):
+        _check(lib().cs_batch_set_params(self._h, _dev_ptr(W), _dev_ptr(L), _dev_ptr(VTH0),
+                                         _stream(stream)), "cs_batch_set_params")
+
+    def info(self) -> dict:
+        nd, nr, nz = C.c_int64(), C.c_int64(), C.c_int64()
+        mc, g, bl, ea, nl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().cs_batch_get_info(self._h, C.byref(nd), C.byref(nr), C.byref(nz), C.byref(mc),
+                                       C.byref(g), C.byref(bl), C.byref(ea), C.byref(nl)),
+               "cs_batch_get_info")
+        return dict(n_dev=nd.value, n_rows=nr.value, nnz=nz.value, max_colors=mc.value, grid=g.value,
+                    block=bl.value, eval_ahead=ea.value, n_local=nl.value)
+
+    def eval_stamp(self, x, ag0: float, hist=None, A=None, b=None, stream=None):
+        import torch
+        if A is None:
+            A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
+        if b is None:
+            b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
+        _check(lib().cs_batch_eval_stamp(self._h, _dev_ptr(x), float(ag0), _dev_ptr(hist), _dev_ptr(A),
+                                         _dev_ptr(b), _stream(stream)), "cs_batch_eval_stamp")
+        return A, b
+
+    def vjp(self, x, ag0: float, A_bar, b_bar, hist=None, stream=None):
+        import torch
+        gW = torch.empty(self.n_dev, dtype=torch.float64, device=x.device)
+        gL = torch.empty_like(gW)
+        gV = torch.empty_like(gW)
+        _check(lib().cs_batch_vjp(self._h, _dev_ptr(x), float(ag0), _dev_ptr(hist), _dev_ptr(A_bar),
+                                  _dev_ptr(b_bar), _dev_ptr(gW), _dev_ptr(gL), _dev_ptr(gV),
+                                  _stream(stream)), "cs_batch_vjp")
+        return gW, gL, gV
+
+    def check(self, stream=None):
+        _check(lib().cs_batch_check(self._h, _stream(stream)), "cs_batch_check")
+
+    def per_circuit_params(self, W, L, VTH0):
+        """Give every member circuit its slice of the packed parameters."""
+        for i, c in enumerate(self.circuits):
+            a, z = int(self.dev_off[i]), int(self.dev_off[i + 1])
+            c.set_params(W[a:z], L[a:z], VTH0[a:z])
+
+    def per_circuit_eval(self, x, ag0, A, b, variant="persistent"):
+        """The comparison schedule: one launch per circuit on packed slices."""
+        for i, c in enumerate(self.circuits):
+            r0, r1 = int(self.row_off[i]), int(self.row_off[i + 1])
+            z0, z1 = int(self.nnz_off[i]), int(self.nnz_off[i + 1])
+            c.eval_stamp(x[r0:r1], ag0, None, A[z0:z1], b[r0:r1], variant)
+        return A, b
+
+
+def _torch_function():
+    import torch
+
+    class StampFn(torch.autograd.Function):
+        """(W, L, VTH0, x) -> (A, b) with the hand-written adjoint in backward.
+
+        The gradient with respect to x is not provided (None)."""
+
+        @staticmethod
+        def forward(ctx, circuit, W, L, VTH0, x, ag0, variant):
+            circuit.set_params(W, L, VTH0)
+            A, b = circuit.eval_stamp(x, ag0, variant=variant)
+            ctx.save_for_backward(W, L, VTH0, x)
+            ctx.circuit = circuit
+            ctx.ag0 = ag0
+            return A, b
+
+        @staticmethod
+        def backward(ctx, A_bar, b_bar):
+            W, L, VTH0, x = ctx.saved_tensors
+            c = ctx.circuit
+            if A_bar is None:
+                A_bar = torch.zeros(c.nnz, dtype=torch.float64, device=x.device)
+            if b_bar is None:
+                b_bar = torch.zeros(c.n_rows, dtype=torch.float64, device=x.device)
+            c.set_params(W, L, VTH0)
+            gW, gL, gV = c.vjp(x, ctx.ag0, A_bar.contiguous(), b_bar.contiguous())
+            return None, gW, gL, gV, None, None, None
+
+    return StampFn
+
+
+_STAMPFN = None
+
+
+def stamp(circuit, W, L, VTH0, x, ag0: float = 1e12, variant: str = "persistent"):
+    """Differentiable evaluate-and-stamp: returns (A_val, b); backward gives dW, dL, dVTH0."""
+    global _STAMPFN
+    if _STAMPFN is None:
+        _STAMPFN = _torch_function()
+    return _STAMPFN.apply(circuit, W, L, VTH0, x, ag0, variant)

@@ -1,0 +1,117 @@
+// Adjoint (vector-Jacobian product) of the stamped (A, b) with respect to each
+// device's W, L and VTH0.
+//
+// A and b are sums of per-device contributions, each depending on its own device's
+// parameters only, so the gradient of <A_bar, A> + <b_bar, b> w.r.t. theta_k is
+//   sum_{(t,u)} A_bar[slot(t,u)] dY_k[t][u]/dtheta_k + sum_t b_bar[row(t)] dbl_k[t]/dtheta_k
+// over the device's non-ground terminals.  One device per lane: the cotangents are
+// gathered through the device's slot map (no colouring, no atomics: every gradient
+// entry has one writer), and three forward-mode sweeps of the model (tangents of W,
+// L and VTH0 carried alongside every value and partial) recompute the intermediates
+// instead of storing them.
+#include <hip/hip_runtime.h>
+
+#include "kernel_args.hpp"
+#include "launch.hpp"
+#include "model.hpp"
+#include "stamp.hpp"
+
+namespace cs {
+
+template <int KEY>
+__device__ __forceinline__ void gather_pattern(const int32_t *acode, int n, int pos,
+                                               const double *A_bar, const double *b_bar,
+                                               double Yb[16], double bb[4]) {
+    if constexpr (Pat<KEY>::valid()) {
+        constexpr int K = Pat<KEY>::k();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int it = Pat<KEY>::idx(t), iu = Pat<KEY>::idx(u);
+                Yb[t * 4 + u] = (it >= 0 && iu >= 0) ? A_bar[acode[(size_t)(it * K + iu) * n + pos]] : 0.0;
+            }
+            const int it = Pat<KEY>::idx(t);
+            bb[t] = it >= 0 ? b_bar[acode[(size_t)(K * K + it) * n + pos]] : 0.0;
+        }
+    }
+}
+
+__device__ __forceinline__ void gather_cotangents(int key, const int32_t *acode, int n, int pos,
+                                                  const double *A_bar, const double *b_bar,
+                                                  double Yb[16], double bb[4]) {
+    for (;;) {
+        const int k0 = __builtin_amdgcn_readfirstlane(key);
+        if (key == k0) {
+            switch (k0) {
+#define CS_G(q) case q: gather_pattern<q>(acode, n, pos, A_bar, b_bar, Yb, bb); break;
+#define CS_G10(q) CS_G(q) CS_G(q + 1) CS_G(q + 2) CS_G(q + 3) CS_G(q + 4) CS_G(q + 5) \
+    CS_G(q + 6) CS_G(q + 7) CS_G(q + 8) CS_G(q + 9)
+                CS_G10(0) CS_G10(10) CS_G10(20) CS_G10(30) CS_G10(40) CS_G10(50)
+                CS_G10(60) CS_G10(70) CS_G10(80) CS_G10(90) CS_G10(100) CS_G10(110)
+#undef CS_G10
+#undef CS_G
+                default: break;
+            }
+            break;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double *A_bar,
+                                             const double *b_bar, double *gW, double *gL,
+                                             double *gV) {
+    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < kc.n; pos += gridDim.x * blockDim.x) {
+        const int32_t t0 = kc.term[pos], t1 = kc.term[(size_t)kc.n + pos];
+        const int32_t t2 = kc.term[2 * (size_t)kc.n + pos], t3 = kc.term[3 * (size_t)kc.n + pos];
+        const int key = pattern_key(t0, t1, t2, t3);
+        double Yb[16], bb[4];
+        gather_cotangents(key, kc.acode, kc.n, pos, A_bar, b_bar, Yb, bb);
+        const double W = kc.par[pos];
+        const double L = kc.par[(size_t)kc.n + pos];
+        const double VTH0 = kc.par[2 * (size_t)kc.n + pos];
+        const double Vd = t0 ? call.x[t0 - 1] : 0.0, Vg = t1 ? call.x[t1 - 1] : 0.0;
+        const double Vs = t2 ? call.x[t2 - 1] : 0.0, Vb = t3 ? call.x[t3 - 1] : 0.0;
+        const int32_t v = kc.perm[pos];
+        const double *hist = call.hist ? call.hist + 4 * (size_t)v : nullptr;
+        const int isP = kc.pol[pos] < 0 ? 1 : 0;
+        double g[3] = {0.0, 0.0, 0.0};
+        for (;;) {
+            const int p0 = __builtin_amdgcn_readfirstlane(isP);
+            if (isP == p0) {
+                const DevCard &cd = kc.card[p0];
+                const double p = p0 ? -1.0 : 1.0;
+#pragma unroll 1
+                for (int dir = 0; dir < 3; ++dir) {
+                    const Tan Wt(W, dir == 0 ? 1.0 : 0.0), Lt(L, dir == 1 ? 1.0 : 0.0);
+                    const Tan Vt(VTH0, dir == 2 ? 1.0 : 0.0);
+                    const SizeDepT<Tan> sd = size_dep(cd, p, Wt, Lt, Vt);
+                    const DevOutT<Tan> o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist);
+                    Tan Y[16];
+                    full_Y(o, Y);
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) acc += Yb[i] * Y[i].t;
+                    acc += bb[0] * o.bd.t + bb[1] * o.bg.t + bb[2] * o.bs.t + bb[3] * o.bb.t;
+                    if (dir == 0) g[0] = acc; else if (dir == 1) g[1] = acc; else g[2] = acc;
+                }
+                break;
+            }
+        }
+        gW[v] = g[0];
+        gL[v] = g[1];
+        gV[v] = g[2];
+    }
+}
+
+hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
+                      double *gW, double *gL, double *gV, hipStream_t s) {
+    if (kc.n == 0) return hipSuccess;
+    const int grid = (kc.n + 255) / 256;
+    hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
+    return hipGetLastError();
+}
+
+}  // namespace cs

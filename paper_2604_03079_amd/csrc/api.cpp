@@ -381,8 +381,10 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
                 }
             }
             const KSync ks{c->d_sync.p, c->spin_limit};
+            const KLocal none{0, nullptr, nullptr};
             CS_CHECK_HIP(launch_persistent(kc, call, ks, c->d_buf.p, mode, grid, c->block,
-                                           c->cooperative, s), "persistent launch");
+                                           c->cooperative, s, grid, kc.n_hub_chunks, none),
+                         "persistent launch");
             return CS_OK;
         }
         case CS_COLOR_PER_KERNEL: {

@@ -111,20 +111,31 @@ struct cs_circuit {
 
 struct cs_batch {
     std::vector<cs_circuit *> circ;
-    std::vector<int64_t> dev_off, row_off, nnz_off;
-    cs::HostCircuit h;                 // block-diagonal union, packed indices
+    std::vector<int64_t> dev_off, row_off, nnz_off;   // n+1 each
     cs::DevCard card[2];
+    // packed instance table (built for the current local_max_dev)
+    bool packed = false;
+    bool params_set = false;
+    cs::HostCircuit h;                 // packed codes, permutation, colour pointers, hubs
+    std::vector<int32_t> pterm;        // [4][positions] x index + 1
+    std::vector<int8_t> ppol;
+    std::vector<int32_t> local_table;  // 6 per workgroup-local circuit
+    std::vector<int32_t> local_cptr;
+    int32_t n_local = 0;
+    int32_t n_global_chunks = 0;
+    int64_t stage_total = 0;
+    // device copies
     int device = -1;
     cs::DevBuf<int32_t> d_term, d_code, d_acode, d_perm, d_cptr, d_fixA_idx, d_fixB_idx,
-        d_hub_ptr, d_hub_target, d_local;
+        d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk, d_local, d_local_cptr;
     cs::DevBuf<int8_t> d_pol;
-    cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage;
-    cs::DevBuf<uint32_t> d_sync;
+    cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_hub_part;
+    cs::DevBuf<uint32_t> d_sync, d_hub_count;
+    // launch
     int32_t block = 256;
     int32_t eval_ahead_req = -1;
     int32_t local_max_dev = 0;
-    int32_t grid = 0;
-    int32_t eval_ahead = 0;
-    int32_t n_local = 0;
+    bool cooperative = true;
+    int32_t grid = 0, n_part = 0, eval_ahead = 0;
     int64_t spin_limit = 1 << 22;
 };

@@ -57,6 +57,16 @@ struct KCirc {
     DevCard card[2];         // 0 NMOS, 1 PMOS
 };
 
+// Circuits of a batch that are stamped entirely inside one workgroup (colour
+// phases separated by workgroup barriers).  table[6*i ..]: first position, last
+// position + 1, offset of its colour pointers in cptr, number of colours, first hub
+// chunk, last hub chunk + 1.
+struct KLocal {
+    int32_t n;
+    const int32_t *table;
+    const int32_t *cptr;
+};
+
 // Per-call operands.
 struct KCall {
     const double *x;

@@ -126,15 +126,15 @@ __device__ __forceinline__ void hub_store(const KCirc &kc, const KCall &call, in
 // folds it.  The wave that completes the last chunk of a hub (a coherent counter)
 // folds the chunk sums, so no grid barrier is needed.  Every wave of the block
 // calls this (it contains workgroup barriers).  lds: (blockDim/64)*HUB_K doubles.
-__device__ void hub_chunks(const KCirc &kc, const KCall &call, int wave0, int nwaves, double *lds) {
+__device__ void hub_chunks(const KCirc &kc, const KCall &call, int q0, int q1, int wave0, int nwaves,
+                           double *lds) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
     double *mine = lds + (size_t)wave * HUB_K;
-    const int rounds = (kc.n_hub_chunks + nwaves - 1) / nwaves;
+    const int rounds = (q1 - q0 + nwaves - 1) / nwaves;
     for (int r = 0; r < rounds; ++r) {
-        const int q = wave0 + wave + r * nwaves;
+        const int q = q0 + wave0 + wave + r * nwaves;
         int h = 0, e = 0, nchunk = 0;
-        if (q < kc.n_hub_chunks) {
+        if (q < q1) {
             h = kc.hub_of_chunk[q];
             const int j = q - kc.hub_cptr[h];
             nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
@@ -144,7 +144,7 @@ __device__ void hub_chunks(const KCirc &kc, const KCall &call, int wave0, int nw
         }
         __syncthreads();
         int last = 0;
-        if (q < kc.n_hub_chunks && lane == 0) {
+        if (q < q1 && lane == 0) {
             const double s = fold_lds(mine, e);
             if (nchunk == 1) {
                 hub_store(kc, call, h, s);
@@ -184,7 +184,6 @@ __device__ void hub_chunks(const KCirc &kc, const KCall &call, int wave0, int nw
         }
         __syncthreads();
     }
-    (void)wpb;
 }
 
 // ---- grid barrier -----------------------------------------------------------------
@@ -208,14 +207,14 @@ __device__ __forceinline__ void drain_memory() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ void grid_barrier(const KSync &ks, uint32_t epoch) {
+__device__ void grid_barrier(const KSync &ks, uint32_t epoch, uint32_t nblocks) {
     uint32_t *rel = ks.sync;
     uint32_t *err = ks.sync + 1;
     uint32_t *arr = ks.sync + 2;
     drain_memory();
     __syncthreads();
     if (blockIdx.x == 0) {
-        for (uint32_t i = threadIdx.x + 1; i < gridDim.x; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x + 1; i < nblocks; i += blockDim.x) {
             int64_t spins = 0;
             while (ld_flag(arr + i) != epoch) {
                 __builtin_amdgcn_s_sleep(1);
@@ -274,33 +273,67 @@ __global__ void k_fixed(KCirc kc, KCall call) {
 
 __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
     __shared__ double lds[4 * HUB_K];
-    hub_chunks(kc, call, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
+    hub_chunks(kc, call, 0, kc.n_hub_chunks, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
 }
 
 // Persistent coloured kernel.  MODE 0: evaluate inside each colour phase (grid-
 // stride).  MODE 1: every thread evaluates its own device before the first phase
 // and keeps the local values in registers (requires grid*block >= n).  MODE 2:
 // stamp phases only, merged values read from the buffer of k_eval_buffer.
+// Circuits stamped inside one workgroup: colour phases separated by workgroup
+// barriers, then the circuit's own hub chunks.
+__device__ void local_circuits(const KCirc &kc, const KCall &call, const KLocal &kl, int first,
+                               int stride, double *lds) {
+    for (int li = first; li < kl.n; li += stride) {
+        const int32_t *t = kl.table + 6 * (size_t)li;
+        const int32_t cp = t[2], nc = t[3];
+        for (int c = 0; c < nc; ++c) {
+            const int beg = kl.cptr[cp + c], end = kl.cptr[cp + c + 1];
+            for (int pos = beg + (int)threadIdx.x; pos < end; pos += blockDim.x) {
+                const DevIn d = load_terms(kc, pos);
+                const DevOut o = eval_pos(kc, call, pos, d);
+                stamp_colour<true>(kc, call, pos, d, o);
+            }
+            drain_memory();
+            __syncthreads();
+        }
+        hub_chunks(kc, call, t[4], t[5], 0, blockDim.x >> 6, lds);
+    }
+}
+
+// Persistent coloured kernel.  Blocks [0, n_part) run the colour schedule with
+// grid barriers among themselves over positions [0, cptr[n_colors]); blocks from
+// n_part on stamp the workgroup-local circuits.  MODE 0: evaluate inside each colour
+// phase (grid-stride).  MODE 1: every thread evaluates its own device before the
+// first phase and keeps the local values in registers (requires n_part*block >=
+// the scheduled positions).  MODE 2: stamp phases only, merged values read from the
+// buffer of k_eval_buffer.
 template <int MODE>
 __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &call,
-                                                const KSync &ks, const double *buf) {
+                                                const KSync &ks, const double *buf, int n_part,
+                                                int n_global_chunks, const KLocal &kl) {
     __shared__ double lds[4 * HUB_K];
     __shared__ uint32_t base_s;
+    if (blockIdx.x == 0) fixed_stores(kc, call, threadIdx.x, blockDim.x);
+    if ((int)blockIdx.x >= n_part) {
+        local_circuits(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part, lds);
+        return;
+    }
     if (threadIdx.x == 0) base_s = ld_flag(ks.sync);
     __syncthreads();
     const uint32_t base = base_s;
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nthr = gridDim.x * blockDim.x;
+    const int nthr = n_part * blockDim.x;
 
     DevIn d{};
     DevOut o{};
+    const int n_sched = kc.cptr[kc.n_colors];
     if constexpr (MODE == 1) {
-        if (gtid < kc.n) {
+        if (gtid < n_sched) {
             d = load_terms(kc, gtid);
             o = eval_pos(kc, call, gtid, d);
         }
     }
-    fixed_stores(kc, call, gtid, nthr);
     uint32_t epoch = base;
     for (int c = 0; c < kc.n_colors; ++c) {
         const int beg = kc.cptr[c], end = kc.cptr[c + 1];
@@ -321,24 +354,27 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
                 }
             }
         }
-        if (c + 1 < kc.n_colors || kc.n_hub > 0) grid_barrier(ks, ++epoch);
+        if (c + 1 < kc.n_colors || n_global_chunks > 0) grid_barrier(ks, ++epoch, n_part);
     }
-    hub_chunks(kc, call, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
+    hub_chunks(kc, call, 0, n_global_chunks, blockIdx.x * (blockDim.x >> 6), n_part * (blockDim.x >> 6), lds);
 }
 
 __global__ void __launch_bounds__(256) k_persistent_phase(KCirc kc, KCall call, KSync ks,
-                                                          const double *buf) {
-    persistent_body<0>(kc, call, ks, buf);
+                                                          const double *buf, int n_part,
+                                                          int n_global_chunks, KLocal kl) {
+    persistent_body<0>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 // Evaluate-ahead holds one device's local values per thread across the colour
 // phases; it needs every device resident at once, hence four waves per SIMD.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_persistent_ahead(KCirc kc, KCall call, KSync ks, const double *buf) {
-    persistent_body<1>(kc, call, ks, buf);
+k_persistent_ahead(KCirc kc, KCall call, KSync ks, const double *buf, int n_part,
+                   int n_global_chunks, KLocal kl) {
+    persistent_body<1>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 __global__ void __launch_bounds__(256) k_persistent_stamp(KCirc kc, KCall call, KSync ks,
-                                                          const double *buf) {
-    persistent_body<2>(kc, call, ks, buf);
+                                                          const double *buf, int n_part,
+                                                          int n_global_chunks, KLocal kl) {
+    persistent_body<2>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 
 // Evaluate every device and write its merged values (buffered variant).
@@ -420,12 +456,14 @@ hipError_t launch_hub(const KCirc &kc, const KCall &call, hipStream_t s) {
 
 hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks,
                              const double *buf, int mode, int grid, int block, bool cooperative,
-                             hipStream_t s) {
+                             hipStream_t s, int n_part, int n_global_chunks, const KLocal &kl) {
     KCirc a = kc;
     KCall b = call;
     KSync c = ks;
     const double *d = buf;
-    void *args[] = {&a, &b, &c, &d};
+    int np = n_part, ng = n_global_chunks;
+    KLocal l = kl;
+    void *args[] = {&a, &b, &c, &d, &np, &ng, &l};
     const void *fn = mode == 1 ? (const void *)k_persistent_ahead
                    : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
     if (!cooperative) return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);

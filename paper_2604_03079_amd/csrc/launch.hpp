@@ -17,10 +17,14 @@ hipError_t launch_fixed(const KCirc &kc, const KCall &call, hipStream_t s);
 hipError_t launch_hub(const KCirc &kc, const KCall &call, hipStream_t s);
 // cooperative: hipLaunchCooperativeKernel (the runtime checks co-residency);
 // otherwise an ordinary launch of a grid the occupancy query says fits at once.
+// n_part: blocks [0, n_part) run the grid-barrier colour schedule over the first
+// n_global_chunks hub chunks; later blocks stamp the workgroup-local circuits of kl.
 hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks,
                              const double *buf, int mode, int grid, int block, bool cooperative,
-                             hipStream_t s);
+                             hipStream_t s, int n_part, int n_global_chunks, const KLocal &kl);
 hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s);
+hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
+                      double *gW, double *gL, double *gV, hipStream_t s);
 hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,
                          hipStream_t s);
 
