@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x FP64 lanes x clock: one op per lane-cycle
+KERNEL_OF = {"persistent": "k_persistent_* (one launch per step)",
+             "region": "k_region (one launch per step)",
+             "per_kernel": "k_colour_phase x colours + k_hub",
+             "buffered": "k_eval_buffer + k_persistent_stamp",
+             "atomic": "k_fill_zero + k_atomic"}
 PEAK_HBM = 8.0e12
 AG0 = 1e12
 
@@ -95,12 +100,10 @@ def algorithmic_counts(circ, exclude=True):
     n = circ.n_dev
     nslot = int((sflag >= 0).sum())
     nbrow = int((bflag >= 0).sum())
-    # bytes: params (3 x 8) + polarity (1) + terminals (4 x 4) + x gathers (8 per row
-    # once) + stamp codes (4 per entry) + value writes (8 per entry) + load-add reads
-    # (8 per add) + hub staging written and read (16 per hub entry)
-    nhub = int((sflag == 2).sum() + (bflag == 2).sum())
-    byts = (n * (24 + 1 + 16) + 8 * circ.n_rows + 4 * (nslot + nbrow)
-            + 8 * (nslot + nbrow) + 8 * add_ops + 16 * nhub)
+    # bytes the step cannot avoid: per device W, L, VTH0 (24), polarity (1) and
+    # terminals (16); x read once (8 per row); one 4-byte stamp code per local entry;
+    # A and b written once (8 per nonzero and per row)
+    byts = n * (24 + 1 + 16) + 8 * circ.n_rows + 4 * (nslot + nbrow) + 8 * len(ci) + 8 * circ.n_rows
     return dict(ops=int(ops), model_ops=int(model_ops), bytes=int(byts), n_colors=int(C))
 
 
@@ -188,6 +191,9 @@ def main():
     ap.add_argument("--variant", default="persistent")
     ap.add_argument("--no-extras", action="store_true", help="skip SRAM/batch/adjoint lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
+    ap.add_argument("--only", action="store_true", help="time only --variant (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: every box here has one GPU (asked for {args.gpus}).",
@@ -200,6 +206,15 @@ def main():
     from paper_2604_03079_amd import netgen as G
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 10 copies of {args.copy_probe} MiB")
+        return
     khash = kernel_sources_hash()
     circ = G.workload(1)
     log(f"workload: chain 100000 stages, {circ.n_dev} devices")
@@ -208,8 +223,11 @@ def main():
 
     variants = {}
     graphs = []
-    for variant, coop in (("persistent", True), ("persistent", False), ("per_kernel", True),
-                          ("buffered", True), ("atomic", True)):
+    todo = (("persistent", True), ("persistent", False), ("per_kernel", True),
+            ("buffered", True), ("region", True), ("atomic", True))
+    if args.only:
+        todo = ((args.variant, True),)
+    for variant, coop in todo:
         c = CS.prepare(circ, exclude=True)
         c.set_launch(256, -1, coop)
         c.set_params(W, L, V)
@@ -250,11 +268,11 @@ def main():
             "peak": round(PEAK_FP64_OPS / 1e12, 2),
             "unit": "TFLOP/s",
             "frac": round(counts["ops"] / secs / PEAK_FP64_OPS, 5),
-            "traffic": traffic_from_profiles(khash, "persistent_chain100k"),
+            "traffic": traffic_from_profiles(khash, f"{args.variant}_chain100k"),
             "algorithmic_ops_per_launch": counts["ops"],
             "algorithmic_bytes_per_launch": counts["bytes"],
             "hbm_frac_at_algorithmic_bytes": round(counts["bytes"] / secs / PEAK_HBM, 5),
-            "kernel": "k_persistent (one launch per step)",
+            "kernel": KERNEL_OF.get(args.variant, args.variant),
         },
         "variants": variants,
         "kernel_sources": khash,
@@ -265,7 +283,7 @@ def main():
         sram = G.workload(2)
         Ws, Ls, Vs, xs = device_tensors(torch, sram, dev)
         ex = {}
-        for variant in ("persistent", "per_kernel", "atomic"):
+        for variant in ("persistent", "per_kernel", "region", "atomic"):
             c = CS.prepare(sram, exclude=True)
             c.set_params(Ws, Ls, Vs)
             A = torch.empty(c.nnz, dtype=torch.float64, device=dev)

@@ -58,8 +58,16 @@ typedef enum {
                                  per-colour parallel-for of the paper's OpenMP form) */
     CS_ATOMIC = 2,            /* comparison: no colouring, FP64 atomic adds (the
                                  paper's lock-based foil, Introduction) */
-    CS_COLOR_BUFFERED = 3     /* Color: evaluate every device into a buffer, then
+    CS_COLOR_BUFFERED = 3,    /* Color: evaluate every device into a buffer, then
                                  stamp colour by colour from the buffer */
+    CS_COLOR_REGION = 4       /* ColorFused at workgroup scope: devices are cut (in
+                                 index order) into regions of one workgroup; a
+                                 region's own entries accumulate in LDS colour phase
+                                 by colour phase (consecutive colours that share no
+                                 entry merged into one phase), entries written from
+                                 several regions are staged and folded in colour
+                                 order by the last contributing region.  Same bits as
+                                 CS_COLOR_PERSISTENT; no grid-wide barrier. */
 } cs_variant;
 
 /* Model card of the BSIM4-core subset (SI units).  One card per polarity. */
@@ -145,6 +153,35 @@ cs_status cs_get_info(const cs_circuit *c, int64_t *n_dev, int32_t *n_rows, int6
                       int32_t *n_colors, int32_t *grid, int32_t *block, int32_t *eval_ahead,
                       int32_t *n_hub);
 
+/* Region schedule (CS_COLOR_REGION).  The plan is built on the host for a region
+ * capacity of `block` threads, by this call or by the first CS_COLOR_REGION call
+ * at the current block size (cs_set_launch).  Host only; no device work. */
+cs_status cs_plan_regions(cs_circuit *c, int32_t block);
+
+/* Facts of the last region plan: regions (= workgroups), largest number of phases
+ * of a region, items (entries shared between regions, and hub chunks), staged
+ * contributions (hub and shared), entries owned by one region, region-to-item links.
+ * Any pointer may be NULL; zeros before a plan exists. */
+cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *max_phases,
+                             int64_t *n_items, int64_t *n_staged, int64_t *n_interior,
+                             int64_t *n_links);
+
+/* Host copies of the region plan tables (any pointer may be NULL), region-major
+ * positions p < n_dev:
+ *   perm[p]      device index;               phase[p]   LDS phase of the device;
+ *   code[j*n_dev + p] (j < 20): bits 31..30 = 0 LDS add, 1 LDS store, 2 staged,
+ *                3 unused; bits 29..0 = LDS slot or staging index;
+ *   rtab[8*r ...] first position, NMOS count, PMOS count (NMOS lanes first, then
+ *                PMOS), phases, owned-entry range, item range;
+ *   interior[i]  target of owned entry i (bits 31..30 = 0 A slot, 1 b row), LDS slot =
+ *                i - range start;
+ *   links[]      item ids per region;
+ *   item[4*i ...] first staged index, count, target (kind 0 A, 1 b, 2 hub chunk),
+ *                number of contributing regions (0: an entry with more than 8
+ *                contributions, folded by the follow-up kernel of the schedule). */
+cs_status cs_get_region_plan(const cs_circuit *c, int32_t *perm, uint16_t *phase, int32_t *code,
+                             int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item);
+
 /* Read and clear the device error word of the last bounded waits (synchronises the
  * stream).  Returns CS_EDOMAIN if a barrier wait ran out of its spin budget. */
 cs_status cs_check(cs_circuit *c, void *stream);
@@ -172,6 +209,20 @@ cs_status cs_batch_set_launch(cs_batch *b, int32_t block, int32_t eval_ahead,
 cs_status cs_batch_get_info(const cs_batch *b, int64_t *n_dev, int64_t *n_rows, int64_t *nnz,
                             int32_t *max_colors, int32_t *grid, int32_t *block,
                             int32_t *eval_ahead, int32_t *n_local);
+/* Schedule of cs_batch_eval_stamp: CS_COLOR_PERSISTENT (default; grid-barrier
+ * colour phases for circuits above local_max_dev devices, workgroup-local ones
+ * below) or CS_COLOR_REGION (every circuit cut into workgroup regions, small
+ * circuits packed whole into regions; see cs_variant). */
+cs_status cs_batch_set_schedule(cs_batch *b, cs_variant schedule);
+/* Batch analogues of cs_plan_regions, cs_get_region_info and cs_get_region_plan
+ * (positions and devices over the packed device order; circuits that fit one
+ * region are never split).  Host only. */
+cs_status cs_batch_plan_regions(cs_batch *b, int32_t block);
+cs_status cs_batch_get_region_info(const cs_batch *b, int32_t *n_regions, int32_t *max_phases,
+                                   int64_t *n_items, int64_t *n_staged, int64_t *n_interior,
+                                   int64_t *n_links);
+cs_status cs_batch_get_region_plan(const cs_batch *b, int32_t *perm, uint16_t *phase, int32_t *code,
+                                   int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item);
 /* One launch over every circuit of the batch. */
 cs_status cs_batch_eval_stamp(cs_batch *b, const double *x, double ag0, const double *hist,
                               double *A, double *b_vec, void *stream);

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_lib", "libcolorstamp.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "setup.cpp", "api.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "setup.cpp", "region.cpp", "api.cpp", "batch.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

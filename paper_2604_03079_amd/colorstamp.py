@@ -14,7 +14,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libcolorstamp.so")
 
-VARIANTS = {"persistent": 0, "per_kernel": 1, "atomic": 2, "buffered": 3}
+VARIANTS = {"persistent": 0, "per_kernel": 1, "atomic": 2, "buffered": 3, "region": 4}
 STATUS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EHIP", -4: "CS_ESTATE",
           -5: "CS_ENOTSUP", -6: "CS_EDOMAIN"}
 CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "dvt0", "dvt1",
@@ -25,10 +25,12 @@ CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "d
 EXPORTS = (
     "cs_circuit_create", "cs_circuit_destroy", "cs_build_coloring", "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
-    "cs_vjp", "cs_set_launch", "cs_get_info", "cs_check", "cs_set_spin_limit",
-    "cs_batch_create", "cs_batch_destroy", "cs_batch_layout", "cs_batch_set_params",
-    "cs_batch_set_launch", "cs_batch_get_info", "cs_batch_eval_stamp", "cs_batch_vjp",
-    "cs_batch_check", "cs_last_error",
+    "cs_vjp", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
+    "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_batch_create", "cs_batch_destroy",
+    "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
+    "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
+    "cs_batch_get_region_plan", "cs_batch_eval_stamp", "cs_batch_vjp", "cs_batch_check",
+    "cs_last_error",
 )
 
 
@@ -70,6 +72,9 @@ def lib():
             "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_set_launch": [p, i32, i32, i32],
             "cs_get_info": [p, p, p, p, p, p, p, p, p],
+            "cs_plan_regions": [p, i32],
+            "cs_get_region_info": [p, p, p, p, p, p, p],
+            "cs_get_region_plan": [p, p, p, p, p, p, p, p],
             "cs_check": [p, p],
             "cs_set_spin_limit": [p, i64],
             "cs_batch_create": [i32, p, p],
@@ -77,6 +82,10 @@ def lib():
             "cs_batch_set_params": [p, p, p, p, p],
             "cs_batch_set_launch": [p, i32, i32, i32],
             "cs_batch_get_info": [p, p, p, p, p, p, p, p, p],
+            "cs_batch_set_schedule": [p, C.c_int],
+            "cs_batch_plan_regions": [p, i32],
+            "cs_batch_get_region_info": [p, p, p, p, p, p, p],
+            "cs_batch_get_region_plan": [p, p, p, p, p, p, p, p],
             "cs_batch_eval_stamp": [p, p, d, p, p, p, p],
             "cs_batch_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_batch_check": [p, p],
@@ -114,6 +123,33 @@ def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+def _region_info(fn, h) -> dict:
+    nr, mp = C.c_int32(), C.c_int32()
+    ni, ns, nn, nl = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(fn(h, C.byref(nr), C.byref(mp), C.byref(ni), C.byref(ns), C.byref(nn), C.byref(nl)),
+           "region info")
+    return dict(n_regions=nr.value, max_phases=mp.value, n_items=ni.value, n_staged=ns.value,
+                n_interior=nn.value, n_links=nl.value)
+
+
+def _region_plan(plan_fn, info_fn, get_fn, h, block, n_dev) -> dict:
+    """Host planning for `block` threads per region, and a copy of the tables."""
+    _check(plan_fn(h, int(block)), "plan regions")
+    inf = _region_info(info_fn, h)
+    t = dict(perm=np.zeros(n_dev, np.int32), phase=np.zeros(n_dev, np.uint16),
+             code=np.zeros(20 * n_dev, np.int32), rtab=np.zeros(8 * inf["n_regions"], np.int32),
+             interior=np.zeros(inf["n_interior"], np.int32), links=np.zeros(inf["n_links"], np.int32),
+             item=np.zeros(4 * inf["n_items"], np.int32))
+    _check(get_fn(h, *[_np_ptr(t[k]) if t[k].size else None
+                       for k in ("perm", "phase", "code", "rtab", "interior", "links", "item")]),
+           "region plan")
+    t["code"] = t["code"].reshape(20, n_dev)
+    t["rtab"] = t["rtab"].reshape(-1, 8)
+    t["item"] = t["item"].reshape(-1, 4)
+    t.update(inf)
+    return t
 
 
 class Circuit:
@@ -204,6 +240,14 @@ class Circuit:
         return dict(n_dev=nd.value, n_rows=nr.value, nnz=nz.value, n_colors=nc.value, grid=g.value,
                     block=bl.value, eval_ahead=ea.value, n_hub=nh.value)
 
+    def region_info(self) -> dict:
+        return _region_info(lib().cs_get_region_info, self._h)
+
+    def region_plan(self, block: int = 256) -> dict:
+        L = lib()
+        return _region_plan(L.cs_plan_regions, L.cs_get_region_info, L.cs_get_region_plan, self._h,
+                            block, self.n_dev)
+
     def eval_stamp(self, x, ag0: float, hist=None, A=None, b=None, variant="persistent", stream=None):
         import torch
         if A is None:
@@ -263,9 +307,19 @@ class Batch:
             _lib.cs_batch_destroy(h)
             self._h = None
 
-    def set_launch(self, block: int = 0, eval_ahead: int = -1, local_max_dev: int = 0):
+    def set_launch(self, block: int = 0, eval_ahead: int = -1, local_max_dev: int = 0,
+                   schedule: str = "persistent"):
         _check(lib().cs_batch_set_launch(self._h, int(block), int(eval_ahead), int(local_max_dev)),
                "cs_batch_set_launch")
+        _check(lib().cs_batch_set_schedule(self._h, VARIANTS[schedule]), "cs_batch_set_schedule")
+
+    def region_info(self) -> dict:
+        return _region_info(lib().cs_batch_get_region_info, self._h)
+
+    def region_plan(self, block: int = 256) -> dict:
+        L = lib()
+        return _region_plan(L.cs_batch_plan_regions, L.cs_batch_get_region_info,
+                            L.cs_batch_get_region_plan, self._h, block, self.n_dev)
 
     def set_params(self, W, L, VTH0, stream=None):
         _check(lib().cs_batch_set_params(self._h, _dev_ptr(W), _dev_ptr(L), _dev_ptr(VTH0),

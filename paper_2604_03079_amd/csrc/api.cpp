@@ -164,6 +164,64 @@ cs_status plan_persistent(cs_circuit *c) {
     return CS_OK;
 }
 
+// Region planner input of a single circuit (colour-major table).
+RegionSource region_source(const HostCircuit &h) {
+    RegionSource src;
+    src.n = h.n_dev;
+    src.code = h.code;
+    src.term = colour_major_terms(h, 0);
+    src.pol.resize((size_t)h.n_dev);
+    src.colour.resize((size_t)h.n_dev);
+    for (size_t p = 0; p < (size_t)h.n_dev; ++p) {
+        src.pol[p] = h.pol[(size_t)h.perm[p]];
+        src.colour[p] = h.colour[(size_t)h.perm[p]];
+    }
+    src.perm = h.perm;
+    src.nnz = h.nnz;
+    src.n_rows = h.n_rows;
+    src.hub_ptr = h.hub_ptr;
+    src.hub_cptr = h.hub_cptr;
+    src.stage_base = h.hub_ptr.empty() ? 0 : h.hub_ptr.back();
+    return src;
+}
+
+cs_status plan_regions(cs_circuit *c, int32_t block) {
+    if (c->rp.built && c->rp.cap == block) return CS_OK;
+    c->rd.ready = false;
+    try {
+        Err e = build_regions(region_source(c->h), block, c->rp);
+        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, block) > 65536)
+            e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
+        if (e.st != CS_OK) {
+            c->rp = RegionPlan{};
+            return fail(e.st, e.msg);
+        }
+    } catch (const std::bad_alloc &) {
+        c->rp = RegionPlan{};
+        return fail(CS_ENOMEM, "host allocation");
+    }
+    return CS_OK;
+}
+
+// Region plan for the current block size, uploaded, and its parameter copy current.
+cs_status ensure_region(cs_circuit *c, hipStream_t s) {
+    cs_status st = plan_regions(c, c->block);
+    if (st != CS_OK) return st;
+    if (!c->rd.ready) {
+        hipError_t e = upload_regions(c->rp, c->rd);
+        if (e != hipSuccess) {
+            c->rd.ready = false;
+            return hip_fail(e, "upload region tables");
+        }
+    }
+    if (c->rd.par_stale) {
+        CS_CHECK_HIP(launch_permute_params(c->h.n_dev, c->rd.cm_pos.p, c->d_par.p, c->h.n_dev, c->rd.par.p, s),
+                     "parameter permute launch");
+        c->rd.par_stale = false;
+    }
+    return CS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -214,6 +272,8 @@ cs_status cs_build_coloring(cs_circuit *c, const uint8_t *exclude, int32_t *n_co
         Err e = build_colouring(c->h, exclude, n_edges);
         if (e.st != CS_OK) return fail(e.st, e.msg);
         order_within_colours(c->h);
+        c->rp = RegionPlan{};
+        c->rd.ready = false;
     } catch (const std::bad_alloc &) {
         return fail(CS_ENOMEM, "host allocation");
     }
@@ -229,6 +289,8 @@ cs_status cs_build_stamp_map(cs_circuit *c, int32_t *n_rows, int64_t *nnz) {
     if (!c->h.coloured) return fail(CS_ESTATE, "cs_build_coloring must come first");
     try {
         Err e = build_map(c->h);
+        c->rp = RegionPlan{};
+        c->rd.ready = false;
         if (e.st != CS_OK) return fail(e.st, e.msg);
     } catch (const std::bad_alloc &) {
         return fail(CS_ENOMEM, "host allocation");
@@ -312,6 +374,7 @@ cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const d
     CS_CHECK_HIP(launch_gather_params(c->h.n_dev, c->d_perm.p, W, L, VTH0, c->d_par.p,
                                       (hipStream_t)stream), "parameter gather launch");
     c->params_set = true;
+    c->rd.par_stale = true;
     return CS_OK;
 }
 
@@ -399,9 +462,38 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
         case CS_ATOMIC:
             CS_CHECK_HIP(launch_atomic(kc, call, c->h.nnz, c->h.n_rows, s), "atomic launch");
             return CS_OK;
+        case CS_COLOR_REGION: {
+            cs_status st = ensure_region(c, s);
+            if (st != CS_OK) return st;
+            CS_CHECK_HIP(launch_region(region_kcirc(kc, c->rp, c->rd), call, region_kregion(c->rp, c->rd),
+                                       c->block, s), "region launch");
+            return CS_OK;
+        }
         default:
             return fail(CS_EINVAL, "unknown variant");
     }
+}
+
+cs_status cs_plan_regions(cs_circuit *c, int32_t block) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    if (block < 64 || block > 256 || block % 64 != 0) return fail(CS_EINVAL, "block must be 64, 128, 192 or 256");
+    return plan_regions(c, block);
+}
+
+cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *max_phases,
+                             int64_t *n_items, int64_t *n_staged, int64_t *n_interior, int64_t *n_links) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    region_info(c->rp, n_regions, max_phases, n_items, n_staged, n_interior, n_links);
+    return CS_OK;
+}
+
+cs_status cs_get_region_plan(const cs_circuit *c, int32_t *perm, uint16_t *phase, int32_t *code,
+                             int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->rp.built) return fail(CS_ESTATE, "no region plan yet");
+    region_tables(c->rp, perm, phase, code, rtab, interior, links, item);
+    return CS_OK;
 }
 
 cs_status cs_check(cs_circuit *c, void *stream) {

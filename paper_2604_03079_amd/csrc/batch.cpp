@@ -99,6 +99,9 @@ cs_status pack(cs_batch *B) {
     const size_t n = (size_t)n_pos;
     B->pterm.assign(4 * n, 0);
     B->ppol.assign(n, 0);
+    B->pcolour.assign(n, 0);
+    B->rp = RegionPlan{};
+    B->rd.ready = false;
     P.code.assign((size_t)NCODE * n, 0);
     P.acode.assign((size_t)NCODE * n, 0);
     for (size_t q = 0; q < n; ++q) {
@@ -110,6 +113,7 @@ cs_status pack(cs_batch *B) {
         for (int j = 0; j < 4; ++j)
             B->pterm[(size_t)j * n + q] = t4[j] == 0 ? 0 : (int32_t)(B->row_off[(size_t)i] + t4[j]);
         B->ppol[q] = h.pol[(size_t)v];
+        B->pcolour[q] = h.colour[(size_t)v];
         P.perm[q] = (int32_t)(B->dev_off[(size_t)i] + v);
         const int k = distinct_nodes(t4);
         for (int j = 0; j < k * k + k; ++j) {
@@ -278,6 +282,56 @@ cs_status plan(cs_batch *B) {
     return CS_OK;
 }
 
+cs_status plan_regions(cs_batch *B, int32_t block) {
+    if (B->rp.built && B->rp.cap == block) return CS_OK;
+    B->rd.ready = false;
+    HostCircuit &P = B->h;
+    try {
+        RegionSource src;
+        src.n = P.n_dev;
+        src.code = P.code;
+        src.term = B->pterm;
+        src.pol = B->ppol;
+        src.perm = P.perm;
+        src.colour = B->pcolour;
+        src.group_ptr = B->dev_off;
+        src.nnz = B->nnz_off.back();
+        src.n_rows = B->row_off.back();
+        src.hub_ptr = P.hub_ptr;
+        src.hub_cptr = P.hub_cptr;
+        src.stage_base = B->stage_total;
+        Err e = build_regions(src, block, B->rp);
+        if (e.st == CS_OK && region_lds_bytes(B->rp.max_lds + 1, block) > 65536)
+            e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
+        if (e.st != CS_OK) {
+            B->rp = RegionPlan{};
+            return bfail(e.st, e.msg);
+        }
+    } catch (const std::bad_alloc &) {
+        B->rp = RegionPlan{};
+        return bfail(CS_ENOMEM, "host allocation");
+    }
+    return CS_OK;
+}
+
+cs_status ensure_region(cs_batch *B, hipStream_t s) {
+    cs_status st = plan_regions(B, B->block);
+    if (st != CS_OK) return st;
+    if (!B->rd.ready) {
+        hipError_t e = upload_regions(B->rp, B->rd);
+        if (e != hipSuccess) {
+            B->rd.ready = false;
+            return bfail(CS_EHIP, std::string("upload region tables: ") + hipGetErrorString(e));
+        }
+    }
+    if (B->rd.par_stale) {
+        CS_BCHECK(launch_permute_params(B->h.n_dev, B->rd.cm_pos.p, B->d_par.p, B->h.n_dev, B->rd.par.p, s),
+                  "parameter permute launch");
+        B->rd.par_stale = false;
+    }
+    return CS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -391,6 +445,7 @@ cs_status cs_batch_set_params(cs_batch *B, const double *W, const double *L, con
     CS_BCHECK(launch_gather_params(B->h.n_dev, B->d_perm.p, W, L, VTH0, B->d_par.p, (hipStream_t)stream),
               "parameter gather launch");
     B->params_set = true;
+    B->rd.par_stale = true;
     return CS_OK;
 }
 
@@ -415,10 +470,18 @@ cs_status cs_batch_eval_stamp(cs_batch *B, const double *x, double ag0, const do
     if (!B->params_set) return bfail(CS_ESTATE, "cs_batch_set_params must come first");
     if (!x || !A || !b_vec) return bfail(CS_EINVAL, "NULL x, A or b");
     if (cur_device() != B->device) return bfail(CS_ESTATE, "batch uploaded to another device");
+    const KCall call{x, ag0, hist, A, b_vec};
+    if (B->schedule == CS_COLOR_REGION) {
+        cs_status st = ensure_region(B, (hipStream_t)stream);
+        if (st != CS_OK) return st;
+        const KCirc kc = make_kc(B);
+        CS_BCHECK(launch_region(region_kcirc(kc, B->rp, B->rd), call, region_kregion(B->rp, B->rd), B->block,
+                                (hipStream_t)stream), "batched region launch");
+        return CS_OK;
+    }
     cs_status st = plan(B);
     if (st != CS_OK) return st;
     const KCirc kc = make_kc(B);
-    const KCall call{x, ag0, hist, A, b_vec};
     const KSync ks{B->d_sync.p, B->spin_limit};
     const KLocal kl{B->n_local, B->d_local.p, B->d_local_cptr.p};
     CS_BCHECK(launch_persistent(kc, call, ks, nullptr, B->eval_ahead, B->grid, B->block, B->cooperative,
@@ -437,6 +500,44 @@ cs_status cs_batch_vjp(cs_batch *B, const double *x, double ag0, const double *h
     const KCirc kc = make_kc(B);
     const KCall call{x, ag0, hist, nullptr, nullptr};
     CS_BCHECK(launch_vjp(kc, call, A_bar, b_bar, W_bar, L_bar, VTH0_bar, (hipStream_t)stream), "vjp launch");
+    return CS_OK;
+}
+
+cs_status cs_batch_set_schedule(cs_batch *B, cs_variant schedule) {
+    if (!B) return bfail(CS_EINVAL, "NULL batch");
+    if (schedule != CS_COLOR_PERSISTENT && schedule != CS_COLOR_REGION)
+        return bfail(CS_EINVAL, "batch schedule must be CS_COLOR_PERSISTENT or CS_COLOR_REGION");
+    B->schedule = schedule;
+    return CS_OK;
+}
+
+cs_status cs_batch_plan_regions(cs_batch *B, int32_t block) {
+    if (!B) return bfail(CS_EINVAL, "NULL batch");
+    if (block < 64 || block > 256 || block % 64 != 0) return bfail(CS_EINVAL, "block must be 64, 128, 192 or 256");
+    if (!B->packed) {
+        try {
+            cs_status st = pack(B);
+            if (st != CS_OK) return st;
+        } catch (const std::bad_alloc &) {
+            return bfail(CS_ENOMEM, "host allocation");
+        }
+    }
+    return plan_regions(B, block);
+}
+
+cs_status cs_batch_get_region_info(const cs_batch *B, int32_t *n_regions, int32_t *max_phases,
+                                   int64_t *n_items, int64_t *n_staged, int64_t *n_interior,
+                                   int64_t *n_links) {
+    if (!B) return bfail(CS_EINVAL, "NULL batch");
+    region_info(B->rp, n_regions, max_phases, n_items, n_staged, n_interior, n_links);
+    return CS_OK;
+}
+
+cs_status cs_batch_get_region_plan(const cs_batch *B, int32_t *perm, uint16_t *phase, int32_t *code,
+                                   int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item) {
+    if (!B) return bfail(CS_EINVAL, "NULL batch");
+    if (!B->rp.built) return bfail(CS_ESTATE, "no region plan yet");
+    region_tables(B->rp, perm, phase, code, rtab, interior, links, item);
     return CS_OK;
 }
 

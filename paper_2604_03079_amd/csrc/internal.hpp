@@ -79,6 +79,51 @@ struct HostCircuit {
     int32_t max_hub_len = 0;
 };
 
+// Input of the region planner: a colour-major table (single circuit or packed batch).
+struct RegionSource {
+    int32_t n = 0;                         // positions
+    std::vector<int32_t> code;             // [NCODE][n] tags ADD/STORE/HUB
+    std::vector<int32_t> term;             // [4][n] x index + 1
+    std::vector<int8_t> pol;               // [n]
+    std::vector<int32_t> perm;             // position -> global device index
+    std::vector<int32_t> colour;           // [n] colour of each position (within its circuit)
+    std::vector<int64_t> group_ptr;        // circuit boundaries over global devices (empty: one)
+    int64_t nnz = 0, n_rows = 0;
+    std::vector<int32_t> hub_ptr, hub_cptr;
+    int64_t stage_base = 0;                // hub staging size; shared entries staged after it
+};
+
+// Region schedule tables (host), region-major positions.
+struct RegionPlan {
+    bool built = false;
+    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0;
+    int64_t stage_size = 0;
+    std::vector<int32_t> perm, cm_pos, term, code, rtab, int_target, ritems, item, deferred;
+    std::vector<int8_t> pol;
+    std::vector<uint16_t> phase;
+};
+
+// Device copies of a region plan.
+struct RegionDev {
+    DevBuf<int32_t> perm, cm_pos, term, code, rtab, int_target, ritems, item, deferred;
+    DevBuf<int8_t> pol;
+    DevBuf<uint16_t> phase;
+    DevBuf<double> par, stage;
+    DevBuf<uint32_t> item_count;
+    bool ready = false;      // uploaded from the current plan
+    bool par_stale = true;
+};
+
+Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R);
+hipError_t upload_regions(const RegionPlan &R, RegionDev &D);
+// Kernel views of the region tables: base supplies the fixed stores and hub tables.
+KCirc region_kcirc(const KCirc &base, const RegionPlan &R, const RegionDev &D);
+KRegion region_kregion(const RegionPlan &R, const RegionDev &D);
+void region_info(const RegionPlan &R, int32_t *n_regions, int32_t *max_phases, int64_t *n_items,
+                 int64_t *n_staged, int64_t *n_interior, int64_t *n_links);
+void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t *code, int32_t *rtab,
+                   int32_t *interior, int32_t *links, int32_t *item);
+
 // Build the greedy colouring (ascending device order) and the colour-major order.
 Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges);
 // Build pattern, stamp codes, fixed stores and hub lists.
@@ -107,6 +152,8 @@ struct cs_circuit {
     int32_t grid = 0;                  // persistent grid
     int32_t eval_ahead = 0;
     int64_t spin_limit = 1 << 22;
+    cs::RegionPlan rp;                 // region schedule (built on first use, per block size)
+    cs::RegionDev rd;
 };
 
 struct cs_batch {
@@ -119,6 +166,7 @@ struct cs_batch {
     cs::HostCircuit h;                 // packed codes, permutation, colour pointers, hubs
     std::vector<int32_t> pterm;        // [4][positions] x index + 1
     std::vector<int8_t> ppol;
+    std::vector<int32_t> pcolour;      // colour of each packed position (within its circuit)
     std::vector<int32_t> local_table;  // 6 per workgroup-local circuit
     std::vector<int32_t> local_cptr;
     int32_t n_local = 0;
@@ -138,4 +186,7 @@ struct cs_batch {
     bool cooperative = true;
     int32_t grid = 0, n_part = 0, eval_ahead = 0;
     int64_t spin_limit = 1 << 22;
+    cs_variant schedule = CS_COLOR_PERSISTENT;
+    cs::RegionPlan rp;
+    cs::RegionDev rd;
 };

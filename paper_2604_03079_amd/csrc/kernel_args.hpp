@@ -13,6 +13,24 @@ constexpr uint32_t TAG_ADD = 0u;    // load-add into A (or b)
 constexpr uint32_t TAG_STORE = 1u;  // plain store (first writer in colour order)
 constexpr uint32_t TAG_HUB = 2u;    // store into the hub staging array
 constexpr int32_t INDEX_LIMIT = 1 << 30;
+
+// Region schedule codes: tag LDS_ADD / LDS_STORE address the workgroup's LDS
+// accumulators, tag STAGE the global staging array (hub and shared-entry
+// contributions).  Tag 3 marks an unused code row.
+constexpr uint32_t TAG_LDS_ADD = 0u;
+constexpr uint32_t TAG_LDS_STORE = 1u;
+constexpr uint32_t TAG_STAGE = 2u;
+// Targets of region items and interior entries: bits 30..31 = kind.
+constexpr uint32_t ITEM_A = 0u;     // A slot
+constexpr uint32_t ITEM_B = 1u;     // b row
+constexpr uint32_t ITEM_HUB = 2u;   // hub chunk (index = chunk id)
+// Per-region table fields: first position, NMOS count, PMOS count (lanes: NMOS
+// first, then PMOS), phases, interior range [4], [5) in int_target,
+// item range [6], [7) in ritems.
+constexpr int RT_FIELDS = 8;
+// Shared entries with more contributions than this are folded by the follow-up
+// kernel; smaller ones by the last contributing region, one lane each.
+constexpr int ITEM_LANE_MAX = 8;
 constexpr uint32_t HUB_B_FLAG = 0x80000000u;  // hub target is a b row
 
 // Fixed-shape hub sum: chunks of HUB_K contributions, folded left, recursively.
@@ -65,6 +83,21 @@ struct KLocal {
     int32_t n;
     const int32_t *table;
     const int32_t *cptr;
+};
+
+// Region schedule (one workgroup per region).
+struct KRegion {
+    int32_t n_regions;
+    const int32_t *rtab;        // [n_regions][RT_FIELDS]
+    const uint16_t *phase;      // [n] phase of each position
+    const int32_t *int_target;  // interior entries: A slot or b row | ITEM_B<<30, LDS slot = rank
+    const int32_t *ritems;      // items each region contributes to
+    const int32_t *item;        // [4] per item: first staged value, count, target, regions
+                                // (0: folded by the follow-up kernel)
+    uint32_t *item_count;       // arrivals per item (returns to 0 after each call)
+    int32_t lds_int;            // LDS doubles reserved for interior entries
+    int32_t n_deferred;         // items folded by the follow-up kernel
+    const int32_t *deferred;
 };
 
 // Per-call operands.

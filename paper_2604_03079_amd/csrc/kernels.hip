@@ -107,12 +107,23 @@ __device__ __forceinline__ void st_coherent(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Left fold of n values in LDS by one thread.
-__device__ __forceinline__ double fold_lds(const double *v, int n) {
-    double s = v[0];
-    for (int i = 1; i < n; ++i) s = s + v[i];
+// s + v[i0] + v[i0+1] + ... + v[n-1], left to right, by one thread; the LDS reads
+// go out sixteen at a time so that their latency is paid once per sixteen adds.
+__device__ __forceinline__ double fold_more(double s, const double *v, int i0, int n) {
+    int i = i0;
+    for (; i + 16 <= n; i += 16) {
+        double t[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t[k] = v[i + k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s = s + t[k];
+    }
+    for (; i < n; ++i) s = s + v[i];
     return s;
 }
+
+// Left fold of n >= 1 values in LDS by one thread.
+__device__ __forceinline__ double fold_lds(const double *v, int n) { return fold_more(v[0], v, 1, n); }
 
 __device__ __forceinline__ void hub_store(const KCirc &kc, const KCall &call, int h, double s) {
     const uint32_t tgt = (uint32_t)kc.hub_target[h];
@@ -126,7 +137,7 @@ __device__ __forceinline__ void hub_store(const KCirc &kc, const KCall &call, in
 // folds it.  The wave that completes the last chunk of a hub (a coherent counter)
 // folds the chunk sums, so no grid barrier is needed.  Every wave of the block
 // calls this (it contains workgroup barriers).  lds: (blockDim/64)*HUB_K doubles.
-__device__ void hub_chunks(const KCirc &kc, const KCall &call, int q0, int q1, int wave0, int nwaves,
+__device__ __forceinline__ void hub_chunks(const KCirc &kc, const KCall &call, int q0, int q1, int wave0, int nwaves,
                            double *lds) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double *mine = lds + (size_t)wave * HUB_K;
@@ -207,7 +218,7 @@ __device__ __forceinline__ void drain_memory() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ void grid_barrier(const KSync &ks, uint32_t epoch, uint32_t nblocks) {
+__device__ __forceinline__ void grid_barrier(const KSync &ks, uint32_t epoch, uint32_t nblocks) {
     uint32_t *rel = ks.sync;
     uint32_t *err = ks.sync + 1;
     uint32_t *arr = ks.sync + 2;
@@ -282,7 +293,7 @@ __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
 // stamp phases only, merged values read from the buffer of k_eval_buffer.
 // Circuits stamped inside one workgroup: colour phases separated by workgroup
 // barriers, then the circuit's own hub chunks.
-__device__ void local_circuits(const KCirc &kc, const KCall &call, const KLocal &kl, int first,
+__device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &call, const KLocal &kl, int first,
                                int stride, double *lds) {
     for (int li = first; li < kl.n; li += stride) {
         const int32_t *t = kl.table + 6 * (size_t)li;
@@ -412,6 +423,217 @@ __global__ void __launch_bounds__(256) k_atomic(KCirc kc, KCall call) {
     fixed_stores(kc, call, gtid, nthr);
 }
 
+// ---- region schedule ------------------------------------------------------------
+// One workgroup per region.  The region's devices are evaluated at once (NMOS lanes
+// first, then PMOS lanes), entries owned by the region accumulate in
+// LDS phase by phase (first writer stores, later writers add, a workgroup barrier
+// between phases), contributions to entries shared with other regions and to hub
+// entries are staged in global memory, and every shared entry or hub chunk is
+// folded by the last region that contributes to it (an arrival counter).  No wave
+// ever waits for another workgroup.
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// (lgkmcnt 0), not for its global stores, which a full __syncthreads would drain.
+// The signal fences keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ void store_target(const KCall &call, uint32_t tgt, double s) {
+    const uint32_t idx = tgt & 0x3FFFFFFFu;
+    if ((tgt >> 30) == ITEM_B) call.b[idx] = s;
+    else call.A[idx] = s;
+}
+
+// Left fold of cnt staged values by one wave (all lanes call it): up to HUB_K values
+// at a time go through the wave's LDS slice, lane 0 folds; the sum is broadcast.
+__device__ __forceinline__ double wave_fold(const double *src, int cnt, double *mine) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int g = 0; g < cnt; g += HUB_K) {
+        const int e = min(HUB_K, cnt - g);
+        for (int k = lane; k < e; k += 64) mine[k] = ld_coherent(src + g + k);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) s = g == 0 ? fold_lds(mine, e) : fold_more(s, mine, 0, e);
+        __builtin_amdgcn_wave_barrier();
+    }
+    return __shfl(s, 0, 64);
+}
+
+// A hub chunk's sum is known (wave-uniform call): store it, or record it as a
+// partial; the wave that records a hub's last partial folds the partials.
+__device__ __forceinline__ void hub_chunk_done(const KCirc &kc, const KCall &call, int q, double s, double *mine) {
+    const int lane = threadIdx.x & 63;
+    const int h = kc.hub_of_chunk[q];
+    const int c0 = kc.hub_cptr[h], nchunk = kc.hub_cptr[h + 1] - c0;
+    if (nchunk == 1) {
+        if (lane == 0) hub_store(kc, call, h, s);
+        return;
+    }
+    int last = 0;
+    if (lane == 0) {
+        st_coherent(kc.hub_part + q, s);
+        drain_memory();
+        last = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+               (uint32_t)nchunk;
+    }
+    last = __shfl(last, 0, 64);
+    if (!last) return;
+    double lvl1 = 0.0;
+    const int n1 = (nchunk + HUB_K - 1) / HUB_K;
+    for (int g = 0; g < n1; ++g) {
+        const double f = wave_fold(kc.hub_part + c0 + (size_t)g * HUB_K, min(HUB_K, nchunk - g * HUB_K), mine);
+        lvl1 = g == 0 ? f : lvl1 + f;
+    }
+    if (lane == 0) {
+        hub_store(kc, call, h, lvl1);
+        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Items of one region, after its staged values are complete: count the arrival;
+// the last region of an item folds it (small shared entries per lane, hub chunks
+// and large entries per wave).
+__device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
+                             double *scratch) {
+    const int lane = threadIdx.x & 63;
+    double *mine = scratch + (size_t)(threadIdx.x >> 6) * HUB_K;
+    for (int base = jb; base < je; base += blockDim.x) {
+        const int i = base + (int)threadIdx.x;
+        int beg = 0, cnt = 0;
+        uint32_t tgt = 0;
+        bool last = false;
+        if (i < je) {
+            const int it = kr.ritems[i];
+            const int32_t *f = kr.item + 4 * (size_t)it;
+            beg = f[0];
+            cnt = f[1];
+            tgt = (uint32_t)f[2];
+            const int need = f[3];
+            if (need == 1) {
+                last = true;
+            } else {
+                last = __hip_atomic_fetch_add(kr.item_count + it, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+                       (uint32_t)need;
+                if (last) __hip_atomic_store(kr.item_count + it, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        const bool small = last && (tgt >> 30) != ITEM_HUB && cnt <= ITEM_LANE_MAX;
+        if (small) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = k < cnt ? ld_coherent(kc.stage + beg + k) : 0.0;
+            double s = v[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k)
+                if (k < cnt) s = s + v[k];
+            store_target(call, tgt, s);
+        }
+        uint64_t big = __ballot(last && !small);
+        while (big) {
+            const int l = __builtin_ctzll(big);
+            big &= big - 1;
+            const int bbeg = __shfl(beg, l, 64), bcnt = __shfl(cnt, l, 64);
+            const uint32_t btgt = (uint32_t)__shfl((int)tgt, l, 64);
+            const double s = wave_fold(kc.stage + bbeg, bcnt, mine);
+            if ((btgt >> 30) == ITEM_HUB) hub_chunk_done(kc, call, (int)(btgt & 0x3FFFFFFFu), s, mine);
+            else if (lane == 0) store_target(call, btgt, s);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_region(KCirc kc, KCall call, KRegion kr) {
+    // LDS: kr.lds_int accumulators, then 13 outputs per lane (later the fold scratch,
+    // HUB_K per wave)
+    extern __shared__ double lds[];
+    fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    if ((int)blockIdx.x >= kr.n_regions) return;
+    const int32_t *rt = kr.rtab + (size_t)blockIdx.x * RT_FIELDS;
+    const int p0 = rt[0], nN = rt[1], nP = rt[2], nph = rt[3], ib = rt[4], ie = rt[5], jb = rt[6], je = rt[7];
+    const int t = threadIdx.x;
+    const int pos = t < nN + nP ? p0 + t : -1;
+    DevIn d{};
+    DevOut o{};
+    if (pos >= 0) {
+        d = load_terms(kc, pos);
+        o = eval_pos(kc, call, pos, d);
+    }
+    // the device's outputs wait for its phase in LDS (registers would spill)
+    double *ost = lds + kr.lds_int;
+    const int B = blockDim.x;
+    if (pos >= 0) {
+        ost[0 * B + t] = o.Ydd; ost[1 * B + t] = o.Ydg; ost[2 * B + t] = o.Ydb;
+        ost[3 * B + t] = o.Ygd; ost[4 * B + t] = o.Ygg; ost[5 * B + t] = o.Ygb;
+        ost[6 * B + t] = o.Ybd; ost[7 * B + t] = o.Ybg; ost[8 * B + t] = o.Ybb;
+        ost[9 * B + t] = o.bd; ost[10 * B + t] = o.bg; ost[11 * B + t] = o.bs; ost[12 * B + t] = o.bb;
+    }
+    uint32_t cd[NCODE];
+    int ph = -1;
+    if (pos >= 0) {
+        const int k = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) +
+                      (d.t2 != 0 && d.t2 != d.t0 && d.t2 != d.t1) +
+                      (d.t3 != 0 && d.t3 != d.t0 && d.t3 != d.t1 && d.t3 != d.t2);
+        const int nc = k * k + k;
+#pragma unroll
+        for (int j = 0; j < NCODE; ++j) cd[j] = j < nc ? (uint32_t)kc.code[(size_t)j * kc.n + pos] : 0xC0000000u;
+        ph = kr.phase[pos];
+    }
+    // each device merges and writes in its own phase; a workgroup barrier between phases
+    for (int q = 0; q < max(nph, 1); ++q) {
+        if (ph == q) {
+            // addresses and tags are formed here, not hoisted out of the loop (that
+            // would keep twenty addresses live across the phases)
+            uint32_t cq[NCODE];
+#pragma unroll
+            for (int j = 0; j < NCODE; ++j) {
+                cq[j] = cd[j];
+                asm volatile("" : "+v"(cq[j]));
+            }
+            RegionSink sink{cq, lds, kc.stage};
+            DevOut oo;
+            oo.Ydd = ost[0 * B + t]; oo.Ydg = ost[1 * B + t]; oo.Ydb = ost[2 * B + t];
+            oo.Ygd = ost[3 * B + t]; oo.Ygg = ost[4 * B + t]; oo.Ygb = ost[5 * B + t];
+            oo.Ybd = ost[6 * B + t]; oo.Ybg = ost[7 * B + t]; oo.Ybb = ost[8 * B + t];
+            oo.bd = ost[9 * B + t]; oo.bg = ost[10 * B + t]; oo.bs = ost[11 * B + t]; oo.bb = ost[12 * B + t];
+            double Y[16];
+            full_Y(oo, Y);
+            const double bl[4] = {oo.bd, oo.bg, oo.bs, oo.bb};
+            emit_merged(d.key, Y, bl, sink);
+        }
+        lds_barrier();
+    }
+    for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
+    drain_memory();
+    __syncthreads();
+    finish_items(kc, call, kr, jb, je, lds + kr.lds_int);
+}
+
+// Follow-up kernel of the region schedule: every large shared entry, one wave each,
+// its staged contributions folded left in colour order (complete at kernel start).
+__global__ void __launch_bounds__(256) k_fold_items(KCirc kc, KCall call, KRegion kr) {
+    __shared__ double lds[4 * HUB_K];
+    const int wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + wave;
+    if (i >= kr.n_deferred) return;
+    const int32_t *f = kr.item + 4 * (size_t)kr.deferred[i];
+    const double s = wave_fold(kc.stage + f[0], f[1], lds + (size_t)wave * HUB_K);
+    if ((threadIdx.x & 63) == 0) store_target(call, (uint32_t)f[2], s);
+}
+
+__global__ void k_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
+                                 double *dst) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const int32_t q = idx[p];
+        dst[p] = src[q];
+        dst[(size_t)n + p] = src[(size_t)n_src + q];
+        dst[2 * (size_t)n + p] = src[2 * (size_t)n_src + q];
+    }
+}
+
 // ---- host launchers ----------------------------------------------------------------
 
 static hipError_t occupancy(const void *fn, int block, int *blocks_per_cu) {
@@ -474,6 +696,31 @@ hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, h
     if (kc.n == 0) return hipSuccess;
     const int grid = (kc.n + 255) / 256;
     hipLaunchKernelGGL(k_eval_buffer, dim3(grid), dim3(256), 0, s, kc, call, buf);
+    return hipGetLastError();
+}
+
+size_t region_lds_bytes(int lds_int, int block) {
+    return sizeof(double) * ((size_t)lds_int + std::max((size_t)13 * block, (size_t)(block / 64) * HUB_K));
+}
+
+hipError_t region_capacity(int block, int lds_int, int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_region, block,
+                                                        region_lds_bytes(lds_int, block));
+}
+
+hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s) {
+    const int grid = std::max(kr.n_regions, 1);
+    hipLaunchKernelGGL(k_region, dim3(grid), dim3(block), region_lds_bytes(kr.lds_int, block), s, kc, call, kr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || kr.n_deferred == 0) return e;
+    hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
+                                 double *dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_params, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, src, n_src, dst);
     return hipGetLastError();
 }
 

@@ -25,6 +25,14 @@ hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks
 hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s);
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s);
+// Region schedule: one workgroup of `block` threads per region; dynamic LDS for
+// lds_int interior accumulators plus the fold scratch.
+size_t region_lds_bytes(int lds_int, int block);
+hipError_t region_capacity(int block, int lds_int, int *blocks_per_cu);
+hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s);
+// dst[j][p] = src[j][idx[p]] for the three parameter rows.
+hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
+                                 double *dst, hipStream_t s);
 hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,
                          hipStream_t s);
 

@@ -1,0 +1,387 @@
+// Region schedule, host planner.
+//
+// The colour order of the paper's schedule (Methodology: colours processed in
+// sequence, a colour's devices in parallel) fixes, for every matrix entry and RHS
+// row, the order in which its writers accumulate: the writer of the smallest colour
+// stores, the others add in ascending colour.  The region schedule keeps exactly
+// that per-entry order but runs it at workgroup scope:
+//   * devices are cut, in ascending device index, into regions of at most one
+//     workgroup (a circuit that fits one region is never split);
+//   * an entry whose writers all lie in one region is accumulated in that
+//     workgroup's LDS, in colour phases separated by workgroup barriers; the phases
+//     are the colours coarsened to levels (a device's level is one more than the
+//     largest level of an earlier-coloured writer of any of its region entries), so
+//     consecutive writers of an entry keep their order while unrelated colours share
+//     a phase;
+//   * an entry written from several regions has its contributions staged, in colour
+//     order, in a global array; the last of its regions to finish (a counter) folds
+//     them left and stores the result, or, for entries with more than ITEM_LANE_MAX
+//     contributions, a follow-up kernel folds them (one wave per entry);
+//   * hub entries keep their fixed-shape sum: contributions staged in ascending
+//     device index, each chunk of HUB_K folded by the last region touching it.
+// The result is bitwise the colour-order accumulation.
+#include <algorithm>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace cs {
+
+namespace {
+
+int distinct_k(const std::vector<int32_t> &term, size_t n, size_t p) {
+    int32_t u[4];
+    int k = 0;
+    for (int t = 0; t < 4; ++t) {
+        const int32_t nd = term[(size_t)t * n + p];
+        if (nd == 0) continue;
+        bool seen = false;
+        for (int j = 0; j < k; ++j) seen = seen || u[j] == nd;
+        if (!seen) u[k++] = nd;
+    }
+    return k;
+}
+
+inline int lanes_needed(int nN, int nP) { return nN + nP; }
+
+}  // namespace
+
+Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
+    const size_t n = (size_t)s.n;
+    const int64_t nnz = s.nnz, nkeys = s.nnz + s.n_rows;
+    if (cap < 64 || cap % 64 != 0) return {CS_EINVAL, "region capacity must be a multiple of 64"};
+    R = RegionPlan{};
+    R.cap = cap;
+
+    std::vector<int32_t> pos_of(n);
+    for (size_t p = 0; p < n; ++p) pos_of[(size_t)s.perm[p]] = (int32_t)p;
+    std::vector<int8_t> kk(n);
+    for (size_t p = 0; p < n; ++p) kk[p] = (int8_t)distinct_k(s.term, n, p);
+
+    // 1. regions over ascending (global) device index
+    std::vector<int32_t> region_of(n, 0);
+    {
+        std::vector<int64_t> gptr = s.group_ptr;
+        if (gptr.empty()) gptr = {0, (int64_t)n};
+        int32_t r = -1;
+        int nN = 0, nP = 0;
+        for (size_t gi = 0; gi + 1 < gptr.size(); ++gi) {
+            const int64_t g0 = gptr[gi], g1 = gptr[gi + 1];
+            int gN = 0, gP = 0;
+            for (int64_t g = g0; g < g1; ++g) (s.pol[(size_t)pos_of[(size_t)g]] > 0 ? gN : gP)++;
+            // a circuit that fits one region is not split: open a fresh one for it
+            if (g1 > g0 && r >= 0 && lanes_needed(gN, gP) <= cap && lanes_needed(nN + gN, nP + gP) > cap) {
+                ++r;
+                nN = nP = 0;
+            }
+            for (int64_t g = g0; g < g1; ++g) {
+                const bool isN = s.pol[(size_t)pos_of[(size_t)g]] > 0;
+                if (r < 0 || lanes_needed(nN + (isN ? 1 : 0), nP + (isN ? 0 : 1)) > cap) {
+                    ++r;
+                    nN = nP = 0;
+                }
+                region_of[(size_t)g] = r;
+                (isN ? nN : nP)++;
+            }
+        }
+        R.n_regions = r + 1;
+    }
+
+    // 2. writers of every non-hub target (A slot, or nnz + b row), sorted by colour
+    std::vector<int64_t> kptr((size_t)nkeys + 1, 0);
+    auto target_of = [&](size_t p, int j, uint32_t c) -> int64_t {
+        const int k = kk[p];
+        const int64_t idx = (int64_t)(c & 0x3FFFFFFFu);
+        return j < k * k ? idx : nnz + idx;
+    };
+    for (size_t p = 0; p < n; ++p) {
+        const int k = kk[p];
+        for (int j = 0; j < k * k + k; ++j) {
+            const uint32_t c = (uint32_t)s.code[(size_t)j * n + p];
+            if ((c >> 30) == TAG_HUB) continue;
+            kptr[(size_t)target_of(p, j, c) + 1]++;
+        }
+    }
+    for (int64_t t = 0; t < nkeys; ++t) kptr[(size_t)t + 1] += kptr[(size_t)t];
+    std::vector<int64_t> wr((size_t)kptr[(size_t)nkeys]);
+    {
+        std::vector<int64_t> fill(kptr.begin(), kptr.end() - 1);
+        for (size_t p = 0; p < n; ++p) {
+            const int k = kk[p];
+            for (int j = 0; j < k * k + k; ++j) {
+                const uint32_t c = (uint32_t)s.code[(size_t)j * n + p];
+                if ((c >> 30) == TAG_HUB) continue;
+                wr[(size_t)fill[(size_t)target_of(p, j, c)]++] = ((int64_t)p << 5) | j;
+            }
+        }
+    }
+    for (int64_t t = 0; t < nkeys; ++t) {
+        std::sort(wr.begin() + kptr[(size_t)t], wr.begin() + kptr[(size_t)t + 1],
+                  [&](int64_t a, int64_t b) { return s.colour[(size_t)(a >> 5)] < s.colour[(size_t)(b >> 5)]; });
+    }
+
+    // new codes, indexed like s.code (colour-major positions)
+    std::vector<int32_t> code(s.code.size(), 0);
+    std::vector<std::vector<int64_t>> interior((size_t)R.n_regions);
+    std::vector<std::vector<int32_t>> rit((size_t)R.n_regions);
+    std::vector<uint8_t> is_interior((size_t)nkeys, 0);
+    int64_t cursor = s.stage_base;
+    std::vector<int32_t> regs;
+    for (int64_t t = 0; t < nkeys; ++t) {
+        const int64_t b0 = kptr[(size_t)t], b1 = kptr[(size_t)t + 1];
+        if (b0 == b1) continue;
+        regs.clear();
+        for (int64_t w = b0; w < b1; ++w) regs.push_back(region_of[(size_t)s.perm[(size_t)(wr[(size_t)w] >> 5)]]);
+        std::sort(regs.begin(), regs.end());
+        regs.erase(std::unique(regs.begin(), regs.end()), regs.end());
+        if (regs.size() == 1) {
+            interior[(size_t)regs[0]].push_back(t);
+            is_interior[(size_t)t] = 1;
+            continue;
+        }
+        if (cursor + (b1 - b0) >= INDEX_LIMIT) return {CS_ENOTSUP, "too many staged contributions"};
+        const int32_t it = (int32_t)(R.item.size() / 4);
+        const uint32_t tgt = t < nnz ? (uint32_t)t : ((uint32_t)(t - nnz) | (ITEM_B << 30));
+        // large shared entries are folded by the follow-up kernel (regions = 0, no
+        // arrival counting); the last arriving region would otherwise fold many
+        const bool deferred = b1 - b0 > ITEM_LANE_MAX;
+        R.item.insert(R.item.end(), {(int32_t)cursor, (int32_t)(b1 - b0), (int32_t)tgt,
+                                     deferred ? 0 : (int32_t)regs.size()});
+        if (deferred) R.deferred.push_back(it);
+        else
+            for (int32_t g : regs) rit[(size_t)g].push_back(it);
+        for (int64_t w = b0; w < b1; ++w) {
+            const size_t p = (size_t)(wr[(size_t)w] >> 5);
+            const int j = (int)(wr[(size_t)w] & 31);
+            code[(size_t)j * n + p] = (int32_t)((TAG_STAGE << 30) | (uint32_t)(cursor + (w - b0)));
+        }
+        cursor += b1 - b0;
+    }
+    R.stage_size = cursor;
+
+    // 3. hub contributions keep their staging index; one item per chunk
+    {
+        std::vector<std::pair<int32_t, int32_t>> qr;   // (chunk, region)
+        for (size_t p = 0; p < n; ++p) {
+            const int k = kk[p];
+            for (int j = 0; j < k * k + k; ++j) {
+                const uint32_t c = (uint32_t)s.code[(size_t)j * n + p];
+                if ((c >> 30) != TAG_HUB) continue;
+                const int32_t si = (int32_t)(c & 0x3FFFFFFFu);
+                code[(size_t)j * n + p] = (int32_t)((TAG_STAGE << 30) | (uint32_t)si);
+                const size_t h = (size_t)(std::upper_bound(s.hub_ptr.begin(), s.hub_ptr.end(), si) - s.hub_ptr.begin()) - 1;
+                const int32_t q = s.hub_cptr[h] + (si - s.hub_ptr[h]) / HUB_K;
+                qr.emplace_back(q, region_of[(size_t)s.perm[p]]);
+            }
+        }
+        std::sort(qr.begin(), qr.end());
+        qr.erase(std::unique(qr.begin(), qr.end()), qr.end());
+        for (size_t a = 0; a < qr.size();) {
+            size_t b = a;
+            while (b < qr.size() && qr[b].first == qr[a].first) ++b;
+            const int32_t q = qr[a].first;
+            const size_t h = (size_t)(std::upper_bound(s.hub_cptr.begin(), s.hub_cptr.end(), q) - s.hub_cptr.begin()) - 1;
+            const int32_t beg = s.hub_ptr[h] + (q - s.hub_cptr[h]) * HUB_K;
+            const int32_t cnt = std::min<int32_t>(HUB_K, s.hub_ptr[h + 1] - beg);
+            const int32_t it = (int32_t)(R.item.size() / 4);
+            R.item.insert(R.item.end(), {beg, cnt, (int32_t)((ITEM_HUB << 30) | (uint32_t)q), (int32_t)(b - a)});
+            for (size_t e = a; e < b; ++e) rit[(size_t)qr[e].second].push_back(it);
+            a = b;
+        }
+    }
+
+    // 4. LDS slots of the interior entries (sorted by target) and their codes
+    std::vector<int32_t> lds_of((size_t)nkeys, -1);
+    std::vector<int32_t> int_ptr((size_t)R.n_regions + 1, 0);
+    for (int32_t g = 0; g < R.n_regions; ++g) {
+        auto &v = interior[(size_t)g];
+        std::sort(v.begin(), v.end());
+        for (size_t i = 0; i < v.size(); ++i) {
+            lds_of[(size_t)v[i]] = (int32_t)i;
+            R.int_target.push_back(v[i] < nnz ? (int32_t)v[i] : (int32_t)((uint32_t)(v[i] - nnz) | (ITEM_B << 30)));
+        }
+        int_ptr[(size_t)g + 1] = (int32_t)R.int_target.size();
+        R.max_lds = std::max<int32_t>(R.max_lds, (int32_t)v.size());
+        std::vector<int64_t>().swap(v);
+    }
+    for (int64_t t = 0; t < nkeys; ++t) {
+        if (!is_interior[(size_t)t]) continue;
+        for (int64_t w = kptr[(size_t)t]; w < kptr[(size_t)t + 1]; ++w) {
+            const size_t p = (size_t)(wr[(size_t)w] >> 5);
+            const int j = (int)(wr[(size_t)w] & 31);
+            const uint32_t tag = w == kptr[(size_t)t] ? TAG_LDS_STORE : TAG_LDS_ADD;
+            code[(size_t)j * n + p] = (int32_t)((tag << 30) | (uint32_t)lds_of[(size_t)t]);
+        }
+    }
+
+    // 5. levels: devices of a region in colour order; a device comes one level after
+    // the previous writer of each of its interior entries
+    std::vector<int32_t> level(n, 0), nphase((size_t)R.n_regions, 0);
+    {
+        std::vector<int32_t> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            const int32_t ra = region_of[(size_t)s.perm[(size_t)a]], rb = region_of[(size_t)s.perm[(size_t)b]];
+            return ra != rb ? ra < rb : s.colour[(size_t)a] < s.colour[(size_t)b];
+        });
+        std::vector<int32_t> last((size_t)nkeys, -1);
+        for (int32_t p : order) {
+            const int k = kk[(size_t)p];
+            int32_t lv = 0;
+            for (int j = 0; j < k * k + k; ++j) {
+                const uint32_t c = (uint32_t)s.code[(size_t)j * n + (size_t)p];
+                if ((c >> 30) == TAG_HUB) continue;
+                const int64_t t = target_of((size_t)p, j, c);
+                if (is_interior[(size_t)t]) lv = std::max(lv, last[(size_t)t] + 1);
+            }
+            for (int j = 0; j < k * k + k; ++j) {
+                const uint32_t c = (uint32_t)s.code[(size_t)j * n + (size_t)p];
+                if ((c >> 30) == TAG_HUB) continue;
+                const int64_t t = target_of((size_t)p, j, c);
+                if (is_interior[(size_t)t]) last[(size_t)t] = lv;
+            }
+            level[(size_t)p] = lv;
+            const int32_t g = region_of[(size_t)s.perm[(size_t)p]];
+            nphase[(size_t)g] = std::max(nphase[(size_t)g], lv + 1);
+        }
+    }
+
+    // 6. region-major positions: per region its NMOS, then its PMOS, each in phase
+    // order (so that a wave's lanes mostly share one phase), then device order
+    R.perm.resize(n);
+    R.cm_pos.resize(n);
+    R.term.assign(4 * n, 0);
+    R.pol.assign(n, 0);
+    R.phase.assign(n, 0);
+    R.code.assign((size_t)NCODE * n, (int32_t)(3u << 30));
+    R.rtab.assign((size_t)R.n_regions * RT_FIELDS, 0);
+    {
+        std::vector<std::vector<int32_t>> members((size_t)R.n_regions);
+        for (size_t g = 0; g < n; ++g) members[(size_t)region_of[g]].push_back((int32_t)g);
+        for (auto &mv : members)
+            std::stable_sort(mv.begin(), mv.end(), [&](int32_t a, int32_t b) {
+                return level[(size_t)pos_of[(size_t)a]] < level[(size_t)pos_of[(size_t)b]];
+            });
+        size_t q = 0;
+        for (int32_t g = 0; g < R.n_regions; ++g) {
+            int32_t *rt = &R.rtab[(size_t)g * RT_FIELDS];
+            rt[0] = (int32_t)q;
+            int nN = 0, nP = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int32_t dv : members[(size_t)g]) {
+                    const size_t p = (size_t)pos_of[(size_t)dv];
+                    const bool isN = s.pol[p] > 0;
+                    if (isN != (pass == 0)) continue;
+                    (isN ? nN : nP)++;
+                    R.perm[q] = dv;
+                    R.cm_pos[q] = (int32_t)p;
+                    for (int t = 0; t < 4; ++t) R.term[(size_t)t * n + q] = s.term[(size_t)t * n + p];
+                    R.pol[q] = s.pol[p];
+                    if (level[p] > 65535) return {CS_ENOTSUP, "too many phases in a region"};
+                    R.phase[q] = (uint16_t)level[p];
+                    const int k = kk[p];
+                    for (int j = 0; j < k * k + k; ++j) R.code[(size_t)j * n + q] = code[(size_t)j * n + p];
+                    ++q;
+                }
+            }
+            rt[1] = nN;
+            rt[2] = nP;
+            rt[3] = nphase[(size_t)g];
+            rt[4] = int_ptr[(size_t)g];
+            rt[5] = int_ptr[(size_t)g + 1];
+            rt[6] = (int32_t)R.ritems.size();
+            auto &li = rit[(size_t)g];
+            std::sort(li.begin(), li.end());
+            R.ritems.insert(R.ritems.end(), li.begin(), li.end());
+            rt[7] = (int32_t)R.ritems.size();
+            R.max_phase = std::max(R.max_phase, nphase[(size_t)g]);
+        }
+    }
+    R.built = true;
+    return {CS_OK, ""};
+}
+
+}  // namespace cs
+
+namespace cs {
+
+hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
+    hipError_t e;
+    if ((e = D.perm.upload(R.perm)) != hipSuccess) return e;
+    if ((e = D.cm_pos.upload(R.cm_pos)) != hipSuccess) return e;
+    if ((e = D.term.upload(R.term)) != hipSuccess) return e;
+    if ((e = D.code.upload(R.code)) != hipSuccess) return e;
+    if ((e = D.rtab.upload(R.rtab)) != hipSuccess) return e;
+    if ((e = D.int_target.upload(R.int_target)) != hipSuccess) return e;
+    if ((e = D.ritems.upload(R.ritems)) != hipSuccess) return e;
+    if ((e = D.item.upload(R.item)) != hipSuccess) return e;
+    if ((e = D.deferred.upload(R.deferred)) != hipSuccess) return e;
+    if ((e = D.pol.upload(R.pol)) != hipSuccess) return e;
+    if ((e = D.phase.upload(R.phase)) != hipSuccess) return e;
+    if ((e = D.par.alloc(3 * R.perm.size())) != hipSuccess) return e;
+    if ((e = D.stage.alloc((size_t)R.stage_size)) != hipSuccess) return e;
+    const size_t n_items = R.item.size() / 4;
+    if ((e = D.item_count.alloc(n_items)) != hipSuccess) return e;
+    if (n_items && (e = hipMemset(D.item_count.p, 0, sizeof(uint32_t) * n_items)) != hipSuccess) return e;
+    D.par_stale = true;
+    D.ready = true;
+    return hipSuccess;
+}
+
+void region_info(const RegionPlan &R, int32_t *n_regions, int32_t *max_phases, int64_t *n_items,
+                 int64_t *n_staged, int64_t *n_interior, int64_t *n_links) {
+    if (n_regions) *n_regions = R.n_regions;
+    if (max_phases) *max_phases = R.max_phase;
+    if (n_items) *n_items = (int64_t)(R.item.size() / 4);
+    if (n_staged) *n_staged = R.stage_size;
+    if (n_interior) *n_interior = (int64_t)R.int_target.size();
+    if (n_links) *n_links = (int64_t)R.ritems.size();
+}
+
+template <class T>
+static void copy_out(const std::vector<T> &v, T *dst) {
+    if (dst && !v.empty()) std::copy(v.begin(), v.end(), dst);
+}
+
+void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t *code, int32_t *rtab,
+                   int32_t *interior, int32_t *links, int32_t *item) {
+    copy_out(R.perm, perm);
+    copy_out(R.phase, phase);
+    copy_out(R.code, code);
+    copy_out(R.rtab, rtab);
+    copy_out(R.int_target, interior);
+    copy_out(R.ritems, links);
+    copy_out(R.item, item);
+}
+
+KCirc region_kcirc(const KCirc &base, const RegionPlan &R, const RegionDev &D) {
+    KCirc k = base;
+    k.n = (int32_t)R.perm.size();
+    k.n_colors = 0;
+    k.term = D.term.p;
+    k.pol = D.pol.p;
+    k.par = D.par.p;
+    k.code = D.code.p;
+    k.acode = nullptr;
+    k.perm = D.perm.p;
+    k.cptr = nullptr;
+    k.stage = D.stage.p;
+    return k;
+}
+
+KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
+    KRegion r{};
+    r.n_regions = R.n_regions;
+    r.rtab = D.rtab.p;
+    r.phase = D.phase.p;
+    r.int_target = D.int_target.p;
+    r.ritems = D.ritems.p;
+    r.item = D.item.p;
+    r.item_count = D.item_count.p;
+    r.n_deferred = (int32_t)R.deferred.size();
+    r.deferred = D.deferred.p;
+    r.lds_int = (R.max_lds + 1) & ~1;
+    return r;
+}
+
+}  // namespace cs

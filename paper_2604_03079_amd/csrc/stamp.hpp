@@ -87,9 +87,38 @@ __device__ __forceinline__ double merged_rhs(const double bl[4]) {
 // Merged values of the pattern in code order (k*k matrix entries row-major over
 // nodes, then k RHS entries), handed to the sink in one call so that the sink can
 // issue all its memory operations back to back.
+template <int KEY, int J, class Sink>
+__device__ __forceinline__ void put_entry(const double Y[16], const double bl[4], Sink &sink) {
+    constexpr int K = Pat<KEY>::k();
+    if constexpr (J < K * K) {
+        switch (J / K * 4 + J % K) {
+#define CS_PE(q) case q: sink.template put<J>(merged_entry<KEY, (q) / 4, (q) % 4>(Y)); break;
+            CS_PE(0) CS_PE(1) CS_PE(2) CS_PE(3) CS_PE(4) CS_PE(5) CS_PE(6) CS_PE(7)
+            CS_PE(8) CS_PE(9) CS_PE(10) CS_PE(11) CS_PE(12) CS_PE(13) CS_PE(14) CS_PE(15)
+#undef CS_PE
+            default: break;
+        }
+    } else {
+        constexpr int A = J - K * K;
+        sink.template put<J>(merged_rhs<KEY, (A < 4 ? A : 3)>(bl));
+    }
+}
+
+template <int KEY, int J, int N, class Sink>
+__device__ __forceinline__ void put_entries(const double Y[16], const double bl[4], Sink &sink) {
+    if constexpr (J < N) {
+        put_entry<KEY, J>(Y, bl, sink);
+        put_entries<KEY, J + 1, N>(Y, bl, sink);
+    }
+}
+
 template <int KEY, class Sink>
 __device__ __forceinline__ void emit_pattern(const double Y[16], const double bl[4], Sink &sink) {
-    if constexpr (Pat<KEY>::valid() && Pat<KEY>::k() > 0) {
+    if constexpr (Pat<KEY>::valid() && Pat<KEY>::k() > 0 && Sink::kStreaming) {
+        // one entry at a time: each merged value is written before the next is formed
+        constexpr int K = Pat<KEY>::k();
+        put_entries<KEY, 0, K * K + K>(Y, bl, sink);
+    } else if constexpr (Pat<KEY>::valid() && Pat<KEY>::k() > 0) {
         constexpr int K = Pat<KEY>::k();
         double m[K * K + K];
 #pragma unroll
@@ -156,6 +185,7 @@ __device__ __forceinline__ void emit_merged(int key, const double Y[16], const d
 // a device are issued before its first store (its entries are distinct).
 template <bool COHERENT>
 struct ColourSinkT {
+    static constexpr bool kStreaming = false;
     const int32_t *code;
     int32_t n, pos;
     double *A, *b, *stage;
@@ -187,6 +217,7 @@ using ColourSink = ColourSinkT<false>;
 
 // Atomic stamping: every entry (hub entries included) is an FP64 atomic add.
 struct AtomicSink {
+    static constexpr bool kStreaming = false;
     const int32_t *acode;
     int32_t n, pos;
     double *A, *b;
@@ -200,8 +231,30 @@ struct AtomicSink {
     }
 };
 
+// Region sink: codes prefetched in registers; tag LDS_STORE / LDS_ADD accumulate in
+// the workgroup's LDS, tag STAGE stores (coherently) into the global staging array.
+struct RegionSink {
+    static constexpr bool kStreaming = true;
+    const uint32_t *cd;
+    double *lds, *stage;
+    template <int J>
+    __device__ __forceinline__ void put(double v) {
+        const uint32_t tag = cd[J] >> 30, idx = cd[J] & 0x3FFFFFFFu;
+        if (tag == TAG_STAGE) {
+            __hip_atomic_store(stage + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (tag == TAG_LDS_ADD) {
+            // current + value, issued without waiting for a read: no other lane of the
+            // phase touches this entry, the LDS add just avoids a read round trip
+            (void)__hip_atomic_fetch_add(lds + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            lds[idx] = v;
+        }
+    }
+};
+
 // Buffer sink: merged values into a [NCODE][n] buffer (the buffered variant).
 struct BufferSink {
+    static constexpr bool kStreaming = false;
     double *buf;
     int32_t n, pos;
     template <int NA, int NB>

@@ -54,19 +54,21 @@ def batch_oracle(orc):
     return circs, ref
 
 
-@pytest.mark.parametrize("block,eval_ahead,local", [(256, -1, 0), (128, 0, 0), (256, 0, 64),
-                                                    (256, -1, 256), (64, 0, 10 ** 9), (256, 1, 400)])
-def test_batch_bit_exact_per_circuit(torch_dev, batch_oracle, block, eval_ahead, local):
+@pytest.mark.parametrize("block,eval_ahead,local,schedule", [
+    (256, -1, 0, "persistent"), (128, 0, 0, "persistent"), (256, 0, 64, "persistent"),
+    (256, -1, 256, "persistent"), (64, 0, 10 ** 9, "persistent"), (256, 1, 400, "persistent"),
+    (256, -1, 0, "region"), (128, -1, 0, "region"), (64, -1, 0, "region")])
+def test_batch_bit_exact_per_circuit(torch_dev, batch_oracle, block, eval_ahead, local, schedule):
     torch = torch_dev
     circs, ref = batch_oracle
     cs = [CS.prepare(c, True) for c in circs]
     B = CS.Batch(cs)
-    B.set_launch(block, eval_ahead, local)
+    B.set_launch(block, eval_ahead, local, schedule)
     W, L, V, x = (packed(torch, circs, a) for a in ("W", "L", "VTH0", "x"))
     B.set_params(W, L, V)
     A = torch.full((B.nnz,), float("nan"), dtype=torch.float64, device="cuda:0")
     b = torch.full((B.n_rows,), float("nan"), dtype=torch.float64, device="cuda:0")
-    say(f"case batch block={block} eval_ahead={eval_ahead} local={local} n_dev={B.n_dev}")
+    say(f"case batch {schedule} block={block} eval_ahead={eval_ahead} local={local} n_dev={B.n_dev}")
     for _ in range(2):
         B.eval_stamp(x, 1e12, None, A, b)
     torch.cuda.synchronize()

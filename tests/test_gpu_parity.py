@@ -1,6 +1,6 @@
 """GPU parity of the evaluate-and-stamp path (through the C-ABI) against the oracle.
 
-Bars: the coloured variants (persistent, per-colour kernels, buffered) reproduce the
+Bars: the coloured variants (persistent, per-colour kernels, buffered, region) reproduce the
 oracle's colour replay bit for bit; the atomic variant (no colour order) agrees with
 the oracle's serial order within 1e-12 of the per-entry sum of |contributions|
 (the reordering bound).  Cases span several workgroups and ragged tails, both
@@ -91,7 +91,8 @@ SMALL = small_cases()
 def test_coloured_variants_bit_exact(torch_dev, orc, name, circ, exclude):
     A0, b0 = oracle_replay(orc, circ, exclude)
     for variant, block, ea in (("persistent", 256, 0), ("persistent", 64, 1), ("persistent", 128, -1),
-                               ("per_kernel", 0, -1), ("buffered", 0, -1)):
+                               ("per_kernel", 0, -1), ("buffered", 0, -1), ("region", 256, -1),
+                               ("region", 64, -1), ("region", 192, -1)):
         say(f"case {name} exclude={exclude} variant={variant} block={block} eval_ahead={ea}")
         A, b, _ = gpu_stamp(torch_dev, circ, exclude, variant, block=block, eval_ahead=ea)
         assert_bit_exact(A, A0, f"{name}/{variant}/A")
@@ -115,7 +116,7 @@ def test_history_and_dc(torch_dev, orc):
     hist = rng.normal(0.0, 1e-5, (circ.n_dev, 4))
     for ag0, h in ((1e12, hist), (0.0, None), (3.7e11, hist)):
         A0, b0 = oracle_replay(orc, circ, True, ag0, h)
-        for variant in ("persistent", "per_kernel"):
+        for variant in ("persistent", "per_kernel", "region"):
             say(f"case chain50 ag0={ag0} hist={h is not None} variant={variant}")
             A, b, _ = gpu_stamp(torch_dev, circ, True, variant, ag0=ag0, hist=h)
             assert_bit_exact(A, A0, "A")
@@ -126,7 +127,7 @@ def test_empty_circuit(torch_dev, orc):
     circ = G.Circuit("empty", 3, np.zeros((0, 4), np.int32), np.zeros(0, np.int8),
                      np.array([[1, 0]], np.int32), np.array([1.1]), np.array([0, 1, 0], np.uint8), 1.1,
                      np.zeros(0), np.zeros(0), np.zeros(0), np.array([1.1, 0.3, 0.0]))
-    for variant in ("persistent", "per_kernel", "atomic", "buffered"):
+    for variant in ("persistent", "per_kernel", "atomic", "buffered", "region"):
         say(f"case empty variant={variant}")
         A, b, _ = gpu_stamp(torch_dev, circ, True, variant)
         # rows: vdd, node 2, branch; entries: (vdd,vdd), (vdd,br), (2,2), (br,vdd)
@@ -135,10 +136,11 @@ def test_empty_circuit(torch_dev, orc):
 
 def test_repeated_calls_are_deterministic(torch_dev, orc):
     circ = G.sram_case(32, 8, 11)
-    A1, b1, _ = gpu_stamp(torch_dev, circ, True, "persistent", repeat=1)
-    A2, b2, _ = gpu_stamp(torch_dev, circ, True, "persistent", repeat=3)
-    assert_bit_exact(A1, A2, "A")
-    assert_bit_exact(b1, b2, "b")
+    for variant in ("persistent", "region"):
+        A1, b1, _ = gpu_stamp(torch_dev, circ, True, variant, repeat=1)
+        A2, b2, _ = gpu_stamp(torch_dev, circ, True, variant, repeat=3)
+        assert_bit_exact(A1, A2, "A")
+        assert_bit_exact(b1, b2, "b")
 
 
 @pytest.mark.parametrize("idx", [1, 2])
@@ -146,7 +148,7 @@ def test_full_size_workloads(torch_dev, orc, idx):
     circ = G.workload(idx)
     A0, b0 = oracle_replay(orc, circ, True)
     variants = [("persistent", 256, -1), ("persistent", 256, 0), ("per_kernel", 0, -1),
-                ("buffered", 0, -1)]
+                ("buffered", 0, -1), ("region", 256, -1), ("region", 128, -1)]
     for variant, block, ea in variants:
         say(f"case workload{idx} variant={variant} eval_ahead={ea}")
         A, b, c = gpu_stamp(torch_dev, circ, True, variant, block=block, eval_ahead=ea)
@@ -162,7 +164,7 @@ def test_full_size_workloads(torch_dev, orc, idx):
     assert np.all(np.abs(b - bs) <= 1e-12 * mb)
 
 
-@pytest.mark.parametrize("variant", ["persistent", "per_kernel", "buffered", "atomic"])
+@pytest.mark.parametrize("variant", ["persistent", "per_kernel", "buffered", "atomic", "region"])
 def test_graph_replay_matches_eager(torch_dev, orc, variant):
     # The NR step captured once and replayed; x changes between replays (eager work
     # in between); every replay must equal the oracle at that x.

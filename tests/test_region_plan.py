@@ -1,0 +1,221 @@
+"""CPU checks of the region schedule's host planner.
+
+The library's plan tables (regions, LDS phases, stamp codes, shared-entry items) are
+replayed here on the host exactly as the region kernel uses them, with every device's
+local values taken from the oracle; the replayed matrix entries and RHS rows must
+equal the oracle's colour-order replay bit for bit.  Structural checks cover the
+region layout (NMOS lanes first, then PMOS lanes, capacity), the code
+rows, the item bookkeeping and, for batches, that a circuit fitting one region is
+never split.  Hub entries keep their staging indices; their fixed-shape sum is a
+kernel step, checked on the GPU."""
+import numpy as np
+import pytest
+
+from paper_2604_03079_amd import colorstamp as CS
+from paper_2604_03079_amd import netgen as G
+
+NC, PC = G.default_card(1), G.default_card(-1)
+AG0 = 1e12
+
+
+def merged_values(orc, circ, v):
+    """Device v's merged contributions in code order (node pairs row-major, then RHS
+    rows), from the oracle's local Y and bl."""
+    t4 = [int(n) for n in circ.term[v]]
+    V = np.array([0.0 if n == 0 else circ.x[n - 1] for n in t4])
+    pol = int(circ.pol[v])
+    Y, bl, _, _ = orc.device_eval(NC if pol > 0 else PC, pol, circ.W[v], circ.L[v], circ.VTH0[v], V, AG0)
+    u = []
+    for n in t4:
+        if n != 0 and n not in u:
+            u.append(n)
+    m = []
+    for a in u:
+        for b in u:
+            acc = None
+            for t in range(4):
+                for s in range(4):
+                    if t4[t] == a and t4[s] == b:
+                        acc = Y[t, s] if acc is None else acc + Y[t, s]
+            m.append(acc)
+    for a in u:
+        acc = None
+        for t in range(4):
+            if t4[t] == a:
+                acc = bl[t] if acc is None else acc + bl[t]
+        m.append(acc)
+    return m
+
+
+def replay(plan, vals, pol, block, nnz, n_rows):
+    """Host replay of the region kernel: returns {('A'|'b', index): value} for every
+    entry the plan owns or shares, and the staging array."""
+    code, rtab, phase, perm = plan["code"], plan["rtab"], plan["phase"], plan["perm"]
+    n = len(perm)
+    stage = np.full(plan["n_staged"], np.nan)
+    out = {}
+    seen = np.zeros(n, bool)
+    nxt = 0
+    for r in range(plan["n_regions"]):
+        p0, nN, nP, nph, ib, ie, jb, je = (int(v) for v in rtab[r])
+        assert p0 == nxt and nN + nP > 0
+        nxt = p0 + nN + nP
+        assert nN + nP <= block
+        pos = list(range(p0, p0 + nN + nP))
+        assert all(pol[perm[p]] > 0 for p in pos[:nN]) and all(pol[perm[p]] < 0 for p in pos[nN:])
+        lds = np.full(ie - ib, np.nan)
+        for p in pos:
+            seen[p] = True
+            for j, mv in enumerate(vals[perm[p]]):
+                c = int(code[j, p]) & 0xFFFFFFFF
+                tag, idx = c >> 30, c & 0x3FFFFFFF
+                assert tag in (0, 1, 2)
+                if tag == 2:
+                    assert np.isnan(stage[idx])
+                    stage[idx] = mv
+            for j in range(len(vals[perm[p]]), 20):
+                assert (int(code[j, p]) & 0xFFFFFFFF) >> 30 == 3
+            assert phase[p] < max(nph, 1)
+        for q in range(nph):
+            for p in pos:
+                if phase[p] != q:
+                    continue
+                for j, mv in enumerate(vals[perm[p]]):
+                    c = int(code[j, p]) & 0xFFFFFFFF
+                    tag, idx = c >> 30, c & 0x3FFFFFFF
+                    if tag == 1:
+                        lds[idx] = mv
+                    elif tag == 0:
+                        assert not np.isnan(lds[idx]), "load-add before the store"
+                        lds[idx] = lds[idx] + mv
+        assert not np.isnan(lds).any()
+        for i in range(ie - ib):
+            tg = int(plan["interior"][ib + i]) & 0xFFFFFFFF
+            key = ("b" if tg >> 30 == 1 else "A", tg & 0x3FFFFFFF)
+            assert key not in out
+            out[key] = lds[i]
+    assert nxt == n and seen.all()
+    # items: linked from exactly the regions that contribute
+    links = {}
+    for r in range(plan["n_regions"]):
+        _, _, _, _, _, _, jb, je = (int(v) for v in rtab[r])
+        for it in plan["links"][jb:je]:
+            links.setdefault(int(it), []).append(r)
+    for it, (beg, cnt, tgt, need) in enumerate(plan["item"]):
+        tgt = int(tgt) & 0xFFFFFFFF
+        assert not np.isnan(stage[beg:beg + cnt]).any()
+        if tgt >> 30 == 2:
+            assert len(links.get(it, [])) == need >= 1
+            assert cnt <= 256
+            continue
+        if need == 0:     # large shared entry: folded by the follow-up kernel
+            assert it not in links and cnt > 8
+        else:
+            assert len(links.get(it, [])) == need >= 2 and cnt <= 8
+        s = stage[beg]
+        for k in range(1, cnt):
+            s = s + stage[beg + k]
+        key = ("b" if tgt >> 30 == 1 else "A", tgt & 0x3FFFFFFF)
+        assert key not in out
+        out[key] = s
+    assert not np.isnan(stage).any()
+    return out
+
+
+def check_against_oracle(orc, circ, c, exclude, block):
+    col, _, _ = orc.colour(circ, exclude)
+    rp, ci = orc.pattern(circ)
+    A0, b0 = orc.assemble(circ, rp, ci, NC, PC, AG0, col=col, exclude=exclude)
+    plan = c.region_plan(block)
+    vals = [merged_values(orc, circ, v) for v in range(circ.n_dev)]
+    out = replay(plan, vals, circ.pol, block, len(ci), circ.n_rows)
+    for (kind, idx), v in out.items():
+        ref = (A0 if kind == "A" else b0)[idx]
+        assert np.float64(v).view(np.int64) == np.float64(ref).view(np.int64), (kind, idx, v, ref)
+    return plan, out
+
+
+CASES = [
+    ("chain50", lambda: G.workload(0)),
+    ("opamp12", lambda: G.draw_params(G.opamp2(12), np.random.default_rng(2), G.W_OPAMP, G.L_OPAMP)),
+    ("sram6x5", lambda: G.sram_case(6, 5, 8)),
+    ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)),
+    ("pchain7x3", lambda: G.draw_params(G.parallel_chain(7, 3), np.random.default_rng(5), G.W_CHAIN, G.L_CHAIN)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("exclude", [True, False])
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_region_replay_equals_colour_replay(orc, name, make, exclude, block):
+    circ = make()
+    c = CS.prepare(circ, exclude)
+    plan, out = check_against_oracle(orc, circ, c, exclude, block)
+    # every non-hub written entry is owned by a region or shared
+    rp, ci = orc.pattern(circ)
+    col, _, _ = orc.colour(circ, exclude)
+    slot, sflag, brow, bflag = orc.stamp_map(circ, rp, ci, col, exclude)
+    written = {("A", int(s)) for s, f in zip(slot.ravel(), sflag.ravel()) if s >= 0 and f != 2}
+    written |= {("b", int(r)) for r, f in zip(brow.ravel(), bflag.ravel()) if r >= 0 and f != 2}
+    assert set(out) == written
+
+
+def test_chain_regions_are_contiguous_and_phases_are_colours(orc):
+    circ = G.workload(0)
+    c = CS.prepare(circ, True)
+    plan = c.region_plan(64)
+    # 100 devices in regions of 64 consecutive devices
+    assert plan["n_regions"] == 2
+    assert plan["max_phases"] <= 4
+    for r in range(plan["n_regions"]):
+        p0, nN, nP = (int(v) for v in plan["rtab"][r][:3])
+        devs = sorted(int(v) for v in plan["perm"][p0:p0 + nN + nP])
+        assert devs == list(range(devs[0], devs[0] + len(devs)))
+
+
+def test_sram_levels_are_far_fewer_than_colours(orc):
+    # regions of 128 devices hold parts of one cell row: the wordline and bitlines
+    # are shared with other regions, and the cell-internal nodes need few levels
+    circ = G.sram_case(32, 32, 8)
+    c = CS.prepare(circ, True)
+    plan = c.region_plan(128)
+    assert c.n_colors == 68
+    assert plan["max_phases"] <= 6
+
+
+def test_batch_plan_keeps_small_circuits_whole_and_replays(orc):
+    circs = G.batch_sweep(seed=9, n_opamp=12, n_chain=3, n_ring=2, chain_range=(50, 300),
+                          ring_range=(31, 201))
+    B = CS.Batch([CS.prepare(cc, True) for cc in circs])
+    plan = B.region_plan(128)
+    region_of = np.zeros(B.n_dev, np.int64)
+    for r in range(plan["n_regions"]):
+        p0, nN, nP = (int(v) for v in plan["rtab"][r][:3])
+        region_of[plan["perm"][p0:p0 + nN + nP]] = r
+    for i, cc in enumerate(circs):
+        regs = set(region_of[B.dev_off[i]:B.dev_off[i + 1]].tolist())
+        nN, nP = int((cc.pol > 0).sum()), int((cc.pol < 0).sum())
+        if nN + nP <= 128:
+            assert len(regs) == 1, cc.name
+    # replay of the packed plan against each circuit's oracle colour replay
+    vals, pol = [], np.concatenate([cc.pol for cc in circs])
+    for cc in circs:
+        vals += [merged_values(orc, cc, v) for v in range(cc.n_dev)]
+    out = replay(plan, vals, pol, 128, B.nnz, B.n_rows)
+    for i, cc in enumerate(circs):
+        col, _, _ = orc.colour(cc, True)
+        rp, ci = orc.pattern(cc)
+        A0, b0 = orc.assemble(cc, rp, ci, NC, PC, AG0, col=col, exclude=True)
+        for (kind, idx), v in out.items():
+            lo, hi = ((B.nnz_off[i], B.nnz_off[i + 1]) if kind == "A" else (B.row_off[i], B.row_off[i + 1]))
+            if lo <= idx < hi:
+                ref = (A0 if kind == "A" else b0)[idx - lo]
+                assert np.float64(v).view(np.int64) == np.float64(ref).view(np.int64)
+
+
+def test_plan_errors(orc):
+    c = CS.prepare(G.workload(0), True)
+    with pytest.raises(CS.CsError):
+        c.region_plan(100)
+    with pytest.raises(CS.CsError):
+        c.region_plan(512)
