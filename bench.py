@@ -73,6 +73,22 @@ def time_graph(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps, g
 
 
+def time_eager(torch, fn, steps, warmup):
+    """Average duration of fn() launched back to back on the current stream, between
+    two events on that stream (the kernel's own time plus launch gaps)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def algorithmic_counts(circ, exclude=True):
     """FP64 operations and bytes one step needs (counted on the oracle's definition)."""
     from oracle import oracle as O
@@ -138,6 +154,37 @@ def traffic_from_profiles(kernel_hash: str, key: str):
     return e.get("bytes_per_launch")
 
 
+def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel, key, copy_mib):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads for a
+    plain device copy of copy_mib MiB; written to profiles/hbm_traffic.json."""
+    import csv
+
+    def per_dispatch(path, name, counter):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Kernel_Name"].split("(")[0].endswith(name) and r["Counter_Name"] == counter]
+        return sum(vals) / len(vals), len(vals)
+
+    kf, nf = per_dispatch(fetch_csv, kernel, "FETCH_SIZE")
+    kw, nw = per_dispatch(write_csv, kernel, "WRITE_SIZE")
+    cf, _ = per_dispatch(copy_fetch_csv, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    cw, _ = per_dispatch(copy_write_csv, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    copy_bytes = copy_mib * (1 << 20)
+    ff, wf = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    entry = dict(kernel=kernel, kernel_hash=kernel_sources_hash(), dispatches=[nf, nw],
+                 fetch_kib=round(kf, 1), write_kib=round(kw, 1), copy_mib=copy_mib,
+                 copy_fetch_kib=round(cf, 1), copy_write_kib=round(cw, 1),
+                 fetch_factor=round(ff, 4), write_factor=round(wf, 4),
+                 bytes_per_launch=int(kf * 1024 * ff + kw * 1024 * wf))
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    d = json.load(open(p)) if os.path.exists(p) else {}
+    d[key] = entry
+    with open(p, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(entry))
+
+
 def bench_batch(torch, CS, G, dev):
     """512 uneven circuits: autotuned batched kernel vs one launch per circuit."""
     from paper_2604_03079_amd import autotune
@@ -188,13 +235,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--variant", default="persistent")
+    ap.add_argument("--variant", default="region")
     ap.add_argument("--no-extras", action="store_true", help="skip SRAM/batch/adjoint lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--only", action="store_true", help="time only --variant (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs and exit")
+    ap.add_argument("--pmc-kernel", default="k_region")
+    ap.add_argument("--pmc-key", default="region_chain100k")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.pmc_kernel, args.pmc_key, 256)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: every box here has one GPU (asked for {args.gpus}).",
               file=sys.stderr)
@@ -237,6 +291,9 @@ def main():
         ms, g = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, args.warmup)
         c.check()
         graphs.append((c, g, A, b))
+        if variant == args.variant and coop:
+            kernel_ms = time_eager(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, args.warmup)
+            log(f"  {variant} kernel launches back to back: {kernel_ms * 1e3:.2f} us")
         name = variant if coop else variant + "_ordinary_launch"
         variants[name] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2),
                               info=c.info(), steps=steps)
@@ -244,7 +301,7 @@ def main():
 
     main_v = variants[args.variant]
     ms = main_v["ms_per_step"]
-    secs = ms * 1e-3
+    ksecs = kernel_ms * 1e-3
     result = {
         "metric": "M devices eval+stamp/s per NR iter (colored vs atomic); batched & fwd+adjoint",
         "value": main_v["value"],
@@ -264,14 +321,15 @@ def main():
                    "variant": args.variant, "ag0": AG0, "graph_replay": True},
         "roofline": {
             "bound": "alu",
-            "achieved": round(counts["ops"] / secs / 1e12, 4),
+            "achieved": round(counts["ops"] / ksecs / 1e12, 4),
             "peak": round(PEAK_FP64_OPS / 1e12, 2),
             "unit": "TFLOP/s",
-            "frac": round(counts["ops"] / secs / PEAK_FP64_OPS, 5),
+            "frac": round(counts["ops"] / ksecs / PEAK_FP64_OPS, 5),
             "traffic": traffic_from_profiles(khash, f"{args.variant}_chain100k"),
             "algorithmic_ops_per_launch": counts["ops"],
             "algorithmic_bytes_per_launch": counts["bytes"],
-            "hbm_frac_at_algorithmic_bytes": round(counts["bytes"] / secs / PEAK_HBM, 5),
+            "hbm_frac_at_algorithmic_bytes": round(counts["bytes"] / ksecs / PEAK_HBM, 5),
+            "kernel_avg_us": round(kernel_ms * 1e3, 3),
             "kernel": KERNEL_OF.get(args.variant, args.variant),
         },
         "variants": variants,

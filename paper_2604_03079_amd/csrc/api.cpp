@@ -190,7 +190,7 @@ cs_status plan_regions(cs_circuit *c, int32_t block) {
     c->rd.ready = false;
     try {
         Err e = build_regions(region_source(c->h), block, c->rp);
-        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, block) > 65536)
+        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, block) > 65536 - 1024)
             e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
         if (e.st != CS_OK) {
             c->rp = RegionPlan{};

@@ -464,15 +464,16 @@ __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *
     return __shfl(s, 0, 64);
 }
 
-// A hub chunk's sum is known (wave-uniform call): store it, or record it as a
-// partial; the wave that records a hub's last partial folds the partials.
-__device__ __forceinline__ void hub_chunk_done(const KCirc &kc, const KCall &call, int q, double s, double *mine) {
+// A hub chunk's sum is known (wave-uniform call): store it if the hub has one
+// chunk, else record it as a partial and count it; true when this wave recorded the
+// hub's last partial (the hub's final fold is then due).
+__device__ __forceinline__ bool hub_chunk_publish(const KCirc &kc, const KCall &call, int q, double s) {
     const int lane = threadIdx.x & 63;
     const int h = kc.hub_of_chunk[q];
-    const int c0 = kc.hub_cptr[h], nchunk = kc.hub_cptr[h + 1] - c0;
+    const int nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
     if (nchunk == 1) {
         if (lane == 0) hub_store(kc, call, h, s);
-        return;
+        return false;
     }
     int last = 0;
     if (lane == 0) {
@@ -481,29 +482,27 @@ __device__ __forceinline__ void hub_chunk_done(const KCirc &kc, const KCall &cal
         last = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
                (uint32_t)nchunk;
     }
-    last = __shfl(last, 0, 64);
-    if (!last) return;
-    double lvl1 = 0.0;
-    const int n1 = (nchunk + HUB_K - 1) / HUB_K;
-    for (int g = 0; g < n1; ++g) {
-        const double f = wave_fold(kc.hub_part + c0 + (size_t)g * HUB_K, min(HUB_K, nchunk - g * HUB_K), mine);
-        lvl1 = g == 0 ? f : lvl1 + f;
-    }
-    if (lane == 0) {
-        hub_store(kc, call, h, lvl1);
-        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    return __shfl(last, 0, 64) != 0;
 }
 
+constexpr int PEND_MAX = 8;   // hubs whose final fold one workgroup runs in parallel
+
 // Items of one region, after its staged values are complete: count the arrival;
-// the last region of an item folds it (small shared entries per lane, hub chunks
-// and large entries per wave).
+// the last region of an item folds it (shared entries one lane each, hub chunks one
+// wave each; consecutive items go to different waves).  Hubs completed here get
+// their final fold from all waves: each group of HUB_K chunk sums by one wave,
+// then the group sums by one lane.  Called by every thread of the workgroup.
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
-                             double *scratch) {
-    const int lane = threadIdx.x & 63;
-    double *mine = scratch + (size_t)(threadIdx.x >> 6) * HUB_K;
+                                             double *scratch) {
+    __shared__ int pend_n;
+    __shared__ int pend_h[PEND_MAX];
+    __shared__ double gsum[PEND_MAX][HUB_MAX_CHUNKS / HUB_K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double *mine = scratch + (size_t)wave * HUB_K;
+    if (threadIdx.x == 0) pend_n = 0;
+    __syncthreads();
     for (int base = jb; base < je; base += blockDim.x) {
-        const int i = base + (int)threadIdx.x;
+        const int i = base + lane * nw + wave;
         int beg = 0, cnt = 0;
         uint32_t tgt = 0;
         bool last = false;
@@ -522,27 +521,69 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
                 if (last) __hip_atomic_store(kr.item_count + it, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        const bool small = last && (tgt >> 30) != ITEM_HUB && cnt <= ITEM_LANE_MAX;
-        if (small) {
-            double v[8];
+        const bool hub = (tgt >> 30) == ITEM_HUB;
+        if (last && !hub) {   // shared entry, at most ITEM_LANE_MAX contributions
+            double v[ITEM_LANE_MAX];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = k < cnt ? ld_coherent(kc.stage + beg + k) : 0.0;
-            double s = v[0];
+            for (int k = 0; k < ITEM_LANE_MAX; ++k) v[k] = k < cnt ? ld_coherent(kc.stage + beg + k) : 0.0;
+            double sum = v[0];
 #pragma unroll
-            for (int k = 1; k < 8; ++k)
-                if (k < cnt) s = s + v[k];
-            store_target(call, tgt, s);
+            for (int k = 1; k < ITEM_LANE_MAX; ++k)
+                if (k < cnt) sum = sum + v[k];
+            store_target(call, tgt, sum);
         }
-        uint64_t big = __ballot(last && !small);
+        uint64_t big = __ballot(last && hub);
         while (big) {
             const int l = __builtin_ctzll(big);
             big &= big - 1;
             const int bbeg = __shfl(beg, l, 64), bcnt = __shfl(cnt, l, 64);
-            const uint32_t btgt = (uint32_t)__shfl((int)tgt, l, 64);
-            const double s = wave_fold(kc.stage + bbeg, bcnt, mine);
-            if ((btgt >> 30) == ITEM_HUB) hub_chunk_done(kc, call, (int)(btgt & 0x3FFFFFFFu), s, mine);
-            else if (lane == 0) store_target(call, btgt, s);
+            const int q = (int)((uint32_t)__shfl((int)tgt, l, 64) & 0x3FFFFFFFu);
+            const double sum = wave_fold(kc.stage + bbeg, bcnt, mine);
+            if (hub_chunk_publish(kc, call, q, sum)) {
+                const int h = kc.hub_of_chunk[q];
+                int k = 0;
+                if (lane == 0) {
+                    k = atomicAdd(&pend_n, 1);
+                    if (k < PEND_MAX) pend_h[k] = h;
+                }
+                k = __shfl(k, 0, 64);
+                if (k >= PEND_MAX) {   // more completed hubs than slots: this wave alone
+                    const int c0 = kc.hub_cptr[h], nchunk = kc.hub_cptr[h + 1] - c0;
+                    double lvl1 = 0.0;
+                    for (int g = 0; g * HUB_K < nchunk; ++g) {
+                        const double f = wave_fold(kc.hub_part + c0 + (size_t)g * HUB_K, min(HUB_K, nchunk - g * HUB_K), mine);
+                        lvl1 = g == 0 ? f : lvl1 + f;
+                    }
+                    if (lane == 0) {
+                        hub_store(kc, call, h, lvl1);
+                        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
         }
+    }
+    __syncthreads();
+    const int np = min(pend_n, PEND_MAX);
+    if (np == 0) return;
+    // group folds: pair k = (pending hub, group), round-robin over the waves
+    int k = 0;
+    for (int p = 0; p < np; ++p) {
+        const int h = pend_h[p];
+        const int c0 = kc.hub_cptr[h], nchunk = kc.hub_cptr[h + 1] - c0;
+        for (int g = 0; g * HUB_K < nchunk; ++g, ++k) {
+            if (k % nw != wave) continue;
+            const double f = wave_fold(kc.hub_part + c0 + (size_t)g * HUB_K, min(HUB_K, nchunk - g * HUB_K), mine);
+            if (lane == 0) gsum[p][g] = f;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < np) {
+        const int p = threadIdx.x, h = pend_h[p];
+        const int nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
+        double lvl1 = gsum[p][0];
+        for (int g = 1; g * HUB_K < nchunk; ++g) lvl1 = lvl1 + gsum[p][g];
+        hub_store(kc, call, h, lvl1);
+        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
