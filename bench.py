@@ -221,7 +221,7 @@ def bench_adjoint(torch, CS, G, dev):
     Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
     A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
     b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
-    ms_f, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "persistent"), 50, 5)
+    ms_f, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "region"), 50, 5)
     ms_a, _ = time_graph(torch, lambda: c.vjp(x, AG0, Ab, bb), 50, 5)
     log(f"  adjoint chain10k: forward {ms_f * 1e3:.1f} us, adjoint {ms_a * 1e3:.1f} us, ratio {ms_a / ms_f:.2f}")
     return dict(workload="inverter_chain_10k_stages", n_dev=circ.n_dev,

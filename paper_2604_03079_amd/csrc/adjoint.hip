@@ -4,12 +4,14 @@
 // A and b are sums of per-device contributions, each depending on its own device's
 // parameters only, so the gradient of <A_bar, A> + <b_bar, b> w.r.t. theta_k is
 //   sum_{(t,u)} A_bar[slot(t,u)] dY_k[t][u]/dtheta_k + sum_t b_bar[row(t)] dbl_k[t]/dtheta_k
-// over the device's non-ground terminals.  One device per lane: the cotangents are
-// gathered through the device's slot map (no colouring, no atomics: every gradient
-// entry has one writer), and three forward-mode sweeps of the model (tangents of W,
-// L and VTH0 carried alongside every value and partial) recompute the intermediates
-// instead of storing them.
+// over the device's non-ground terminals.  The cotangents are gathered through the
+// device's slot map (no colouring, no atomics: every gradient entry has one writer),
+// and a forward-mode sweep of the model per parameter (the tangent of W, L or VTH0
+// carried alongside every value and partial) recomputes the intermediates instead
+// of storing them.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernel_args.hpp"
 #include "launch.hpp"
@@ -60,10 +62,17 @@ __device__ __forceinline__ void gather_cotangents(int key, const int32_t *acode,
     }
 }
 
+// One (device, parameter) pair per thread: thread i takes parameter dir = i / n of
+// device position i % n, so the three forward-mode sweeps of a device run in three
+// lanes at once (a wave holds one parameter and consecutive devices).
 __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double *A_bar,
                                              const double *b_bar, double *gW, double *gL,
                                              double *gV) {
-    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < kc.n; pos += gridDim.x * blockDim.x) {
+    const int64_t total = 3 * (int64_t)kc.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int dir = (int)(i / kc.n);
+        const int pos = (int)(i - (int64_t)dir * kc.n);
         const int32_t t0 = kc.term[pos], t1 = kc.term[(size_t)kc.n + pos];
         const int32_t t2 = kc.term[2 * (size_t)kc.n + pos], t3 = kc.term[3 * (size_t)kc.n + pos];
         const int key = pattern_key(t0, t1, t2, t3);
@@ -77,39 +86,35 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
         const int32_t v = kc.perm[pos];
         const double *hist = call.hist ? call.hist + 4 * (size_t)v : nullptr;
         const int isP = kc.pol[pos] < 0 ? 1 : 0;
-        double g[3] = {0.0, 0.0, 0.0};
+        double g = 0.0;
         for (;;) {
             const int p0 = __builtin_amdgcn_readfirstlane(isP);
             if (isP == p0) {
                 const DevCard &cd = kc.card[p0];
                 const double p = p0 ? -1.0 : 1.0;
-#pragma unroll 1
-                for (int dir = 0; dir < 3; ++dir) {
-                    const Tan Wt(W, dir == 0 ? 1.0 : 0.0), Lt(L, dir == 1 ? 1.0 : 0.0);
-                    const Tan Vt(VTH0, dir == 2 ? 1.0 : 0.0);
-                    const SizeDepT<Tan> sd = size_dep(cd, p, Wt, Lt, Vt);
-                    const DevOutT<Tan> o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist);
-                    Tan Y[16];
-                    full_Y(o, Y);
-                    double acc = 0.0;
+                const Tan Wt(W, dir == 0 ? 1.0 : 0.0), Lt(L, dir == 1 ? 1.0 : 0.0);
+                const Tan Vt(VTH0, dir == 2 ? 1.0 : 0.0);
+                const SizeDepT<Tan> sd = size_dep(cd, p, Wt, Lt, Vt);
+                const DevOutT<Tan> o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist);
+                Tan Y[16];
+                full_Y(o, Y);
+                double acc = 0.0;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) acc += Yb[i] * Y[i].t;
-                    acc += bb[0] * o.bd.t + bb[1] * o.bg.t + bb[2] * o.bs.t + bb[3] * o.bb.t;
-                    if (dir == 0) g[0] = acc; else if (dir == 1) g[1] = acc; else g[2] = acc;
-                }
+                for (int k = 0; k < 16; ++k) acc += Yb[k] * Y[k].t;
+                acc += bb[0] * o.bd.t + bb[1] * o.bg.t + bb[2] * o.bs.t + bb[3] * o.bb.t;
+                g = acc;
                 break;
             }
         }
-        gW[v] = g[0];
-        gL[v] = g[1];
-        gV[v] = g[2];
+        (dir == 0 ? gW : dir == 1 ? gL : gV)[v] = g;
     }
 }
 
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s) {
     if (kc.n == 0) return hipSuccess;
-    const int grid = (kc.n + 255) / 256;
+    const int64_t total = 3 * (int64_t)kc.n;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
     hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
     return hipGetLastError();
 }
