@@ -110,6 +110,7 @@ KCirc make_kcirc(cs_circuit *c) {
     const HostCircuit &h = c->h;
     k.n = h.n_dev;
     k.n_colors = h.n_colors;
+    k.nc_max = h.max_nc;
     k.term = c->d_term.p;
     k.pol = c->d_pol.p;
     k.par = c->d_par.p;
@@ -144,8 +145,8 @@ cs_status plan_persistent(cs_circuit *c) {
     CS_CHECK_HIP(hipGetDeviceProperties(&prop, c->device), "device properties");
     const int block = c->block;
     int per_cu_ahead = 0, per_cu_phase = 0;
-    CS_CHECK_HIP(persistent_capacity(1, block, &per_cu_ahead), "occupancy");
-    CS_CHECK_HIP(persistent_capacity(0, block, &per_cu_phase), "occupancy");
+    CS_CHECK_HIP(persistent_capacity(1, block, c->h.max_nc, &per_cu_ahead), "occupancy");
+    CS_CHECK_HIP(persistent_capacity(0, block, c->h.max_nc, &per_cu_phase), "occupancy");
     const int64_t cap_ahead = (int64_t)per_cu_ahead * prop.multiProcessorCount;
     const int64_t cap_phase = (int64_t)per_cu_phase * prop.multiProcessorCount;
     const int64_t need_ahead = std::max<int64_t>(1, (c->h.n_dev + block - 1) / block);
@@ -190,7 +191,7 @@ cs_status plan_regions(cs_circuit *c, int32_t block) {
     c->rd.ready = false;
     try {
         Err e = build_regions(region_source(c->h), block, c->rp);
-        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, block) > 65536 - 1024)
+        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, c->rp.max_nc, block) > 65536 - 1024)
             e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
         if (e.st != CS_OK) {
             c->rp = RegionPlan{};

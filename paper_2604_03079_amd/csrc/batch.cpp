@@ -73,6 +73,8 @@ cs_status pack(cs_batch *B) {
     HostCircuit &P = B->h;
     P.n_dev = (int32_t)n_pos;
     P.n_colors = cmax;
+    P.max_nc = 0;
+    for (size_t i = 0; i < nc; ++i) P.max_nc = std::max(P.max_nc, B->circ[i]->h.max_nc);
     P.perm.assign((size_t)n_pos, 0);
     P.colour_ptr.assign((size_t)cmax + 1, 0);
     std::vector<std::pair<int32_t, int32_t>> src;   // (circuit, position) per packed position
@@ -214,6 +216,7 @@ KCirc make_kc(cs_batch *B) {
     const HostCircuit &P = B->h;
     k.n = P.n_dev;
     k.n_colors = P.n_colors;
+    k.nc_max = P.max_nc;
     k.term = B->d_term.p;
     k.pol = B->d_pol.p;
     k.par = B->d_par.p;
@@ -248,8 +251,8 @@ cs_status plan(cs_batch *B) {
     CS_BCHECK(hipGetDeviceProperties(&prop, B->device), "device properties");
     const int block = B->block;
     int per_cu_ahead = 0, per_cu_phase = 0;
-    CS_BCHECK(persistent_capacity(1, block, &per_cu_ahead), "occupancy");
-    CS_BCHECK(persistent_capacity(0, block, &per_cu_phase), "occupancy");
+    CS_BCHECK(persistent_capacity(1, block, B->h.max_nc, &per_cu_ahead), "occupancy");
+    CS_BCHECK(persistent_capacity(0, block, B->h.max_nc, &per_cu_phase), "occupancy");
     const HostCircuit &P = B->h;
     const int64_t n_sched = P.colour_ptr.empty() ? 0 : P.colour_ptr.back();
     int64_t max_colour = 0;
@@ -301,7 +304,7 @@ cs_status plan_regions(cs_batch *B, int32_t block) {
         src.hub_cptr = P.hub_cptr;
         src.stage_base = B->stage_total;
         Err e = build_regions(src, block, B->rp);
-        if (e.st == CS_OK && region_lds_bytes(B->rp.max_lds + 1, block) > 65536 - 1024)
+        if (e.st == CS_OK && region_lds_bytes(B->rp.max_lds + 1, B->rp.max_nc, block) > 65536 - 1024)
             e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
         if (e.st != CS_OK) {
             B->rp = RegionPlan{};

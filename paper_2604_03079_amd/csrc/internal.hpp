@@ -77,6 +77,7 @@ struct HostCircuit {
     std::vector<int32_t> hub_cptr;    // n_hub+1: chunk ranges (chunks of HUB_K)
     std::vector<int32_t> hub_of_chunk;
     int32_t max_hub_len = 0;
+    int32_t max_nc = 0;               // largest k*k + k over the devices
 };
 
 // Input of the region planner: a colour-major table (single circuit or packed batch).
@@ -96,7 +97,7 @@ struct RegionSource {
 // Region schedule tables (host), region-major positions.
 struct RegionPlan {
     bool built = false;
-    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0;
+    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0, max_nc = 0;
     int64_t stage_size = 0;
     std::vector<int32_t> perm, cm_pos, term, code, rtab, int_target, ritems, item, deferred;
     std::vector<int8_t> pol;

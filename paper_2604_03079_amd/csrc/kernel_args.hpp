@@ -51,6 +51,7 @@ struct DevCard {
 struct KCirc {
     int32_t n;               // devices
     int32_t n_colors;
+    int32_t nc_max;          // largest number of code rows of a device (k*k + k)
     const int32_t *term;     // [4][n]: x index + 1 of d, g, s, b (0 = ground)
     const int8_t *pol;       // [n]
     const double *par;       // [3][n]: W, L, VTH0
@@ -96,6 +97,7 @@ struct KRegion {
                                 // (0: folded by the follow-up kernel)
     uint32_t *item_count;       // arrivals per item (returns to 0 after each call)
     int32_t lds_int;            // LDS doubles reserved for interior entries
+    int32_t nc_max;             // largest number of code rows of a device (k*k + k)
     int32_t n_deferred;         // items folded by the follow-up kernel
     const int32_t *deferred;
 };

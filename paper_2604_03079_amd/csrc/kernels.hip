@@ -93,6 +93,36 @@ __device__ __forceinline__ void stamp_from_buffer(Sink &sink, const double *buf,
     }
 }
 
+// Coloured stamping of one device from its merged values in LDS rows (value of code
+// row j at rows[j * stride + lane]): every load of a load-add entry is issued first
+// (coherent across the XCDs), then every store; first writers store -0.0 + value.
+__device__ __forceinline__ void apply_rows(const KCall &call, double *stage, const uint32_t cdv_in[NCODE], int k,
+                                           const double *rows, int lane, int stride) {
+    // addresses are formed here, not hoisted out of the caller's colour loop (that
+    // would keep forty addresses live across the phases)
+    uint32_t cdv[NCODE];
+#pragma unroll
+    for (int j = 0; j < NCODE; ++j) {
+        cdv[j] = cdv_in[j];
+        asm volatile("" : "+v"(cdv[j]));
+    }
+    double old[NCODE];
+#pragma unroll
+    for (int j = 0; j < NCODE; ++j) {
+        old[j] = -0.0;
+        const uint32_t tag = cdv[j] >> 30, idx = cdv[j] & 0x3FFFFFFFu;
+        if (tag == TAG_ADD)
+            old[j] = __hip_atomic_load((j >= k * k ? call.b : call.A) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int j = 0; j < NCODE; ++j) {
+        const uint32_t tag = cdv[j] >> 30, idx = cdv[j] & 0x3FFFFFFFu;
+        if (tag == 3u) continue;
+        double *p = tag == TAG_HUB ? stage + idx : (j >= k * k ? call.b : call.A) + idx;
+        __hip_atomic_store(p, old[j] + rows[j * stride + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Voltage-source stamps and entries no device writes (grid-stride).
 __device__ __forceinline__ void fixed_stores(const KCirc &kc, const KCall &call, int tid,
                                              int nthreads) {
@@ -316,19 +346,21 @@ __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &cal
 // grid barriers among themselves over positions [0, cptr[n_colors]); blocks from
 // n_part on stamp the workgroup-local circuits.  MODE 0: evaluate inside each colour
 // phase (grid-stride).  MODE 1: every thread evaluates its own device before the
-// first phase and keeps the local values in registers (requires n_part*block >=
-// the scheduled positions).  MODE 2: stamp phases only, merged values read from the
-// buffer of k_eval_buffer.
-template <int MODE>
+// first phase and keeps the merged values in LDS (requires n_part*block >= the
+// scheduled positions; dynamic LDS of nc_max doubles per thread).  MODE 2: stamp
+// phases only, merged values read from the buffer of k_eval_buffer.
+template <int MODE, bool LOCAL = true>
 __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &call,
                                                 const KSync &ks, const double *buf, int n_part,
                                                 int n_global_chunks, const KLocal &kl) {
     __shared__ double lds[4 * HUB_K];
     __shared__ uint32_t base_s;
     if (blockIdx.x == 0) fixed_stores(kc, call, threadIdx.x, blockDim.x);
-    if ((int)blockIdx.x >= n_part) {
-        local_circuits(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part, lds);
-        return;
+    if constexpr (LOCAL) {
+        if ((int)blockIdx.x >= n_part) {
+            local_circuits(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part, lds);
+            return;
+        }
     }
     if (threadIdx.x == 0) base_s = ld_flag(ks.sync);
     __syncthreads();
@@ -336,20 +368,35 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nthr = n_part * blockDim.x;
 
-    DevIn d{};
-    DevOut o{};
     const int n_sched = kc.cptr[kc.n_colors];
+    // MODE 1: every thread evaluates and merges its own device first; the merged values
+    // wait in LDS ([code row][thread]), the code words in registers (tag 3 = unused)
+    extern __shared__ double rows[];
+    uint32_t cdv[NCODE];
+    int kq = 0;
     if constexpr (MODE == 1) {
+#pragma unroll
+        for (int j = 0; j < NCODE; ++j) cdv[j] = 0xC0000000u;
         if (gtid < n_sched) {
-            d = load_terms(kc, gtid);
-            o = eval_pos(kc, call, gtid, d);
+            const DevIn d = load_terms(kc, gtid);
+            const DevOut o = eval_pos(kc, call, gtid, d);
+            double Y[16];
+            full_Y(o, Y);
+            const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+            LdsRowSink sink{rows + threadIdx.x, (int)blockDim.x};
+            emit_merged(d.key, Y, bl, sink);
+            kq = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) + (d.t2 != 0 && d.t2 != d.t0 && d.t2 != d.t1) +
+                 (d.t3 != 0 && d.t3 != d.t0 && d.t3 != d.t1 && d.t3 != d.t2);
+#pragma unroll
+            for (int j = 0; j < NCODE; ++j)
+                if (j < kq * kq + kq) cdv[j] = (uint32_t)kc.code[(size_t)j * kc.n + gtid];
         }
     }
     uint32_t epoch = base;
     for (int c = 0; c < kc.n_colors; ++c) {
         const int beg = kc.cptr[c], end = kc.cptr[c + 1];
         if constexpr (MODE == 1) {
-            if (gtid >= beg && gtid < end) stamp_colour<true>(kc, call, gtid, d, o);
+            if (gtid >= beg && gtid < end) apply_rows(call, kc.stage, cdv, kq, rows, threadIdx.x, blockDim.x);
         } else {
             for (int pos = beg + gtid; pos < end; pos += nthr) {
                 const DevIn dd = load_terms(kc, pos);
@@ -375,12 +422,19 @@ __global__ void __launch_bounds__(256) k_persistent_phase(KCirc kc, KCall call, 
                                                           int n_global_chunks, KLocal kl) {
     persistent_body<0>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
-// Evaluate-ahead holds one device's local values per thread across the colour
-// phases; it needs every device resident at once, hence four waves per SIMD.
+// Evaluate-ahead keeps one device's merged values per thread across the colour
+// phases (in LDS); it needs every device resident at once, hence four waves per SIMD.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_persistent_ahead(KCirc kc, KCall call, KSync ks, const double *buf, int n_part,
                    int n_global_chunks, KLocal kl) {
     persistent_body<1>(kc, call, ks, buf, n_part, n_global_chunks, kl);
+}
+// The same without workgroup-local circuits (single circuits): less register
+// pressure in the one path it has.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_persistent_ahead_single(KCirc kc, KCall call, KSync ks, const double *buf, int n_part,
+                          int n_global_chunks, KLocal kl) {
+    persistent_body<1, false>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 __global__ void __launch_bounds__(256) k_persistent_stamp(KCirc kc, KCall call, KSync ks,
                                                           const double *buf, int n_part,
@@ -588,8 +642,8 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_region(KCirc kc, KCall call, KRegion kr) {
-    // LDS: kr.lds_int accumulators, then 13 outputs per lane (later the fold scratch,
-    // HUB_K per wave)
+    // LDS: kr.lds_int accumulators, then kr.nc_max merged values per lane (later the
+    // fold scratch, HUB_K per wave)
     extern __shared__ double lds[];
     fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
     if ((int)blockIdx.x >= kr.n_regions) return;
@@ -597,22 +651,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     const int p0 = rt[0], nN = rt[1], nP = rt[2], nph = rt[3], ib = rt[4], ie = rt[5], jb = rt[6], je = rt[7];
     const int t = threadIdx.x;
     const int pos = t < nN + nP ? p0 + t : -1;
+    // the region's accumulators start at -0.0, the exact identity of IEEE addition, so
+    // a first writer's add equals its store (visible after the barrier below)
+    for (int i = t; i < ie - ib; i += blockDim.x) lds[i] = -0.0;
+    // evaluate and merge at once (all waves in parallel); the merged values wait for
+    // the device's phase in LDS, [code row][lane]
+    double *mst = lds + kr.lds_int;
+    const int B = blockDim.x;
     DevIn d{};
-    DevOut o{};
     if (pos >= 0) {
         d = load_terms(kc, pos);
-        o = eval_pos(kc, call, pos, d);
+        const DevOut o = eval_pos(kc, call, pos, d);
+        double Y[16];
+        full_Y(o, Y);
+        const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+        LdsRowSink sink{mst + t, B};
+        emit_merged(d.key, Y, bl, sink);
     }
-    // the device's outputs wait for its phase in LDS (registers would spill)
-    double *ost = lds + kr.lds_int;
-    const int B = blockDim.x;
-    if (pos >= 0) {
-        ost[0 * B + t] = o.Ydd; ost[1 * B + t] = o.Ydg; ost[2 * B + t] = o.Ydb;
-        ost[3 * B + t] = o.Ygd; ost[4 * B + t] = o.Ygg; ost[5 * B + t] = o.Ygb;
-        ost[6 * B + t] = o.Ybd; ost[7 * B + t] = o.Ybg; ost[8 * B + t] = o.Ybb;
-        ost[9 * B + t] = o.bd; ost[10 * B + t] = o.bg; ost[11 * B + t] = o.bs; ost[12 * B + t] = o.bb;
-    }
+    // code words: tag 3 (unused) on every lane, loaded for the lanes holding a device
     uint32_t cd[NCODE];
+#pragma unroll
+    for (int j = 0; j < NCODE; ++j) cd[j] = 0xC0000000u;
     int ph = -1;
     if (pos >= 0) {
         const int k = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) +
@@ -623,34 +682,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         for (int j = 0; j < NCODE; ++j) cd[j] = j < nc ? (uint32_t)kc.code[(size_t)j * kc.n + pos] : 0xC0000000u;
         ph = kr.phase[pos];
     }
-    // each device merges and writes in its own phase; a workgroup barrier between phases
+    // values of shared entries and hubs: staged at once (no order among them)
+#pragma unroll
+    for (int j = 0; j < NCODE; ++j)
+        if ((cd[j] >> 30) == TAG_STAGE) st_coherent(kc.stage + (cd[j] & 0x3FFFFFFFu), mst[j * B + t]);
+    lds_barrier();
+    // phases: each device adds its values to its own entries in its own phase (no
+    // other lane of the phase touches them; the LDS add only saves the read round
+    // trip), a workgroup barrier between phases
     for (int q = 0; q < max(nph, 1); ++q) {
         if (ph == q) {
-            // addresses and tags are formed here, not hoisted out of the loop (that
-            // would keep twenty addresses live across the phases)
-            uint32_t cq[NCODE];
+            double v[NCODE];
 #pragma unroll
-            for (int j = 0; j < NCODE; ++j) {
-                cq[j] = cd[j];
-                asm volatile("" : "+v"(cq[j]));
-            }
-            RegionSink sink{cq, lds, kc.stage};
-            DevOut oo;
-            oo.Ydd = ost[0 * B + t]; oo.Ydg = ost[1 * B + t]; oo.Ydb = ost[2 * B + t];
-            oo.Ygd = ost[3 * B + t]; oo.Ygg = ost[4 * B + t]; oo.Ygb = ost[5 * B + t];
-            oo.Ybd = ost[6 * B + t]; oo.Ybg = ost[7 * B + t]; oo.Ybb = ost[8 * B + t];
-            oo.bd = ost[9 * B + t]; oo.bg = ost[10 * B + t]; oo.bs = ost[11 * B + t]; oo.bb = ost[12 * B + t];
-            double Y[16];
-            full_Y(oo, Y);
-            const double bl[4] = {oo.bd, oo.bg, oo.bs, oo.bb};
-            emit_merged(d.key, Y, bl, sink);
+            for (int j = 0; j < NCODE; ++j) v[j] = (cd[j] >> 30) <= TAG_LDS_STORE ? mst[j * B + t] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NCODE; ++j)
+                if ((cd[j] >> 30) <= TAG_LDS_STORE)
+                    (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), v[j], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         lds_barrier();
     }
-    for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
+    // staged values complete before the arrivals are counted; the region's own
+    // entries are stored last (nothing waits for them)
     drain_memory();
     __syncthreads();
     finish_items(kc, call, kr, jb, je, lds + kr.lds_int);
+    for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
 }
 
 // Follow-up kernel of the region schedule: every large shared entry, one wave each,
@@ -681,10 +739,15 @@ static hipError_t occupancy(const void *fn, int block, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
-hipError_t persistent_capacity(int mode, int block, int *blocks_per_cu) {
+static size_t persistent_lds(int mode, int block, int nc_max) {
+    return mode == 1 ? sizeof(double) * (size_t)nc_max * block : 0;
+}
+
+hipError_t persistent_capacity(int mode, int block, int nc_max, int *blocks_per_cu) {
     const void *fn = mode == 1 ? (const void *)k_persistent_ahead
                    : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
-    return occupancy(fn, block, blocks_per_cu);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block,
+                                                        persistent_lds(mode, block, nc_max));
 }
 
 hipError_t launch_gather_params(int32_t n, const int32_t *perm, const double *W, const double *L,
@@ -727,10 +790,12 @@ hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks
     int np = n_part, ng = n_global_chunks;
     KLocal l = kl;
     void *args[] = {&a, &b, &c, &d, &np, &ng, &l};
-    const void *fn = mode == 1 ? (const void *)k_persistent_ahead
+    const void *fn = mode == 1 ? (kl.n == 0 && n_part == grid ? (const void *)k_persistent_ahead_single
+                                                                 : (const void *)k_persistent_ahead)
                    : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
-    if (!cooperative) return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, s);
+    const size_t shm = persistent_lds(mode, block, kc.nc_max);
+    if (!cooperative) return hipLaunchKernel(fn, dim3(grid), dim3(block), args, shm, s);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, shm, s);
 }
 
 hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s) {
@@ -740,18 +805,19 @@ hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, h
     return hipGetLastError();
 }
 
-size_t region_lds_bytes(int lds_int, int block) {
-    return sizeof(double) * ((size_t)lds_int + std::max((size_t)13 * block, (size_t)(block / 64) * HUB_K));
+size_t region_lds_bytes(int lds_int, int nc_max, int block) {
+    return sizeof(double) * ((size_t)lds_int + std::max((size_t)nc_max * block, (size_t)(block / 64) * HUB_K));
 }
 
-hipError_t region_capacity(int block, int lds_int, int *blocks_per_cu) {
+hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_region, block,
-                                                        region_lds_bytes(lds_int, block));
+                                                        region_lds_bytes(lds_int, nc_max, block));
 }
 
 hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s) {
     const int grid = std::max(kr.n_regions, 1);
-    hipLaunchKernelGGL(k_region, dim3(grid), dim3(block), region_lds_bytes(kr.lds_int, block), s, kc, call, kr);
+    hipLaunchKernelGGL(k_region, dim3(grid), dim3(block), region_lds_bytes(kr.lds_int, kr.nc_max, block), s, kc,
+                       call, kr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || kr.n_deferred == 0) return e;
     hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);

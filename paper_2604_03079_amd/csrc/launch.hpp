@@ -7,8 +7,9 @@
 namespace cs {
 
 // Resident blocks per CU of the persistent kernel in `mode` (0 phase-evaluate,
-// 1 evaluate-ahead, 2 stamp from buffer) at `block` threads.
-hipError_t persistent_capacity(int mode, int block, int *blocks_per_cu);
+// 1 evaluate-ahead, 2 stamp from buffer) at `block` threads; nc_max = largest number
+// of code rows of a device (evaluate-ahead keeps that many values per thread in LDS).
+hipError_t persistent_capacity(int mode, int block, int nc_max, int *blocks_per_cu);
 hipError_t launch_gather_params(int32_t n, const int32_t *perm, const double *W, const double *L,
                                 const double *V, double *par, hipStream_t s);
 hipError_t launch_colour_phase(const KCirc &kc, const KCall &call, int c, int count,
@@ -26,9 +27,10 @@ hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, h
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s);
 // Region schedule: one workgroup of `block` threads per region; dynamic LDS for
-// lds_int interior accumulators plus the fold scratch.
-size_t region_lds_bytes(int lds_int, int block);
-hipError_t region_capacity(int block, int lds_int, int *blocks_per_cu);
+// lds_int interior accumulators plus nc_max merged values per lane (reused as the
+// fold scratch).
+size_t region_lds_bytes(int lds_int, int nc_max, int block);
+hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu);
 hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s);
 // dst[j][p] = src[j][idx[p]] for the three parameter rows.
 hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,

@@ -56,7 +56,10 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     std::vector<int32_t> pos_of(n);
     for (size_t p = 0; p < n; ++p) pos_of[(size_t)s.perm[p]] = (int32_t)p;
     std::vector<int8_t> kk(n);
-    for (size_t p = 0; p < n; ++p) kk[p] = (int8_t)distinct_k(s.term, n, p);
+    for (size_t p = 0; p < n; ++p) {
+        kk[p] = (int8_t)distinct_k(s.term, n, p);
+        R.max_nc = std::max<int32_t>(R.max_nc, kk[p] * kk[p] + kk[p]);
+    }
 
     // 1. regions over ascending (global) device index
     std::vector<int32_t> region_of(n, 0);
@@ -381,6 +384,7 @@ KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
     r.n_deferred = (int32_t)R.deferred.size();
     r.deferred = D.deferred.p;
     r.lds_int = (R.max_lds + 1) & ~1;
+    r.nc_max = R.max_nc;
     return r;
 }
 

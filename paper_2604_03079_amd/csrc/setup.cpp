@@ -172,6 +172,7 @@ Err build_map(HostCircuit &h) {
     h.code.assign((size_t)NCODE * n, 0);
     h.acode.assign((size_t)NCODE * n, 0);
     std::vector<int32_t> wrote_A((size_t)h.nnz, -1), wrote_b((size_t)n_rows, -1);
+    h.max_nc = 0;
     struct HubRef { int64_t target; int32_t dev; int32_t pos; int32_t j; };
     std::vector<HubRef> hubs;
     for (size_t p = 0; p < n; ++p) {
@@ -179,6 +180,7 @@ Err build_map(HostCircuit &h) {
         const int32_t col = h.colour[(size_t)v];
         int32_t u[4];
         int k = unique_nodes(&h.term[4 * (size_t)v], u);
+        h.max_nc = std::max(h.max_nc, k * k + k);
         for (int a = 0; a < k; ++a) {
             for (int b = 0; b < k; ++b) {
                 const int j = a * k + b;

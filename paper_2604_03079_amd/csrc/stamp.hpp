@@ -231,24 +231,14 @@ struct AtomicSink {
     }
 };
 
-// Region sink: codes prefetched in registers; tag LDS_STORE / LDS_ADD accumulate in
-// the workgroup's LDS, tag STAGE stores (coherently) into the global staging array.
-struct RegionSink {
+// LDS row sink (region schedule): merged value j of a lane goes to p[j * stride].
+struct LdsRowSink {
     static constexpr bool kStreaming = true;
-    const uint32_t *cd;
-    double *lds, *stage;
+    double *p;
+    int stride;
     template <int J>
     __device__ __forceinline__ void put(double v) {
-        const uint32_t tag = cd[J] >> 30, idx = cd[J] & 0x3FFFFFFFu;
-        if (tag == TAG_STAGE) {
-            __hip_atomic_store(stage + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (tag == TAG_LDS_ADD) {
-            // current + value, issued without waiting for a read: no other lane of the
-            // phase touches this entry, the LDS add just avoids a read round trip
-            (void)__hip_atomic_fetch_add(lds + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            lds[idx] = v;
-        }
+        p[J * stride] = v;
     }
 };
 
