@@ -3,8 +3,9 @@
 Workload (default): inverter chain of 100,000 stages (200,000 MOSFETs, 100,003 MNA
 rows, 500,006 nonzeros), rail-excluded conflict rule (4 colours), FP64, one NR step
 = evaluate every device at x and stamp A, b (ag0 = 1e12, backward Euler with h = 1
-ps).  Synthetic seeded inputs (W, L, VTH0, x).  Each step is one replay of a HIP
-graph holding the whole step; the timed region is K replays between events.
+ps).  Synthetic seeded inputs (W, L, VTH0, x).  Every variant is timed as K replays
+of a HIP graph holding one step; the headline variant also as K launches back to
+back on the stream, and the faster of the two gives `value`.
 
 Prints one JSON line.  Extra keys report the other kernel variants, the 6T SRAM
 array, the batched sweep and the adjoint, plus the roofline of the dominant kernel
@@ -296,15 +297,20 @@ def main():
             log(f"  {variant} kernel launches back to back: {kernel_ms * 1e3:.2f} us")
         name = variant if coop else variant + "_ordinary_launch"
         variants[name] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2),
-                              info=c.info(), steps=steps)
+                              info=c.info(), steps=steps, launch="graph replay")
+        if variant == args.variant and coop:
+            variants[name]["stream_ms_per_step"] = round(kernel_ms, 5)
         log(f"  {name:28s} {ms * 1e3:9.2f} us/step  {circ.n_dev / ms / 1e3:9.1f} M devices/s")
 
     main_v = variants[args.variant]
-    ms = main_v["ms_per_step"]
+    # a step is one launch sequence of the variant; K steps run either as K replays of
+    # a captured graph or as K launches back to back on the stream: the faster counts
+    launch = "graph replay" if main_v["ms_per_step"] <= kernel_ms else "stream, back to back"
+    ms = min(main_v["ms_per_step"], round(kernel_ms, 5))
     ksecs = kernel_ms * 1e-3
     result = {
         "metric": "M devices eval+stamp/s per NR iter (colored vs atomic); batched & fwd+adjoint",
-        "value": main_v["value"],
+        "value": round(circ.n_dev / ms / 1e3, 2),
         "unit": "M devices/s",
         "n_gpus": 1,
         "steps": main_v["steps"],
@@ -318,7 +324,7 @@ def main():
         "config": {"workload": "inverter_chain_100k_stages", "n_dev": circ.n_dev,
                    "n_rows": int(main_v["info"]["n_rows"]), "nnz": int(main_v["info"]["nnz"]),
                    "n_colors": counts["n_colors"], "conflict_rule": "rails_excluded",
-                   "variant": args.variant, "ag0": AG0, "graph_replay": True},
+                   "variant": args.variant, "ag0": AG0, "launch": launch},
         "roofline": {
             "bound": "alu",
             "achieved": round(counts["ops"] / ksecs / 1e12, 4),

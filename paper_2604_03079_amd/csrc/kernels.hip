@@ -658,22 +658,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     // the device's phase in LDS, [code row][lane]
     double *mst = lds + kr.lds_int;
     const int B = blockDim.x;
-    DevIn d{};
-    if (pos >= 0) {
-        d = load_terms(kc, pos);
-        const DevOut o = eval_pos(kc, call, pos, d);
-        double Y[16];
-        full_Y(o, Y);
-        const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
-        LdsRowSink sink{mst + t, B};
-        emit_merged(d.key, Y, bl, sink);
-    }
     // code words: tag 3 (unused) on every lane, loaded for the lanes holding a device
+    // right after the evaluation, so that the loads overlap the merge
     uint32_t cd[NCODE];
 #pragma unroll
     for (int j = 0; j < NCODE; ++j) cd[j] = 0xC0000000u;
     int ph = -1;
     if (pos >= 0) {
+        const DevIn d = load_terms(kc, pos);
+        const DevOut o = eval_pos(kc, call, pos, d);
         const int k = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) +
                       (d.t2 != 0 && d.t2 != d.t0 && d.t2 != d.t1) +
                       (d.t3 != 0 && d.t3 != d.t0 && d.t3 != d.t1 && d.t3 != d.t2);
@@ -681,6 +674,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
         for (int j = 0; j < NCODE; ++j) cd[j] = j < nc ? (uint32_t)kc.code[(size_t)j * kc.n + pos] : 0xC0000000u;
         ph = kr.phase[pos];
+        double Y[16];
+        full_Y(o, Y);
+        const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+        LdsRowSink sink{mst + t, B};
+        emit_merged(d.key, Y, bl, sink);
     }
     // values of shared entries and hubs: staged at once (no order among them)
 #pragma unroll
