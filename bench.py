@@ -137,8 +137,16 @@ def cpu_baseline(circ, budget_s=12.0):
         O.assemble(circ, rp, ci, nc, pc, AG0, col=col, exclude=True)
         it += 1
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=round(circ.n_dev * it / dt / 1e6, 4), unit="M devices/s", cores=1,
-                kind="oracle",
+                kind="oracle", host=f"{model}, {os.cpu_count()} logical CPUs visible",
                 sample=f"{it} NR steps of the full {circ.n_dev}-device chain, serial colour-replay "
                        f"oracle (C, -O2), {dt:.1f} s")
 
@@ -361,6 +369,15 @@ def main():
         extras["adjoint"] = bench_adjoint(torch, CS, G, dev)
         result["extras"] = extras
 
+    # the paper's own CPU figures, for context only (another machine, full BSIM 4.82):
+    # FET evaluations per second derived from its Device-Eval times (1792 FETs x NR
+    # iterations / seconds) on a 64-core Threadripper PRO 5995WX, and its best speedup
+    result["paper_context"] = {
+        "hardware": "AMD Ryzen Threadripper PRO 5995WX, 64 cores, C++/OpenMP, BSIM 4.82",
+        "colorfused_fet_evals_per_s_M": {"adder_base_C896": 0.707, "adder_R14_C64": 7.74, "adder_R89_C1": 24.8},
+        "loadomp_fet_evals_per_s_M": 7.42, "ngspice_fet_evals_per_s_M": 4.93,
+        "colorfused_best_speedup_vs_1_thread": 45,
+    }
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(circ)
         log(f"  cpu oracle: {result['cpu_baseline']['value']} M devices/s")

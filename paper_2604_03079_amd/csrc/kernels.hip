@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     const int t = threadIdx.x;
     const int pos = t < nN + nP ? p0 + t : -1;
     // the region's accumulators start at -0.0, the exact identity of IEEE addition, so
-    // a first writer's add equals its store (visible after the barrier below)
+    // a first writer's load-add equals its store (visible after the barrier below)
     for (int i = t; i < ie - ib; i += blockDim.x) lds[i] = -0.0;
     // evaluate and merge at once (all waves in parallel); the merged values wait for
     // the device's phase in LDS, [code row][lane]
@@ -685,19 +685,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     for (int j = 0; j < NCODE; ++j)
         if ((cd[j] >> 30) == TAG_STAGE) st_coherent(kc.stage + (cd[j] & 0x3FFFFFFFu), mst[j * B + t]);
     lds_barrier();
-    // phases: each device adds its values to its own entries in its own phase (no
-    // other lane of the phase touches them; the LDS add only saves the read round
-    // trip), a workgroup barrier between phases
+    // phases: in its own phase each device loads its entries, adds its values and
+    // stores them back (plain LDS loads and stores: no other lane of the phase touches
+    // those entries; a device's entries are distinct, so all loads go first), a
+    // workgroup barrier between phases
     for (int q = 0; q < max(nph, 1); ++q) {
         if (ph == q) {
-            double v[NCODE];
+            double v[NCODE], cur[NCODE];
 #pragma unroll
-            for (int j = 0; j < NCODE; ++j) v[j] = (cd[j] >> 30) <= TAG_LDS_STORE ? mst[j * B + t] : 0.0;
+            for (int j = 0; j < NCODE; ++j) {
+                const bool mine = (cd[j] >> 30) <= TAG_LDS_STORE;
+                v[j] = mine ? mst[j * B + t] : 0.0;
+                cur[j] = mine ? lds[cd[j] & 0x3FFFFFFFu] : 0.0;
+            }
 #pragma unroll
             for (int j = 0; j < NCODE; ++j)
-                if ((cd[j] >> 30) <= TAG_LDS_STORE)
-                    (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), v[j], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+                if ((cd[j] >> 30) <= TAG_LDS_STORE) lds[cd[j] & 0x3FFFFFFFu] = cur[j] + v[j];
         }
         lds_barrier();
     }
