@@ -138,9 +138,12 @@ KCirc make_kcirc(cs_circuit *c) {
     return k;
 }
 
-// Grid of the persistent kernel for the current configuration.
-cs_status plan_persistent(cs_circuit *c) {
-    if (c->grid > 0) return CS_OK;
+// Grid of the persistent kernel for the current configuration.  phase_only: the
+// evaluate-in-phase mode (the persistent variant's fallback when the regions cannot
+// all be resident).
+cs_status plan_persistent(cs_circuit *c, bool phase_only) {
+    const int key = phase_only ? 1 : 2;
+    if (c->grid > 0 && c->grid_key == key) return CS_OK;
     hipDeviceProp_t prop;
     CS_CHECK_HIP(hipGetDeviceProperties(&prop, c->device), "device properties");
     const int block = c->block;
@@ -153,8 +156,8 @@ cs_status plan_persistent(cs_circuit *c) {
     int64_t max_colour = 0;
     for (int32_t k = 0; k < c->h.n_colors; ++k)
         max_colour = std::max<int64_t>(max_colour, c->h.colour_ptr[k + 1] - c->h.colour_ptr[k]);
-    const bool fits = need_ahead <= cap_ahead;
-    if (c->eval_ahead_req == 1 && !fits)
+    const bool fits = !phase_only && need_ahead <= cap_ahead;
+    if (!phase_only && c->eval_ahead_req == 1 && !fits)
         return fail(CS_ENOTSUP, "evaluate-ahead needs one resident thread per device");
     c->eval_ahead = c->eval_ahead_req == 0 ? 0 : (fits ? 1 : 0);
     int64_t grid = c->eval_ahead ? need_ahead
@@ -162,6 +165,7 @@ cs_status plan_persistent(cs_circuit *c) {
     if (grid < 1 || cap_phase < 1) return fail(CS_ENOTSUP, "persistent kernel does not fit the device");
     if ((size_t)grid + 2 > c->d_sync.n) return fail(CS_ENOTSUP, "grid larger than the barrier state");
     c->grid = (int32_t)grid;
+    c->grid_key = key;
     return CS_OK;
 }
 
@@ -426,8 +430,38 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
     const KCall call{x, ag0, hist, A_val, b};
     switch (variant) {
         case CS_COLOR_PERSISTENT:
+            if (c->eval_ahead_req != 0) {
+                // every region resident at once: the grid-barrier form of the region
+                // schedule (workgroup colour phases in LDS, shared entries in place)
+                cs_status st = ensure_region(c, s);
+                if (st != CS_OK) return st;
+                if (c->rg_cap_block != c->block || c->rg_cap_regions != c->rp.n_regions) {
+                    int per_cu = 0;
+                    CS_CHECK_HIP(region_grid_capacity(c->block, (c->rp.max_lds + 1) & ~1, c->rp.max_nc, &per_cu),
+                                 "occupancy");
+                    hipDeviceProp_t prop;
+                    CS_CHECK_HIP(hipGetDeviceProperties(&prop, c->device), "device properties");
+                    c->rg_cap = (int64_t)per_cu * prop.multiProcessorCount;
+                    c->rg_cap_block = c->block;
+                    c->rg_cap_regions = c->rp.n_regions;
+                }
+                const int64_t cap = c->rg_cap;
+                const int32_t nr = c->rp.n_regions;
+                if (nr >= 1 && nr <= cap && (size_t)nr + 2 <= c->d_sync.n) {
+                    const KSync ks{c->d_sync.p, c->spin_limit};
+                    CS_CHECK_HIP(launch_region_grid(region_kcirc(kc, c->rp, c->rd), call, region_kregion(c->rp, c->rd),
+                                                    ks, c->block, c->cooperative, s), "persistent launch");
+                    c->grid = nr;
+                    c->grid_key = 3;
+                    c->eval_ahead = 1;
+                    return CS_OK;
+                }
+                if (c->eval_ahead_req == 1 && nr >= 1)
+                    return fail(CS_ENOTSUP, "evaluate-ahead needs every region resident at once");
+            }
+            [[fallthrough]];
         case CS_COLOR_BUFFERED: {
-            cs_status st = plan_persistent(c);
+            cs_status st = plan_persistent(c, variant == CS_COLOR_PERSISTENT);
             if (st != CS_OK) return st;
             int mode = c->eval_ahead;
             int grid = c->grid;

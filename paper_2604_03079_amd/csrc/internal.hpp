@@ -97,18 +97,22 @@ struct RegionSource {
 // Region schedule tables (host), region-major positions.
 struct RegionPlan {
     bool built = false;
-    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0, max_nc = 0;
+    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0, max_nc = 0, max_glevel = 0;
     int64_t stage_size = 0;
     std::vector<int32_t> perm, cm_pos, term, code, rtab, int_target, ritems, item, deferred;
     std::vector<int8_t> pol;
-    std::vector<uint16_t> phase;
+    std::vector<uint16_t> phase, glevel;
+    std::vector<int32_t> slot_tgt;     // per staged slot: target of a shared entry (-1: hub)
+    std::vector<uint8_t> slot_first;   // SLOT_STORE / SLOT_ADD / SLOT_HUB
 };
 
 // Device copies of a region plan.
 struct RegionDev {
     DevBuf<int32_t> perm, cm_pos, term, code, rtab, int_target, ritems, item, deferred;
     DevBuf<int8_t> pol;
-    DevBuf<uint16_t> phase;
+    DevBuf<uint16_t> phase, glevel;
+    DevBuf<int32_t> slot_tgt;
+    DevBuf<uint8_t> slot_first;
     DevBuf<double> par, stage;
     DevBuf<uint32_t> item_count;
     bool ready = false;      // uploaded from the current plan
@@ -153,8 +157,11 @@ struct cs_circuit {
     int32_t grid = 0;                  // persistent grid
     int32_t eval_ahead = 0;
     int64_t spin_limit = 1 << 22;
+    int32_t grid_key = 0;              // which plan c->grid belongs to
     cs::RegionPlan rp;                 // region schedule (built on first use, per block size)
     cs::RegionDev rd;
+    int32_t rg_cap_block = 0, rg_cap_regions = -1;   // resident-region capacity cache
+    int64_t rg_cap = 0;
 };
 
 struct cs_batch {

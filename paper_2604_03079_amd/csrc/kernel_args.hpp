@@ -31,6 +31,11 @@ constexpr int RT_FIELDS = 8;
 // Shared entries with more contributions than this are folded by the follow-up
 // kernel; smaller ones by the last contributing region, one lane each.
 constexpr int ITEM_LANE_MAX = 8;
+// Staged slots in the grid-barrier form of the region schedule: a shared entry's
+// first writer (colour order) stores, the others load-add; hub slots are staged.
+constexpr uint8_t SLOT_STORE = 0;
+constexpr uint8_t SLOT_ADD = 1;
+constexpr uint8_t SLOT_HUB = 2;
 constexpr uint32_t HUB_B_FLAG = 0x80000000u;  // hub target is a b row
 
 // Fixed-shape hub sum: chunks of HUB_K contributions, folded left, recursively.
@@ -100,6 +105,11 @@ struct KRegion {
     int32_t nc_max;             // largest number of code rows of a device (k*k + k)
     int32_t n_deferred;         // items folded by the follow-up kernel
     const int32_t *deferred;
+    // grid-barrier form: shared entries written in place, level by level
+    int32_t max_glevel;         // levels of shared-entry writers
+    const uint16_t *glevel;     // [n] level of each position's shared entries
+    const int32_t *slot_tgt;    // [staged slots] target of a shared entry
+    const uint8_t *slot_first;  // [staged slots] SLOT_STORE / SLOT_ADD / SLOT_HUB
 };
 
 // Per-call operands.

@@ -547,7 +547,7 @@ constexpr int PEND_MAX = 8;   // hubs whose final fold one workgroup runs in par
 // their final fold from all waves: each group of HUB_K chunk sums by one wave,
 // then the group sums by one lane.  Called by every thread of the workgroup.
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
-                                             double *scratch) {
+                                             double *scratch, bool hub_only = false) {
     __shared__ int pend_n;
     __shared__ int pend_h[PEND_MAX];
     __shared__ double gsum[PEND_MAX][HUB_MAX_CHUNKS / HUB_K];
@@ -560,7 +560,7 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
         int beg = 0, cnt = 0;
         uint32_t tgt = 0;
         bool last = false;
-        if (i < je) {
+        if (i < je && !(hub_only && ((uint32_t)kr.item[4 * (size_t)kr.ritems[i] + 2] >> 30) != ITEM_HUB)) {
             const int it = kr.ritems[i];
             const int32_t *f = kr.item + 4 * (size_t)it;
             beg = f[0];
@@ -641,14 +641,33 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
     }
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_region(KCirc kc, KCall call, KRegion kr) {
+// Region schedule body.  GRID = false: the region kernel (shared entries staged and
+// folded by the last contributing region).  GRID = true: the same inside one
+// persistent launch (every region resident, one workgroup each): shared entries are
+// written in place, level by level in colour order (first writer stores, later ones
+// load-add, coherent across XCDs), with a grid-wide barrier between levels; then the
+// hub sums.
+template <bool GRID>
+__device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks) {
     // LDS: kr.lds_int accumulators, then kr.nc_max merged values per lane (later the
     // fold scratch, HUB_K per wave)
     extern __shared__ double lds[];
+    __shared__ uint32_t base_s;
     fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-    if ((int)blockIdx.x >= kr.n_regions) return;
-    const int32_t *rt = kr.rtab + (size_t)blockIdx.x * RT_FIELDS;
-    const int p0 = rt[0], nN = rt[1], nP = rt[2], nph = rt[3], ib = rt[4], ie = rt[5], jb = rt[6], je = rt[7];
+    if constexpr (GRID) {
+        if (threadIdx.x == 0) base_s = ld_flag(ks.sync);
+    } else {
+        if ((int)blockIdx.x >= kr.n_regions) return;
+    }
+    // (the grid form is launched with exactly one workgroup per region; a workgroup
+    // beyond them would own nothing and only take part in the barriers)
+    int f[RT_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if ((int)blockIdx.x < kr.n_regions) {
+        const int32_t *rt = kr.rtab + (size_t)blockIdx.x * RT_FIELDS;
+#pragma unroll
+        for (int k = 0; k < RT_FIELDS; ++k) f[k] = rt[k];
+    }
+    const int p0 = f[0], nN = f[1], nP = f[2], nph = f[3], ib = f[4], ie = f[5], jb = f[6], je = f[7];
     const int t = threadIdx.x;
     const int pos = t < nN + nP ? p0 + t : -1;
     // the region's accumulators start at -0.0, the exact identity of IEEE addition, so
@@ -680,10 +699,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         LdsRowSink sink{mst + t, B};
         emit_merged(d.key, Y, bl, sink);
     }
-    // values of shared entries and hubs: staged at once (no order among them)
+    // values of shared entries and hubs: staged at once (no order among them); the grid
+    // form stages only the hub values
 #pragma unroll
-    for (int j = 0; j < NCODE; ++j)
-        if ((cd[j] >> 30) == TAG_STAGE) st_coherent(kc.stage + (cd[j] & 0x3FFFFFFFu), mst[j * B + t]);
+    for (int j = 0; j < NCODE; ++j) {
+        if ((cd[j] >> 30) != TAG_STAGE) continue;
+        const uint32_t sl = cd[j] & 0x3FFFFFFFu;
+        if (GRID && kr.slot_first[sl] != SLOT_HUB) continue;
+        st_coherent(kc.stage + sl, mst[j * B + t]);
+    }
     lds_barrier();
     // phases: in its own phase each device loads its entries, adds its values and
     // stores them back (plain LDS loads and stores: no other lane of the phase touches
@@ -704,12 +728,61 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         }
         lds_barrier();
     }
-    // staged values complete before the arrivals are counted; the region's own
-    // entries are stored last (nothing waits for them)
-    drain_memory();
-    __syncthreads();
-    finish_items(kc, call, kr, jb, je, lds + kr.lds_int);
-    for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
+    if constexpr (GRID) {
+        // the region's own entries, then the shared entries level by level, then the
+        // hub sums by arrival counting (they need no grid barrier; their fold scratch
+        // reuses the merged-value rows, so they come last)
+        for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
+        const int gl = pos >= 0 ? (int)kr.glevel[pos] : -1;
+        uint32_t epoch = base_s;
+        for (int g = 0; g < kr.max_glevel; ++g) {
+            if (gl == g) {
+                // this device's shared entries: all loads, then all stores
+                double old[NCODE];
+#pragma unroll
+                for (int j = 0; j < NCODE; ++j) {
+                    old[j] = -0.0;
+                    if ((cd[j] >> 30) != TAG_STAGE) continue;
+                    const uint32_t sl = cd[j] & 0x3FFFFFFFu;
+                    if (kr.slot_first[sl] == SLOT_ADD) {
+                        const uint32_t tg = (uint32_t)kr.slot_tgt[sl];
+                        old[j] = ld_coherent(((tg >> 30) == ITEM_B ? call.b : call.A) + (tg & 0x3FFFFFFFu));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NCODE; ++j) {
+                    if ((cd[j] >> 30) != TAG_STAGE) continue;
+                    const uint32_t sl = cd[j] & 0x3FFFFFFFu;
+                    if (kr.slot_first[sl] == SLOT_HUB) continue;
+                    const uint32_t tg = (uint32_t)kr.slot_tgt[sl];
+                    st_coherent(((tg >> 30) == ITEM_B ? call.b : call.A) + (tg & 0x3FFFFFFFu), old[j] + mst[j * B + t]);
+                }
+            }
+            if (g + 1 < kr.max_glevel) grid_barrier(ks, ++epoch, gridDim.x);
+        }
+        drain_memory();
+        __syncthreads();
+        finish_items(kc, call, kr, jb, je, lds + kr.lds_int, true);
+    } else {
+        // staged values complete before the arrivals are counted; the region's own
+        // entries are stored last (nothing waits for them)
+        drain_memory();
+        __syncthreads();
+        finish_items(kc, call, kr, jb, je, lds + kr.lds_int);
+        for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_region(KCirc kc, KCall call, KRegion kr) {
+    const KSync none{nullptr, 0};
+    region_body<false>(kc, call, kr, none);
+}
+
+// Grid-barrier form: launched with one resident workgroup per region (cooperative
+// launch, or an ordinary one that the occupancy query says fits at once).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_region_grid(KCirc kc, KCall call, KRegion kr, KSync ks) {
+    region_body<true>(kc, call, kr, ks);
 }
 
 // Follow-up kernel of the region schedule: every large shared entry, one wave each,
@@ -823,6 +896,24 @@ hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, 
     if (e != hipSuccess || kr.n_deferred == 0) return e;
     hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
     return hipGetLastError();
+}
+
+hipError_t region_grid_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_region_grid, block,
+                                                        region_lds_bytes(lds_int, nc_max, block));
+}
+
+hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks, int block,
+                              bool cooperative, hipStream_t s) {
+    KCirc a = kc;
+    KCall b = call;
+    KRegion r = kr;
+    KSync k = ks;
+    void *args[] = {&a, &b, &r, &k};
+    const int grid = std::max(kr.n_regions, 1);
+    const size_t shm = region_lds_bytes(kr.lds_int, kr.nc_max, block);
+    if (!cooperative) return hipLaunchKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s);
+    return hipLaunchCooperativeKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s);
 }
 
 hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,

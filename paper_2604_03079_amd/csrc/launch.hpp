@@ -32,6 +32,10 @@ hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, c
 size_t region_lds_bytes(int lds_int, int nc_max, int block);
 hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu);
 hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s);
+// Grid-barrier form of the region schedule: every region resident at once.
+hipError_t region_grid_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu);
+hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks, int block,
+                              bool cooperative, hipStream_t s);
 // dst[j][p] = src[j][idx[p]] for the three parameter rows.
 hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
                                  double *dst, hipStream_t s);

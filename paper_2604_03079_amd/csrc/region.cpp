@@ -130,6 +130,10 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     std::vector<uint8_t> is_interior((size_t)nkeys, 0);
     int64_t cursor = s.stage_base;
     std::vector<int32_t> regs;
+    // per staged slot of a shared entry (from stage_base on): target, first writer or
+    // not, and the writer's position; hub slots below stage_base
+    std::vector<int32_t> slot_tgt((size_t)s.stage_base, -1), slot_pos((size_t)s.stage_base, -1);
+    std::vector<uint8_t> slot_first((size_t)s.stage_base, SLOT_HUB);
     for (int64_t t = 0; t < nkeys; ++t) {
         const int64_t b0 = kptr[(size_t)t], b1 = kptr[(size_t)t + 1];
         if (b0 == b1) continue;
@@ -157,6 +161,9 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             const size_t p = (size_t)(wr[(size_t)w] >> 5);
             const int j = (int)(wr[(size_t)w] & 31);
             code[(size_t)j * n + p] = (int32_t)((TAG_STAGE << 30) | (uint32_t)(cursor + (w - b0)));
+            slot_tgt.push_back((int32_t)tgt);
+            slot_first.push_back(w == b0 ? SLOT_STORE : SLOT_ADD);
+            slot_pos.push_back((int32_t)p);
         }
         cursor += b1 - b0;
     }
@@ -249,6 +256,41 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
         }
     }
 
+    // 5b. global levels of the shared entries (grid-barrier schedule): a device's level
+    // is one more than the largest level of the previous writer (in colour order) of
+    // any of its shared entries; devices visited in colour order
+    std::vector<int32_t> glevel(n, 0);
+    R.max_glevel = 0;
+    {
+        std::vector<int32_t> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return s.colour[(size_t)a] < s.colour[(size_t)b]; });
+        bool any = false;
+        for (int32_t p : order) {
+            const int k = kk[(size_t)p];
+            int32_t lv = 0;
+            bool shared = false;
+            for (int j = 0; j < k * k + k; ++j) {
+                const uint32_t c = (uint32_t)code[(size_t)j * n + (size_t)p];
+                if ((c >> 30) != TAG_STAGE) continue;
+                const int64_t sl = (int64_t)(c & 0x3FFFFFFFu);
+                if (sl < s.stage_base) continue;
+                shared = true;
+                if (slot_first[(size_t)sl] == SLOT_ADD) lv = std::max(lv, glevel[(size_t)slot_pos[(size_t)sl - 1]] + 1);
+            }
+            glevel[(size_t)p] = lv;
+            if (shared) {
+                any = true;
+                R.max_glevel = std::max(R.max_glevel, lv + 1);
+            }
+        }
+        (void)any;
+        if (R.max_glevel > 65535) return {CS_ENOTSUP, "too many shared-entry levels"};
+    }
+    R.slot_tgt = std::move(slot_tgt);
+    R.slot_first = std::move(slot_first);
+
     // 6. region-major positions: per region its NMOS, then its PMOS, each in phase
     // order (so that a wave's lanes mostly share one phase), then device order
     R.perm.resize(n);
@@ -256,6 +298,7 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     R.term.assign(4 * n, 0);
     R.pol.assign(n, 0);
     R.phase.assign(n, 0);
+    R.glevel.assign(n, 0);
     R.code.assign((size_t)NCODE * n, (int32_t)(3u << 30));
     R.rtab.assign((size_t)R.n_regions * RT_FIELDS, 0);
     {
@@ -282,6 +325,7 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
                     R.pol[q] = s.pol[p];
                     if (level[p] > 65535) return {CS_ENOTSUP, "too many phases in a region"};
                     R.phase[q] = (uint16_t)level[p];
+                    R.glevel[q] = (uint16_t)glevel[p];
                     const int k = kk[p];
                     for (int j = 0; j < k * k + k; ++j) R.code[(size_t)j * n + q] = code[(size_t)j * n + p];
                     ++q;
@@ -321,6 +365,9 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
     if ((e = D.deferred.upload(R.deferred)) != hipSuccess) return e;
     if ((e = D.pol.upload(R.pol)) != hipSuccess) return e;
     if ((e = D.phase.upload(R.phase)) != hipSuccess) return e;
+    if ((e = D.glevel.upload(R.glevel)) != hipSuccess) return e;
+    if ((e = D.slot_tgt.upload(R.slot_tgt)) != hipSuccess) return e;
+    if ((e = D.slot_first.upload(R.slot_first)) != hipSuccess) return e;
     if ((e = D.par.alloc(3 * R.perm.size())) != hipSuccess) return e;
     if ((e = D.stage.alloc((size_t)R.stage_size)) != hipSuccess) return e;
     const size_t n_items = R.item.size() / 4;
@@ -383,6 +430,10 @@ KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
     r.item_count = D.item_count.p;
     r.n_deferred = (int32_t)R.deferred.size();
     r.deferred = D.deferred.p;
+    r.max_glevel = R.max_glevel;
+    r.glevel = D.glevel.p;
+    r.slot_tgt = D.slot_tgt.p;
+    r.slot_first = D.slot_first.p;
     r.lds_int = (R.max_lds + 1) & ~1;
     r.nc_max = R.max_nc;
     return r;
