@@ -90,6 +90,22 @@ def time_eager(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def time_cold(torch, fn, steps, flush_mib=512):
+    """Median duration of fn() with a flush of flush_mib MiB written to HBM before each
+    step (outside the timed interval), so that no input is cache resident."""
+    flush = torch.empty(flush_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for i, (e0, e1) in enumerate(ev):
+        flush.fill_(float(i))
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+
 def algorithmic_counts(circ, exclude=True):
     """FP64 operations and bytes one step needs (counted on the oracle's definition)."""
     from oracle import oracle as O
@@ -220,6 +236,59 @@ def bench_batch(torch, CS, G, dev):
                 speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2))
 
 
+SWEEP_GROUPS = (1, 2, 4, 8, 16, 32, 64, 128, 256)
+SWEEP_SIZES = (200_000, 2_000)
+SWEEP_MAX_PHASES = 5000   # per-colour and phase-only persistent runs above this are not timed
+
+
+def bench_csweep(torch, CS, G, dev, steps=20):
+    """Colour-count sweep: parallel-inverter chains (group g inverters per stage, so
+    adjacent stages form a clique of 4g devices and the rail-excluded colouring needs
+    4g colours) at about 200,000 and 2,000 devices, then the plain chain with the rail
+    excluded or not (4 colours vs one per PMOS plus one).  Every variant per point."""
+    cases = []
+    for n in SWEEP_SIZES:
+        for g in SWEEP_GROUPS:
+            cases.append((f"pchain_n{n}_g{g}", lambda n=n, g=g: G.pchain_case(n, g, seed=7), True))
+    for n in SWEEP_SIZES:
+        for excl in (True, False):
+            cases.append((f"chain_n{n}_{'excl' if excl else 'strict'}",
+                          lambda n=n: G.chain_case(n // 2, seed=8), excl))
+    out = []
+    for name, make, excl in cases:
+        circ = make()
+        W, L, V, x = device_tensors(torch, circ, dev)
+        row = dict(case=name, n_dev=circ.n_dev, rails_excluded=excl)
+        for variant in ("region", "persistent", "per_kernel", "atomic"):
+            c = CS.prepare(circ, exclude=excl)
+            row["n_colors"] = c.info()["n_colors"]
+            many = row["n_colors"] > SWEEP_MAX_PHASES
+            if variant == "per_kernel" and many:
+                row[variant] = None
+                continue
+            # above the phase limit the persistent variant runs only in its grid-barrier
+            # form (every region resident), never as one grid phase per colour
+            c.set_launch(256, 1 if many else -1, True)
+            c.set_params(W, L, V)
+            A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+            b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+            try:
+                ms, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, 3)
+            except CS.CsError as e:
+                log(f"  {name} {variant}: {e}")
+                row[variant] = None
+                continue
+            c.check()
+            row[variant] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2))
+            if variant == "persistent":
+                row[variant]["grid_barrier_form"] = c.info()["eval_ahead"] == 1
+        fmt = lambda v: f"{row[v]['value']:9.1f}" if row[v] else "        -"
+        log(f"  {name:24s} n_dev {circ.n_dev:7d} C {row['n_colors']:6d}  M dev/s: region {fmt('region')} "
+            f"persistent {fmt('persistent')} per-colour {fmt('per_kernel')} atomic {fmt('atomic')}")
+        out.append(row)
+    return out
+
+
 def bench_adjoint(torch, CS, G, dev):
     """Forward + hand-written adjoint: chain of 10,000 stages, cotangents N(0,1)."""
     circ = G.workload(4)
@@ -252,6 +321,8 @@ def main():
                     help="only run a plain device copy of MIB MiB ten times (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs and exit")
+    ap.add_argument("--csweep", action="store_true",
+                    help="run only the colour-count sweep and print it as one JSON line")
     ap.add_argument("--pmc-kernel", default="k_region")
     ap.add_argument("--pmc-key", default="region_chain100k")
     args = ap.parse_args()
@@ -278,6 +349,11 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 10 copies of {args.copy_probe} MiB")
         return
+    if args.csweep:
+        rows = bench_csweep(torch, CS, G, dev, steps=args.steps)
+        print(json.dumps({"sweep": "colour count", "unit": "M devices/s", "launch": "graph replay",
+                          "steps": args.steps, "rows": rows}), flush=True)
+        return
     khash = kernel_sources_hash()
     circ = G.workload(1)
     log(f"workload: chain 100000 stages, {circ.n_dev} devices")
@@ -303,11 +379,20 @@ def main():
         if variant == args.variant and coop:
             kernel_ms = time_eager(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, args.warmup)
             log(f"  {variant} kernel launches back to back: {kernel_ms * 1e3:.2f} us")
+            trials = sorted(time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps,
+                                       args.warmup)[0] for _ in range(5))
+            cold_ms = time_cold(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), max(10, steps // 4))
+            log(f"  {variant} graph replay, median of 5 trials: {trials[2] * 1e3:.2f} us; "
+                f"cold (512 MiB flushed before each step): {cold_ms * 1e3:.2f} us")
         name = variant if coop else variant + "_ordinary_launch"
         variants[name] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2),
                               info=c.info(), steps=steps, launch="graph replay")
         if variant == args.variant and coop:
             variants[name]["stream_ms_per_step"] = round(kernel_ms, 5)
+            variants[name]["graph_trials_ms"] = [round(t, 5) for t in trials]
+            variants[name]["graph_median_of_5_trials_ms"] = round(trials[2], 5)
+            variants[name]["cold_ms_per_step"] = round(cold_ms, 5)
+            variants[name]["cold_value"] = round(circ.n_dev / cold_ms / 1e3, 2)
         log(f"  {name:28s} {ms * 1e3:9.2f} us/step  {circ.n_dev / ms / 1e3:9.1f} M devices/s")
 
     main_v = variants[args.variant]

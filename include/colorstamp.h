@@ -160,27 +160,35 @@ cs_status cs_plan_regions(cs_circuit *c, int32_t block);
 
 /* Facts of the last region plan: regions (= workgroups), largest number of phases
  * of a region, items (entries shared between regions, and hub chunks), staged
- * contributions (hub and shared), entries owned by one region, region-to-item links.
+ * contributions (hub and shared), entries owned by one region and accumulated in
+ * its LDS (at most 8 writers), region-to-item links, lane folds (entries owned by
+ * one region with more than 8 writers) and their writer references.
  * Any pointer may be NULL; zeros before a plan exists. */
 cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *max_phases,
                              int64_t *n_items, int64_t *n_staged, int64_t *n_interior,
-                             int64_t *n_links);
+                             int64_t *n_links, int64_t *n_folds, int64_t *n_fold_src);
 
 /* Host copies of the region plan tables (any pointer may be NULL), region-major
  * positions p < n_dev:
  *   perm[p]      device index;               phase[p]   LDS phase of the device;
  *   code[j*n_dev + p] (j < 20): bits 31..30 = 0 LDS add, 1 LDS store, 2 staged,
- *                3 unused; bits 29..0 = LDS slot or staging index;
- *   rtab[8*r ...] first position, NMOS count, PMOS count (NMOS lanes first, then
- *                PMOS), phases, owned-entry range, item range;
+ *                3 unused or read by a lane fold; bits 29..0 = LDS slot or staging
+ *                index;
+ *   rtab[10*r ...] first position, NMOS count, PMOS count (NMOS lanes first, then
+ *                PMOS), phases, owned-entry range, item range, lane-fold range;
  *   interior[i]  target of owned entry i (bits 31..30 = 0 A slot, 1 b row), LDS slot =
  *                i - range start;
  *   links[]      item ids per region;
  *   item[4*i ...] first staged index, count, target (kind 0 A, 1 b, 2 hub chunk),
  *                number of contributing regions (0: an entry with more than 8
- *                contributions, folded by the follow-up kernel of the schedule). */
+ *                contributions, folded by the follow-up kernel of the schedule);
+ *   fold[3*i ...] target (as for interior), first index in fold_src, writer count;
+ *   fold_src[]   writers of a lane fold in colour order, each (code row j << 16) |
+ *                lane of the writer within its region: one lane of the region folds
+ *                the writers' merged values left and stores the entry. */
 cs_status cs_get_region_plan(const cs_circuit *c, int32_t *perm, uint16_t *phase, int32_t *code,
-                             int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item);
+                             int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item,
+                             int32_t *fold, int32_t *fold_src);
 
 /* Read and clear the device error word of the last bounded waits (synchronises the
  * stream).  Returns CS_EDOMAIN if a barrier wait ran out of its spin budget. */
@@ -220,9 +228,10 @@ cs_status cs_batch_set_schedule(cs_batch *b, cs_variant schedule);
 cs_status cs_batch_plan_regions(cs_batch *b, int32_t block);
 cs_status cs_batch_get_region_info(const cs_batch *b, int32_t *n_regions, int32_t *max_phases,
                                    int64_t *n_items, int64_t *n_staged, int64_t *n_interior,
-                                   int64_t *n_links);
+                                   int64_t *n_links, int64_t *n_folds, int64_t *n_fold_src);
 cs_status cs_batch_get_region_plan(const cs_batch *b, int32_t *perm, uint16_t *phase, int32_t *code,
-                                   int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item);
+                                   int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item,
+                                   int32_t *fold, int32_t *fold_src);
 /* One launch over every circuit of the batch. */
 cs_status cs_batch_eval_stamp(cs_batch *b, const double *x, double ag0, const double *hist,
                               double *A, double *b_vec, void *stream);

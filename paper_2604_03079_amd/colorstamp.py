@@ -73,8 +73,8 @@ def lib():
             "cs_set_launch": [p, i32, i32, i32],
             "cs_get_info": [p, p, p, p, p, p, p, p, p],
             "cs_plan_regions": [p, i32],
-            "cs_get_region_info": [p, p, p, p, p, p, p],
-            "cs_get_region_plan": [p, p, p, p, p, p, p, p],
+            "cs_get_region_info": [p, p, p, p, p, p, p, p, p],
+            "cs_get_region_plan": [p, p, p, p, p, p, p, p, p, p],
             "cs_check": [p, p],
             "cs_set_spin_limit": [p, i64],
             "cs_batch_create": [i32, p, p],
@@ -84,8 +84,8 @@ def lib():
             "cs_batch_get_info": [p, p, p, p, p, p, p, p, p],
             "cs_batch_set_schedule": [p, C.c_int],
             "cs_batch_plan_regions": [p, i32],
-            "cs_batch_get_region_info": [p, p, p, p, p, p, p],
-            "cs_batch_get_region_plan": [p, p, p, p, p, p, p, p],
+            "cs_batch_get_region_info": [p, p, p, p, p, p, p, p, p],
+            "cs_batch_get_region_plan": [p, p, p, p, p, p, p, p, p, p],
             "cs_batch_eval_stamp": [p, p, d, p, p, p, p],
             "cs_batch_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_batch_check": [p, p],
@@ -125,13 +125,16 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+RT_FIELDS = 10   # fields per region in the plan's region table
+
+
 def _region_info(fn, h) -> dict:
     nr, mp = C.c_int32(), C.c_int32()
-    ni, ns, nn, nl = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
-    _check(fn(h, C.byref(nr), C.byref(mp), C.byref(ni), C.byref(ns), C.byref(nn), C.byref(nl)),
-           "region info")
+    ni, ns, nn, nl, nf, nfs = (C.c_int64() for _ in range(6))
+    _check(fn(h, C.byref(nr), C.byref(mp), C.byref(ni), C.byref(ns), C.byref(nn), C.byref(nl),
+              C.byref(nf), C.byref(nfs)), "region info")
     return dict(n_regions=nr.value, max_phases=mp.value, n_items=ni.value, n_staged=ns.value,
-                n_interior=nn.value, n_links=nl.value)
+                n_interior=nn.value, n_links=nl.value, n_folds=nf.value, n_fold_src=nfs.value)
 
 
 def _region_plan(plan_fn, info_fn, get_fn, h, block, n_dev) -> dict:
@@ -139,15 +142,18 @@ def _region_plan(plan_fn, info_fn, get_fn, h, block, n_dev) -> dict:
     _check(plan_fn(h, int(block)), "plan regions")
     inf = _region_info(info_fn, h)
     t = dict(perm=np.zeros(n_dev, np.int32), phase=np.zeros(n_dev, np.uint16),
-             code=np.zeros(20 * n_dev, np.int32), rtab=np.zeros(8 * inf["n_regions"], np.int32),
+             code=np.zeros(20 * n_dev, np.int32), rtab=np.zeros(RT_FIELDS * inf["n_regions"], np.int32),
              interior=np.zeros(inf["n_interior"], np.int32), links=np.zeros(inf["n_links"], np.int32),
-             item=np.zeros(4 * inf["n_items"], np.int32))
+             item=np.zeros(4 * inf["n_items"], np.int32), fold=np.zeros(3 * inf["n_folds"], np.int32),
+             fold_src=np.zeros(inf["n_fold_src"], np.int32))
     _check(get_fn(h, *[_np_ptr(t[k]) if t[k].size else None
-                       for k in ("perm", "phase", "code", "rtab", "interior", "links", "item")]),
+                       for k in ("perm", "phase", "code", "rtab", "interior", "links", "item", "fold",
+                                 "fold_src")]),
            "region plan")
     t["code"] = t["code"].reshape(20, n_dev)
-    t["rtab"] = t["rtab"].reshape(-1, 8)
+    t["rtab"] = t["rtab"].reshape(-1, RT_FIELDS)
     t["item"] = t["item"].reshape(-1, 4)
+    t["fold"] = t["fold"].reshape(-1, 3)
     t.update(inf)
     return t
 

@@ -447,7 +447,7 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
                 }
                 const int64_t cap = c->rg_cap;
                 const int32_t nr = c->rp.n_regions;
-                if (nr >= 1 && nr <= cap && (size_t)nr + 2 <= c->d_sync.n) {
+                if (nr >= 1 && nr <= cap && (size_t)nr + 2 <= c->d_sync.n && c->rp.max_glevel >= 0) {
                     const KSync ks{c->d_sync.p, c->spin_limit};
                     CS_CHECK_HIP(launch_region_grid(region_kcirc(kc, c->rp, c->rd), call, region_kregion(c->rp, c->rd),
                                                     ks, c->block, c->cooperative, s), "persistent launch");
@@ -517,17 +517,19 @@ cs_status cs_plan_regions(cs_circuit *c, int32_t block) {
 }
 
 cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *max_phases,
-                             int64_t *n_items, int64_t *n_staged, int64_t *n_interior, int64_t *n_links) {
+                             int64_t *n_items, int64_t *n_staged, int64_t *n_interior, int64_t *n_links,
+                             int64_t *n_folds, int64_t *n_fold_src) {
     if (!c) return fail(CS_EINVAL, "NULL circuit");
-    region_info(c->rp, n_regions, max_phases, n_items, n_staged, n_interior, n_links);
+    region_info(c->rp, n_regions, max_phases, n_items, n_staged, n_interior, n_links, n_folds, n_fold_src);
     return CS_OK;
 }
 
 cs_status cs_get_region_plan(const cs_circuit *c, int32_t *perm, uint16_t *phase, int32_t *code,
-                             int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item) {
+                             int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item, int32_t *fold,
+                             int32_t *fold_src) {
     if (!c) return fail(CS_EINVAL, "NULL circuit");
     if (!c->rp.built) return fail(CS_ESTATE, "no region plan yet");
-    region_tables(c->rp, perm, phase, code, rtab, interior, links, item);
+    region_tables(c->rp, perm, phase, code, rtab, interior, links, item, fold, fold_src);
     return CS_OK;
 }
 

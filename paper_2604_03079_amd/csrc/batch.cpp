@@ -530,17 +530,18 @@ cs_status cs_batch_plan_regions(cs_batch *B, int32_t block) {
 
 cs_status cs_batch_get_region_info(const cs_batch *B, int32_t *n_regions, int32_t *max_phases,
                                    int64_t *n_items, int64_t *n_staged, int64_t *n_interior,
-                                   int64_t *n_links) {
+                                   int64_t *n_links, int64_t *n_folds, int64_t *n_fold_src) {
     if (!B) return bfail(CS_EINVAL, "NULL batch");
-    region_info(B->rp, n_regions, max_phases, n_items, n_staged, n_interior, n_links);
+    region_info(B->rp, n_regions, max_phases, n_items, n_staged, n_interior, n_links, n_folds, n_fold_src);
     return CS_OK;
 }
 
 cs_status cs_batch_get_region_plan(const cs_batch *B, int32_t *perm, uint16_t *phase, int32_t *code,
-                                   int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item) {
+                                   int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item,
+                                   int32_t *fold, int32_t *fold_src) {
     if (!B) return bfail(CS_EINVAL, "NULL batch");
     if (!B->rp.built) return bfail(CS_ESTATE, "no region plan yet");
-    region_tables(B->rp, perm, phase, code, rtab, interior, links, item);
+    region_tables(B->rp, perm, phase, code, rtab, interior, links, item, fold, fold_src);
     return CS_OK;
 }
 

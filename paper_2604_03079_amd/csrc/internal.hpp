@@ -103,7 +103,8 @@ struct RegionPlan {
     std::vector<int8_t> pol;
     std::vector<uint16_t> phase, glevel;
     std::vector<int32_t> slot_tgt;     // per staged slot: target of a shared entry (-1: hub)
-    std::vector<uint8_t> slot_first;   // SLOT_STORE / SLOT_ADD / SLOT_HUB
+    std::vector<uint8_t> slot_first;   // SLOT_STORE / SLOT_ADD / SLOT_HUB / SLOT_DEFER
+    std::vector<int32_t> fold, fold_src;   // lane folds (see KRegion)
 };
 
 // Device copies of a region plan.
@@ -113,6 +114,7 @@ struct RegionDev {
     DevBuf<uint16_t> phase, glevel;
     DevBuf<int32_t> slot_tgt;
     DevBuf<uint8_t> slot_first;
+    DevBuf<int32_t> fold, fold_src;
     DevBuf<double> par, stage;
     DevBuf<uint32_t> item_count;
     bool ready = false;      // uploaded from the current plan
@@ -125,9 +127,10 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D);
 KCirc region_kcirc(const KCirc &base, const RegionPlan &R, const RegionDev &D);
 KRegion region_kregion(const RegionPlan &R, const RegionDev &D);
 void region_info(const RegionPlan &R, int32_t *n_regions, int32_t *max_phases, int64_t *n_items,
-                 int64_t *n_staged, int64_t *n_interior, int64_t *n_links);
+                 int64_t *n_staged, int64_t *n_interior, int64_t *n_links, int64_t *n_folds,
+                 int64_t *n_fold_src);
 void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t *code, int32_t *rtab,
-                   int32_t *interior, int32_t *links, int32_t *item);
+                   int32_t *interior, int32_t *links, int32_t *item, int32_t *fold, int32_t *fold_src);
 
 // Build the greedy colouring (ascending device order) and the colour-major order.
 Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges);

@@ -26,16 +26,22 @@ constexpr uint32_t ITEM_B = 1u;     // b row
 constexpr uint32_t ITEM_HUB = 2u;   // hub chunk (index = chunk id)
 // Per-region table fields: first position, NMOS count, PMOS count (lanes: NMOS
 // first, then PMOS), phases, interior range [4], [5) in int_target,
-// item range [6], [7) in ritems.
-constexpr int RT_FIELDS = 8;
+// item range [6], [7) in ritems, lane-fold range [8], [9) in fold.
+constexpr int RT_FIELDS = 10;
 // Shared entries with more contributions than this are folded by the follow-up
 // kernel; smaller ones by the last contributing region, one lane each.
 constexpr int ITEM_LANE_MAX = 8;
+// An entry whose writers all lie in one region is accumulated in that region's LDS
+// by phases only if it has at most this many writers (each writer costs a phase in
+// the worst case); a larger one is a lane fold: one lane of the region folds the
+// writers' merged values, read from LDS in colour order, and stores the result.
+constexpr int LDS_WRITERS_MAX = 8;
 // Staged slots in the grid-barrier form of the region schedule: a shared entry's
 // first writer (colour order) stores, the others load-add; hub slots are staged.
 constexpr uint8_t SLOT_STORE = 0;
 constexpr uint8_t SLOT_ADD = 1;
 constexpr uint8_t SLOT_HUB = 2;
+constexpr uint8_t SLOT_DEFER = 3;   // large shared entry: staged, folded by the follow-up kernel
 constexpr uint32_t HUB_B_FLAG = 0x80000000u;  // hub target is a b row
 
 // Fixed-shape hub sum: chunks of HUB_K contributions, folded left, recursively.
@@ -106,10 +112,14 @@ struct KRegion {
     int32_t n_deferred;         // items folded by the follow-up kernel
     const int32_t *deferred;
     // grid-barrier form: shared entries written in place, level by level
-    int32_t max_glevel;         // levels of shared-entry writers
+    int32_t max_glevel;         // levels of shared-entry writers (-1: beyond 16 bits, form unavailable)
     const uint16_t *glevel;     // [n] level of each position's shared entries
     const int32_t *slot_tgt;    // [staged slots] target of a shared entry
-    const uint8_t *slot_first;  // [staged slots] SLOT_STORE / SLOT_ADD / SLOT_HUB
+    const uint8_t *slot_first;  // [staged slots] SLOT_STORE / SLOT_ADD / SLOT_HUB / SLOT_DEFER
+    // lane folds: [3 per fold] target, first source, count; sources in colour order,
+    // each (code row << 16) | lane of a writer in the region
+    const int32_t *fold;
+    const int32_t *fold_src;
 };
 
 // Per-call operands.

@@ -661,13 +661,14 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     }
     // (the grid form is launched with exactly one workgroup per region; a workgroup
     // beyond them would own nothing and only take part in the barriers)
-    int f[RT_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int f[RT_FIELDS] = {};
     if ((int)blockIdx.x < kr.n_regions) {
         const int32_t *rt = kr.rtab + (size_t)blockIdx.x * RT_FIELDS;
 #pragma unroll
         for (int k = 0; k < RT_FIELDS; ++k) f[k] = rt[k];
     }
     const int p0 = f[0], nN = f[1], nP = f[2], nph = f[3], ib = f[4], ie = f[5], jb = f[6], je = f[7];
+    const int fb = f[8], fe = f[9];
     const int t = threadIdx.x;
     const int pos = t < nN + nP ? p0 + t : -1;
     // the region's accumulators start at -0.0, the exact identity of IEEE addition, so
@@ -705,7 +706,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     for (int j = 0; j < NCODE; ++j) {
         if ((cd[j] >> 30) != TAG_STAGE) continue;
         const uint32_t sl = cd[j] & 0x3FFFFFFFu;
-        if (GRID && kr.slot_first[sl] != SLOT_HUB) continue;
+        if (GRID && kr.slot_first[sl] < SLOT_HUB) continue;
         st_coherent(kc.stage + sl, mst[j * B + t]);
     }
     lds_barrier();
@@ -727,6 +728,17 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
                 if ((cd[j] >> 30) <= TAG_LDS_STORE) lds[cd[j] & 0x3FFFFFFFu] = cur[j] + v[j];
         }
         lds_barrier();
+    }
+    // lane folds: entries of the region with many writers, one lane each, the
+    // writers' merged values read from LDS in colour order (no phase per writer)
+    for (int i = fb + t; i < fe; i += B) {
+        const int32_t *fd = kr.fold + 3 * (size_t)i;
+        const int32_t *src = kr.fold_src + fd[1];
+        const int cnt = fd[2];
+        double s = mst[(src[0] >> 16) * B + (src[0] & 0xFFFF)];
+#pragma unroll 8
+        for (int k = 1; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
+        store_target(call, (uint32_t)fd[0], s);
     }
     if constexpr (GRID) {
         // the region's own entries, then the shared entries level by level, then the
@@ -753,7 +765,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
                 for (int j = 0; j < NCODE; ++j) {
                     if ((cd[j] >> 30) != TAG_STAGE) continue;
                     const uint32_t sl = cd[j] & 0x3FFFFFFFu;
-                    if (kr.slot_first[sl] == SLOT_HUB) continue;
+                    if (kr.slot_first[sl] >= SLOT_HUB) continue;
                     const uint32_t tg = (uint32_t)kr.slot_tgt[sl];
                     st_coherent(((tg >> 30) == ITEM_B ? call.b : call.A) + (tg & 0x3FFFFFFFu), old[j] + mst[j * B + t]);
                 }
@@ -912,8 +924,12 @@ hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion 
     void *args[] = {&a, &b, &r, &k};
     const int grid = std::max(kr.n_regions, 1);
     const size_t shm = region_lds_bytes(kr.lds_int, kr.nc_max, block);
-    if (!cooperative) return hipLaunchKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s);
-    return hipLaunchCooperativeKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s);
+    hipError_t e = cooperative
+        ? hipLaunchCooperativeKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s)
+        : hipLaunchKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s);
+    if (e != hipSuccess || kr.n_deferred == 0) return e;
+    hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
+    return hipGetLastError();
 }
 
 hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,

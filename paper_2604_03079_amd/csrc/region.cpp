@@ -7,16 +7,19 @@
 // that per-entry order but runs it at workgroup scope:
 //   * devices are cut, in ascending device index, into regions of at most one
 //     workgroup (a circuit that fits one region is never split);
-//   * an entry whose writers all lie in one region is accumulated in that
-//     workgroup's LDS, in colour phases separated by workgroup barriers; the phases
+//   * an entry whose writers (at most LDS_WRITERS_MAX) all lie in one region is
+//     accumulated in that workgroup's LDS, in colour phases separated by workgroup
+//     barriers; the phases
 //     are the colours coarsened to levels (a device's level is one more than the
 //     largest level of an earlier-coloured writer of any of its region entries), so
 //     consecutive writers of an entry keep their order while unrelated colours share
 //     a phase;
-//   * an entry written from several regions has its contributions staged, in colour
-//     order, in a global array; the last of its regions to finish (a counter) folds
-//     them left and stores the result, or, for entries with more than ITEM_LANE_MAX
-//     contributions, a follow-up kernel folds them (one wave per entry);
+//   * an entry written from several regions, or with more writers than that, has
+//     its contributions staged, in colour order, in a global array; the last of its
+//     regions to finish (a counter) folds them left and stores the result, or, for
+//     entries with more than ITEM_LANE_MAX contributions, a follow-up kernel folds
+//     them (one wave per entry), so a long chain of writers of one entry costs a
+//     sequential fold instead of one workgroup phase per writer;
 //   * hub entries keep their fixed-shape sum: contributions staged in ascending
 //     device index, each chunk of HUB_K folded by the last region touching it.
 // The result is bitwise the colour-order accumulation.
@@ -128,6 +131,7 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     std::vector<std::vector<int64_t>> interior((size_t)R.n_regions);
     std::vector<std::vector<int32_t>> rit((size_t)R.n_regions);
     std::vector<uint8_t> is_interior((size_t)nkeys, 0);
+    std::vector<std::vector<int64_t>> lfold((size_t)R.n_regions);
     int64_t cursor = s.stage_base;
     std::vector<int32_t> regs;
     // per staged slot of a shared entry (from stage_base on): target, first writer or
@@ -141,9 +145,16 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
         for (int64_t w = b0; w < b1; ++w) regs.push_back(region_of[(size_t)s.perm[(size_t)(wr[(size_t)w] >> 5)]]);
         std::sort(regs.begin(), regs.end());
         regs.erase(std::unique(regs.begin(), regs.end()), regs.end());
-        if (regs.size() == 1) {
+        if (regs.size() == 1 && b1 - b0 <= LDS_WRITERS_MAX) {
             interior[(size_t)regs[0]].push_back(t);
             is_interior[(size_t)t] = 1;
+            continue;
+        }
+        if (regs.size() == 1) {
+            // lane fold: the writers keep their merged values in LDS (code tag 3)
+            lfold[(size_t)regs[0]].push_back(t);
+            for (int64_t w = b0; w < b1; ++w)
+                code[(size_t)(wr[(size_t)w] & 31) * n + (size_t)(wr[(size_t)w] >> 5)] = (int32_t)(3u << 30);
             continue;
         }
         if (cursor + (b1 - b0) >= INDEX_LIMIT) return {CS_ENOTSUP, "too many staged contributions"};
@@ -162,7 +173,7 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             const int j = (int)(wr[(size_t)w] & 31);
             code[(size_t)j * n + p] = (int32_t)((TAG_STAGE << 30) | (uint32_t)(cursor + (w - b0)));
             slot_tgt.push_back((int32_t)tgt);
-            slot_first.push_back(w == b0 ? SLOT_STORE : SLOT_ADD);
+            slot_first.push_back(deferred ? SLOT_DEFER : w == b0 ? SLOT_STORE : SLOT_ADD);
             slot_pos.push_back((int32_t)p);
         }
         cursor += b1 - b0;
@@ -275,7 +286,7 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
                 const uint32_t c = (uint32_t)code[(size_t)j * n + (size_t)p];
                 if ((c >> 30) != TAG_STAGE) continue;
                 const int64_t sl = (int64_t)(c & 0x3FFFFFFFu);
-                if (sl < s.stage_base) continue;
+                if (sl < s.stage_base || slot_first[(size_t)sl] == SLOT_DEFER) continue;
                 shared = true;
                 if (slot_first[(size_t)sl] == SLOT_ADD) lv = std::max(lv, glevel[(size_t)slot_pos[(size_t)sl - 1]] + 1);
             }
@@ -286,7 +297,12 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             }
         }
         (void)any;
-        if (R.max_glevel > 65535) return {CS_ENOTSUP, "too many shared-entry levels"};
+        // beyond 16-bit levels the grid-barrier form is unavailable (the workgroup
+        // schedule does not use the levels); -1 marks that
+        if (R.max_glevel > 65535) {
+            R.max_glevel = -1;
+            std::fill(glevel.begin(), glevel.end(), 0);
+        }
     }
     R.slot_tgt = std::move(slot_tgt);
     R.slot_first = std::move(slot_first);
@@ -343,6 +359,26 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             rt[7] = (int32_t)R.ritems.size();
             R.max_phase = std::max(R.max_phase, nphase[(size_t)g]);
         }
+        // lane folds: per region its entries in target order, each with its writers'
+        // (code row, lane) in colour order
+        std::vector<int32_t> new_pos(n);
+        for (size_t q2 = 0; q2 < n; ++q2) new_pos[(size_t)R.cm_pos[q2]] = (int32_t)q2;
+        for (int32_t g = 0; g < R.n_regions; ++g) {
+            int32_t *rt = &R.rtab[(size_t)g * RT_FIELDS];
+            rt[8] = (int32_t)(R.fold.size() / 3);
+            for (int64_t t : lfold[(size_t)g]) {
+                const uint32_t tgt = t < nnz ? (uint32_t)t : ((uint32_t)(t - nnz) | (ITEM_B << 30));
+                const int64_t b0 = kptr[(size_t)t], b1 = kptr[(size_t)t + 1];
+                if ((int64_t)R.fold_src.size() + (b1 - b0) >= INDEX_LIMIT) return {CS_ENOTSUP, "too many lane-fold sources"};
+                R.fold.insert(R.fold.end(), {(int32_t)tgt, (int32_t)R.fold_src.size(), (int32_t)(b1 - b0)});
+                for (int64_t w = b0; w < b1; ++w) {
+                    const size_t p = (size_t)(wr[(size_t)w] >> 5);
+                    const int32_t j = (int32_t)(wr[(size_t)w] & 31);
+                    R.fold_src.push_back((j << 16) | (new_pos[p] - rt[0]));
+                }
+            }
+            rt[9] = (int32_t)(R.fold.size() / 3);
+        }
     }
     R.built = true;
     return {CS_OK, ""};
@@ -368,6 +404,8 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
     if ((e = D.glevel.upload(R.glevel)) != hipSuccess) return e;
     if ((e = D.slot_tgt.upload(R.slot_tgt)) != hipSuccess) return e;
     if ((e = D.slot_first.upload(R.slot_first)) != hipSuccess) return e;
+    if ((e = D.fold.upload(R.fold)) != hipSuccess) return e;
+    if ((e = D.fold_src.upload(R.fold_src)) != hipSuccess) return e;
     if ((e = D.par.alloc(3 * R.perm.size())) != hipSuccess) return e;
     if ((e = D.stage.alloc((size_t)R.stage_size)) != hipSuccess) return e;
     const size_t n_items = R.item.size() / 4;
@@ -379,7 +417,10 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
 }
 
 void region_info(const RegionPlan &R, int32_t *n_regions, int32_t *max_phases, int64_t *n_items,
-                 int64_t *n_staged, int64_t *n_interior, int64_t *n_links) {
+                 int64_t *n_staged, int64_t *n_interior, int64_t *n_links, int64_t *n_folds,
+                 int64_t *n_fold_src) {
+    if (n_folds) *n_folds = (int64_t)(R.fold.size() / 3);
+    if (n_fold_src) *n_fold_src = (int64_t)R.fold_src.size();
     if (n_regions) *n_regions = R.n_regions;
     if (max_phases) *max_phases = R.max_phase;
     if (n_items) *n_items = (int64_t)(R.item.size() / 4);
@@ -394,7 +435,9 @@ static void copy_out(const std::vector<T> &v, T *dst) {
 }
 
 void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t *code, int32_t *rtab,
-                   int32_t *interior, int32_t *links, int32_t *item) {
+                   int32_t *interior, int32_t *links, int32_t *item, int32_t *fold, int32_t *fold_src) {
+    copy_out(R.fold, fold);
+    copy_out(R.fold_src, fold_src);
     copy_out(R.perm, perm);
     copy_out(R.phase, phase);
     copy_out(R.code, code);
@@ -434,6 +477,8 @@ KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
     r.glevel = D.glevel.p;
     r.slot_tgt = D.slot_tgt.p;
     r.slot_first = D.slot_first.p;
+    r.fold = D.fold.p;
+    r.fold_src = D.fold_src.p;
     r.lds_int = (R.max_lds + 1) & ~1;
     r.nc_max = R.max_nc;
     return r;

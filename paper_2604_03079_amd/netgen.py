@@ -268,6 +268,13 @@ def chain_case(n_stages: int, seed: int) -> Circuit:
     return draw_params(c, rng, W_CHAIN, L_CHAIN)
 
 
+def pchain_case(n_dev: int, group: int, seed: int) -> Circuit:
+    """Parallel-inverter chain of about ``n_dev`` devices, ``group`` inverters per stage
+    (at least two stages), chain parameter ranges."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return draw_params(parallel_chain(max(2, n_dev // (2 * group)), group), rng, W_CHAIN, L_CHAIN)
+
+
 def sram_case(rows: int, cols: int, seed: int) -> Circuit:
     rng = np.random.Generator(np.random.PCG64(seed))
     return draw_params(sram6t(rows, cols), rng, W_SRAM, L_SRAM)

@@ -76,6 +76,7 @@ def small_cases():
         ("sram16x16", G.sram_case(16, 16, 5)),
         ("sram3x40", G.sram_case(3, 40, 6)),
         ("pchain50x6", G.draw_params(G.parallel_chain(50, 6), rng, G.W_CHAIN, G.L_CHAIN)),
+        ("pchain40x33", G.draw_params(G.parallel_chain(40, 33), rng, G.W_CHAIN, G.L_CHAIN)),
         ("private700", G.draw_params(G.no_shared_nets(700), rng, G.W_CHAIN, G.L_CHAIN)),
     ]
     for k in range(8, 15):
@@ -162,6 +163,19 @@ def test_full_size_workloads(torch_dev, orc, idx):
     A, b, _ = gpu_stamp(torch_dev, circ, True, "atomic")
     assert np.all(np.abs(A - As) <= 1e-12 * mA)
     assert np.all(np.abs(b - bs) <= 1e-12 * mb)
+
+
+def test_full_size_strict_chain(torch_dev, orc):
+    # rails not excluded: 100,001 colours; the vdd diagonal and vdd RHS row take one
+    # contribution per PMOS, folded in colour order by the follow-up kernel (in the
+    # grid-barrier form too, where they take no level)
+    circ = G.workload(1)
+    A0, b0 = oracle_replay(orc, circ, False)
+    for variant, block, ea in (("region", 256, -1), ("region", 128, -1), ("persistent", 256, 1)):
+        say(f"case workload1 strict variant={variant} block={block} eval_ahead={ea}")
+        A, b, c = gpu_stamp(torch_dev, circ, False, variant, block=block, eval_ahead=ea)
+        assert_bit_exact(A, A0, f"strict/{variant}{block}/A")
+        assert_bit_exact(b, b0, f"strict/{variant}{block}/b")
 
 
 @pytest.mark.parametrize("variant", ["persistent", "per_kernel", "buffered", "atomic", "region"])

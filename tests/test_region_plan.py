@@ -57,19 +57,28 @@ def replay(plan, vals, pol, block, nnz, n_rows):
     seen = np.zeros(n, bool)
     nxt = 0
     for r in range(plan["n_regions"]):
-        p0, nN, nP, nph, ib, ie, jb, je = (int(v) for v in rtab[r])
+        p0, nN, nP, nph, ib, ie, jb, je, fb, fe = (int(v) for v in rtab[r])
         assert p0 == nxt and nN + nP > 0
         nxt = p0 + nN + nP
         assert nN + nP <= block
         pos = list(range(p0, p0 + nN + nP))
         assert all(pol[perm[p]] > 0 for p in pos[:nN]) and all(pol[perm[p]] < 0 for p in pos[nN:])
         lds = np.full(ie - ib, np.nan)
+        folded = set()
+        for i in range(fb, fe):
+            _, sb, cnt = (int(v) for v in plan["fold"][i])
+            assert cnt > 8
+            for src in plan["fold_src"][sb:sb + cnt]:
+                j, lane = int(src) >> 16, int(src) & 0xFFFF
+                assert lane < nN + nP and (j, lane) not in folded
+                folded.add((j, lane))
         for p in pos:
             seen[p] = True
             for j, mv in enumerate(vals[perm[p]]):
                 c = int(code[j, p]) & 0xFFFFFFFF
                 tag, idx = c >> 30, c & 0x3FFFFFFF
-                assert tag in (0, 1, 2)
+                # tag 3 within a device's codes: read by a lane fold of the region
+                assert tag in (0, 1, 2) or (tag == 3 and (j, p - p0) in folded)
                 if tag == 2:
                     assert np.isnan(stage[idx])
                     stage[idx] = mv
@@ -89,6 +98,17 @@ def replay(plan, vals, pol, block, nnz, n_rows):
                         assert not np.isnan(lds[idx]), "load-add before the store"
                         lds[idx] = lds[idx] + mv
         assert not np.isnan(lds).any()
+        # lane folds: the writers' merged values, left to right in colour order
+        for i in range(fb, fe):
+            tg, sb, cnt = (int(v) for v in plan["fold"][i])
+            tg &= 0xFFFFFFFF
+            srcs = [int(v) for v in plan["fold_src"][sb:sb + cnt]]
+            s = vals[perm[p0 + (srcs[0] & 0xFFFF)]][srcs[0] >> 16]
+            for src in srcs[1:]:
+                s = s + vals[perm[p0 + (src & 0xFFFF)]][src >> 16]
+            key = ("b" if tg >> 30 == 1 else "A", tg & 0x3FFFFFFF)
+            assert key not in out
+            out[key] = s
         for i in range(ie - ib):
             tg = int(plan["interior"][ib + i]) & 0xFFFFFFFF
             key = ("b" if tg >> 30 == 1 else "A", tg & 0x3FFFFFFF)
@@ -98,7 +118,7 @@ def replay(plan, vals, pol, block, nnz, n_rows):
     # items: linked from exactly the regions that contribute
     links = {}
     for r in range(plan["n_regions"]):
-        _, _, _, _, _, _, jb, je = (int(v) for v in rtab[r])
+        jb, je = int(rtab[r][6]), int(rtab[r][7])
         for it in plan["links"][jb:je]:
             links.setdefault(int(it), []).append(r)
     for it, (beg, cnt, tgt, need) in enumerate(plan["item"]):
@@ -141,6 +161,7 @@ CASES = [
     ("sram6x5", lambda: G.sram_case(6, 5, 8)),
     ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)),
     ("pchain7x3", lambda: G.draw_params(G.parallel_chain(7, 3), np.random.default_rng(5), G.W_CHAIN, G.L_CHAIN)),
+    ("pchain9x20", lambda: G.draw_params(G.parallel_chain(9, 20), np.random.default_rng(6), G.W_CHAIN, G.L_CHAIN)),
 ]
 
 
@@ -219,3 +240,30 @@ def test_plan_errors(orc):
         c.region_plan(100)
     with pytest.raises(CS.CsError):
         c.region_plan(512)
+
+
+def test_strict_chain_vdd_entries_are_deferred():
+    # without the rail exclusion every PMOS of a chain writes the vdd diagonal and
+    # the vdd RHS row: 70,000 writers each, in colour order; they become deferred
+    # items (folded by the follow-up kernel), so they chain no levels
+    circ = G.chain_case(70_000, seed=8)
+    c = CS.prepare(circ, False)
+    assert c.n_colors == 70_001
+    plan = c.region_plan(256)
+    assert plan["n_regions"] == (circ.n_dev + 255) // 256
+    assert plan["max_phases"] <= 130
+    it = plan["item"]
+    # the vdd diagonal and the vdd RHS row: one writer per PMOS, folded by the
+    # follow-up kernel (need 0)
+    big = it[it[:, 1] == 70_000]
+    assert len(big) == 2 and (big[:, 3] == 0).all()
+
+
+def test_lane_folds_take_many_writer_entries(orc):
+    # 20 inverters per stage: the output node's diagonal has 80 writers inside one
+    # region of 256, folded by one lane instead of 80 phases
+    circ = G.draw_params(G.parallel_chain(9, 20), np.random.default_rng(6), G.W_CHAIN, G.L_CHAIN)
+    c = CS.prepare(circ, True)
+    plan = c.region_plan(256)
+    assert plan["n_folds"] > 0 and plan["max_phases"] <= 8
+    assert int(plan["fold"][:, 2].max()) == 80
