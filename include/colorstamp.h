@@ -161,8 +161,8 @@ cs_status cs_plan_regions(cs_circuit *c, int32_t block);
 /* Facts of the last region plan: regions (= workgroups), largest number of phases
  * of a region, items (entries shared between regions, and hub chunks), staged
  * contributions (hub and shared), entries owned by one region and accumulated in
- * its LDS (at most 8 writers), region-to-item links, lane folds (entries owned by
- * one region with more than 8 writers) and their writer references.
+ * its LDS (one or two writers), region-to-item links, lane folds (entries owned by
+ * one region with three or more writers) and their writer references.
  * Any pointer may be NULL; zeros before a plan exists. */
 cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *max_phases,
                              int64_t *n_items, int64_t *n_staged, int64_t *n_interior,

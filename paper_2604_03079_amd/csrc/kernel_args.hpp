@@ -32,10 +32,11 @@ constexpr int RT_FIELDS = 10;
 // kernel; smaller ones by the last contributing region, one lane each.
 constexpr int ITEM_LANE_MAX = 8;
 // An entry whose writers all lie in one region is accumulated in that region's LDS
-// by phases only if it has at most this many writers (each writer costs a phase in
-// the worst case); a larger one is a lane fold: one lane of the region folds the
-// writers' merged values, read from LDS in colour order, and stores the result.
-constexpr int LDS_WRITERS_MAX = 8;
+// by phases only if it has at most this many writers (one or two: two writers need
+// only distinct phases, not an order); a larger one is a lane fold: one lane of the
+// region folds the writers' merged values, read from LDS in colour order, and
+// stores the result.
+constexpr int LDS_WRITERS_MAX = 2;
 // Staged slots in the grid-barrier form of the region schedule: a shared entry's
 // first writer (colour order) stores, the others load-add; hub slots are staged.
 constexpr uint8_t SLOT_STORE = 0;

@@ -138,13 +138,23 @@ __device__ __forceinline__ void st_coherent(double *p, double v) {
 }
 
 // s + v[i0] + v[i0+1] + ... + v[n-1], left to right, by one thread; the LDS reads
-// go out sixteen at a time so that their latency is paid once per sixteen adds.
+// go out sixteen at a time, the next sixteen before the current sixteen are added,
+// so that their latency hides behind the dependent adds.
 __device__ __forceinline__ double fold_more(double s, const double *v, int i0, int n) {
     int i = i0;
-    for (; i + 16 <= n; i += 16) {
+    if (i + 16 <= n) {
         double t[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) t[k] = v[i + k];
+        for (i += 16; i + 16 <= n; i += 16) {
+            double u[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) u[k] = v[i + k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s = s + t[k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) t[k] = u[k];
+        }
 #pragma unroll
         for (int k = 0; k < 16; ++k) s = s + t[k];
     }
@@ -506,12 +516,23 @@ __device__ __forceinline__ void store_target(const KCall &call, uint32_t tgt, do
 // at a time go through the wave's LDS slice, lane 0 folds; the sum is broadcast.
 __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *mine) {
     const int lane = threadIdx.x & 63;
+    constexpr int R = HUB_K / 64;
     double s = 0.0;
+    // chunk g + HUB_K is loaded into registers while lane 0 folds chunk g
+    double r[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) r[k] = lane + 64 * k < cnt ? ld_coherent(src + lane + 64 * k) : 0.0;
     for (int g = 0; g < cnt; g += HUB_K) {
         const int e = min(HUB_K, cnt - g);
-        for (int k = lane; k < e; k += 64) mine[k] = ld_coherent(src + g + k);
-        __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (lane + 64 * k < e) mine[lane + 64 * k] = r[k];
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the chunk is in LDS
         __builtin_amdgcn_wave_barrier();
+        const int e2 = min(HUB_K, cnt - g - HUB_K);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (lane + 64 * k < e2) r[k] = ld_coherent(src + g + HUB_K + lane + 64 * k);
         if (lane == 0) s = g == 0 ? fold_lds(mine, e) : fold_more(s, mine, 0, e);
         __builtin_amdgcn_wave_barrier();
     }

@@ -7,19 +7,18 @@
 // that per-entry order but runs it at workgroup scope:
 //   * devices are cut, in ascending device index, into regions of at most one
 //     workgroup (a circuit that fits one region is never split);
-//   * an entry whose writers (at most LDS_WRITERS_MAX) all lie in one region is
-//     accumulated in that workgroup's LDS, in colour phases separated by workgroup
-//     barriers; the phases
-//     are the colours coarsened to levels (a device's level is one more than the
-//     largest level of an earlier-coloured writer of any of its region entries), so
-//     consecutive writers of an entry keep their order while unrelated colours share
-//     a phase;
-//   * an entry written from several regions, or with more writers than that, has
-//     its contributions staged, in colour order, in a global array; the last of its
-//     regions to finish (a counter) folds them left and stores the result, or, for
-//     entries with more than ITEM_LANE_MAX contributions, a follow-up kernel folds
-//     them (one wave per entry), so a long chain of writers of one entry costs a
-//     sequential fold instead of one workgroup phase per writer;
+//   * an entry whose writers all lie in one region and are at most LDS_WRITERS_MAX
+//     (one or two) is accumulated in that workgroup's LDS, in phases separated by
+//     workgroup barriers; two writers of an entry take distinct phases (two values
+//     added to the -0.0 start give the same bits in either order), so a handful of
+//     phases serve any number of colours;
+//   * an entry whose writers all lie in one region and are more is a lane fold: one
+//     lane folds the writers' merged values, read from LDS in colour order, and
+//     stores the result (no phase per writer);
+//   * an entry written from several regions has its contributions staged, in colour
+//     order, in a global array; the last of its regions to finish (a counter) folds
+//     them left and stores the result, or, for entries with more than ITEM_LANE_MAX
+//     contributions, a follow-up kernel folds them (one wave per entry);
 //   * hub entries keep their fixed-shape sum: contributions staged in ascending
 //     device index, each chunk of HUB_K folded by the last region touching it.
 // The result is bitwise the colour-order accumulation.
@@ -236,7 +235,9 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     }
 
     // 5. levels: devices of a region in colour order; a device comes one level after
-    // the previous writer of each of its interior entries
+    // the previous writer of each of its interior entries with three or more
+    // writers, and at another level than the other writer of each two-writer entry
+    // (two contributions added to the -0.0 start give the same bits in either order)
     std::vector<int32_t> level(n, 0), nphase((size_t)R.n_regions, 0);
     {
         std::vector<int32_t> order(n);
@@ -246,15 +247,25 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             return ra != rb ? ra < rb : s.colour[(size_t)a] < s.colour[(size_t)b];
         });
         std::vector<int32_t> last((size_t)nkeys, -1);
+        std::vector<int32_t> avoid;
         for (int32_t p : order) {
             const int k = kk[(size_t)p];
             int32_t lv = 0;
+            avoid.clear();
             for (int j = 0; j < k * k + k; ++j) {
                 const uint32_t c = (uint32_t)s.code[(size_t)j * n + (size_t)p];
                 if ((c >> 30) == TAG_HUB) continue;
                 const int64_t t = target_of((size_t)p, j, c);
-                if (is_interior[(size_t)t]) lv = std::max(lv, last[(size_t)t] + 1);
+                if (!is_interior[(size_t)t]) continue;
+                if (kptr[(size_t)t + 1] - kptr[(size_t)t] == 2) {
+                    if (last[(size_t)t] >= 0) avoid.push_back(last[(size_t)t]);
+                } else {
+                    lv = std::max(lv, last[(size_t)t] + 1);
+                }
             }
+            std::sort(avoid.begin(), avoid.end());
+            for (int32_t a : avoid)
+                if (a == lv) ++lv;
             for (int j = 0; j < k * k + k; ++j) {
                 const uint32_t c = (uint32_t)s.code[(size_t)j * n + (size_t)p];
                 if ((c >> 30) == TAG_HUB) continue;

@@ -67,7 +67,7 @@ def replay(plan, vals, pol, block, nnz, n_rows):
         folded = set()
         for i in range(fb, fe):
             _, sb, cnt = (int(v) for v in plan["fold"][i])
-            assert cnt > 8
+            assert cnt > 2
             for src in plan["fold_src"][sb:sb + cnt]:
                 j, lane = int(src) >> 16, int(src) & 0xFFFF
                 assert lane < nN + nP and (j, lane) not in folded
@@ -85,6 +85,10 @@ def replay(plan, vals, pol, block, nnz, n_rows):
             for j in range(len(vals[perm[p]]), 20):
                 assert (int(code[j, p]) & 0xFFFFFFFF) >> 30 == 3
             assert phase[p] < max(nph, 1)
+        # as the kernel: accumulators start at -0.0 and every writer load-adds in its
+        # phase; two writers of one entry never share a phase
+        lds[:] = -0.0
+        written = [set() for _ in range(ie - ib)]
         for q in range(nph):
             for p in pos:
                 if phase[p] != q:
@@ -92,12 +96,11 @@ def replay(plan, vals, pol, block, nnz, n_rows):
                 for j, mv in enumerate(vals[perm[p]]):
                     c = int(code[j, p]) & 0xFFFFFFFF
                     tag, idx = c >> 30, c & 0x3FFFFFFF
-                    if tag == 1:
-                        lds[idx] = mv
-                    elif tag == 0:
-                        assert not np.isnan(lds[idx]), "load-add before the store"
+                    if tag in (0, 1):
+                        assert q not in written[idx], "two writers of an entry in one phase"
+                        written[idx].add(q)
                         lds[idx] = lds[idx] + mv
-        assert not np.isnan(lds).any()
+        assert all(written)
         # lane folds: the writers' merged values, left to right in colour order
         for i in range(fb, fe):
             tg, sb, cnt = (int(v) for v in plan["fold"][i])
