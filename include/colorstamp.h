@@ -197,6 +197,13 @@ cs_status cs_check(cs_circuit *c, void *stream);
 /* Spin budget of the persistent kernel's barrier waits (iterations; 0 = default). */
 cs_status cs_set_spin_limit(cs_circuit *c, int64_t spins);
 
+/* Compute units the region planner sizes the last regions for: -1 (default) = the
+ * current GPU's count, 0 = no sizing, n > 0 = n units.  When the full regions
+ * (block devices each) fill their last dispatch round on only a few units (at most
+ * a quarter), that round is cut into regions of 64 devices, so its extra waves
+ * spread over more units.  Takes effect at the next planning. */
+cs_status cs_set_plan_units(cs_circuit *c, int32_t cus);
+
 /* ---- batches: many independent circuits stamped in one launch ------------------
  * The batch packs its circuits (each already coloured and mapped, models set) into
  * one instance table.  Packed layouts concatenate per-circuit arrays in batch order:

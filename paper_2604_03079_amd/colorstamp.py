@@ -26,7 +26,7 @@ EXPORTS = (
     "cs_circuit_create", "cs_circuit_destroy", "cs_build_coloring", "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
     "cs_vjp", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
-    "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_batch_create", "cs_batch_destroy",
+    "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_set_plan_units", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
     "cs_batch_get_region_plan", "cs_batch_eval_stamp", "cs_batch_vjp", "cs_batch_check",
@@ -77,6 +77,7 @@ def lib():
             "cs_get_region_plan": [p, p, p, p, p, p, p, p, p, p],
             "cs_check": [p, p],
             "cs_set_spin_limit": [p, i64],
+            "cs_set_plan_units": [p, i32],
             "cs_batch_create": [i32, p, p],
             "cs_batch_layout": [p, p, p, p],
             "cs_batch_set_params": [p, p, p, p, p],
@@ -237,6 +238,9 @@ class Circuit:
 
     def set_spin_limit(self, spins: int):
         _check(lib().cs_set_spin_limit(self._h, int(spins)), "cs_set_spin_limit")
+
+    def set_plan_units(self, cus: int):
+        _check(lib().cs_set_plan_units(self._h, int(cus)), "cs_set_plan_units")
 
     def info(self) -> dict:
         nd, nr, nz = C.c_int64(), C.c_int32(), C.c_int64()

@@ -190,11 +190,24 @@ RegionSource region_source(const HostCircuit &h) {
     return src;
 }
 
+// Compute units of the current GPU, 0 when there is none (host-only planning).
+int32_t device_cus() {
+    int dev = -1, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+    (void)hipGetLastError();
+    return cus;
+}
+
 cs_status plan_regions(cs_circuit *c, int32_t block) {
-    if (c->rp.built && c->rp.cap == block) return CS_OK;
+    const int32_t cus = c->plan_cus >= 0 ? c->plan_cus : device_cus();
+    if (c->rp.built && c->rp.cap == block && c->rp.cus == cus) return CS_OK;
     c->rd.ready = false;
     try {
-        Err e = build_regions(region_source(c->h), block, c->rp);
+        RegionSource src = region_source(c->h);
+        src.cus = cus;
+        Err e = build_regions(src, block, c->rp);
         if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, c->rp.max_nc, block) > 65536 - 1024)
             e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
         if (e.st != CS_OK) {
@@ -393,6 +406,12 @@ cs_status cs_set_launch(cs_circuit *c, int32_t block, int32_t eval_ahead, int32_
     c->block = block ? block : 256;
     c->eval_ahead_req = eval_ahead;
     c->grid = 0;
+    return CS_OK;
+}
+
+cs_status cs_set_plan_units(cs_circuit *c, int32_t cus) {
+    if (!c || cus < -1) return fail(CS_EINVAL, "bad argument");
+    c->plan_cus = cus;
     return CS_OK;
 }
 

@@ -92,12 +92,13 @@ struct RegionSource {
     int64_t nnz = 0, n_rows = 0;
     std::vector<int32_t> hub_ptr, hub_cptr;
     int64_t stage_base = 0;                // hub staging size; shared entries staged after it
+    int32_t cus = 0;                       // compute units of the target GPU (0: unknown)
 };
 
 // Region schedule tables (host), region-major positions.
 struct RegionPlan {
     bool built = false;
-    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0, max_nc = 0, max_glevel = 0;
+    int32_t cap = 0, n_regions = 0, max_lds = 0, max_phase = 0, max_nc = 0, max_glevel = 0, cus = 0;
     int64_t stage_size = 0;
     std::vector<int32_t> perm, cm_pos, term, code, rtab, int_target, ritems, item, deferred;
     std::vector<int8_t> pol;
@@ -164,6 +165,7 @@ struct cs_circuit {
     cs::RegionPlan rp;                 // region schedule (built on first use, per block size)
     cs::RegionDev rd;
     int32_t rg_cap_block = 0, rg_cap_regions = -1;   // resident-region capacity cache
+    int32_t plan_cus = -1;   // compute units the region planner targets (-1: the current GPU's)
     int64_t rg_cap = 0;
 };
 

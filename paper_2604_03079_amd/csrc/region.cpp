@@ -90,6 +90,28 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             }
         }
         R.n_regions = r + 1;
+        // wave quantisation: regions are dispatched round-robin over the compute
+        // units, so when the last round of full regions reaches only a few of them
+        // (the chain: 782 regions of 256 on 256 units, 14 units with a fourth), those
+        // units' late waves finish last; cutting that round into one-wave regions
+        // spreads the same waves over up to four times as many units
+        R.cus = s.cus;
+        const int32_t tail = s.cus > 0 ? R.n_regions % s.cus : 0;
+        if (s.group_ptr.size() <= 2 && cap > 64 && R.n_regions > s.cus && tail > 0 && 4 * tail <= s.cus) {
+            const int32_t first = R.n_regions - tail;
+            int32_t rr = first - 1;
+            int used = 64;
+            for (size_t g = 0; g < n; ++g) {
+                if (region_of[g] < first) continue;
+                if (used == 64) {
+                    ++rr;
+                    used = 0;
+                }
+                region_of[g] = rr;
+                ++used;
+            }
+            R.n_regions = rr + 1;
+        }
     }
 
     // 2. writers of every non-hub target (A slot, or nnz + b row), sorted by colour

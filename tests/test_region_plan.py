@@ -270,3 +270,21 @@ def test_lane_folds_take_many_writer_entries(orc):
     plan = c.region_plan(256)
     assert plan["n_folds"] > 0 and plan["max_phases"] <= 8
     assert int(plan["fold"][:, 2].max()) == 80
+
+
+def test_last_round_cut_into_one_wave_regions(orc):
+    # 5,000 stages at 256 devices per region: 40 regions; planned for 32 compute
+    # units the last round (8 regions, 1,808 devices) becomes 29 regions of at most
+    # 64 devices, and the replay still equals the colour replay
+    circ = G.chain_case(5000, seed=12)
+    c = CS.prepare(circ, True)
+    c.set_plan_units(0)
+    assert c.region_plan(256)["n_regions"] == 40
+    c.set_plan_units(32)
+    plan, _ = check_against_oracle(orc, circ, c, True, 256)
+    assert plan["n_regions"] == 32 + 29
+    sizes = plan["rtab"][:, 1] + plan["rtab"][:, 2]
+    assert (sizes[:32] == 256).all() and (sizes[32:] <= 64).all() and sizes.sum() == circ.n_dev
+    # fewer regions than units: nothing to cut
+    c.set_plan_units(48)
+    assert c.region_plan(256)["n_regions"] == 40
