@@ -30,7 +30,8 @@ KERNEL_OF = {"persistent": "k_persistent_* (one launch per step)",
              "region": "k_region (one launch per step)",
              "per_kernel": "k_colour_phase x colours + k_hub",
              "buffered": "k_eval_buffer + k_persistent_stamp",
-             "atomic": "k_fill_zero + k_atomic"}
+             "atomic": "k_fill_zero + k_atomic",
+             "serial": "k_fill_zero + k_eval_buffer + k_serial_stamp (one lane)"}
 PEAK_HBM = 8.0e12
 AG0 = 1e12
 
@@ -302,10 +303,19 @@ def bench_adjoint(torch, CS, G, dev):
     ms_f, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "region"), 50, 5)
     ms_a, _ = time_graph(torch, lambda: c.vjp(x, AG0, Ab, bb), 50, 5)
     log(f"  adjoint chain10k: forward {ms_f * 1e3:.1f} us, adjoint {ms_a * 1e3:.1f} us, ratio {ms_a / ms_f:.2f}")
+    # the paper's four evaluation-kernel variants on the same step: serial stamping
+    # after a parallel evaluation (loadomp), buffered evaluation then colour phases
+    # (Color), and the fused coloured schedule (ColorFused: region)
+    ms_b, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "buffered"), 20, 3)
+    ms_s, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "serial"), 3, 1)
+    c.check()
+    log(f"  chain10k: serial stamp (loadomp) {ms_s * 1e3:.1f} us, buffered (Color) {ms_b * 1e3:.1f} us, "
+        f"region {ms_f * 1e3:.1f} us")
     return dict(workload="inverter_chain_10k_stages", n_dev=circ.n_dev,
                 forward_ms=round(ms_f, 5), adjoint_ms=round(ms_a, 5),
                 adjoint_over_forward=round(ms_a / ms_f, 3),
-                forward_plus_adjoint_value=round(circ.n_dev / (ms_f + ms_a) / 1e3, 2))
+                forward_plus_adjoint_value=round(circ.n_dev / (ms_f + ms_a) / 1e3, 2),
+                variants_ms=dict(serial_stamp=round(ms_s, 5), buffered=round(ms_b, 5), region=round(ms_f, 5)))
 
 
 def main():

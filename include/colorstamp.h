@@ -53,21 +53,29 @@ typedef enum {
 typedef enum {
     CS_COLOR_PERSISTENT = 0,  /* ColorFused: one persistent kernel; colours in sequence,
                                  grid-wide barrier between colours; plain stores and
-                                 load-adds only */
+                                 load-adds only.  When every region of the region
+                                 schedule fits on the GPU at once, the same launch runs
+                                 that schedule with a grid-wide barrier between levels
+                                 of shared entries instead (same bits). */
     CS_COLOR_PER_KERNEL = 1,  /* ColorFused with one kernel launch per colour (the
                                  per-colour parallel-for of the paper's OpenMP form) */
     CS_ATOMIC = 2,            /* comparison: no colouring, FP64 atomic adds (the
                                  paper's lock-based foil, Introduction) */
     CS_COLOR_BUFFERED = 3,    /* Color: evaluate every device into a buffer, then
                                  stamp colour by colour from the buffer */
-    CS_COLOR_REGION = 4       /* ColorFused at workgroup scope: devices are cut (in
-                                 index order) into regions of one workgroup; a
-                                 region's own entries accumulate in LDS colour phase
-                                 by colour phase (consecutive colours that share no
-                                 entry merged into one phase), entries written from
-                                 several regions are staged and folded in colour
-                                 order by the last contributing region.  Same bits as
-                                 CS_COLOR_PERSISTENT; no grid-wide barrier. */
+    CS_COLOR_REGION = 4,      /* ColorFused at workgroup scope: devices are cut (in
+                                 index order) into regions of one workgroup; an entry
+                                 written by one or two devices of a region accumulates
+                                 in LDS in phases, one written by more devices of a
+                                 region is folded by one lane in colour order, and
+                                 entries written from several regions are staged and
+                                 folded in colour order by the last contributing
+                                 region.  Same bits as CS_COLOR_PERSISTENT; no
+                                 grid-wide barrier. */
+    CS_SERIAL_STAMP = 5       /* loadomp: evaluate every device into a buffer in
+                                 parallel, then one lane adds every device's values in
+                                 ascending device index onto zeroed A and b (the serial
+                                 order of accumulation, hub entries included). */
 } cs_variant;
 
 /* Model card of the BSIM4-core subset (SI units).  One card per polarity. */

@@ -77,6 +77,7 @@ cs_status upload_circuit(cs_circuit *c) {
     CS_CHECK_HIP(c->d_code.upload(h.code), "upload stamp codes");
     CS_CHECK_HIP(c->d_acode.upload(h.acode), "upload atomic codes");
     CS_CHECK_HIP(c->d_perm.upload(h.perm), "upload permutation");
+    c->d_ipos.release();   // rebuilt from the new positions at the next serial stamp
     CS_CHECK_HIP(c->d_cptr.upload(h.colour_ptr), "upload colour pointers");
     CS_CHECK_HIP(c->d_fixA_idx.upload(h.fixA_idx), "upload fixed stores");
     CS_CHECK_HIP(c->d_fixA_val.upload(h.fixA_val), "upload fixed stores");
@@ -516,6 +517,18 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
         case CS_ATOMIC:
             CS_CHECK_HIP(launch_atomic(kc, call, c->h.nnz, c->h.n_rows, s), "atomic launch");
             return CS_OK;
+        case CS_SERIAL_STAMP: {
+            const HostCircuit &h = c->h;
+            if (c->d_buf.n < (size_t)NCODE * h.n_dev)
+                CS_CHECK_HIP(c->d_buf.alloc((size_t)NCODE * h.n_dev), "alloc buffer");
+            if (c->d_ipos.n != (size_t)h.n_dev) {
+                std::vector<int32_t> ipos((size_t)h.n_dev);
+                for (int32_t p = 0; p < h.n_dev; ++p) ipos[(size_t)h.perm[(size_t)p]] = p;
+                CS_CHECK_HIP(c->d_ipos.upload(ipos), "upload positions");
+            }
+            CS_CHECK_HIP(launch_serial(kc, call, h.nnz, h.n_rows, c->d_buf.p, c->d_ipos.p, s), "serial launch");
+            return CS_OK;
+        }
         case CS_COLOR_REGION: {
             cs_status st = ensure_region(c, s);
             if (st != CS_OK) return st;

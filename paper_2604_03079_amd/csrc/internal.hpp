@@ -153,6 +153,7 @@ struct cs_circuit {
         d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk;
     cs::DevBuf<int8_t> d_pol;
     cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_buf, d_hub_part;
+    cs::DevBuf<int32_t> d_ipos;   // device index -> position (serial stamping)
     cs::DevBuf<uint32_t> d_sync;       // barrier words + per-block arrival flags + error
     cs::DevBuf<uint32_t> d_hub_count;
     int32_t block = 256;

@@ -465,6 +465,26 @@ __global__ void __launch_bounds__(256) k_eval_buffer(KCirc kc, KCall call, doubl
     }
 }
 
+// Serial stamping after the buffered evaluation (the paper's loadomp form): one lane
+// adds every device's merged values, devices in ascending index, onto the zeroed A
+// and b, i.e. the serial order of accumulation.  The fixed stores touch other
+// entries and are made by the whole wave first.
+__global__ void __launch_bounds__(64) k_serial_stamp(KCirc kc, KCall call, const double *buf,
+                                                     const int32_t *ipos) {
+    fixed_stores(kc, call, threadIdx.x, blockDim.x);
+    if (threadIdx.x != 0) return;
+    for (int32_t v = 0; v < kc.n; ++v) {
+        const int32_t p = ipos[v];
+        const DevIn d = load_terms(kc, p);
+        const int k = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) + (d.t2 != 0 && d.t2 != d.t0 && d.t2 != d.t1) +
+                      (d.t3 != 0 && d.t3 != d.t0 && d.t3 != d.t1 && d.t3 != d.t2);
+        for (int j = 0; j < k * k + k; ++j) {
+            double *dst = (j < k * k ? call.A : call.b) + kc.acode[(size_t)j * kc.n + p];
+            *dst = *dst + buf[(size_t)j * kc.n + p];
+        }
+    }
+}
+
 __global__ void k_fill_zero(double *A, int64_t nA, double *b, int64_t nb) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nA + nb;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -957,6 +977,18 @@ hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *sr
                                  double *dst, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_permute_params, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, src, n_src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_serial(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows, double *buf,
+                         const int32_t *ipos, hipStream_t s) {
+    const int64_t tot = nnz + n_rows;
+    const int gz = (int)std::min<int64_t>((tot + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_zero, dim3(std::max(gz, 1)), dim3(256), 0, s, call.A, nnz, call.b, n_rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_eval_buffer(kc, call, buf, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_serial_stamp, dim3(1), dim3(64), 0, s, kc, call, buf, ipos);
     return hipGetLastError();
 }
 

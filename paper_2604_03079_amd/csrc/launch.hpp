@@ -39,6 +39,8 @@ hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion 
 // dst[j][p] = src[j][idx[p]] for the three parameter rows.
 hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
                                  double *dst, hipStream_t s);
+hipError_t launch_serial(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows, double *buf,
+                         const int32_t *ipos, hipStream_t s);
 hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,
                          hipStream_t s);
 

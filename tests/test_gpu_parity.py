@@ -111,6 +111,19 @@ def test_atomic_within_reordering_bound(torch_dev, orc, name, circ):
     assert np.all(np.abs(b - bs) <= 1e-12 * mb)
 
 
+@pytest.mark.parametrize("name,circ", SMALL[:9], ids=[s[0] for s in SMALL[:9]])
+def test_serial_stamp_equals_serial_order(torch_dev, orc, name, circ):
+    # buffered evaluation, then one lane adds the devices in ascending index onto
+    # zeroed A and b: bitwise the oracle's serial accumulation (hubs included)
+    rp, ci = orc.pattern(circ)
+    As, bs = orc.assemble(circ, rp, ci, NC, PC, 1e12)
+    for exclude in (True, False):
+        say(f"case {name} exclude={exclude} variant=serial")
+        A, b, _ = gpu_stamp(torch_dev, circ, exclude, "serial")
+        assert_bit_exact(A, As, f"{name}/serial/A")
+        assert_bit_exact(b, bs, f"{name}/serial/b")
+
+
 def test_history_and_dc(torch_dev, orc):
     circ = G.workload(0)
     rng = np.random.default_rng(3)
@@ -128,7 +141,7 @@ def test_empty_circuit(torch_dev, orc):
     circ = G.Circuit("empty", 3, np.zeros((0, 4), np.int32), np.zeros(0, np.int8),
                      np.array([[1, 0]], np.int32), np.array([1.1]), np.array([0, 1, 0], np.uint8), 1.1,
                      np.zeros(0), np.zeros(0), np.zeros(0), np.array([1.1, 0.3, 0.0]))
-    for variant in ("persistent", "per_kernel", "atomic", "buffered", "region"):
+    for variant in ("persistent", "per_kernel", "atomic", "buffered", "region", "serial"):
         say(f"case empty variant={variant}")
         A, b, _ = gpu_stamp(torch_dev, circ, True, variant)
         # rows: vdd, node 2, branch; entries: (vdd,vdd), (vdd,br), (2,2), (br,vdd)
