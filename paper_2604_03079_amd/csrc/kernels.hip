@@ -1,6 +1,8 @@
-// HIP kernels for gfx950: coloured fused evaluate-and-stamp (persistent, with
-// grid-wide barriers between colours), one-kernel-per-colour, buffered-colour and
-// atomic variants, the hub reduction, and the adjoint (VJP) kernel.
+// HIP kernels for gfx950: the region schedule of the coloured fused
+// evaluate-and-stamp (one workgroup per region, and its grid-barrier form), the
+// persistent colour-phase kernel, one-kernel-per-colour, buffered-colour,
+// serial-stamp and atomic variants, and the hub reduction.  The adjoint kernel is in
+// adjoint.hip.
 //
 // Paper, Methodology: colours are processed sequentially; within a colour every
 // device is evaluated and stamped in parallel, no two of them touching the same
@@ -327,12 +329,9 @@ __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
     hub_chunks(kc, call, 0, kc.n_hub_chunks, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
 }
 
-// Persistent coloured kernel.  MODE 0: evaluate inside each colour phase (grid-
-// stride).  MODE 1: every thread evaluates its own device before the first phase
-// and keeps the local values in registers (requires grid*block >= n).  MODE 2:
-// stamp phases only, merged values read from the buffer of k_eval_buffer.
-// Circuits stamped inside one workgroup: colour phases separated by workgroup
-// barriers, then the circuit's own hub chunks.
+// Circuits stamped inside one workgroup (batches): colour phases separated by
+// workgroup barriers, each device evaluated in its phase, then the circuit's own
+// hub chunks.
 __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &call, const KLocal &kl, int first,
                                int stride, double *lds) {
     for (int li = first; li < kl.n; li += stride) {
@@ -509,12 +508,14 @@ __global__ void __launch_bounds__(256) k_atomic(KCirc kc, KCall call) {
 
 // ---- region schedule ------------------------------------------------------------
 // One workgroup per region.  The region's devices are evaluated at once (NMOS lanes
-// first, then PMOS lanes), entries owned by the region accumulate in
-// LDS phase by phase (first writer stores, later writers add, a workgroup barrier
-// between phases), contributions to entries shared with other regions and to hub
-// entries are staged in global memory, and every shared entry or hub chunk is
-// folded by the last region that contributes to it (an arrival counter).  No wave
-// ever waits for another workgroup.
+// first, then PMOS lanes) and their merged values parked in LDS rows.  An entry
+// written by one or two devices of the region accumulates in an LDS slot phase by
+// phase (a workgroup barrier between phases); an entry written by more devices of
+// the region is folded by one lane from the parked values in colour order;
+// contributions to entries shared with other regions and to hub entries are staged
+// in global memory, and every shared entry or hub chunk is folded by the last region
+// that contributes to it (an arrival counter), large shared entries by a follow-up
+// kernel.  No wave ever waits for another workgroup.
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
 // (lgkmcnt 0), not for its global stores, which a full __syncthreads would drain.
@@ -533,7 +534,8 @@ __device__ __forceinline__ void store_target(const KCall &call, uint32_t tgt, do
 }
 
 // Left fold of cnt staged values by one wave (all lanes call it): up to HUB_K values
-// at a time go through the wave's LDS slice, lane 0 folds; the sum is broadcast.
+// at a time go through the wave's LDS slice, lane 0 folds while the other lanes'
+// loads of the next HUB_K values are in flight; the sum is broadcast.
 __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *mine) {
     const int lane = threadIdx.x & 63;
     constexpr int R = HUB_K / 64;
