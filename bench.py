@@ -237,6 +237,33 @@ def bench_batch(torch, CS, G, dev):
                 speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2))
 
 
+def bench_adder(torch, CS, G, dev):
+    """The paper's benchmark shape: a 64-bit ripple-carry adder of 28-transistor
+    mirror cells (1,792 FETs), under the paper's conflict rule (896 colours, Table I)
+    and with the rail excluded; every variant, one NR step each."""
+    circ = G.adder_case(64, seed=9)
+    W, L, V, x = device_tensors(torch, circ, dev)
+    out = dict(n_dev=circ.n_dev)
+    for excl in (False, True):
+        row = {}
+        for variant in ("region", "persistent", "per_kernel", "buffered", "atomic", "serial"):
+            c = CS.prepare(circ, exclude=excl)
+            c.set_params(W, L, V)
+            A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+            b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+            steps = 3 if variant == "serial" else 20
+            ms, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, 2)
+            c.check()
+            row[variant] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2))
+            row["n_colors"] = c.info()["n_colors"]
+        key = "rails_excluded" if excl else "paper_rule"
+        out[key] = row
+        log(f"  adder 64x28T {key:14s} C {row['n_colors']:4d}: " +
+            ", ".join(f"{v} {row[v]['ms_per_step'] * 1e3:.1f} us" for v in
+                      ("region", "persistent", "per_kernel", "buffered", "atomic", "serial")))
+    return out
+
+
 SWEEP_GROUPS = (1, 2, 4, 8, 16, 32, 64, 128, 256)
 SWEEP_SIZES = (200_000, 2_000)
 SWEEP_MAX_PHASES = 5000   # per-colour and phase-only persistent runs above this are not timed
@@ -460,6 +487,7 @@ def main():
             ex[variant] = dict(ms_per_step=round(msv, 4), value=round(sram.n_dev / msv / 1e3, 2))
             log(f"  sram {variant:12s} {msv:8.3f} ms/step {sram.n_dev / msv / 1e3:9.1f} M devices/s")
         extras["sram_256x256"] = dict(n_dev=sram.n_dev, n_colors=c.info()["n_colors"], **ex)
+        extras["adder_64bit_28T"] = bench_adder(torch, CS, G, dev)
         extras["batch_512"] = bench_batch(torch, CS, G, dev)
         extras["adjoint"] = bench_adjoint(torch, CS, G, dev)
         result["extras"] = extras

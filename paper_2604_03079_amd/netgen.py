@@ -226,6 +226,45 @@ def opamp2(n_fet: int, vdd: float = 1.0) -> Circuit:
     return _finish(f"opamp{n_fet}", n_nodes, devs, vdd)
 
 
+def ripple_adder28(n_bits: int, vdd: float = 1.0) -> Circuit:
+    """Ripple-carry adder of ``n_bits`` 28-transistor mirror full adders (14 PMOS, 14
+    NMOS per bit), the cell shape of the paper's 64-bit adder benchmark (Fig.
+    "schematic", Table I: 1,792 FETs for 64 bits).  Nodes: 0 gnd, 1 vdd, 2 c0, then per
+    bit i sixteen nodes: a, b, cob, x1, x2, y1, y2, sb, x3, x4, x5, y3, y4, y5, s, co
+    (co is the next bit's carry in c).  Per bit, the pull-up devices first:
+      P(y1,a,vdd) P(cob,b,y1) P(y2,a,vdd) P(y2,b,vdd) P(cob,c,y2)       carry mirror
+      P(y3,a,vdd) P(y4,b,y3) P(sb,c,y4) P(y5,a,vdd) P(y5,b,vdd) P(y5,c,vdd) P(sb,cob,y5)
+      P(s,sb,vdd) P(co,cob,vdd)                                          inverters
+    then the pull-down devices:
+      N(cob,a,x1) N(x1,b,gnd) N(cob,c,x2) N(x2,a,gnd) N(x2,b,gnd)        cob = not(ab + c(a+b))
+      N(sb,a,x3) N(x3,b,x4) N(x4,c,gnd) N(sb,cob,x5) N(x5,a,gnd) N(x5,b,gnd) N(x5,c,gnd)
+                                                            sb = not(abc + cob(a+b+c))
+      N(s,sb,gnd) N(co,cob,gnd)                                          s, co
+    Bodies: NMOS on ground, PMOS on vdd.  With this listing the greedy colouring under
+    the paper's rule (only ground excluded) needs exactly one colour per PMOS, 14 per
+    bit (every PMOS body is on vdd), the 896 of Table I for 64 bits."""
+    devs = []
+    c = 2
+    for i in range(n_bits):
+        base = 3 + 16 * i
+        a, b, cob, x1, x2, y1, y2, sb, x3, x4, x5, y3, y4, y5, sn, co = range(base, base + 16)
+        N = lambda d, g, s_: devs.append(((d, g, s_, 0), NMOS))
+        P = lambda d, g, s_: devs.append(((d, g, s_, 1), PMOS))
+        P(y1, a, 1); P(cob, b, y1); P(y2, a, 1); P(y2, b, 1); P(cob, c, y2)
+        P(y3, a, 1); P(y4, b, y3); P(sb, c, y4); P(y5, a, 1); P(y5, b, 1); P(y5, c, 1); P(sb, cob, y5)
+        P(sn, sb, 1); P(co, cob, 1)
+        N(cob, a, x1); N(x1, b, 0); N(cob, c, x2); N(x2, a, 0); N(x2, b, 0)
+        N(sb, a, x3); N(x3, b, x4); N(x4, c, 0); N(sb, cob, x5); N(x5, a, 0); N(x5, b, 0); N(x5, c, 0)
+        N(sn, sb, 0); N(co, cob, 0)
+        c = co
+    return _finish(f"adder{n_bits}x28", 3 + 16 * n_bits, devs, vdd)
+
+
+def adder_case(n_bits: int, seed: int) -> Circuit:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return draw_params(ripple_adder28(n_bits), rng, W_CHAIN, L_CHAIN)
+
+
 def no_shared_nets(n_dev: int, vdd: float = 1.0) -> Circuit:
     """Devices whose terminals all sit on private nodes or ground (every net split,
     as by the series-resistor transform of Benchmark 2): the conflict graph is empty."""

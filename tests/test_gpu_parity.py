@@ -78,6 +78,7 @@ def small_cases():
         ("pchain50x6", G.draw_params(G.parallel_chain(50, 6), rng, G.W_CHAIN, G.L_CHAIN)),
         ("pchain40x33", G.draw_params(G.parallel_chain(40, 33), rng, G.W_CHAIN, G.L_CHAIN)),
         ("private700", G.draw_params(G.no_shared_nets(700), rng, G.W_CHAIN, G.L_CHAIN)),
+        ("adder64x28", G.draw_params(G.ripple_adder28(64), rng, G.W_CHAIN, G.L_CHAIN)),
     ]
     for k in range(8, 15):
         out.append((f"opamp{k}", G.draw_params(G.opamp2(k, 0.9), rng, G.W_OPAMP, G.L_OPAMP)))

@@ -32,6 +32,7 @@ CASES = [
     ("pchain9x4", lambda: G.parallel_chain(9, 4)),
     ("private13", lambda: G.no_shared_nets(13)),
     ("chain1", lambda: G.inverter_chain(1)),
+    ("adder3x28", lambda: G.ripple_adder28(3)),
 ]
 
 

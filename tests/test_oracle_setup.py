@@ -118,6 +118,20 @@ def test_parallel_chain_colours(orc, g):
     assert C == 4 * g
 
 
+def test_adder_colours_match_table1(orc):
+    # 64 mirror full adders of 28 transistors: the FET count and the colour count of
+    # the paper's unmodified adder under its conflict rule (only ground excluded);
+    # every PMOS body sits on vdd, so the 896 PMOS form a clique and 896 is optimal
+    gold = json.load(open(os.path.join(GOLD, "adder64_table1.json")))
+    circ = G.ripple_adder28(64)
+    assert circ.n_dev == gold["fets"] and int((circ.pol < 0).sum()) == gold["colours"]
+    col, C, _ = orc.colour(circ, False)
+    assert C == gold["colours"]
+    # with the rail excluded the cells' own nets decide: a handful of colours
+    _, Cx, _ = orc.colour(circ, True)
+    assert 8 <= Cx < 16
+
+
 def test_chain1_pattern_matches_hand_derivation(orc):
     gold = json.load(open(os.path.join(GOLD, "chain1_pattern.json")))
     rp, ci = orc.pattern(G.inverter_chain(1))
