@@ -239,12 +239,14 @@ def bench_batch(torch, CS, G, dev):
 
 def bench_adder(torch, CS, G, dev):
     """The paper's benchmark shape: a 64-bit ripple-carry adder of 28-transistor
-    mirror cells (1,792 FETs), under the paper's conflict rule (896 colours, Table I)
-    and with the rail excluded; every variant, one NR step each."""
-    circ = G.adder_case(64, seed=9)
-    W, L, V, x = device_tensors(torch, circ, dev)
-    out = dict(n_dev=circ.n_dev)
-    for excl in (False, True):
+    mirror cells (1,792 FETs), under the paper's conflict rule (896 colours, Table I),
+    with the rail excluded, and with every net split by series resistors (Table I's
+    R89 row: one colour); every variant, one NR step each."""
+    out = dict(n_dev=1792)
+    for key, split, excl in (("paper_rule", None, False), ("rails_excluded", None, True),
+                             ("r89_split_paper_rule", "all", False)):
+        circ = G.adder_case(64, seed=9, split=split)
+        W, L, V, x = device_tensors(torch, circ, dev)
         row = {}
         for variant in ("region", "persistent", "per_kernel", "buffered", "atomic", "serial"):
             c = CS.prepare(circ, exclude=excl)
@@ -256,9 +258,8 @@ def bench_adder(torch, CS, G, dev):
             c.check()
             row[variant] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2))
             row["n_colors"] = c.info()["n_colors"]
-        key = "rails_excluded" if excl else "paper_rule"
         out[key] = row
-        log(f"  adder 64x28T {key:14s} C {row['n_colors']:4d}: " +
+        log(f"  adder 64x28T {key:20s} C {row['n_colors']:4d}: " +
             ", ".join(f"{v} {row[v]['ms_per_step'] * 1e3:.1f} us" for v in
                       ("region", "persistent", "per_kernel", "buffered", "atomic", "serial")))
     return out

@@ -209,7 +209,7 @@ cs_status plan_regions(cs_circuit *c, int32_t block) {
         RegionSource src = region_source(c->h);
         src.cus = cus;
         Err e = build_regions(src, block, c->rp);
-        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, c->rp.max_nc, block) > 65536 - 1024)
+        if (e.st == CS_OK && region_lds_bytes(c->rp.max_lds + 1, c->rp.max_nc, block) > (size_t)REGION_LDS_LIMIT)
             e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
         if (e.st != CS_OK) {
             c->rp = RegionPlan{};

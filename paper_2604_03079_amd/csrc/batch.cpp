@@ -304,7 +304,7 @@ cs_status plan_regions(cs_batch *B, int32_t block) {
         src.hub_cptr = P.hub_cptr;
         src.stage_base = B->stage_total;
         Err e = build_regions(src, block, B->rp);
-        if (e.st == CS_OK && region_lds_bytes(B->rp.max_lds + 1, B->rp.max_nc, block) > 65536 - 1024)
+        if (e.st == CS_OK && region_lds_bytes(B->rp.max_lds + 1, B->rp.max_nc, block) > (size_t)REGION_LDS_LIMIT)
             e = {CS_ENOTSUP, "region LDS exceeds 64 KiB; use a smaller block"};
         if (e.st != CS_OK) {
             B->rp = RegionPlan{};

@@ -37,6 +37,8 @@ constexpr int ITEM_LANE_MAX = 8;
 // region folds the writers' merged values, read from LDS in colour order, and
 // stores the result.
 constexpr int LDS_WRITERS_MAX = 2;
+// LDS a region workgroup may use (bytes): owned-entry slots plus merged-value rows.
+constexpr int64_t REGION_LDS_LIMIT = 65536 - 1024;
 // Staged slots in the grid-barrier form of the region schedule: a shared entry's
 // first writer (colour order) stores, the others load-add; hub slots are staged.
 constexpr uint8_t SLOT_STORE = 0;

@@ -14,7 +14,9 @@
 //     phases serve any number of colours;
 //   * an entry whose writers all lie in one region and are more is a lane fold: one
 //     lane folds the writers' merged values, read from LDS in colour order, and
-//     stores the result (no phase per writer);
+//     stores the result (no phase per writer); so are single-writer entries of a
+//     region whose LDS slots would not fit the workgroup's LDS (one lane stores the
+//     writer's value);
 //   * an entry written from several regions has its contributions staged, in colour
 //     order, in a global array; the last of its regions to finish (a counter) folds
 //     them left and stores the result, or, for entries with more than ITEM_LANE_MAX
@@ -229,6 +231,31 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             R.item.insert(R.item.end(), {beg, cnt, (int32_t)((ITEM_HUB << 30) | (uint32_t)q), (int32_t)(b - a)});
             for (size_t e = a; e < b; ++e) rit[(size_t)qr[e].second].push_back(it);
             a = b;
+        }
+    }
+
+    // 3b. LDS budget: a region whose owned entries would not fit the workgroup's LDS
+    // next to the merged-value rows hands single-writer entries to lane folds
+    {
+        const int64_t rows = std::max<int64_t>((int64_t)R.max_nc * cap, (int64_t)(cap / 64) * HUB_K);
+        const int64_t budget = REGION_LDS_LIMIT / 8 - rows - 2;
+        for (int32_t g = 0; g < R.n_regions; ++g) {
+            auto &v = interior[(size_t)g];
+            int64_t excess = (int64_t)v.size() - budget;
+            if (excess <= 0) continue;
+            std::vector<int64_t> keep;
+            for (int64_t t : v) {
+                const int64_t w0 = kptr[(size_t)t];
+                if (excess > 0 && kptr[(size_t)t + 1] - w0 == 1) {
+                    lfold[(size_t)g].push_back(t);
+                    is_interior[(size_t)t] = 0;
+                    code[(size_t)(wr[(size_t)w0] & 31) * n + (size_t)(wr[(size_t)w0] >> 5)] = (int32_t)(3u << 30);
+                    --excess;
+                } else {
+                    keep.push_back(t);
+                }
+            }
+            v.swap(keep);
         }
     }
 

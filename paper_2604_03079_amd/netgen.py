@@ -260,9 +260,46 @@ def ripple_adder28(n_bits: int, vdd: float = 1.0) -> Circuit:
     return _finish(f"adder{n_bits}x28", 3 + 16 * n_bits, devs, vdd)
 
 
-def adder_case(n_bits: int, seed: int) -> Circuit:
+def split_nets(circ: Circuit, rule: str) -> tuple[Circuit, int]:
+    """Series-resistor net splitting (Table I's R rows): chosen terminal connections
+    of each FET move to a private node, which a series resistor would tie back to the
+    original net.  Returns the FET netlist (private nodes appended after the original
+    ones, in device then terminal order) and the number of resistors.  The resistors
+    are linear elements outside the FET evaluate-and-stamp path; the FET conflict graph
+    only sees that the FETs no longer share those nets.
+      rule "all":  every non-ground terminal connection (no two FETs share a node)
+      rule "rail": the vdd connections of each FET (its vdd-tied terminals share one
+                   private node per FET)"""
+    term = circ.term.copy()
+    n_nodes = circ.n_nodes
+    n_res = 0
+    for k in range(circ.n_dev):
+        if rule == "all":
+            for t in range(4):
+                if term[k, t] != 0:
+                    term[k, t] = n_nodes
+                    n_nodes += 1
+                    n_res += 1
+        elif rule == "rail":
+            on = [t for t in range(4) if circ.term[k, t] == 1]
+            if on:
+                term[k, on] = n_nodes
+                n_nodes += 1
+                n_res += 1
+        else:
+            raise ValueError(rule)
+    excl = np.zeros(n_nodes, dtype=np.uint8)
+    excl[:circ.n_nodes] = circ.exclude
+    return Circuit(f"{circ.name}_{rule}", n_nodes, term, circ.pol.copy(), circ.vsrc.copy(),
+                   circ.vsrc_volts.copy(), excl, circ.vdd), n_res
+
+
+def adder_case(n_bits: int, seed: int, split: str | None = None) -> Circuit:
     rng = np.random.Generator(np.random.PCG64(seed))
-    return draw_params(ripple_adder28(n_bits), rng, W_CHAIN, L_CHAIN)
+    c = ripple_adder28(n_bits)
+    if split:
+        c, _ = split_nets(c, split)
+    return draw_params(c, rng, W_CHAIN, L_CHAIN)
 
 
 def no_shared_nets(n_dev: int, vdd: float = 1.0) -> Circuit:

@@ -79,6 +79,8 @@ def small_cases():
         ("pchain40x33", G.draw_params(G.parallel_chain(40, 33), rng, G.W_CHAIN, G.L_CHAIN)),
         ("private700", G.draw_params(G.no_shared_nets(700), rng, G.W_CHAIN, G.L_CHAIN)),
         ("adder64x28", G.draw_params(G.ripple_adder28(64), rng, G.W_CHAIN, G.L_CHAIN)),
+        # every net split (one colour; PMOS with four distinct nodes: 20 codes)
+        ("adder8r89", G.draw_params(G.split_nets(G.ripple_adder28(8), "all")[0], rng, G.W_CHAIN, G.L_CHAIN)),
     ]
     for k in range(8, 15):
         out.append((f"opamp{k}", G.draw_params(G.opamp2(k, 0.9), rng, G.W_OPAMP, G.L_OPAMP)))

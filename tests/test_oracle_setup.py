@@ -130,6 +130,17 @@ def test_adder_colours_match_table1(orc):
     # with the rail excluded the cells' own nets decide: a handful of colours
     _, Cx, _ = orc.colour(circ, True)
     assert 8 <= Cx < 16
+    # R89: a series resistor on every non-ground terminal connection (89 per cell)
+    # leaves no shared node, one colour
+    r89, n_res = G.split_nets(circ, "all")
+    _, C89, E89 = orc.colour(r89, False)
+    assert n_res == gold["r89_series_resistors"] and C89 == gold["r89_colours"] and E89 == 0
+    # one resistor per FET on its vdd connections: Table I's R14 resistor count; the
+    # colour count then is the rail-excluded one (the paper's 64 keeps some shared net
+    # that this placement splits)
+    r14, n14 = G.split_nets(circ, "rail")
+    assert n14 == gold["r14_series_resistors"]
+    assert orc.colour(r14, False)[1] == Cx
 
 
 def test_chain1_pattern_matches_hand_derivation(orc):

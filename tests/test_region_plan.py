@@ -67,7 +67,7 @@ def replay(plan, vals, pol, block, nnz, n_rows):
         folded = set()
         for i in range(fb, fe):
             _, sb, cnt = (int(v) for v in plan["fold"][i])
-            assert cnt > 2
+            assert cnt == 1 or cnt > 2
             for src in plan["fold_src"][sb:sb + cnt]:
                 j, lane = int(src) >> 16, int(src) & 0xFFFF
                 assert lane < nN + nP and (j, lane) not in folded
