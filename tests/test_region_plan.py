@@ -165,6 +165,10 @@ CASES = [
     ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)),
     ("pchain7x3", lambda: G.draw_params(G.parallel_chain(7, 3), np.random.default_rng(5), G.W_CHAIN, G.L_CHAIN)),
     ("pchain9x20", lambda: G.draw_params(G.parallel_chain(9, 20), np.random.default_rng(6), G.W_CHAIN, G.L_CHAIN)),
+    # every net split: almost only single-writer entries, more than one region's LDS
+    # holds at 256 devices (one-source lane folds)
+    ("adder8r89", lambda: G.draw_params(G.split_nets(G.ripple_adder28(8), "all")[0], np.random.default_rng(7),
+                                        G.W_CHAIN, G.L_CHAIN)),
 ]
 
 
@@ -288,3 +292,15 @@ def test_last_round_cut_into_one_wave_regions(orc):
     # fewer regions than units: nothing to cut
     c.set_plan_units(48)
     assert c.region_plan(256)["n_regions"] == 40
+
+
+def test_lds_budget_moves_single_writer_entries_to_lane_folds(orc):
+    circ = G.draw_params(G.split_nets(G.ripple_adder28(8), "all")[0], np.random.default_rng(7),
+                         G.W_CHAIN, G.L_CHAIN)
+    c = CS.prepare(circ, True)
+    small = c.region_plan(128)
+    assert small["n_folds"] == 0
+    plan = c.region_plan(256)
+    assert plan["n_regions"] == 1 and plan["n_folds"] > 0 and (plan["fold"][:, 2] == 1).all()
+    # slots left in LDS: at most 64 KiB - 1 KiB with the 20 x 256 merged-value rows
+    assert plan["n_interior"] + 20 * 256 + 2 <= (65536 - 1024) // 8
