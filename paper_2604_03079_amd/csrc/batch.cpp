@@ -261,10 +261,14 @@ cs_status plan(cs_batch *B) {
     const int64_t local_dev = P.n_dev - n_sched;
     const int64_t cap_phase = (int64_t)per_cu_phase * prop.multiProcessorCount;
     const int64_t cap_ahead = (int64_t)per_cu_ahead * prop.multiProcessorCount;
+    // workgroups for the local circuits: each runs its colour phases at the latency
+    // of one small evaluation, so their count (not their share of devices) sets the
+    // time: at least an eighth of the resident workgroups, one per circuit at most
     int64_t n_lb = 0;
     if (B->n_local > 0) {
         n_lb = n_sched == 0 ? std::min<int64_t>(cap_phase, B->n_local)
-                            : std::max<int64_t>(1, (int64_t)((double)cap_phase * (double)local_dev / (double)P.n_dev));
+                            : std::max<int64_t>({(int64_t)1, cap_phase / 8,
+                                                 (int64_t)((double)cap_phase * (double)local_dev / (double)P.n_dev)});
         n_lb = std::min<int64_t>(n_lb, B->n_local);
     }
     const int64_t need_ahead = (n_sched + block - 1) / block;
