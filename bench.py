@@ -226,6 +226,12 @@ def bench_batch(torch, CS, G, dev):
     best = autotune.tune(B, W, L, V, x, AG0, A, b, cache_path=None, reps=5, log=log)
     ms_b, _ = time_graph(torch, lambda: B.eval_stamp(x, AG0, None, A, b), 20, 3)
     B.check()
+    # adjoint of the batched step: cotangents N(0,1) on every circuit's A and b
+    Ab, bb = G.cotangents(B.nnz, B.n_rows, seed=50)
+    Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
+    ms_a, _ = time_graph(torch, lambda: B.vjp(x, AG0, Ab, bb), 20, 3)
+    B.check()
+    log(f"  batch 512: adjoint {ms_a:.3f} ms ({ms_a / ms_b:.2f} x the batched forward)")
     B.per_circuit_params(W, L, V)
     ms_p, _ = time_graph(torch, lambda: B.per_circuit_eval(x, AG0, A, b), 5, 1)
     log(f"  batch 512: batched {ms_b:.3f} ms ({B.n_dev / ms_b / 1e3:.1f} M dev/s), "
@@ -234,7 +240,8 @@ def bench_batch(torch, CS, G, dev):
                 max_colors=B.info()["max_colors"], tuned=best,
                 batched=dict(ms_per_step=round(ms_b, 4), value=round(B.n_dev / ms_b / 1e3, 2)),
                 per_circuit_launches=dict(ms_per_step=round(ms_p, 4), value=round(B.n_dev / ms_p / 1e3, 2)),
-                speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2))
+                speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2),
+                adjoint=dict(ms_per_step=round(ms_a, 4), adjoint_over_forward=round(ms_a / ms_b, 3)))
 
 
 def bench_adder(torch, CS, G, dev):
