@@ -57,6 +57,11 @@ void or_device_eval(const or_card *card, int pol, double W, double L, double VTH
 int or_colour(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint8_t *excl,
               int32_t *colour, int32_t *n_colours, int64_t *n_edges);
 
+/* Colouring in another vertex order: 0 ascending index (or_colour), 1 largest
+ * degree first, 2 DSATUR.  Same conventions as or_colour; quadratic time. */
+int or_colour_order(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint8_t *excl, int order,
+                    int32_t *colour, int32_t *n_colours, int64_t *n_edges);
+
 /* CSR pattern.  row_ptr has n_rows+1 entries; col_idx must hold at least
  * 16*n_dev + n_rows + 4*n_vsrc entries.  *nnz receives the count. */
 int or_pattern(int32_t n_nodes, int32_t n_dev, const int32_t *term, int32_t n_vsrc,

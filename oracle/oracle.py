@@ -49,6 +49,7 @@ def lib():
         _lib.or_count_ops.argtypes = [C.c_int]
         _lib.or_device_eval.argtypes = [p, C.c_int, d, d, d, p, d, p, p, p, p, p, p]
         _lib.or_colour.argtypes = [i32, i32, p, p, p, p, p]
+        _lib.or_colour_order.argtypes = [i32, i32, p, p, C.c_int, p, p, p]
         _lib.or_pattern.argtypes = [i32, i32, p, i32, p, p, p, p]
         _lib.or_stamp_map.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p]
         _lib.or_assemble.argtypes = [i32, i32, p, p, i32, p, p, p, p, p, p, p, p, p, p, p, p, d, p, p, p]
@@ -150,6 +151,23 @@ def colour(circ, exclude: bool):
                          C.byref(nc), C.byref(ne))
     if rc != 0:
         raise RuntimeError(f"or_colour failed: {rc}")
+    return col, int(nc.value), int(ne.value)
+
+
+ORDERS = {"natural": 0, "largest_first": 1, "dsatur": 2}
+
+
+def colour_order(circ, exclude: bool, order: str):
+    """Greedy colouring in another vertex order (largest first, DSATUR)."""
+    term = np.ascontiguousarray(circ.term, dtype=np.int32)
+    excl = np.ascontiguousarray(circ.exclude, dtype=np.uint8) if exclude else None
+    col = np.zeros(circ.n_dev, dtype=np.int32)
+    nc = C.c_int32(0)
+    ne = C.c_int64(0)
+    rc = lib().or_colour_order(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(excl), ORDERS[order], _ptr(col),
+                               C.byref(nc), C.byref(ne))
+    if rc != 0:
+        raise RuntimeError(f"or_colour_order failed: {rc}")
     return col, int(nc.value), int(ne.value)
 
 

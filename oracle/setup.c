@@ -197,3 +197,136 @@ int or_stamp_map(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint
     free(stores); free(minc); free(minr);
     return rc;
 }
+
+/* ---- colouring in other vertex orders (test infrastructure) -------------------
+ * Explicit conflict graph (adjacency lists, each neighbour once), then:
+ *   order 1, largest first (Welsh and Powell): vertices by decreasing degree, ties
+ *     by ascending index, each given the smallest colour not used by an already
+ *     coloured neighbour;
+ *   order 2, DSATUR (Brelaz): repeatedly the uncoloured vertex with the most
+ *     distinct colours among its neighbours, ties by larger degree, then smaller
+ *     index, given the smallest colour not used by its neighbours.
+ * Plain and quadratic: meant for the small graphs of the tests. */
+static int build_adjacency(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint8_t *excl,
+                           int64_t **adj_ptr, int32_t **adj) {
+    int64_t *cnt = calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    if (!cnt) return -1;
+    for (int32_t v = 0; v < n_dev; ++v) {
+        int32_t u[4]; int a[4];
+        int k = or_unique_nodes(term + 4 * (int64_t)v, u, a);
+        for (int j = 0; j < k; ++j) {
+            if (u[j] < 0 || u[j] >= n_nodes) { free(cnt); return -2; }
+            if (conflict_node(u[j], excl)) cnt[u[j] + 1]++;
+        }
+    }
+    for (int32_t n = 0; n < n_nodes; ++n) cnt[n + 1] += cnt[n];
+    int32_t *inc = malloc(sizeof(int32_t) * (size_t)(cnt[n_nodes] + 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
+    int32_t *mark = malloc(sizeof(int32_t) * ((size_t)n_dev + 1));
+    int64_t *ptr = calloc((size_t)n_dev + 1, sizeof(int64_t));
+    if (!inc || !fill || !mark || !ptr) { free(cnt); free(inc); free(fill); free(mark); free(ptr); return -1; }
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)(n_nodes + 1));
+    for (int32_t v = 0; v < n_dev; ++v) {
+        int32_t u[4]; int a[4];
+        int k = or_unique_nodes(term + 4 * (int64_t)v, u, a);
+        for (int j = 0; j < k; ++j)
+            if (conflict_node(u[j], excl)) inc[fill[u[j]]++] = v;
+    }
+    /* two passes over every device's incident nodes: count, then fill */
+    int32_t *list = NULL;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t v = 0; v <= n_dev; ++v) mark[v] = -1;
+        for (int32_t v = 0; v < n_dev; ++v) {
+            int32_t u[4]; int a[4];
+            int k = or_unique_nodes(term + 4 * (int64_t)v, u, a);
+            int64_t d = 0;
+            for (int j = 0; j < k; ++j) {
+                if (!conflict_node(u[j], excl)) continue;
+                for (int64_t e = cnt[u[j]]; e < cnt[u[j] + 1]; ++e) {
+                    int32_t w = inc[e];
+                    if (w == v || mark[w] == v) continue;
+                    mark[w] = v;
+                    if (pass == 1) list[ptr[v] + d] = w;
+                    ++d;
+                }
+            }
+            if (pass == 0) ptr[v + 1] = d;
+        }
+        if (pass == 0) {
+            for (int32_t v = 0; v < n_dev; ++v) ptr[v + 1] += ptr[v];
+            list = malloc(sizeof(int32_t) * (size_t)(ptr[n_dev] + 1));
+            if (!list) { free(cnt); free(inc); free(fill); free(mark); free(ptr); return -1; }
+        }
+    }
+    free(cnt); free(inc); free(fill); free(mark);
+    *adj_ptr = ptr;
+    *adj = list;
+    return 0;
+}
+
+/* smallest colour not used by a coloured neighbour of v (colour -1 = none yet) */
+static int32_t smallest_free(const int64_t *ptr, const int32_t *adj, const int32_t *colour, int32_t v,
+                             int32_t *stamp, int32_t tag) {
+    for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e)
+        if (colour[adj[e]] >= 0) stamp[colour[adj[e]]] = tag;
+    int32_t c = 0;
+    while (stamp[c] == tag) ++c;
+    return c;
+}
+
+int or_colour_order(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint8_t *excl, int order,
+                    int32_t *colour, int32_t *n_colours, int64_t *n_edges) {
+    if (order == 0) return or_colour(n_nodes, n_dev, term, excl, colour, n_colours, n_edges);
+    if (order != 1 && order != 2) return -3;
+    int64_t *ptr; int32_t *adj;
+    int rc = build_adjacency(n_nodes, n_dev, term, excl, &ptr, &adj);
+    if (rc) return rc;
+    int32_t *stamp = malloc(sizeof(int32_t) * ((size_t)n_dev + 1));
+    int32_t *sat = calloc((size_t)n_dev + 1, sizeof(int32_t));
+    int32_t *seq = malloc(sizeof(int32_t) * ((size_t)n_dev + 1));
+    if (!stamp || !sat || !seq) { free(ptr); free(adj); free(stamp); free(sat); free(seq); return -1; }
+    for (int32_t v = 0; v <= n_dev; ++v) stamp[v] = -1;
+    for (int32_t v = 0; v < n_dev; ++v) colour[v] = -1;
+    int32_t C = 0;
+    if (order == 1) {
+        /* insertion sort by (degree descending, index ascending): stable and plain */
+        for (int32_t i = 0; i < n_dev; ++i) {
+            int32_t v = i, j = i;
+            int64_t dv = ptr[v + 1] - ptr[v];
+            while (j > 0 && ptr[seq[j - 1] + 1] - ptr[seq[j - 1]] < dv) { seq[j] = seq[j - 1]; --j; }
+            seq[j] = v;
+        }
+        for (int32_t i = 0; i < n_dev; ++i) {
+            int32_t v = seq[i];
+            colour[v] = smallest_free(ptr, adj, colour, v, stamp, i);
+            if (colour[v] + 1 > C) C = colour[v] + 1;
+        }
+    } else {
+        for (int32_t step = 0; step < n_dev; ++step) {
+            int32_t best = -1;
+            for (int32_t v = 0; v < n_dev; ++v) {
+                if (colour[v] >= 0) continue;
+                if (best < 0 || sat[v] > sat[best] ||
+                    (sat[v] == sat[best] && ptr[v + 1] - ptr[v] > ptr[best + 1] - ptr[best]))
+                    best = v;
+            }
+            int32_t c = smallest_free(ptr, adj, colour, best, stamp, step);
+            colour[best] = c;
+            if (c + 1 > C) C = c + 1;
+            /* saturation: a neighbour gains one when c is new among its coloured
+             * neighbours (best is now one of them) */
+            for (int64_t e = ptr[best]; e < ptr[best + 1]; ++e) {
+                int32_t u = adj[e];
+                if (colour[u] >= 0) continue;
+                int seen = 0;
+                for (int64_t f = ptr[u]; f < ptr[u + 1]; ++f)
+                    if (adj[f] != best && colour[adj[f]] == c) { seen = 1; break; }
+                if (!seen) sat[u]++;
+            }
+        }
+    }
+    if (n_colours) *n_colours = C;
+    if (n_edges) *n_edges = ptr[n_dev] / 2;
+    free(ptr); free(adj); free(stamp); free(sat); free(seq);
+    return 0;
+}

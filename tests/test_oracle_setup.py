@@ -183,3 +183,82 @@ def test_stamp_map_flags(orc):
                         assert (sflag[v, j] == 2) == bool(hub)
                     assert brow[v, a] == nodes[a] - 1
                 assert np.all(slot[v, k * k:] == -1) and np.all(brow[v, k:] == -1)
+
+
+# ---- colouring in other vertex orders ---------------------------------------------
+
+def _cycle_netlist(order):
+    """FETs on a cycle of conflicts: device order[i] shares one node with order[i+1]
+    (the node of edge i), through its drain or gate; sources and bodies on ground."""
+    m = len(order)
+    term = np.zeros((m, 4), dtype=np.int32)
+    for i in range(m):
+        v, w = order[i], order[(i + 1) % m]
+        node = 2 + i                      # node of edge (v, w)
+        term[v, 1 if term[v, 0] else 0] = node
+        term[w, 1 if term[w, 0] else 0] = node
+    pol = np.ones(m, dtype=np.int8)
+    excl = np.zeros(2 + m, dtype=np.uint8)
+    excl[1] = 1
+    return G.Circuit("cycle", 2 + m, term, pol, np.array([[1, 0]], np.int32), np.array([1.0]), excl, 1.0)
+
+
+def _valid(circ, exclude, col):
+    ex = circ.exclude if exclude else np.zeros(circ.n_nodes, np.uint8)
+    nodes = [set(int(n) for n in t if n != 0 and not ex[n]) for t in circ.term]
+    for v in range(circ.n_dev):
+        for w in range(v):
+            if nodes[v] & nodes[w] and col[v] == col[w]:
+                return False
+    return True
+
+
+def test_dsatur_two_colours_a_six_cycle_natural_order_needs_three(orc):
+    # the cycle a1-b2-a3-b1-a2-b3 with devices listed a1, b1, a2, b2, a3, b3: the
+    # ascending-index greedy uses 3 colours, largest first too (all degrees 2, ties by
+    # index), DSATUR is exact on bipartite graphs: 2
+    circ = _cycle_netlist([0, 3, 4, 1, 2, 5])
+    for order, want in (("natural", 3), ("largest_first", 3), ("dsatur", 2)):
+        col, C, E = orc.colour_order(circ, True, order)
+        assert C == want and E == 6 and _valid(circ, True, col), order
+
+
+@pytest.mark.parametrize("m", [4, 8, 10, 16])
+def test_dsatur_exact_on_even_cycles(orc, m):
+    rng = np.random.default_rng(m)
+    circ = _cycle_netlist(list(rng.permutation(m)))
+    col, C, _ = orc.colour_order(circ, True, "dsatur")
+    assert C == 2 and _valid(circ, True, col)
+
+
+@pytest.mark.parametrize("make,exclude", [
+    (lambda: G.workload(0), True), (lambda: G.workload(0), False), (G.ota5t, True),
+    (lambda: G.sram6t(6, 5), True), (lambda: G.ripple_adder28(2), False), (lambda: G.parallel_chain(7, 3), True),
+    (lambda: G.ring_oscillator(11), True)])
+@pytest.mark.parametrize("order", ["largest_first", "dsatur"])
+def test_other_orders_give_valid_colourings_within_bounds(orc, make, exclude, order):
+    circ = make()
+    col, C, E = orc.colour_order(circ, exclude, order)
+    assert _valid(circ, exclude, col)
+    assert C == int(col.max()) + 1
+    # the edge count does not depend on the order
+    assert E == orc.colour(circ, exclude)[2]
+    ex = circ.exclude if exclude else np.zeros(circ.n_nodes, np.uint8)
+    nodes = [set(int(n) for n in t if n != 0 and not ex[n]) for t in circ.term]
+    deg = sorted((sum(1 for w in range(circ.n_dev) if w != v and nodes[v] & nodes[w])
+                  for v in range(circ.n_dev)), reverse=True)
+    assert C <= deg[0] + 1
+    if order == "largest_first":
+        # Welsh and Powell: the i-th vertex of the sequence (1-based) gets a colour
+        # below min(i, its degree + 1)
+        assert C <= max(min(i + 1, d + 1) for i, d in enumerate(deg))
+
+
+def test_other_orders_reach_the_clique_bounds(orc):
+    # the strict chain's 50 PMOS all sit on vdd (a 50-clique); a small SRAM's
+    # wordline gates 2 x columns access transistors (a clique of that size)
+    assert orc.colour_order(G.workload(0), False, "dsatur")[1] == 50
+    assert orc.colour_order(G.workload(0), False, "largest_first")[1] == 50
+    assert orc.colour(G.workload(0), False)[1] == 51
+    for order in ("largest_first", "dsatur"):
+        assert orc.colour_order(G.sram6t(8, 8), True, order)[1] == 16
