@@ -103,6 +103,20 @@ void cs_circuit_destroy(cs_circuit *c);
 cs_status cs_build_coloring(cs_circuit *c, const uint8_t *exclude, int32_t *n_colors,
                             int32_t *colour_out, int64_t *n_edges);
 
+/* Vertex orders of the greedy colouring. */
+typedef enum {
+    CS_ORDER_NATURAL = 0,        /* ascending device index (the paper's; cs_build_coloring) */
+    CS_ORDER_LARGEST_FIRST = 1,  /* decreasing conflict degree, ties by ascending index
+                                    (Welsh and Powell) */
+    CS_ORDER_DSATUR = 2          /* most distinct colours among coloured neighbours first,
+                                    ties by larger degree, then smaller index (Brelaz) */
+} cs_colour_order;
+
+/* cs_build_coloring with another vertex order (same outputs and conventions; every
+ * later step works with any proper colouring).  CS_EINVAL for an unknown order. */
+cs_status cs_build_coloring_order(cs_circuit *c, const uint8_t *exclude, int32_t order, int32_t *n_colors,
+                                  int32_t *colour_out, int64_t *n_edges);
+
 /* CSR pattern and the device-to-slot stamp map (Methodology: stamps touch common
  * MNA rows/columns).  Requires cs_build_coloring.  Uploads topology and map to the
  * current HIP device.  Outputs: number of rows and nonzeros. */

@@ -23,7 +23,8 @@ CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "d
 
 # Every entry point of include/colorstamp.h.
 EXPORTS = (
-    "cs_circuit_create", "cs_circuit_destroy", "cs_build_coloring", "cs_build_stamp_map",
+    "cs_circuit_create", "cs_circuit_destroy", "cs_build_coloring", "cs_build_coloring_order",
+    "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
     "cs_vjp", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
     "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_set_plan_units", "cs_batch_create", "cs_batch_destroy",
@@ -63,6 +64,7 @@ def lib():
         sig = {
             "cs_circuit_create": [i32, i32, p, p, i32, p, p, p],
             "cs_build_coloring": [p, p, p, p, p],
+            "cs_build_coloring_order": [p, p, i32, p, p, p],
             "cs_build_stamp_map": [p, p, p],
             "cs_get_pattern": [p, p, p],
             "cs_get_stamp_map": [p, p, p, p, p],
@@ -127,6 +129,7 @@ def _stream(stream):
 
 
 RT_FIELDS = 10   # fields per region in the plan's region table
+ORDERS = {"natural": 0, "largest_first": 1, "dsatur": 2}   # cs_colour_order
 
 
 def _region_info(fn, h) -> dict:
@@ -192,14 +195,15 @@ class Circuit:
     def handle(self):
         return self._h
 
-    def colour(self, exclude=None):
-        """Greedy colouring; exclude = None (paper rule) or per-node flags."""
+    def colour(self, exclude=None, order: str = "natural"):
+        """Greedy colouring; exclude = None (paper rule) or per-node flags; order =
+        natural (ascending index, the paper's), largest_first or dsatur."""
         ex = None if exclude is None else np.ascontiguousarray(exclude, dtype=np.uint8)
         col = np.zeros(self.n_dev, dtype=np.int32)
         nc = C.c_int32()
         ne = C.c_int64()
-        _check(lib().cs_build_coloring(self._h, _np_ptr(ex), C.byref(nc), _np_ptr(col), C.byref(ne)),
-               "cs_build_coloring")
+        _check(lib().cs_build_coloring_order(self._h, _np_ptr(ex), ORDERS[order], C.byref(nc), _np_ptr(col),
+                                             C.byref(ne)), "cs_build_coloring_order")
         self.n_colors = nc.value
         return col, nc.value, ne.value
 
@@ -282,11 +286,12 @@ class Circuit:
         _check(lib().cs_check(self._h, _stream(stream)), "cs_check")
 
 
-def prepare(circ, exclude: bool = True, nmos=None, pmos=None):
-    """Circuit from a generator netlist: coloured (rails excluded or not) and mapped."""
+def prepare(circ, exclude: bool = True, nmos=None, pmos=None, order: str = "natural"):
+    """Circuit from a generator netlist: coloured (rails excluded or not, in the given
+    vertex order) and mapped."""
     from . import netgen
     c = Circuit.from_netlist(circ)
-    c.colour(circ.exclude if exclude else None)
+    c.colour(circ.exclude if exclude else None, order)
     c.build_map()
     c.set_models(nmos or netgen.default_card(1), pmos or netgen.default_card(-1))
     return c

@@ -286,9 +286,14 @@ void cs_circuit_destroy(cs_circuit *c) { delete c; }
 
 cs_status cs_build_coloring(cs_circuit *c, const uint8_t *exclude, int32_t *n_colors,
                             int32_t *colour_out, int64_t *n_edges) {
+    return cs_build_coloring_order(c, exclude, CS_ORDER_NATURAL, n_colors, colour_out, n_edges);
+}
+
+cs_status cs_build_coloring_order(cs_circuit *c, const uint8_t *exclude, int32_t order, int32_t *n_colors,
+                                  int32_t *colour_out, int64_t *n_edges) {
     if (!c) return fail(CS_EINVAL, "NULL circuit");
     try {
-        Err e = build_colouring(c->h, exclude, n_edges);
+        Err e = build_colouring(c->h, exclude, n_edges, order);
         if (e.st != CS_OK) return fail(e.st, e.msg);
         order_within_colours(c->h);
         c->rp = RegionPlan{};

@@ -134,7 +134,8 @@ void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t 
                    int32_t *interior, int32_t *links, int32_t *item, int32_t *fold, int32_t *fold_src);
 
 // Build the greedy colouring (ascending device order) and the colour-major order.
-Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges);
+// order: 0 ascending device index (the paper's), 1 largest degree first, 2 DSATUR.
+Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges, int order = 0);
 // Build pattern, stamp codes, fixed stores and hub lists.
 Err build_map(HostCircuit &h);
 // Card-derived constants, in the model's operation order.

@@ -5,8 +5,12 @@
 // (Introduction) visits vertices in order and gives each the smallest colour not
 // used by an already coloured neighbour.  The graph stays implicit here: a colour
 // is forbidden for a device exactly when it is already used on one of the
-// device's conflict nodes, so each node keeps a bitset of its used colours.
+// device's conflict nodes, so each node keeps a bitset of its used colours.  Besides
+// the paper's ascending order, the vertices can be visited largest degree first
+// (Welsh and Powell) or by DSATUR (Brelaz), which often reach the clique bound.
 #include <algorithm>
+#include <set>
+#include <tuple>
 #include <cmath>
 #include <unordered_map>
 
@@ -76,37 +80,122 @@ int64_t count_edges(const HostCircuit &h) {
 
 }  // namespace
 
-Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges) {
+Err build_colouring(HostCircuit &h, const uint8_t *exclude, int64_t *n_edges, int order) {
+    if (order < 0 || order > 2) return {CS_EINVAL, "unknown colouring order"};
     h.excl.assign((size_t)h.n_nodes, 0);
     if (exclude)
         for (int32_t n = 0; n < h.n_nodes; ++n) h.excl[n] = exclude[n] ? 1 : 0;
     h.excl[0] = 1;  // ground never conflicts
-    std::vector<std::vector<uint64_t>> used((size_t)h.n_nodes);
-    h.colour.assign((size_t)h.n_dev, 0);
-    int32_t C = 0;
-    std::vector<uint64_t> acc;
-    for (int32_t v = 0; v < h.n_dev; ++v) {
+    const size_t n = (size_t)h.n_dev;
+    // conflict nodes of each device (distinct, non-excluded)
+    std::vector<int32_t> cn(4 * n, -1);
+    std::vector<int8_t> ncn(n, 0);
+    for (size_t v = 0; v < n; ++v) {
         int32_t u[4];
-        int k = unique_nodes(&h.term[4 * (size_t)v], u);
-        size_t words = 0;
+        const int k = unique_nodes(&h.term[4 * v], u);
         for (int j = 0; j < k; ++j)
-            if (!h.excl[u[j]]) words = std::max(words, used[u[j]].size());
+            if (!h.excl[u[j]]) cn[4 * v + (size_t)ncn[v]++] = u[j];
+    }
+    std::vector<std::vector<uint64_t>> used((size_t)h.n_nodes);
+    auto smallest_free = [&](size_t v, std::vector<uint64_t> &acc) {
+        size_t words = 0;
+        for (int j = 0; j < ncn[v]; ++j) words = std::max(words, used[(size_t)cn[4 * v + j]].size());
         acc.assign(words + 1, 0);
-        for (int j = 0; j < k; ++j) {
-            if (h.excl[u[j]]) continue;
-            const auto &bs = used[u[j]];
+        for (int j = 0; j < ncn[v]; ++j) {
+            const auto &bs = used[(size_t)cn[4 * v + j]];
             for (size_t w = 0; w < bs.size(); ++w) acc[w] |= bs[w];
         }
         size_t w = 0;
         while (acc[w] == ~0ull) ++w;
-        int32_t c = (int32_t)(w * 64 + __builtin_ctzll(~acc[w]));
-        h.colour[v] = c;
-        C = std::max(C, c + 1);
-        for (int j = 0; j < k; ++j) {
-            if (h.excl[u[j]]) continue;
-            auto &bs = used[u[j]];
-            if (bs.size() <= (size_t)(c / 64)) bs.resize((size_t)(c / 64) + 1, 0);
-            bs[(size_t)(c / 64)] |= 1ull << (c % 64);
+        return (int32_t)(w * 64 + __builtin_ctzll(~acc[w]));
+    };
+    auto node_has = [&](int32_t node, int32_t c) {
+        const auto &bs = used[(size_t)node];
+        return (size_t)(c / 64) < bs.size() && ((bs[(size_t)(c / 64)] >> (c % 64)) & 1ull);
+    };
+    auto mark = [&](int32_t node, int32_t c) {
+        auto &bs = used[(size_t)node];
+        if (bs.size() <= (size_t)(c / 64)) bs.resize((size_t)(c / 64) + 1, 0);
+        bs[(size_t)(c / 64)] |= 1ull << (c % 64);
+    };
+    h.colour.assign(n, -1);
+    int32_t C = 0;
+    std::vector<uint64_t> acc;
+    if (order == 0) {
+        // the paper's order: ascending device index
+        for (size_t v = 0; v < n; ++v) {
+            const int32_t c = smallest_free(v, acc);
+            h.colour[v] = c;
+            C = std::max(C, c + 1);
+            for (int j = 0; j < ncn[v]; ++j) mark(cn[4 * v + j], c);
+        }
+    } else {
+        // devices on each conflict node, and each device's degree (distinct neighbours)
+        std::vector<int64_t> nptr((size_t)h.n_nodes + 1, 0);
+        for (size_t v = 0; v < n; ++v)
+            for (int j = 0; j < ncn[v]; ++j) nptr[(size_t)cn[4 * v + j] + 1]++;
+        for (int32_t x = 0; x < h.n_nodes; ++x) nptr[(size_t)x + 1] += nptr[(size_t)x];
+        std::vector<int32_t> on((size_t)nptr[(size_t)h.n_nodes]);
+        {
+            std::vector<int64_t> f(nptr.begin(), nptr.end() - 1);
+            for (size_t v = 0; v < n; ++v)
+                for (int j = 0; j < ncn[v]; ++j) on[(size_t)f[(size_t)cn[4 * v + j]]++] = (int32_t)v;
+        }
+        std::vector<int64_t> deg(n, 0);
+        {
+            std::vector<int32_t> seen(n, -1);
+            for (size_t v = 0; v < n; ++v)
+                for (int j = 0; j < ncn[v]; ++j) {
+                    const int32_t x = cn[4 * v + j];
+                    for (int64_t e = nptr[(size_t)x]; e < nptr[(size_t)x + 1]; ++e) {
+                        const int32_t w = on[(size_t)e];
+                        if ((size_t)w == v || seen[(size_t)w] == (int32_t)v) continue;
+                        seen[(size_t)w] = (int32_t)v;
+                        ++deg[v];
+                    }
+                }
+        }
+        if (order == 1) {
+            // largest degree first, ties by ascending index
+            std::vector<int32_t> seq(n);
+            for (size_t v = 0; v < n; ++v) seq[v] = (int32_t)v;
+            std::stable_sort(seq.begin(), seq.end(), [&](int32_t a, int32_t b) { return deg[(size_t)a] > deg[(size_t)b]; });
+            for (int32_t vv : seq) {
+                const size_t v = (size_t)vv;
+                const int32_t c = smallest_free(v, acc);
+                h.colour[v] = c;
+                C = std::max(C, c + 1);
+                for (int j = 0; j < ncn[v]; ++j) mark(cn[4 * v + j], c);
+            }
+        } else {
+            // DSATUR: most distinct neighbour colours first, then larger degree, then
+            // smaller index; a neighbour's saturation grows when a colour first
+            // appears on one of its conflict nodes
+            std::vector<int32_t> sat(n, 0);
+            auto key = [&](size_t v) { return std::make_tuple(-(int64_t)sat[v], -deg[v], (int64_t)v); };
+            std::set<std::tuple<int64_t, int64_t, int64_t>> open;
+            for (size_t v = 0; v < n; ++v) open.insert(key(v));
+            while (!open.empty()) {
+                const size_t v = (size_t)std::get<2>(*open.begin());
+                open.erase(open.begin());
+                const int32_t c = smallest_free(v, acc);
+                h.colour[v] = c;
+                C = std::max(C, c + 1);
+                for (int j = 0; j < ncn[v]; ++j) {
+                    const int32_t x = cn[4 * v + j];
+                    for (int64_t e = nptr[(size_t)x]; e < nptr[(size_t)x + 1]; ++e) {
+                        const size_t u = (size_t)on[(size_t)e];
+                        if (u == v || h.colour[u] >= 0) continue;
+                        bool present = false;
+                        for (int i2 = 0; i2 < ncn[u] && !present; ++i2) present = node_has(cn[4 * u + i2], c);
+                        if (present) continue;
+                        open.erase(key(u));
+                        ++sat[u];
+                        open.insert(key(u));
+                    }
+                    mark(x, c);
+                }
+            }
         }
     }
     h.n_colors = C;

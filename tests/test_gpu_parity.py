@@ -30,8 +30,8 @@ def say(*a):
 
 
 def gpu_stamp(torch, circ, exclude, variant, ag0=1e12, hist=None, block=0, eval_ahead=-1, cooperative=True,
-              repeat=1):
-    c = CS.prepare(circ, exclude)
+              repeat=1, order="natural"):
+    c = CS.prepare(circ, exclude, order=order)
     c.set_launch(block, eval_ahead, cooperative)
     dev = torch.device("cuda:0")
     W = torch.from_numpy(circ.W).to(dev)
@@ -125,6 +125,23 @@ def test_serial_stamp_equals_serial_order(torch_dev, orc, name, circ):
         A, b, _ = gpu_stamp(torch_dev, circ, exclude, "serial")
         assert_bit_exact(A, As, f"{name}/serial/A")
         assert_bit_exact(b, bs, f"{name}/serial/b")
+
+
+@pytest.mark.parametrize("order", ["largest_first", "dsatur"])
+def test_other_colouring_orders_bit_exact(torch_dev, orc, order):
+    # any proper colouring fixes a colour order; every coloured variant reproduces the
+    # oracle's replay in the order of the oracle's own colouring of that kind
+    cases = [("chain50", G.workload(0), False), ("sram16x16", G.sram_case(16, 16, 5), True),
+             ("adder64x28", G.adder_case(64, 9), False), ("pchain50x6", SMALL[7][1], True)]
+    for name, circ, exclude in cases:
+        rp, ci = orc.pattern(circ)
+        col, _, _ = orc.colour_order(circ, exclude, order)
+        A0, b0 = orc.assemble(circ, rp, ci, NC, PC, 1e12, col=col, exclude=exclude)
+        for variant, block in (("region", 256), ("region", 64), ("persistent", 256), ("per_kernel", 0)):
+            say(f"case {name} exclude={exclude} order={order} variant={variant} block={block}")
+            A, b, _ = gpu_stamp(torch_dev, circ, exclude, variant, block=block, order=order)
+            assert_bit_exact(A, A0, f"{name}/{order}/{variant}/A")
+            assert_bit_exact(b, b0, f"{name}/{order}/{variant}/b")
 
 
 def test_history_and_dc(torch_dev, orc):

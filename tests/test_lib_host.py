@@ -52,6 +52,27 @@ def test_setup_equals_oracle(orc, name, make, exclude):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("exclude", [False, True])
+@pytest.mark.parametrize("order", ["largest_first", "dsatur"])
+def test_ordered_colouring_and_map_equal_oracle(orc, name, make, exclude, order):
+    # the colouring in another vertex order, and the stamp map built on it
+    circ = make()
+    c = CS.Circuit.from_netlist(circ)
+    col, C, E = c.colour(circ.exclude if exclude else None, order)
+    ocol, oC, oE = orc.colour_order(circ, exclude, order)
+    assert np.array_equal(col, ocol) and C == oC and E == oE
+    c.build_map()
+    orp, oci = orc.pattern(circ)
+    for a, b in zip(c.stamp_map(), orc.stamp_map(circ, orp, oci, ocol, exclude)):
+        assert np.array_equal(a, b)
+
+
+def test_unknown_colouring_order_is_refused():
+    c = CS.Circuit.from_netlist(G.workload(0))
+    assert CS.lib().cs_build_coloring_order(c.handle, None, 7, None, None, None) == -1   # CS_EINVAL
+
+
 @pytest.mark.parametrize("idx", [1, 2])
 def test_setup_equals_oracle_full_size(orc, idx):
     circ = G.workload(idx)
@@ -110,3 +131,11 @@ def test_error_paths():
     bad_card = CS.make_card(G.default_card(1))
     bad_card.size = 3
     assert L.cs_set_models(c.handle, ctypes.byref(bad_card), ctypes.byref(bad_card)) == -1
+
+
+def test_largest_first_reaches_the_sram_wordline_clique():
+    # each wordline gates 512 access transistors: 512 colours are needed, and the
+    # largest-first order attains them (the ascending order needs 516)
+    circ = G.workload(2)
+    c = CS.Circuit.from_netlist(circ)
+    assert c.colour(circ.exclude, "largest_first")[1] == 512
