@@ -302,6 +302,23 @@ def adder_case(n_bits: int, seed: int, split: str | None = None) -> Circuit:
     return draw_params(c, rng, W_CHAIN, L_CHAIN)
 
 
+def random_netlist(n_dev: int, n_nodes: int, seed: int, vdd: float = 1.0) -> Circuit:
+    """FETs whose four terminals are drawn uniformly from nodes 0..n_nodes-1 (0
+    ground, 1 vdd), polarity at random; with few nodes every coincidence pattern of
+    the terminals occurs.  The first devices are degenerate on purpose: all four
+    terminals on ground, drain and source on one node, every terminal on vdd."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    term = rng.integers(0, n_nodes, size=(n_dev, 4)).astype(np.int32)
+    pol = np.where(rng.random(n_dev) < 0.5, NMOS, PMOS).astype(np.int8)
+    special = [(0, 0, 0, 0), (2, 3, 2, 0), (1, 1, 1, 1), (2, 2, 2, 2), (3, 0, 3, 3)]
+    for i, t in enumerate(special[:n_dev]):
+        term[i] = t
+    excl = np.zeros(n_nodes, dtype=np.uint8)
+    excl[1] = 1
+    return Circuit(f"random{n_dev}x{n_nodes}", n_nodes, term, pol, np.array([[1, 0]], np.int32),
+                   np.array([vdd]), excl, vdd)
+
+
 def no_shared_nets(n_dev: int, vdd: float = 1.0) -> Circuit:
     """Devices whose terminals all sit on private nodes or ground (every net split,
     as by the series-resistor transform of Benchmark 2): the conflict graph is empty."""

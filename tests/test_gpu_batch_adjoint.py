@@ -123,7 +123,9 @@ def gpu_vjp(torch, circ, Ab, bb, ag0=1e12):
 VJP_CASES = [("chain50", lambda: G.workload(0)),
              ("opamp12", lambda: G.draw_params(G.opamp2(12), np.random.default_rng(2), G.W_OPAMP, G.L_OPAMP)),
              ("sram6x6", lambda: G.sram_case(6, 6, 8)),
-             ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN))]
+             ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)),
+             ("random600x6", lambda: G.draw_params(G.random_netlist(600, 6, 21), np.random.default_rng(31),
+                                                   G.W_CHAIN, G.L_CHAIN))]
 
 
 @pytest.mark.parametrize("name,make", VJP_CASES, ids=[v[0] for v in VJP_CASES])
@@ -135,9 +137,21 @@ def test_vjp_matches_oracle_complex_step(torch_dev, orc, name, make):
     mag = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb, magnitude=True)
     say(f"case vjp {name}")
     got, _ = gpu_vjp(torch_dev, circ, Ab, bb)
+    # 1e-8 of the sensitivity scale.  The random netlist also holds near-singular
+    # bias points, where the oracle's complex step and the kernel's tangent sweep
+    # round differently: with drain and source on one node (vds = 0 exactly) the
+    # smoothed Vdseff and Vdcv cancel to zero for every W and L, so their L and W
+    # sensitivities are rounding residue (allowed 1e-3 of the scale), and the other
+    # devices of that netlist get 1e-6
+    tol = np.full(circ.n_dev, 1e-8)
+    if name.startswith("random"):
+        tol[:] = 1e-6
+        tol[circ.term[:, 0] == circ.term[:, 2]] = 1e-3
     for g, r, m, what in zip(got, ref, mag, ("W", "L", "VTH0")):
         err = np.abs(g - r) / (m + 1e-300)
-        assert np.all(np.abs(g - r) <= 1e-8 * m + 1e-300), (what, err.max())
+        assert np.all(np.abs(g - r) <= tol * m + 1e-300), (what, err.max())
+        if name.startswith("random"):
+            assert np.sum(err > 1e-8) <= 2, what
 
 
 def test_vjp_full_size_chain10k(torch_dev, orc):

@@ -79,6 +79,8 @@ def small_cases():
         ("pchain40x33", G.draw_params(G.parallel_chain(40, 33), rng, G.W_CHAIN, G.L_CHAIN)),
         ("private700", G.draw_params(G.no_shared_nets(700), rng, G.W_CHAIN, G.L_CHAIN)),
         ("adder64x28", G.draw_params(G.ripple_adder28(64), rng, G.W_CHAIN, G.L_CHAIN)),
+        # every coincidence pattern of the four terminals, degenerate devices included
+        ("random600x6", G.draw_params(G.random_netlist(600, 6, 21), rng, G.W_CHAIN, G.L_CHAIN)),
         # every net split (one colour; PMOS with four distinct nodes: 20 codes)
         ("adder8r89", G.draw_params(G.split_nets(G.ripple_adder28(8), "all")[0], rng, G.W_CHAIN, G.L_CHAIN)),
     ]

@@ -1,6 +1,7 @@
 """CPU checks of the C-ABI library: it loads, exports every entry point declared in
 include/colorstamp.h, its host setup (colouring, CSR pattern, stamp map) equals the
 oracle's bit for bit, and argument/state errors are reported before any launch."""
+import itertools
 import os
 import re
 
@@ -33,6 +34,8 @@ CASES = [
     ("private13", lambda: G.no_shared_nets(13)),
     ("chain1", lambda: G.inverter_chain(1)),
     ("adder3x28", lambda: G.ripple_adder28(3)),
+    ("random600x6", lambda: G.random_netlist(600, 6, 21)),
+    ("random2000x1500", lambda: G.random_netlist(2000, 1500, 22)),
 ]
 
 
@@ -139,3 +142,17 @@ def test_largest_first_reaches_the_sram_wordline_clique():
     circ = G.workload(2)
     c = CS.Circuit.from_netlist(circ)
     assert c.colour(circ.exclude, "largest_first")[1] == 512
+
+
+def test_random_netlist_covers_every_terminal_pattern():
+    # the 52 ways four terminals can coincide or sit on ground (stamp patterns)
+    def key(t):
+        t0, t1, t2, t3 = (int(v) for v in t)
+        c0 = 1 if t0 == 0 else 0
+        c1 = 2 if t1 == 0 else (0 if t1 == t0 else 1)
+        c2 = 3 if t2 == 0 else (0 if t2 == t0 else (1 if t2 == t1 else 2))
+        c3 = 4 if t3 == 0 else (0 if t3 == t0 else (1 if t3 == t1 else (2 if t3 == t2 else 3)))
+        return c0 + 2 * (c1 + 3 * (c2 + 4 * c3))
+    every = {key(t) for t in itertools.product(range(5), repeat=4)}
+    assert len(every) == 52
+    assert {key(t) for t in G.random_netlist(600, 6, 21).term} == every

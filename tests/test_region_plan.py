@@ -165,6 +165,8 @@ CASES = [
     ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)),
     ("pchain7x3", lambda: G.draw_params(G.parallel_chain(7, 3), np.random.default_rng(5), G.W_CHAIN, G.L_CHAIN)),
     ("pchain9x20", lambda: G.draw_params(G.parallel_chain(9, 20), np.random.default_rng(6), G.W_CHAIN, G.L_CHAIN)),
+    ("random600x6", lambda: G.draw_params(G.random_netlist(600, 6, 21), np.random.default_rng(8), G.W_CHAIN,
+                                          G.L_CHAIN)),
     # every net split: almost only single-writer entries, more than one region's LDS
     # holds at 256 devices (one-source lane folds)
     ("adder8r89", lambda: G.draw_params(G.split_nets(G.ripple_adder28(8), "all")[0], np.random.default_rng(7),
