@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip SRAM/batch/adjoint lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--only", action="store_true", help="time only --variant (profiling runs)")
+    ap.add_argument("--ordinary", action="store_true",
+                    help="with --only: launch grid-barrier kernels without the cooperative launch API")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -411,9 +413,10 @@ def main():
             ("buffered", True), ("region", True), ("atomic", True))
     if args.only:
         todo = ((args.variant, True),)
+    coop_main = not (args.only and args.ordinary)
     for variant, coop in todo:
         c = CS.prepare(circ, exclude=True)
-        c.set_launch(256, -1, coop)
+        c.set_launch(256, -1, coop and coop_main)
         c.set_params(W, L, V)
         A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
         b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
