@@ -58,7 +58,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"libcolorstamp.so not built ({LIB_PATH}); run __graft_entry__.build()")
+            raise ImportError(f"libcolorstamp.so not built ({LIB_PATH}); build it with paper_2604_03079_amd.build.build()")
         L = C.CDLL(LIB_PATH)
         i32, i64, d, p = C.c_int32, C.c_int64, C.c_double, C.c_void_p
         sig = {
