@@ -12,6 +12,9 @@
  * Per device, the 4x4 local matrix Y is merged onto its unique node pairs: each
  * merged value is the left-to-right sum of the Y entries mapping to it in (t, u)
  * row-major order over (d, g, s, b); b rows likewise in terminal order.
+ * The series resistors of a split netlist (Benchmark 2, Table I's R rows) are linear:
+ * their stamps form a constant per-entry sum (or_linear_stamp) that is added once to
+ * each entry they touch, after all device contributions, in both orders.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -72,8 +75,30 @@ static int cmp_hub(const void *x, const void *y) {
     return (a->dev > b->dev) - (a->dev < b->dev);
 }
 
+int or_linear_stamp(int32_t n_nodes, int32_t n_res, const int32_t *res, const double *g,
+                    const int32_t *row_ptr, const int32_t *col_idx, int64_t nnz, double *Lin,
+                    uint8_t *touched, int magnitude) {
+    for (int64_t i = 0; i < nnz; ++i) { Lin[i] = 0.0; touched[i] = 0; }
+    for (int32_t j = 0; j < n_res; ++j) {
+        const int32_t nd[2] = {res[2 * (int64_t)j], res[2 * (int64_t)j + 1]};
+        if (nd[0] < 0 || nd[0] >= n_nodes || nd[1] < 0 || nd[1] >= n_nodes) return -2;
+        /* +g on the diagonals, -g between the two nodes, in (p,p) (p,q) (q,p) (q,q) order */
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                if (nd[r] == 0 || nd[c] == 0) continue;
+                int64_t s = or_find_slot(row_ptr, col_idx, nd[r] - 1, nd[c] - 1);
+                if (s < 0) return -3;
+                double v = r == c ? g[j] : -g[j];
+                Lin[s] = Lin[s] + (magnitude ? fabs(v) : v);
+                touched[s] = 1;
+            }
+    }
+    return 0;
+}
+
 static int assemble_impl(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
                          int32_t n_vsrc, const int32_t *vsrc, const double *vsrc_volts,
+                         int32_t n_res, const int32_t *res, const double *res_g,
                          const or_card *nmos, const or_card *pmos, const double *W,
                          const double *L, const double *VTH0, const int32_t *row_ptr,
                          const int32_t *col_idx, const int32_t *colour, const uint8_t *excl,
@@ -183,26 +208,41 @@ static int assemble_impl(int32_t n_nodes, int32_t n_dev, const int32_t *term, co
         free(vals); free(doneA); free(doneB); free(hubs); free(cptr); free(order); free(fillp);
     }
     free(mA); free(mB); free(sl); free(kk);
+    /* linear part, added once per entry after every device contribution */
+    if (n_res > 0) {
+        double *Lin = malloc(sizeof(double) * ((size_t)nnz + 1));
+        uint8_t *touched = malloc((size_t)nnz + 1);
+        if (!Lin || !touched) { free(Lin); free(touched); return -1; }
+        int rc = or_linear_stamp(n_nodes, n_res, res, res_g, row_ptr, col_idx, nnz, Lin, touched,
+                                 magnitude);
+        if (rc == 0)
+            for (int64_t i = 0; i < nnz; ++i)
+                if (touched[i]) A[i] = A[i] + Lin[i];
+        free(Lin); free(touched);
+        return rc;
+    }
     return 0;
 }
 
 int or_assemble(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
                 int32_t n_vsrc, const int32_t *vsrc, const double *vsrc_volts,
-                const or_card *nmos, const or_card *pmos, const double *W, const double *L,
-                const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
-                const int32_t *colour, const uint8_t *excl, const double *x, double ag0,
-                const double *hist, double *A, double *b) {
-    return assemble_impl(n_nodes, n_dev, term, pol, n_vsrc, vsrc, vsrc_volts, nmos, pmos, W, L,
-                         VTH0, row_ptr, col_idx, colour, excl, x, ag0, hist, A, b, 0);
+                int32_t n_res, const int32_t *res, const double *res_g, const or_card *nmos,
+                const or_card *pmos, const double *W, const double *L, const double *VTH0,
+                const int32_t *row_ptr, const int32_t *col_idx, const int32_t *colour,
+                const uint8_t *excl, const double *x, double ag0, const double *hist, double *A,
+                double *b) {
+    return assemble_impl(n_nodes, n_dev, term, pol, n_vsrc, vsrc, vsrc_volts, n_res, res, res_g, nmos,
+                         pmos, W, L, VTH0, row_ptr, col_idx, colour, excl, x, ag0, hist, A, b, 0);
 }
 
 /* Sum of |contribution| per entry (serial), the natural scale of a reordered sum. */
 int or_assemble_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term,
                           const int8_t *pol, int32_t n_vsrc, const int32_t *vsrc,
-                          const double *vsrc_volts, const or_card *nmos, const or_card *pmos,
+                          const double *vsrc_volts, int32_t n_res, const int32_t *res,
+                          const double *res_g, const or_card *nmos, const or_card *pmos,
                           const double *W, const double *L, const double *VTH0,
                           const int32_t *row_ptr, const int32_t *col_idx, const double *x,
                           double ag0, const double *hist, double *A, double *b) {
-    return assemble_impl(n_nodes, n_dev, term, pol, n_vsrc, vsrc, vsrc_volts, nmos, pmos, W, L,
-                         VTH0, row_ptr, col_idx, NULL, NULL, x, ag0, hist, A, b, 1);
+    return assemble_impl(n_nodes, n_dev, term, pol, n_vsrc, vsrc, vsrc_volts, n_res, res, res_g, nmos,
+                         pmos, W, L, VTH0, row_ptr, col_idx, NULL, NULL, x, ag0, hist, A, b, 1);
 }

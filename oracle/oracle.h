@@ -62,10 +62,20 @@ int or_colour(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint8_t
 int or_colour_order(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint8_t *excl, int order,
                     int32_t *colour, int32_t *n_colours, int64_t *n_edges);
 
-/* CSR pattern.  row_ptr has n_rows+1 entries; col_idx must hold at least
- * 16*n_dev + n_rows + 4*n_vsrc entries.  *nnz receives the count. */
+/* CSR pattern.  res: 2*n_res node pairs of series resistors (may be NULL when
+ * n_res == 0).  row_ptr has n_rows+1 entries; col_idx must hold at least
+ * 16*n_dev + n_rows + 4*n_vsrc + 2*n_res entries.  *nnz receives the count. */
 int or_pattern(int32_t n_nodes, int32_t n_dev, const int32_t *term, int32_t n_vsrc,
-               const int32_t *vsrc, int32_t *row_ptr, int32_t *col_idx, int64_t *nnz);
+               const int32_t *vsrc, int32_t n_res, const int32_t *res, int32_t *row_ptr,
+               int32_t *col_idx, int64_t *nnz);
+
+/* Linear part of the matrix: resistor j (conductance g[j], nodes res[2j], res[2j+1])
+ * stamps +g, -g, -g, +g at (p,p), (p,q), (q,p), (q,q), ground dropped.  Lin (nnz
+ * values) starts at zero and takes the stamps in resistor order; touched flags the
+ * entries that received any.  magnitude: |stamp|.  -2 bad node, -3 entry missing. */
+int or_linear_stamp(int32_t n_nodes, int32_t n_res, const int32_t *res, const double *g,
+                    const int32_t *row_ptr, const int32_t *col_idx, int64_t nnz, double *Lin,
+                    uint8_t *touched, int magnitude);
 
 /* Expected stamp map in original device order: slot[16*v + j] (j < k*k, else -1),
  * sflag (0 add, 1 store, 2 hub), brow[4*v + a] (a < k, else -1), bflag. */
@@ -76,11 +86,13 @@ int or_stamp_map(int32_t n_nodes, int32_t n_dev, const int32_t *term, const uint
 /* Assembly of A (CSR values) and b.  colour == NULL: serial order (devices
  * ascending, A and b zero-initialised, +=).  Otherwise colour replay (colours
  * ascending; first writer stores, later writers add; hub outputs summed by
- * or_hubsum in ascending device order).  excl (replay only) defines hub outputs. */
+ * or_hubsum in ascending device order).  excl (replay only) defines hub outputs.
+ * Then, in both orders, each entry touched by a series resistor gets its linear
+ * part (or_linear_stamp) added once. */
 int or_assemble(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
                 int32_t n_vsrc, const int32_t *vsrc, const double *vsrc_volts,
-                const or_card *nmos, const or_card *pmos, const double *W, const double *L,
-                const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+                int32_t n_res, const int32_t *res, const double *res_g, const or_card *nmos,
+                const or_card *pmos, const double *W, const double *L, const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
                 const int32_t *colour, const uint8_t *excl, const double *x, double ag0,
                 const double *hist, double *A, double *b);
 
@@ -88,7 +100,8 @@ int or_assemble(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_
  * the rounding difference between two accumulation orders. */
 int or_assemble_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term,
                           const int8_t *pol, int32_t n_vsrc, const int32_t *vsrc,
-                          const double *vsrc_volts, const or_card *nmos, const or_card *pmos,
+                          const double *vsrc_volts, int32_t n_res, const int32_t *res,
+                          const double *res_g, const or_card *nmos, const or_card *pmos,
                           const double *W, const double *L, const double *VTH0,
                           const int32_t *row_ptr, const int32_t *col_idx, const double *x,
                           double ag0, const double *hist, double *A, double *b);

@@ -50,16 +50,19 @@ def lib():
         _lib.or_device_eval.argtypes = [p, C.c_int, d, d, d, p, d, p, p, p, p, p, p]
         _lib.or_colour.argtypes = [i32, i32, p, p, p, p, p]
         _lib.or_colour_order.argtypes = [i32, i32, p, p, C.c_int, p, p, p]
-        _lib.or_pattern.argtypes = [i32, i32, p, i32, p, p, p, p]
+        _lib.or_pattern.argtypes = [i32, i32, p, i32, p, i32, p, p, p, p]
+        _lib.or_linear_stamp.argtypes = [i32, i32, p, p, p, p, i64, p, p, C.c_int]
         _lib.or_stamp_map.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p]
-        _lib.or_assemble.argtypes = [i32, i32, p, p, i32, p, p, p, p, p, p, p, p, p, p, p, p, d, p, p, p]
+        _lib.or_assemble.argtypes = [i32, i32, p, p, i32, p, p, i32, p, p, p, p, p, p, p, p, p, p, p, p,
+                                     d, p, p, p]
         _lib.or_hubsum.restype = d
         _lib.or_hubsum.argtypes = [p, i64]
         _lib.or_vjp.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_vjp_magnitude.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_device_dparam.argtypes = [p, C.c_int, d, d, d, p, d, p, C.c_int, p, p]
         _lib.or_elem_array.argtypes = [C.c_int, p, p, i64]
-        _lib.or_assemble_magnitude.argtypes = [i32, i32, p, p, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p]
+        _lib.or_assemble_magnitude.argtypes = [i32, i32, p, p, i32, p, p, i32, p, p, p, p, p, p, p, p,
+                                               p, p, d, p, p, p]
     return _lib
 
 
@@ -171,18 +174,41 @@ def colour_order(circ, exclude: bool, order: str):
     return col, int(nc.value), int(ne.value)
 
 
+def _resistors(circ):
+    """Series resistors of a split netlist: (n_res, 2) nodes and conductances."""
+    r = getattr(circ, "res", None)
+    if r is None:
+        return np.zeros((0, 2), np.int32), np.zeros(0)
+    return (np.ascontiguousarray(r, dtype=np.int32).reshape(-1, 2),
+            np.ascontiguousarray(circ.res_g, dtype=np.float64))
+
+
 def pattern(circ):
     term = np.ascontiguousarray(circ.term, dtype=np.int32)
     vs = np.ascontiguousarray(circ.vsrc, dtype=np.int32)
+    res, _ = _resistors(circ)
     rp = np.zeros(circ.n_rows + 1, dtype=np.int32)
-    cap = 16 * circ.n_dev + circ.n_rows + 4 * vs.shape[0]
+    cap = 16 * circ.n_dev + circ.n_rows + 4 * vs.shape[0] + 2 * res.shape[0]
     ci = np.zeros(cap, dtype=np.int32)
     nnz = C.c_int64(0)
-    rc = lib().or_pattern(circ.n_nodes, circ.n_dev, _ptr(term), vs.shape[0], _ptr(vs), _ptr(rp),
-                          _ptr(ci), C.byref(nnz))
+    rc = lib().or_pattern(circ.n_nodes, circ.n_dev, _ptr(term), vs.shape[0], _ptr(vs), res.shape[0],
+                          _ptr(res), _ptr(rp), _ptr(ci), C.byref(nnz))
     if rc != 0:
         raise RuntimeError(f"or_pattern failed: {rc}")
     return rp, ci[:nnz.value].copy()
+
+
+def linear_stamp(circ, rp, ci, magnitude: bool = False):
+    """Linear part of A (the series resistors' stamps, resistor order) and the flags
+    of the entries it touches."""
+    res, g = _resistors(circ)
+    nnz = int(rp[-1])
+    Lin = np.zeros(nnz); touched = np.zeros(nnz, np.uint8)
+    rc = lib().or_linear_stamp(circ.n_nodes, res.shape[0], _ptr(res), _ptr(g), _ptr(rp), _ptr(ci), nnz,
+                               _ptr(Lin), _ptr(touched), int(magnitude))
+    if rc != 0:
+        raise RuntimeError(f"or_linear_stamp failed: {rc}")
+    return Lin, touched.astype(bool)
 
 
 def stamp_map(circ, rp, ci, col, exclude: bool):
@@ -200,7 +226,8 @@ def stamp_map(circ, rp, ci, col, exclude: bool):
 
 def assemble(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=None, col=None,
              exclude: bool = False, x=None, W=None, L=None, VTH0=None):
-    """A (CSR values) and b; col=None -> serial order, else colour replay."""
+    """A (CSR values) and b; col=None -> serial order, else colour replay; then the
+    linear part of a split netlist's series resistors, added once per entry."""
     term = np.ascontiguousarray(circ.term, dtype=np.int32)
     pol = np.ascontiguousarray(circ.pol, dtype=np.int8)
     vs = np.ascontiguousarray(circ.vsrc, dtype=np.int32)
@@ -212,10 +239,12 @@ def assemble(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=None, col=No
     Va = np.ascontiguousarray(circ.VTH0 if VTH0 is None else VTH0, dtype=np.float64)
     h = None if hist is None else np.ascontiguousarray(hist, dtype=np.float64)
     colp = None if col is None else np.ascontiguousarray(col, dtype=np.int32)
+    res, g = _resistors(circ)
     A = np.zeros(int(rp[-1])); b = np.zeros(circ.n_rows)
     cn, cp = card(nmos), card(pmos)
     rc = lib().or_assemble(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), vs.shape[0], _ptr(vs),
-                           _ptr(vv), C.byref(cn), C.byref(cp), _ptr(Wa), _ptr(La), _ptr(Va),
+                           _ptr(vv), res.shape[0], _ptr(res), _ptr(g), C.byref(cn), C.byref(cp),
+                           _ptr(Wa), _ptr(La), _ptr(Va),
                            _ptr(rp), _ptr(ci), _ptr(colp), _ptr(excl), _ptr(xx), float(ag0),
                            _ptr(h), _ptr(A), _ptr(b))
     if rc != 0:
@@ -231,10 +260,12 @@ def assemble_magnitude(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=No
     vv = np.ascontiguousarray(circ.vsrc_volts, dtype=np.float64)
     xx = np.ascontiguousarray(circ.x, dtype=np.float64)
     h = None if hist is None else np.ascontiguousarray(hist, dtype=np.float64)
+    res, g = _resistors(circ)
     A = np.zeros(int(rp[-1])); b = np.zeros(circ.n_rows)
     cn, cp = card(nmos), card(pmos)
     rc = lib().or_assemble_magnitude(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), vs.shape[0],
-                                     _ptr(vs), _ptr(vv), C.byref(cn), C.byref(cp), _ptr(circ.W),
+                                     _ptr(vs), _ptr(vv), res.shape[0], _ptr(res), _ptr(g), C.byref(cn),
+                                     C.byref(cp), _ptr(circ.W),
                                      _ptr(circ.L), _ptr(circ.VTH0), _ptr(rp), _ptr(ci), _ptr(xx),
                                      float(ag0), _ptr(h), _ptr(A), _ptr(b))
     if rc != 0:

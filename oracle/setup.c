@@ -96,12 +96,14 @@ static int cmp_i64(const void *x, const void *y) {
 
 /* MNA pattern: non-ground node n -> row n-1; voltage-source branch j -> row
  * (n_nodes-1)+j.  Entries: every ordered pair of a device's non-ground terminal
- * nodes, every node-row diagonal, and (pos,br), (br,pos) (and neg likewise when
- * non-ground) for each voltage source.  Columns ascending and unique. */
+ * nodes, every node-row diagonal, (pos,br), (br,pos) (and neg likewise when
+ * non-ground) for each voltage source, and (p,q), (q,p) for each series resistor
+ * between non-ground nodes p and q.  Columns ascending and unique. */
 int or_pattern(int32_t n_nodes, int32_t n_dev, const int32_t *term, int32_t n_vsrc,
-               const int32_t *vsrc, int32_t *row_ptr, int32_t *col_idx, int64_t *nnz) {
+               const int32_t *vsrc, int32_t n_res, const int32_t *res, int32_t *row_ptr,
+               int32_t *col_idx, int64_t *nnz) {
     const int64_t n_rows = (int64_t)n_nodes - 1 + n_vsrc;
-    const int64_t cap = 16 * (int64_t)n_dev + n_rows + 4 * (int64_t)n_vsrc;
+    const int64_t cap = 16 * (int64_t)n_dev + n_rows + 4 * (int64_t)n_vsrc + 2 * (int64_t)n_res;
     int64_t *key = malloc(sizeof(int64_t) * (size_t)(cap + 1));
     if (!key) return -1;
     int64_t m = 0;
@@ -121,6 +123,13 @@ int or_pattern(int32_t n_nodes, int32_t n_dev, const int32_t *term, int32_t n_vs
             key[m++] = (int64_t)(nd - 1) * n_rows + br;
             key[m++] = br * n_rows + (nd - 1);
         }
+    }
+    /* series resistors: the off-diagonal pair between their two nodes */
+    for (int32_t j = 0; j < n_res; ++j) {
+        int32_t p = res[2 * (int64_t)j], q = res[2 * (int64_t)j + 1];
+        if (p == 0 || q == 0) continue;
+        key[m++] = (int64_t)(p - 1) * n_rows + (q - 1);
+        key[m++] = (int64_t)(q - 1) * n_rows + (p - 1);
     }
     qsort(key, (size_t)m, sizeof(int64_t), cmp_i64);
     int64_t w = 0;

@@ -9,7 +9,12 @@ accumulated into the global MNA matrix A and right-hand side b).
   the same sums up to reordering: per entry within 1e-12 of the sum of
   |contributions|.  Replay is bitwise repeatable.
 * The fixed-shape hub sum (chunks of 256, then recursively) is pinned by a case
-  where the chunk shape decides the result."""
+  where the chunk shape decides the result.
+* Series resistors of a split netlist (Benchmark 2, Table I's R rows): their linear
+  part is the incidence-matrix Laplacian N diag(g) N^T; a resistor divider solved
+  from the assembled system gives the closed-form divider voltages; merging every
+  private node back onto its original net gives the unsplit circuit's system; and
+  the split system is Newton's linearisation of KCL with resistor currents."""
 import numpy as np
 import pytest
 
@@ -20,6 +25,12 @@ NC, PC = G.default_card(1), G.default_card(-1)
 
 def residual(orc, circ, x, ag0, hist=None):
     F = np.zeros(circ.n_rows)
+    for (p, q), g in zip(circ.res if circ.res is not None else [], circ.res_g if circ.res is not None else []):
+        i = g * ((0.0 if p == 0 else x[p - 1]) - (0.0 if q == 0 else x[q - 1]))   # p -> q
+        if p:
+            F[p - 1] += i
+        if q:
+            F[q - 1] -= i
     for v in range(circ.n_dev):
         t = circ.term[v]
         V = np.array([0.0 if n == 0 else x[n - 1] for n in t])
@@ -39,9 +50,19 @@ def dense(rp, ci, A, n):
     return M
 
 
+def split_case(rule, seed):
+    # a one-bit adder cell split by series resistors whose conductances are drawn so
+    # that resistor and FET currents are of one order
+    circ, _ = G.split_nets(G.ripple_adder28(1), rule)
+    circ = G.draw_params(circ, np.random.default_rng(seed), G.W_CHAIN, G.L_CHAIN)
+    circ.res_g = np.random.default_rng(seed + 1).uniform(1e-5, 1e-3, circ.n_res)
+    return circ
+
+
 @pytest.mark.parametrize("make", [lambda: G.workload(0), lambda: G.draw_params(
-    G.opamp2(12), np.random.default_rng(3), G.W_OPAMP, G.L_OPAMP), lambda: G.sram_case(3, 4, 9)],
-    ids=["chain50", "opamp12", "sram3x4"])
+    G.opamp2(12), np.random.default_rng(3), G.W_OPAMP, G.L_OPAMP), lambda: G.sram_case(3, 4, 9),
+    lambda: split_case("all", 5), lambda: split_case("rail", 6)],
+    ids=["chain50", "opamp12", "sram3x4", "adder1r89", "adder1r14"])
 def test_assembly_is_newtons_linearisation(orc, make):
     circ = make()
     rng = np.random.default_rng(0)
@@ -119,3 +140,107 @@ def test_replay_uses_hubsum_for_rail_entries(orc):
     for x in vals[1:]:
         s = s + x
     assert A[rp[0]] == s          # (vdd, vdd) is the first entry of row 0
+
+
+def netlist(n_nodes, res, g, term=None, pol=None, vdd=1.0):
+    """A circuit of series resistors (and optional FETs) with vdd on node 1."""
+    term = np.zeros((0, 4), np.int32) if term is None else np.asarray(term, np.int32).reshape(-1, 4)
+    pol = np.zeros(0, np.int8) if pol is None else np.asarray(pol, np.int8)
+    excl = np.zeros(n_nodes, np.uint8)
+    c = G.Circuit("resnet", n_nodes, term, pol, np.array([[1, 0]], np.int32), np.array([vdd]), excl,
+                  vdd, res=np.asarray(res, np.int32).reshape(-1, 2), res_g=np.asarray(g, np.float64))
+    c.W = np.full(c.n_dev, 1e-6); c.L = np.full(c.n_dev, 50e-9); c.VTH0 = 0.4 * c.pol.astype(float)
+    c.x = np.zeros(c.n_rows)
+    return c
+
+
+def test_linear_part_is_the_incidence_laplacian(orc):
+    # dyadic conductances add exactly in any order, so the stamp sums must equal the
+    # product N diag(g) N^T of the node-resistor incidence matrix bit for bit;
+    # grounded resistors, parallel resistors and a self-loop (no effect) included
+    rng = np.random.default_rng(11)
+    n_nodes, m = 40, 300
+    res = rng.integers(0, n_nodes, (m, 2)).astype(np.int32)
+    res[:5] = [(3, 0), (0, 7), (5, 5), (9, 12), (12, 9)]
+    g = rng.integers(1, 64, m) / 8.0
+    circ = netlist(n_nodes, res, g)
+    rp, ci = orc.pattern(circ)
+    Lin, touched = orc.linear_stamp(circ, rp, ci)
+    N = np.zeros((n_nodes, m))
+    N[res[:, 0], np.arange(m)] += 1.0
+    N[res[:, 1], np.arange(m)] -= 1.0
+    lap = (N * g) @ N.T
+    n = circ.n_rows
+    D = dense(rp, ci, Lin, n)
+    assert np.array_equal(D[:n_nodes - 1, :n_nodes - 1], lap[1:, 1:])
+    assert not D[n_nodes - 1:].any() and not D[:, n_nodes - 1:].any()   # branch row untouched
+    # touched: exactly the entries of non-ground resistor ends (self-loop's diagonal too)
+    want = np.zeros((n, n), bool)
+    for (p, q) in res:
+        for r, c in ((p, p), (p, q), (q, p), (q, q)):
+            if r and c:
+                want[r - 1, c - 1] = True
+    assert np.array_equal(dense(rp, ci, touched.astype(float), n) > 0, want)
+    # magnitude: sum of |stamps|, the same product with the unsigned incidence matrix
+    Lm, _ = orc.linear_stamp(circ, rp, ci, magnitude=True)
+    U = np.zeros((n_nodes, m))
+    U[res[:, 0], np.arange(m)] += 1.0
+    U[res[:, 1], np.arange(m)] += 1.0
+    lm = (U * g) @ U.T
+    assert np.array_equal(dense(rp, ci, Lm, n)[:n_nodes - 1, :n_nodes - 1], lm[1:, 1:])
+
+
+def test_resistor_divider_closed_form(orc):
+    # vdd -> R0 -> node 2 -> R1 -> ... -> R_{k-1} -> ground: node j carries
+    # Vdd * (sum of the resistances below it) / (total), the source carries Vdd / total
+    R = np.array([1.0, 2.0, 3.0, 5.0, 8.0, 13.0])
+    k = R.size
+    nodes = [1] + list(range(2, k + 1)) + [0]
+    res = [(nodes[i], nodes[i + 1]) for i in range(k)]
+    vdd = 1.8
+    circ = netlist(k + 1, res, 1.0 / R, vdd=vdd)
+    rp, ci = orc.pattern(circ)
+    for col in (None, np.zeros(0, np.int32)):
+        A, b = orc.assemble(circ, rp, ci, NC, PC, 1e12, col=col)
+        x = np.linalg.solve(dense(rp, ci, A, circ.n_rows), b)
+        below = np.cumsum(R[::-1])[::-1]          # resistance from each node down to ground
+        assert np.allclose(x[:k], vdd * below / R.sum(), rtol=1e-14, atol=0)
+        assert np.isclose(x[k], -vdd / R.sum(), rtol=1e-14)   # branch current: into pos, out of neg
+
+
+@pytest.mark.parametrize("rule", ["all", "rail"])
+@pytest.mark.parametrize("make", [lambda: G.ripple_adder28(2), lambda: G.random_netlist(120, 9, 3),
+                                  lambda: G.workload(0)], ids=["adder2", "random120x9", "chain50"])
+def test_split_netlist_merges_back_onto_the_unsplit_system(orc, rule, make):
+    # folding every private node back onto the net its resistor ties it to, with the
+    # private nodes at their net's voltage, cancels the resistor stamps and leaves the
+    # unsplit circuit's A and b (up to the reordering of the sums)
+    base = make()
+    if base.W is None:
+        base = G.draw_params(base, np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)
+    split, n_res = G.split_nets(base, rule)
+    assert n_res == split.n_res > 0
+    owner = np.arange(split.n_nodes)
+    for p, q in split.res:
+        owner[p] = q                               # private node -> original net
+    assert np.all(owner[owner] == owner)
+    n0, n1 = base.n_nodes - 1, split.n_nodes - 1
+    rowmap = np.concatenate([owner[1:] - 1, n0 + np.arange(base.vsrc.shape[0])])
+    split.W, split.L, split.VTH0 = base.W, base.L, base.VTH0
+    split.x = base.x[rowmap]
+    rp, ci = orc.pattern(base)
+    A0, b0 = orc.assemble(base, rp, ci, NC, PC, 1e12)
+    mA0, mb0 = orc.assemble_magnitude(base, rp, ci, NC, PC, 1e12)
+    srp, sci = orc.pattern(split)
+    for col in (None, orc.colour(split, False)[0]):
+        A1, b1 = orc.assemble(split, srp, sci, NC, PC, 1e12, col=col)
+        mA1, _ = orc.assemble_magnitude(split, srp, sci, NC, PC, 1e12)
+        P = np.zeros((split.n_rows, base.n_rows))
+        P[np.arange(split.n_rows), rowmap] = 1.0
+        M = P.T @ dense(srp, sci, A1, split.n_rows) @ P
+        Mm = P.T @ dense(srp, sci, mA1, split.n_rows) @ P
+        assert np.all(np.abs(M - dense(rp, ci, A0, base.n_rows)) <= 1e-13 * (Mm + dense(rp, ci, mA0, base.n_rows)))
+        assert np.all(np.abs(P.T @ b1 - b0) <= 1e-13 * mb0)
+    # the split netlist's FETs share no net that the rule split
+    if rule == "all":
+        assert orc.colour(split, False)[1] == 1
