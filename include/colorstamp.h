@@ -93,6 +93,18 @@ cs_status cs_circuit_create(int32_t n_nodes, int32_t n_dev, const int32_t *term,
                             const double *vsrc_volts, cs_circuit **out);
 void cs_circuit_destroy(cs_circuit *c);
 
+/* Series resistors of a split netlist (Benchmark 2: Table I's R14 and R89 adders,
+ * where small resistors cut shared nets so fewer FETs conflict).  nodes: n_res*2
+ * (p, q) node ids, 0 <= id < n_nodes (0 ground); g: n_res conductances in siemens,
+ * finite.  Host pointers, copied; a later call replaces the set (n_res = 0 clears).
+ * Resistors are linear and do not enter the FET conflict graph: each adds +g at
+ * (p,p) and (q,q) and -g at (p,q) and (q,p) of A (ground rows and columns
+ * dropped), nothing to b.  Per entry these stamps are summed from zero in resistor
+ * order, and the sum is added once to A after every device contribution (an entry
+ * no device writes receives 0 + sum).  Must precede cs_build_stamp_map (CS_ESTATE
+ * after it, until the next colouring). */
+cs_status cs_set_resistors(cs_circuit *c, int32_t n_res, const int32_t *nodes, const double *g);
+
 /* Conflict graph and greedy colouring (Methodology; Introduction for the greedy
  * rule).  exclude: n_nodes host flags of nodes that do not create conflicts (NULL:
  * only ground, the paper's rule).  Devices are visited in ascending index and take
@@ -118,8 +130,10 @@ cs_status cs_build_coloring_order(cs_circuit *c, const uint8_t *exclude, int32_t
                                   int32_t *colour_out, int64_t *n_edges);
 
 /* CSR pattern and the device-to-slot stamp map (Methodology: stamps touch common
- * MNA rows/columns).  Requires cs_build_coloring.  Uploads topology and map to the
- * current HIP device.  Outputs: number of rows and nonzeros. */
+ * MNA rows/columns).  The pattern holds every node pair of a device, every node
+ * diagonal, the voltage-source pairs and each resistor's (p,q), (q,p).  Requires
+ * cs_build_coloring.  Uploads topology and map to the current HIP device.
+ * Outputs: number of rows and nonzeros. */
 cs_status cs_build_stamp_map(cs_circuit *c, int32_t *n_rows, int64_t *nnz);
 
 /* Host copies of the pattern: row_ptr[n_rows+1], col_idx[nnz]. */
@@ -146,7 +160,8 @@ cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const d
  * (0 for a DC stamp); hist: device, n_dev*4 history terms in original device order,
  * or NULL.  Per device the local conductance matrix Y = dI/dV + ag0*dQ/dV and
  * right-hand side Y*(V - Vs) - I - ag0*Q (+ hist) are merged onto its node pairs and
- * accumulated: colour by colour, first writer stores, later writers add. */
+ * accumulated: colour by colour, first writer stores, later writers add.  The
+ * linear part of the series resistors (cs_set_resistors) follows on `stream`. */
 cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
                         const double *hist, double *A_val, double *b, void *stream);
 

@@ -23,7 +23,8 @@ CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "d
 
 # Every entry point of include/colorstamp.h.
 EXPORTS = (
-    "cs_circuit_create", "cs_circuit_destroy", "cs_build_coloring", "cs_build_coloring_order",
+    "cs_circuit_create", "cs_circuit_destroy", "cs_set_resistors", "cs_build_coloring",
+    "cs_build_coloring_order",
     "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
     "cs_vjp", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
@@ -63,6 +64,7 @@ def lib():
         i32, i64, d, p = C.c_int32, C.c_int64, C.c_double, C.c_void_p
         sig = {
             "cs_circuit_create": [i32, i32, p, p, i32, p, p, p],
+            "cs_set_resistors": [p, i32, p, p],
             "cs_build_coloring": [p, p, p, p, p],
             "cs_build_coloring_order": [p, p, i32, p, p, p],
             "cs_build_stamp_map": [p, p, p],
@@ -183,7 +185,20 @@ class Circuit:
 
     @classmethod
     def from_netlist(cls, circ):
-        return cls(circ.n_nodes, circ.term, circ.pol, circ.vsrc, circ.vsrc_volts)
+        c = cls(circ.n_nodes, circ.term, circ.pol, circ.vsrc, circ.vsrc_volts)
+        if getattr(circ, "res", None) is not None and len(circ.res):
+            c.set_resistors(circ.res, circ.res_g)
+        return c
+
+    def set_resistors(self, nodes, g):
+        """Series resistors (linear, stamped after the FETs): (n, 2) node pairs and
+        conductances in siemens.  Before build_map."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32).reshape(-1, 2)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        if g.shape[0] != nodes.shape[0]:
+            raise ValueError("one conductance per resistor")
+        _check(lib().cs_set_resistors(self._h, nodes.shape[0], _np_ptr(nodes), _np_ptr(g)),
+               "cs_set_resistors")
 
     def __del__(self):
         h = getattr(self, "_h", None)

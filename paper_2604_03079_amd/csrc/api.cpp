@@ -1,6 +1,7 @@
 // C-ABI of the colorstamp library: argument and state checks, uploads, dispatch of
 // the kernel variants.  No exception crosses the ABI.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -83,6 +84,8 @@ cs_status upload_circuit(cs_circuit *c) {
     CS_CHECK_HIP(c->d_fixA_val.upload(h.fixA_val), "upload fixed stores");
     CS_CHECK_HIP(c->d_fixB_idx.upload(h.fixB_idx), "upload fixed stores");
     CS_CHECK_HIP(c->d_fixB_val.upload(h.fixB_val), "upload fixed stores");
+    CS_CHECK_HIP(c->d_linA_idx.upload(h.linA_idx), "upload linear part");
+    CS_CHECK_HIP(c->d_linA_val.upload(h.linA_val), "upload linear part");
     CS_CHECK_HIP(c->d_hub_ptr.upload(h.hub_ptr), "upload hub lists");
     CS_CHECK_HIP(c->d_hub_target.upload(h.hub_target), "upload hub lists");
     CS_CHECK_HIP(c->d_stage.alloc(h.hub_ptr.empty() ? 0 : (size_t)h.hub_ptr.back()), "alloc staging");
@@ -284,6 +287,25 @@ cs_status cs_circuit_create(int32_t n_nodes, int32_t n_dev, const int32_t *term,
 
 void cs_circuit_destroy(cs_circuit *c) { delete c; }
 
+cs_status cs_set_resistors(cs_circuit *c, int32_t n_res, const int32_t *nodes, const double *g) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (n_res < 0) return fail(CS_EINVAL, "negative resistor count");
+    if (n_res > 0 && (!nodes || !g)) return fail(CS_EINVAL, "NULL input array");
+    if (c->h.mapped) return fail(CS_ESTATE, "resistors must be set before cs_build_stamp_map");
+    if (2 * (int64_t)n_res >= INDEX_LIMIT) return fail(CS_ENOTSUP, "too many resistors");
+    for (int64_t i = 0; i < 2 * (int64_t)n_res; ++i)
+        if (nodes[i] < 0 || nodes[i] >= c->h.n_nodes) return fail(CS_EINVAL, "resistor node id out of range");
+    for (int32_t i = 0; i < n_res; ++i)
+        if (!std::isfinite(g[i])) return fail(CS_EINVAL, "resistor conductance not finite");
+    try {
+        c->h.res.assign(nodes, nodes + 2 * (size_t)n_res);
+        c->h.res_g.assign(g, g + (size_t)n_res);
+    } catch (...) {
+        return fail(CS_ENOMEM, "host allocation");
+    }
+    return CS_OK;
+}
+
 cs_status cs_build_coloring(cs_circuit *c, const uint8_t *exclude, int32_t *n_colors,
                             int32_t *colour_out, int64_t *n_edges) {
     return cs_build_coloring_order(c, exclude, CS_ORDER_NATURAL, n_colors, colour_out, n_edges);
@@ -442,17 +464,9 @@ cs_status cs_get_info(const cs_circuit *c, int64_t *n_dev, int32_t *n_rows, int6
     return CS_OK;
 }
 
-cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
-                        const double *hist, double *A_val, double *b, void *stream) {
-    if (!c) return fail(CS_EINVAL, "NULL circuit");
-    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
-    if (!c->models_set) return fail(CS_ESTATE, "cs_set_models must come first");
-    if (!c->params_set) return fail(CS_ESTATE, "cs_set_params must come first");
-    if (!x || !A_val || !b) return fail(CS_EINVAL, "NULL x, A or b");
-    if (current_device() != c->device) return fail(CS_ESTATE, "circuit uploaded to another device");
-    hipStream_t s = (hipStream_t)stream;
+// The device contributions under one schedule (everything but the linear part).
+static cs_status eval_devices(cs_circuit *c, cs_variant variant, const KCall &call, hipStream_t s) {
     const KCirc kc = make_kcirc(c);
-    const KCall call{x, ag0, hist, A_val, b};
     switch (variant) {
         case CS_COLOR_PERSISTENT:
             if (c->eval_ahead_req != 0) {
@@ -544,6 +558,24 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
         default:
             return fail(CS_EINVAL, "unknown variant");
     }
+}
+
+cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
+                        const double *hist, double *A_val, double *b, void *stream) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    if (!c->models_set) return fail(CS_ESTATE, "cs_set_models must come first");
+    if (!c->params_set) return fail(CS_ESTATE, "cs_set_params must come first");
+    if (!x || !A_val || !b) return fail(CS_EINVAL, "NULL x, A or b");
+    if (current_device() != c->device) return fail(CS_ESTATE, "circuit uploaded to another device");
+    hipStream_t s = (hipStream_t)stream;
+    const KCall call{x, ag0, hist, A_val, b};
+    cs_status st = eval_devices(c, variant, call, s);
+    if (st != CS_OK) return st;
+    // series resistors on entries that devices also write: added after every contribution
+    CS_CHECK_HIP(launch_linear_add((int32_t)c->h.linA_idx.size(), c->d_linA_idx.p, c->d_linA_val.p, A_val, s),
+                 "linear-part launch");
+    return CS_OK;
 }
 
 cs_status cs_plan_regions(cs_circuit *c, int32_t block) {

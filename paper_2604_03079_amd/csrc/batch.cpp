@@ -142,6 +142,15 @@ cs_status pack(cs_batch *B) {
             P.fixB_val.push_back(h.fixB_val[e]);
         }
     }
+    // linear parts of the circuits' series resistors
+    P.linA_idx.clear(); P.linA_val.clear();
+    for (size_t i = 0; i < nc; ++i) {
+        const HostCircuit &h = B->circ[i]->h;
+        for (size_t e = 0; e < h.linA_idx.size(); ++e) {
+            P.linA_idx.push_back((int32_t)(h.linA_idx[e] + B->nnz_off[i]));
+            P.linA_val.push_back(h.linA_val[e]);
+        }
+    }
     // hubs: global circuits first (their chunks form the global hub phase), then
     // each local circuit's own chunk range
     P.hub_ptr.assign(1, 0);
@@ -187,6 +196,8 @@ cs_status upload(cs_batch *B) {
     CS_BCHECK(B->d_fixA_val.upload(P.fixA_val), "upload fixed stores");
     CS_BCHECK(B->d_fixB_idx.upload(P.fixB_idx), "upload fixed stores");
     CS_BCHECK(B->d_fixB_val.upload(P.fixB_val), "upload fixed stores");
+    CS_BCHECK(B->d_linA_idx.upload(P.linA_idx), "upload linear part");
+    CS_BCHECK(B->d_linA_val.upload(P.linA_val), "upload linear part");
     CS_BCHECK(B->d_hub_ptr.upload(P.hub_ptr), "upload hubs");
     CS_BCHECK(B->d_hub_target.upload(P.hub_target), "upload hubs");
     CS_BCHECK(B->d_hub_cptr.upload(P.hub_cptr), "upload hubs");
@@ -484,16 +495,18 @@ cs_status cs_batch_eval_stamp(cs_batch *B, const double *x, double ag0, const do
         const KCirc kc = make_kc(B);
         CS_BCHECK(launch_region(region_kcirc(kc, B->rp, B->rd), call, region_kregion(B->rp, B->rd), B->block,
                                 (hipStream_t)stream), "batched region launch");
-        return CS_OK;
+    } else {
+        cs_status st = plan(B);
+        if (st != CS_OK) return st;
+        const KCirc kc = make_kc(B);
+        const KSync ks{B->d_sync.p, B->spin_limit};
+        const KLocal kl{B->n_local, B->d_local.p, B->d_local_cptr.p};
+        CS_BCHECK(launch_persistent(kc, call, ks, nullptr, B->eval_ahead, B->grid, B->block, B->cooperative,
+                                    (hipStream_t)stream, B->n_part, B->n_global_chunks, kl),
+                  "batched persistent launch");
     }
-    cs_status st = plan(B);
-    if (st != CS_OK) return st;
-    const KCirc kc = make_kc(B);
-    const KSync ks{B->d_sync.p, B->spin_limit};
-    const KLocal kl{B->n_local, B->d_local.p, B->d_local_cptr.p};
-    CS_BCHECK(launch_persistent(kc, call, ks, nullptr, B->eval_ahead, B->grid, B->block, B->cooperative,
-                                (hipStream_t)stream, B->n_part, B->n_global_chunks, kl),
-              "batched persistent launch");
+    CS_BCHECK(launch_linear_add((int32_t)B->h.linA_idx.size(), B->d_linA_idx.p, B->d_linA_val.p, A,
+                                (hipStream_t)stream), "linear-part launch");
     return CS_OK;
 }
 

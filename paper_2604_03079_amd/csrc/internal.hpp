@@ -54,6 +54,8 @@ struct HostCircuit {
     std::vector<int8_t> pol;          // n_dev
     std::vector<int32_t> vsrc;        // n_vsrc*2
     std::vector<double> vsrc_volts;   // n_vsrc
+    std::vector<int32_t> res;         // 2*n_res: series resistors' nodes (linear, stamped after the FETs)
+    std::vector<double> res_g;        // n_res: their conductances
 
     // colouring
     bool coloured = false;
@@ -72,6 +74,8 @@ struct HostCircuit {
     std::vector<int32_t> acode;       // NCODE*n_dev, plain A/b targets (atomic variant)
     std::vector<int32_t> fixA_idx, fixB_idx;
     std::vector<double> fixA_val, fixB_val;
+    std::vector<int32_t> linA_idx;    // entries with device writers and a linear part
+    std::vector<double> linA_val;     // that part, added after the device contributions
     std::vector<int32_t> hub_ptr;     // n_hub+1 into the staging array
     std::vector<int32_t> hub_target;  // A index, or b row | HUB_B_FLAG
     std::vector<int32_t> hub_cptr;    // n_hub+1: chunk ranges (chunks of HUB_K)
@@ -154,6 +158,8 @@ struct cs_circuit {
         d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk;
     cs::DevBuf<int8_t> d_pol;
     cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_buf, d_hub_part;
+    cs::DevBuf<int32_t> d_linA_idx;
+    cs::DevBuf<double> d_linA_val;
     cs::DevBuf<int32_t> d_ipos;   // device index -> position (serial stamping)
     cs::DevBuf<uint32_t> d_sync;       // barrier words + per-block arrival flags + error
     cs::DevBuf<uint32_t> d_hub_count;
@@ -193,6 +199,8 @@ struct cs_batch {
         d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk, d_local, d_local_cptr;
     cs::DevBuf<int8_t> d_pol;
     cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_hub_part;
+    cs::DevBuf<int32_t> d_linA_idx;
+    cs::DevBuf<double> d_linA_val;
     cs::DevBuf<uint32_t> d_sync, d_hub_count;
     // launch
     int32_t block = 256;

@@ -324,6 +324,17 @@ __global__ void k_fixed(KCirc kc, KCall call) {
     fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
+// Linear part (series resistors) of entries that devices also write, after the
+// device contributions: one entry per lane, each listed once.
+__global__ void __launch_bounds__(256) k_linear_add(int32_t n, const int32_t *__restrict__ idx,
+                                                     const double *__restrict__ val, double *__restrict__ A) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int32_t s = idx[i];
+        A[s] = A[s] + val[i];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
     __shared__ double lds[4 * HUB_K];
     hub_chunks(kc, call, 0, kc.n_hub_chunks, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
@@ -899,6 +910,12 @@ hipError_t launch_colour_phase(const KCirc &kc, const KCall &call, int c, int co
 hipError_t launch_fixed(const KCirc &kc, const KCall &call, hipStream_t s) {
     const int grid = std::max(1, std::min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
     hipLaunchKernelGGL(k_fixed, dim3(grid), dim3(256), 0, s, kc, call);
+    return hipGetLastError();
+}
+
+hipError_t launch_linear_add(int32_t n, const int32_t *idx, const double *val, double *A, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_linear_add, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, val, A);
     return hipGetLastError();
 }
 

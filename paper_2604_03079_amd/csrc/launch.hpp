@@ -16,6 +16,9 @@ hipError_t launch_colour_phase(const KCirc &kc, const KCall &call, int c, int co
                                int with_fixed, hipStream_t s);
 hipError_t launch_fixed(const KCirc &kc, const KCall &call, hipStream_t s);
 hipError_t launch_hub(const KCirc &kc, const KCall &call, hipStream_t s);
+// A[idx[i]] = A[idx[i]] + val[i] for i < n (the linear part of entries that devices
+// also write); nothing is launched when n == 0.
+hipError_t launch_linear_add(int32_t n, const int32_t *idx, const double *val, double *A, hipStream_t s);
 // cooperative: hipLaunchCooperativeKernel (the runtime checks co-residency);
 // otherwise an ordinary launch of a grid the occupancy query says fits at once.
 // n_part: blocks [0, n_part) run the grid-barrier colour schedule over the first

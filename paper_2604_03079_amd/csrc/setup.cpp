@@ -236,6 +236,13 @@ Err build_map(HostCircuit &h) {
             cols[(size_t)br].push_back(nd - 1);
         }
     }
+    const size_t n_res = h.res_g.size();
+    for (size_t j = 0; j < n_res; ++j) {
+        const int32_t p = h.res[2 * j], q = h.res[2 * j + 1];
+        if (p == 0 || q == 0) continue;
+        cols[(size_t)p - 1].push_back(q - 1);
+        cols[(size_t)q - 1].push_back(p - 1);
+    }
     h.row_ptr.assign((size_t)n_rows + 1, 0);
     h.col_idx.clear();
     for (int64_t r = 0; r < n_rows; ++r) {
@@ -353,8 +360,37 @@ Err build_map(HostCircuit &h) {
         h.fixB_val.push_back(h.vsrc_volts[(size_t)j]);
         wrote_b[(size_t)br] = -2;
     }
-    for (int64_t s = 0; s < h.nnz; ++s)
-        if (wrote_A[(size_t)s] == -1) { h.fixA_idx.push_back((int32_t)s); h.fixA_val.push_back(0.0); }
+    // linear part of the series resistors: +g on the two diagonals, -g between the
+    // nodes, summed per entry in resistor order from zero.  It is added once after the
+    // device contributions: as the fixed store (0 + part) of an entry no device
+    // writes, else by the linear-add pass that follows every schedule.
+    std::vector<double> lin;
+    std::vector<uint8_t> lin_on;
+    if (n_res) {
+        lin.assign((size_t)h.nnz, 0.0);
+        lin_on.assign((size_t)h.nnz, 0);
+        for (size_t j = 0; j < n_res; ++j) {
+            const int32_t nd[2] = {h.res[2 * j], h.res[2 * j + 1]};
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) {
+                    if (nd[r] == 0 || nd[c] == 0) continue;
+                    const int32_t s = slot_of(nd[r] - 1, nd[c] - 1);
+                    lin[(size_t)s] = lin[(size_t)s] + (r == c ? h.res_g[j] : -h.res_g[j]);
+                    lin_on[(size_t)s] = 1;
+                }
+        }
+    }
+    h.linA_idx.clear(); h.linA_val.clear();
+    for (int64_t s = 0; s < h.nnz; ++s) {
+        const bool on = n_res && lin_on[(size_t)s];
+        if (wrote_A[(size_t)s] == -1) {
+            h.fixA_idx.push_back((int32_t)s);
+            h.fixA_val.push_back(on ? 0.0 + lin[(size_t)s] : 0.0);
+        } else if (on) {
+            h.linA_idx.push_back((int32_t)s);
+            h.linA_val.push_back(lin[(size_t)s]);
+        }
+    }
     for (int64_t r = 0; r < n_rows; ++r)
         if (wrote_b[(size_t)r] == -1) { h.fixB_idx.push_back((int32_t)r); h.fixB_val.push_back(0.0); }
     h.mapped = true;

@@ -48,6 +48,12 @@ class Circuit:
     L: np.ndarray | None = None
     VTH0: np.ndarray | None = None
     x: np.ndarray | None = None  # float64 (n_rows,)
+    res: np.ndarray | None = None    # int32 (n_res, 2): series resistors' nodes (linear elements)
+    res_g: np.ndarray | None = None  # float64 (n_res,): their conductances, siemens
+
+    @property
+    def n_res(self) -> int:
+        return 0 if self.res is None else int(self.res.shape[0])
 
     @property
     def n_dev(self) -> int:
@@ -260,38 +266,58 @@ def ripple_adder28(n_bits: int, vdd: float = 1.0) -> Circuit:
     return _finish(f"adder{n_bits}x28", 3 + 16 * n_bits, devs, vdd)
 
 
+R_SERIES = 1e-3   # ohm: the series resistors of Table I's R14 and R89 netlists
+
+
 def split_nets(circ: Circuit, rule: str) -> tuple[Circuit, int]:
     """Series-resistor net splitting (Table I's R rows): chosen terminal connections
-    of each FET move to a private node, which a series resistor would tie back to the
-    original net.  Returns the FET netlist (private nodes appended after the original
-    ones, in device then terminal order) and the number of resistors.  The resistors
-    are linear elements outside the FET evaluate-and-stamp path; the FET conflict graph
-    only sees that the FETs no longer share those nets.
+    of each FET move to a private node, tied back to the original net by a series
+    resistor of R_SERIES.  Returns the netlist (private nodes appended after the
+    original ones, in device then terminal order; resistor j joins private node and
+    original net, in that order, with conductance 1/R_SERIES) and the number of
+    resistors.  The resistors are linear elements stamped after the FETs; the FET
+    conflict graph only sees that the FETs no longer share those nets.
       rule "all":  every non-ground terminal connection (no two FETs share a node)
       rule "rail": the vdd connections of each FET (its vdd-tied terminals share one
                    private node per FET)"""
     term = circ.term.copy()
     n_nodes = circ.n_nodes
-    n_res = 0
+    res = []
     for k in range(circ.n_dev):
         if rule == "all":
             for t in range(4):
                 if term[k, t] != 0:
+                    res.append((n_nodes, int(circ.term[k, t])))
                     term[k, t] = n_nodes
                     n_nodes += 1
-                    n_res += 1
         elif rule == "rail":
             on = [t for t in range(4) if circ.term[k, t] == 1]
             if on:
+                res.append((n_nodes, 1))
                 term[k, on] = n_nodes
                 n_nodes += 1
-                n_res += 1
         else:
             raise ValueError(rule)
     excl = np.zeros(n_nodes, dtype=np.uint8)
     excl[:circ.n_nodes] = circ.exclude
+    r = np.array(res, dtype=np.int32).reshape(-1, 2)
+    g = np.full(r.shape[0], 1.0 / R_SERIES)
     return Circuit(f"{circ.name}_{rule}", n_nodes, term, circ.pol.copy(), circ.vsrc.copy(),
-                   circ.vsrc_volts.copy(), excl, circ.vdd), n_res
+                   circ.vsrc_volts.copy(), excl, circ.vdd, res=r, res_g=g), r.shape[0]
+
+
+def with_random_resistors(circ: Circuit, n_res: int, seed: int) -> Circuit:
+    """Add resistors between uniformly drawn nodes (ground, vdd, self-loops and
+    parallel pairs included) with conductances uniform in [1e-4, 1e-2] S: linear
+    parts on entries the FETs also write, on rail entries and on new entries."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = rng.integers(0, circ.n_nodes, size=(n_res, 2)).astype(np.int32)
+    g = rng.uniform(1e-4, 1e-2, n_res)
+    if circ.res is not None:
+        r = np.concatenate([circ.res, r])
+        g = np.concatenate([circ.res_g, g])
+    circ.res, circ.res_g = r, g
+    return circ
 
 
 def adder_case(n_bits: int, seed: int, split: str | None = None) -> Circuit:

@@ -110,6 +110,41 @@ def test_autotuner_picks_a_valid_configuration(torch_dev, batch_oracle, tmp_path
         assert np.array_equal(bits(Ah[B.nnz_off[i]:B.nnz_off[i + 1]]), bits(A0))
 
 
+@pytest.mark.parametrize("schedule", ["persistent", "region"])
+def test_batch_with_series_resistors(torch_dev, orc, schedule):
+    # split netlists and random resistors in one batch: each circuit's linear part
+    # is added after the batched schedule, bitwise the oracle's replay
+    torch = torch_dev
+    rng = np.random.default_rng(12)
+    circs = [G.draw_params(G.split_nets(G.ripple_adder28(3), "all")[0], rng, G.W_CHAIN, G.L_CHAIN),
+             G.workload(0),
+             G.draw_params(G.split_nets(G.ripple_adder28(2), "rail")[0], rng, G.W_CHAIN, G.L_CHAIN),
+             G.with_random_resistors(G.draw_params(G.random_netlist(200, 6, 26), rng, G.W_CHAIN, G.L_CHAIN),
+                                     80, 27)]
+    ref = []
+    for c in circs:
+        rp, ci = orc.pattern(c)
+        col, _, _ = orc.colour(c, True)
+        ref.append(orc.assemble(c, rp, ci, NC, PC, 1e12, col=col, exclude=True))
+    B = CS.Batch([CS.prepare(c, True) for c in circs])
+    B.set_launch(256, -1, 0, schedule)
+    W, L, V, x = (packed(torch, circs, a) for a in ("W", "L", "VTH0", "x"))
+    B.set_params(W, L, V)
+    A = torch.full((B.nnz,), float("nan"), dtype=torch.float64, device="cuda:0")
+    b = torch.full((B.n_rows,), float("nan"), dtype=torch.float64, device="cuda:0")
+    say(f"case batch with resistors {schedule} n_dev={B.n_dev}")
+    for _ in range(2):
+        B.eval_stamp(x, 1e12, None, A, b)
+    torch.cuda.synchronize()
+    B.check()
+    Ah, bh = A.cpu().numpy(), b.cpu().numpy()
+    for i, (A0, b0) in enumerate(ref):
+        z0, z1 = B.nnz_off[i], B.nnz_off[i + 1]
+        r0, r1 = B.row_off[i], B.row_off[i + 1]
+        assert np.array_equal(bits(Ah[z0:z1]), bits(A0)), f"circuit {i} ({circs[i].name}) A"
+        assert np.array_equal(bits(bh[r0:r1]), bits(b0)), f"circuit {i} ({circs[i].name}) b"
+
+
 def gpu_vjp(torch, circ, Ab, bb, ag0=1e12):
     c = CS.prepare(circ, True)
     dev = torch.device("cuda:0")
@@ -125,7 +160,10 @@ VJP_CASES = [("chain50", lambda: G.workload(0)),
              ("sram6x6", lambda: G.sram_case(6, 6, 8)),
              ("ring301", lambda: G.draw_params(G.ring_oscillator(301), np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)),
              ("random600x6", lambda: G.draw_params(G.random_netlist(600, 6, 21), np.random.default_rng(31),
-                                                   G.W_CHAIN, G.L_CHAIN))]
+                                                   G.W_CHAIN, G.L_CHAIN)),
+             # series resistors are constants: the gradients are the FETs' alone
+             ("adder4r89", lambda: G.draw_params(G.split_nets(G.ripple_adder28(4), "all")[0],
+                                                 np.random.default_rng(32), G.W_CHAIN, G.L_CHAIN))]
 
 
 @pytest.mark.parametrize("name,make", VJP_CASES, ids=[v[0] for v in VJP_CASES])

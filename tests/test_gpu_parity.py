@@ -4,7 +4,8 @@ Bars: the coloured variants (persistent, per-colour kernels, buffered, region) r
 oracle's colour replay bit for bit; the atomic variant (no colour order) agrees with
 the oracle's serial order within 1e-12 of the per-entry sum of |contributions|
 (the reordering bound).  Cases span several workgroups and ragged tails, both
-conflict rules, history terms, the empty circuit and the full workload sizes."""
+conflict rules, history terms, the empty circuit and the full workload sizes, and
+split netlists whose series resistors add a linear part after the FETs."""
 import sys
 
 import numpy as np
@@ -83,6 +84,11 @@ def small_cases():
         ("random600x6", G.draw_params(G.random_netlist(600, 6, 21), rng, G.W_CHAIN, G.L_CHAIN)),
         # every net split (one colour; PMOS with four distinct nodes: 20 codes)
         ("adder8r89", G.draw_params(G.split_nets(G.ripple_adder28(8), "all")[0], rng, G.W_CHAIN, G.L_CHAIN)),
+        # vdd connections split (the resistors' vdd ends are an entry no FET writes)
+        ("adder8r14", G.draw_params(G.split_nets(G.ripple_adder28(8), "rail")[0], rng, G.W_CHAIN, G.L_CHAIN)),
+        # resistors on FET-written, rail (hub) and new entries, self-loops and ground
+        ("random600x6r", G.with_random_resistors(G.draw_params(G.random_netlist(600, 6, 24), rng, G.W_CHAIN,
+                                                                G.L_CHAIN), 300, 25)),
     ]
     for k in range(8, 15):
         out.append((f"opamp{k}", G.draw_params(G.opamp2(k, 0.9), rng, G.W_OPAMP, G.L_OPAMP)))
@@ -116,7 +122,10 @@ def test_atomic_within_reordering_bound(torch_dev, orc, name, circ):
     assert np.all(np.abs(b - bs) <= 1e-12 * mb)
 
 
-@pytest.mark.parametrize("name,circ", SMALL[:9], ids=[s[0] for s in SMALL[:9]])
+SERIAL = SMALL[:9] + [s for s in SMALL if s[0] in ("adder8r89", "adder8r14", "random600x6r")]
+
+
+@pytest.mark.parametrize("name,circ", SERIAL, ids=[s[0] for s in SERIAL])
 def test_serial_stamp_equals_serial_order(torch_dev, orc, name, circ):
     # buffered evaluation, then one lane adds the devices in ascending index onto
     # zeroed A and b: bitwise the oracle's serial accumulation (hubs included)

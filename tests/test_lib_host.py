@@ -36,6 +36,9 @@ CASES = [
     ("adder3x28", lambda: G.ripple_adder28(3)),
     ("random600x6", lambda: G.random_netlist(600, 6, 21)),
     ("random2000x1500", lambda: G.random_netlist(2000, 1500, 22)),
+    ("adder2r89", lambda: G.split_nets(G.ripple_adder28(2), "all")[0]),
+    ("adder2r14", lambda: G.split_nets(G.ripple_adder28(2), "rail")[0]),
+    ("random300x7r", lambda: G.split_nets(G.random_netlist(300, 7, 23), "all")[0]),
 ]
 
 
@@ -156,3 +159,33 @@ def test_random_netlist_covers_every_terminal_pattern():
     every = {key(t) for t in itertools.product(range(5), repeat=4)}
     assert len(every) == 52
     assert {key(t) for t in G.random_netlist(600, 6, 21).term} == every
+
+
+def test_resistor_errors():
+    import ctypes
+    L = CS.lib()
+    circ = G.split_nets(G.ripple_adder28(1), "all")[0]
+    c = CS.Circuit.from_netlist(circ)
+    bad = circ.res.copy()
+    bad[4, 1] = circ.n_nodes
+    with pytest.raises(CS.CsError) as e:
+        c.set_resistors(bad, circ.res_g)
+    assert e.value.status == -1
+    g = circ.res_g.copy()
+    g[2] = np.nan
+    with pytest.raises(CS.CsError) as e:
+        c.set_resistors(circ.res, g)
+    assert e.value.status == -1
+    assert L.cs_set_resistors(c.handle, 3, None, None) == -1
+    assert L.cs_set_resistors(c.handle, -1, None, None) == -1
+    c.set_resistors(circ.res, circ.res_g)
+    c.colour(None)
+    c.build_map()
+    with pytest.raises(CS.CsError) as e:
+        c.set_resistors(circ.res, circ.res_g)     # after the map
+    assert e.value.status == -4
+    # the pattern grows by the resistors' off-diagonal pairs (every pair is new here)
+    p = CS.Circuit.from_netlist(circ)
+    p.set_resistors(np.zeros((0, 2), np.int32), np.zeros(0))
+    p.colour(None)
+    assert c.nnz - p.build_map()[1] == 2 * int(np.count_nonzero(circ.res.min(axis=1)))

@@ -152,7 +152,11 @@ def check_against_oracle(orc, circ, c, exclude, block):
     plan = c.region_plan(block)
     vals = [merged_values(orc, circ, v) for v in range(circ.n_dev)]
     out = replay(plan, vals, circ.pol, block, len(ci), circ.n_rows)
+    # a split netlist's series resistors: their linear part follows the schedule
+    Lin, touched = orc.linear_stamp(circ, rp, ci)
     for (kind, idx), v in out.items():
+        if kind == "A" and touched[idx]:
+            v = v + Lin[idx]
         ref = (A0 if kind == "A" else b0)[idx]
         assert np.float64(v).view(np.int64) == np.float64(ref).view(np.int64), (kind, idx, v, ref)
     return plan, out
