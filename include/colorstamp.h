@@ -165,6 +165,35 @@ cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const d
 cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
                         const double *hist, double *A_val, double *b, void *stream);
 
+/* Newton-Raphson loop around cs_eval_stamp (Introduction: each iteration evaluates
+ * the devices at x, stamps the linearised MNA system and solves it; the paper solves
+ * with KLU, Benchmark 2).  Per iteration on `stream`: cs_eval_stamp(variant) into
+ * A_val and b (caller-owned device workspace, nnz and n_rows), a sparse LU
+ * refactorisation of A and its triangular solves (rocSOLVER, with the pivots of one
+ * host factorisation made at the first call on this stamp map: nested-dissection
+ * order, threshold partial pivoting), leaving the Newton point y in b, then
+ * d = y - x with node rows clamped to [-vstep, vstep], x += d.  Stops when
+ * max |d| <= tol or after max_iter iterations.  x: device, n_rows, the start point
+ * on entry and the last iterate on return.  ag0 and hist as in cs_eval_stamp (a
+ * backward-Euler step when ag0 > 0; ag0 = 0 is a DC operating point).  Host
+ * outputs (each may be NULL): iterations done, converged (0/1), max |d| of the
+ * last iteration, times_ms[5] = summed milliseconds of stamping, refactorisation,
+ * solve and update, and the one-time host factorisation.  Returns CS_OK whether or
+ * not it converged; CS_EDOMAIN when a step is not finite (x then holds it) or the
+ * host factorisation finds the matrix singular. */
+cs_status cs_newton(cs_circuit *c, cs_variant variant, double *x, double ag0, const double *hist,
+                    int32_t max_iter, double vstep, double tol, double *A_val, double *b,
+                    int32_t *n_iter, int32_t *converged, double *last_step, double *times_ms,
+                    void *stream);
+
+/* The host factorisation cs_newton starts from, for inspection: A_host holds nnz
+ * values on the circuit's pattern.  *nnzT receives the size of T = (L - I) + U of
+ * P A Q (CSR over the permuted indices, columns ascending); P[k] is the row and Q[k]
+ * the column taken at step k.  Arrays (n_rows, n_rows, n_rows+1, nnzT, nnzT) may be
+ * NULL; call once with them NULL for the size.  CS_EDOMAIN if singular. */
+cs_status cs_factor_host(const cs_circuit *c, const double *A_host, int64_t *nnzT, int32_t *P,
+                         int32_t *Q, int32_t *ptrT, int32_t *indT, double *valT);
+
 /* Vector-Jacobian product of the stamped (A, b) with respect to W, L, VTH0:
  * W_bar[k] = sum_j A_bar[slot] * dA_contrib/dW_k + sum_r b_bar[r] * db_contrib/dW_k,
  * likewise L and VTH0.  All pointers are device memory in original device order;

@@ -9,7 +9,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_lib", "libcolorstamp.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "setup.cpp", "region.cpp", "api.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "setup.cpp", "region.cpp", "api.cpp", "batch.cpp", "sparse_lu.cpp",
+           "newton.cpp"]
+# the Newton loop's sparse refactorisation and triangular solves
+LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -27,7 +30,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     cmd = ["/opt/rocm/bin/hipcc"] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                                             "-o", OUT + ".tmp"] + srcs
+                                             "-o", OUT + ".tmp"] + srcs + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

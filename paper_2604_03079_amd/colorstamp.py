@@ -27,7 +27,7 @@ EXPORTS = (
     "cs_build_coloring_order",
     "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
-    "cs_vjp", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
+    "cs_vjp", "cs_newton", "cs_factor_host", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
     "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_set_plan_units", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
@@ -74,6 +74,8 @@ def lib():
             "cs_set_params": [p, p, p, p, p],
             "cs_eval_stamp": [p, C.c_int, p, d, p, p, p, p],
             "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
+            "cs_newton": [p, C.c_int, p, d, p, i32, d, d, p, p, p, p, p, p, p],
+            "cs_factor_host": [p, p, p, p, p, p, p, p],
             "cs_set_launch": [p, i32, i32, i32],
             "cs_get_info": [p, p, p, p, p, p, p, p, p],
             "cs_plan_regions": [p, i32],
@@ -299,6 +301,36 @@ class Circuit:
 
     def check(self, stream=None):
         _check(lib().cs_check(self._h, _stream(stream)), "cs_check")
+
+    def newton(self, x, ag0: float = 0.0, hist=None, max_iter: int = 100, vstep: float = 0.3,
+               tol: float = 1e-9, variant="region", A=None, b=None, stream=None) -> dict:
+        """Newton loop on the GPU from x (device, updated in place): iterations,
+        convergence, last max |step| and the summed phase times (ms)."""
+        import torch
+        if A is None:
+            A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
+        if b is None:
+            b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
+        it, conv, step = C.c_int32(), C.c_int32(), C.c_double()
+        t = (C.c_double * 5)()
+        _check(lib().cs_newton(self._h, VARIANTS[variant], _dev_ptr(x), float(ag0), _dev_ptr(hist), int(max_iter),
+                               float(vstep), float(tol), _dev_ptr(A), _dev_ptr(b), C.byref(it), C.byref(conv),
+                               C.byref(step), t, _stream(stream)), "cs_newton")
+        return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,
+                    ms=dict(stamp=t[0], refactor=t[1], solve=t[2], update=t[3], host_factor=t[4]))
+
+    def factor_host(self, A_host):
+        """The host LU the Newton loop starts from: P, Q and T = (L - I) + U (CSR)."""
+        Ah = np.ascontiguousarray(A_host, dtype=np.float64)
+        nz = C.c_int64()
+        L = lib()
+        _check(L.cs_factor_host(self._h, _np_ptr(Ah), C.byref(nz), None, None, None, None, None), "cs_factor_host")
+        n = self.n_rows
+        P, Q = np.zeros(n, np.int32), np.zeros(n, np.int32)
+        Tp, Ti, Tx = np.zeros(n + 1, np.int32), np.zeros(max(nz.value, 1), np.int32), np.zeros(max(nz.value, 1))
+        _check(L.cs_factor_host(self._h, _np_ptr(Ah), C.byref(nz), _np_ptr(P), _np_ptr(Q), _np_ptr(Tp), _np_ptr(Ti),
+                                _np_ptr(Tx)), "cs_factor_host")
+        return P, Q, Tp, Ti[:nz.value], Tx[:nz.value]
 
 
 def prepare(circ, exclude: bool = True, nmos=None, pmos=None, order: str = "natural"):

@@ -334,6 +334,8 @@ cs_status cs_build_stamp_map(cs_circuit *c, int32_t *n_rows, int64_t *nnz) {
     if (!c) return fail(CS_EINVAL, "NULL circuit");
     if (!c->h.coloured) return fail(CS_ESTATE, "cs_build_coloring must come first");
     try {
+        destroy_newton(c->newton);   // the solver's factor pattern belongs to the old map
+        c->newton = nullptr;
         Err e = build_map(c->h);
         c->rp = RegionPlan{};
         c->rd.ready = false;

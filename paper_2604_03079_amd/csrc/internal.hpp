@@ -145,6 +145,23 @@ Err build_map(HostCircuit &h);
 // Card-derived constants, in the model's operation order.
 DevCard derive_card(const cs_model_card &c);
 
+// Sparse LU of P A Q: row order P (P[k] = row pivoted at step k), column order Q,
+// and the bundle T = (L - I) + U in CSR over the permuted indices.
+struct HostLU {
+    std::vector<int32_t> P, Q, Tp, Ti;
+    std::vector<double> Tx;
+};
+// Column order Q of the circuit's MNA matrix (source pairs first, then nested
+// dissection) and the preferred pivot row of each column (-1: its own row).
+void mna_order(const HostCircuit &h, std::vector<int32_t> &Q, std::vector<int32_t> &pref);
+// One factorisation with threshold partial pivoting (host values of A in CSR).
+Err host_lu(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx,
+            const double *val, const std::vector<int32_t> &Q, const std::vector<int32_t> &pref, HostLU &F);
+
+// GPU state of the Newton loop (solver handles, factor pattern); released with the circuit.
+struct NewtonState;
+void destroy_newton(NewtonState *s);
+
 }  // namespace cs
 
 struct cs_circuit {
@@ -175,6 +192,11 @@ struct cs_circuit {
     int32_t rg_cap_block = 0, rg_cap_regions = -1;   // resident-region capacity cache
     int32_t plan_cus = -1;   // compute units the region planner targets (-1: the current GPU's)
     int64_t rg_cap = 0;
+    cs::NewtonState *newton = nullptr;   // built by the first cs_newton on this stamp map
+    cs_circuit() = default;
+    cs_circuit(const cs_circuit &) = delete;
+    cs_circuit &operator=(const cs_circuit &) = delete;
+    ~cs_circuit() { cs::destroy_newton(newton); }
 };
 
 struct cs_batch {

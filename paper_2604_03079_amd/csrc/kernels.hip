@@ -335,6 +335,34 @@ __global__ void __launch_bounds__(256) k_linear_add(int32_t n, const int32_t *__
     }
 }
 
+// Newton update after the solve (y = solution of A y = b at the present x).  The
+// clamp compares explicitly so that a NaN step stays NaN; the largest |d| of the
+// block is reduced in LDS and merged with one 64-bit atomic max on its bits (the
+// order of non-negative doubles, NaN above infinity).
+__global__ void __launch_bounds__(256) k_newton_update(int32_t n, int32_t n_clamp, const double *__restrict__ y,
+                                                       double *__restrict__ x, double vstep,
+                                                       unsigned long long *step_bits) {
+    __shared__ unsigned long long red[256];
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long m = 0;
+    if (i < n) {
+        double d = y[i] - x[i];
+        if (i < n_clamp) {
+            if (d > vstep) d = vstep;
+            else if (d < -vstep) d = -vstep;
+        }
+        x[i] = x[i] + d;
+        m = (unsigned long long)__double_as_longlong(fabs(d));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(step_bits, red[0]);
+}
+
 __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
     __shared__ double lds[4 * HUB_K];
     hub_chunks(kc, call, 0, kc.n_hub_chunks, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
@@ -916,6 +944,13 @@ hipError_t launch_fixed(const KCirc &kc, const KCall &call, hipStream_t s) {
 hipError_t launch_linear_add(int32_t n, const int32_t *idx, const double *val, double *A, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_linear_add, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, val, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const double *y, double *x, double vstep,
+                                unsigned long long *step_bits, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_update, dim3((n + 255) / 256), dim3(256), 0, s, n, n_clamp, y, x, vstep, step_bits);
     return hipGetLastError();
 }
 

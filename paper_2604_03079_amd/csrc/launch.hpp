@@ -19,6 +19,11 @@ hipError_t launch_hub(const KCirc &kc, const KCall &call, hipStream_t s);
 // A[idx[i]] = A[idx[i]] + val[i] for i < n (the linear part of entries that devices
 // also write); nothing is launched when n == 0.
 hipError_t launch_linear_add(int32_t n, const int32_t *idx, const double *val, double *A, hipStream_t s);
+// Damped Newton update: d = y - x, rows below n_clamp clamped to [-vstep, vstep],
+// x += d; *step_bits = max over rows of |d| as IEEE bits (NaN above every finite),
+// which the caller clears first.
+hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const double *y, double *x, double vstep,
+                                unsigned long long *step_bits, hipStream_t s);
 // cooperative: hipLaunchCooperativeKernel (the runtime checks co-residency);
 // otherwise an ordinary launch of a grid the occupancy query says fits at once.
 // n_part: blocks [0, n_part) run the grid-barrier colour schedule over the first

@@ -387,6 +387,22 @@ def chain_case(n_stages: int, seed: int) -> Circuit:
     return draw_params(c, rng, W_CHAIN, L_CHAIN)
 
 
+def drive(circ: Circuit, node: int, volts: float) -> Circuit:
+    """Hold `node` at `volts` with one more voltage source to ground (its branch row
+    follows the existing ones).  Before ``draw_params``, which sizes x."""
+    circ.vsrc = np.concatenate([circ.vsrc, np.array([[node, 0]], np.int32)])
+    circ.vsrc_volts = np.concatenate([circ.vsrc_volts, [float(volts)]])
+    return circ
+
+
+def chain_dc_case(n_stages: int, seed: int, vin: float = 0.0) -> Circuit:
+    """Inverter chain with its input (node 2) held at `vin`: a circuit with a unique
+    DC operating point (every node has a conductive path; gates are driven)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = inverter_chain_fast(n_stages) if n_stages > 64 else inverter_chain(n_stages)
+    return draw_params(drive(c, 2, vin), rng, W_CHAIN, L_CHAIN)
+
+
 def pchain_case(n_dev: int, group: int, seed: int) -> Circuit:
     """Parallel-inverter chain of about ``n_dev`` devices, ``group`` inverters per stage
     (at least two stages), chain parameter ranges."""

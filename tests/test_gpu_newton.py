@@ -1,0 +1,117 @@
+"""GPU Newton loop (cs_newton: stamp, sparse LU refactorisation and solve, damped
+update) against the oracle's Newton loop from the same start.
+
+Both sides take the same steps (stamp at x, solve, clamp node rows to +-vstep,
+stop at max |step| <= tol); they differ only in how the linear solve rounds, which
+the contraction of Newton's method removes: the converged points agree within
+1e-9 (the convergence tolerance) and the iteration counts within one.  Cases: DC
+operating points of short chains (the symmetric chain at half supply, exact),
+backward-Euler steps with history terms on chains and on a split adder with its
+series resistors, and the 100,000-stage chain, checked by the KCL residual of the
+oracle's stamp at the GPU's point."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import newton as ON
+from paper_2604_03079_amd import colorstamp as CS
+from paper_2604_03079_amd import netgen as G
+
+pytestmark = pytest.mark.gpu
+NC, PC = G.default_card(1), G.default_card(-1)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    CS.lib()
+    return torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_newton(torch, circ, ag0=0.0, hist=None, pmos=None, variant="region", **kw):
+    c = CS.prepare(circ, True, NC, pmos or PC)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    c.set_params(t(circ.W), t(circ.L), t(circ.VTH0))
+    x = t(circ.x).clone()
+    r = c.newton(x, ag0, None if hist is None else t(hist), variant=variant, **kw)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), r, c
+
+
+def test_symmetric_chain_at_half_supply(torch_dev):
+    circ = G.drive(G.inverter_chain(2), 2, 0.5)
+    n = circ.n_dev
+    circ.W, circ.L = np.full(n, 1e-6), np.full(n, 60e-9)
+    circ.VTH0 = 0.4 * circ.pol.astype(np.float64)
+    circ.x = np.zeros(circ.n_rows)
+    circ.x[:circ.n_nodes - 1] = np.random.default_rng(3).uniform(0, 1, circ.n_nodes - 1)
+    say("case newton symmetric chain2 DC")
+    x, r, _ = gpu_newton(torch_dev, circ, pmos=G.default_card(-1, symmetric=True))
+    assert r["converged"]
+    assert np.all(np.abs(x[2:circ.n_nodes - 1] - 0.5) <= 1e-12)
+
+
+CASES = [("chain40dc", lambda: G.chain_dc_case(40, 6, 0.0), 0.0, None),
+         ("chain9dc_high", lambda: G.chain_dc_case(9, 5, 1.0), 0.0, None),
+         ("chain2000be", lambda: G.chain_dc_case(2000, 7, 0.3), 1e12, 11),
+         ("adder4r89be", lambda: G.draw_params(G.split_nets(G.drive(G.drive(G.drive(
+             G.ripple_adder28(4), 2, 1.0), 3, 0.0), 4, 1.0), "all")[0], np.random.default_rng(8),
+             G.W_CHAIN, G.L_CHAIN), 1e12, 12),
+         ("adder4r14be", lambda: G.draw_params(G.split_nets(G.ripple_adder28(4), "rail")[0],
+                                               np.random.default_rng(9), G.W_CHAIN, G.L_CHAIN), 1e12, 13)]
+
+
+@pytest.mark.parametrize("name,make,ag0,hseed", CASES, ids=[c[0] for c in CASES])
+def test_newton_matches_oracle(torch_dev, name, make, ag0, hseed):
+    circ = make()
+    hist = None if hseed is None else np.random.default_rng(hseed).normal(0, 1e-5, (circ.n_dev, 4))
+    xo, ito, steps = ON.newton(circ, NC, PC, ag0=ag0, hist=hist)
+    assert steps[-1] <= 1e-9, "oracle did not converge"
+    say(f"case newton {name} ag0={ag0}")
+    x, r, _ = gpu_newton(torch_dev, circ, ag0, hist)
+    say("  ", r)
+    assert r["converged"] and abs(r["iterations"] - ito) <= 1
+    assert np.abs(x - xo).max() <= 1e-9
+
+
+def test_variants_give_the_same_iterates(torch_dev):
+    # the coloured variants stamp bit-identical systems: the loop ends at the same bits
+    circ = G.chain_dc_case(2000, 7, 0.3)
+    hist = np.random.default_rng(11).normal(0, 1e-5, (circ.n_dev, 4))
+    out = []
+    for v in ("region", "persistent", "per_kernel", "buffered"):
+        say(f"case newton variant {v}")
+        x, r, _ = gpu_newton(torch_dev, circ, 1e12, hist, variant=v)
+        out.append((x, r["iterations"]))
+    for x, it in out[1:]:
+        assert it == out[0][1] and np.array_equal(x.view(np.int64), out[0][0].view(np.int64))
+
+
+def test_full_size_chain_backward_euler_step(torch_dev, orc):
+    circ = G.chain_dc_case(100_000, 2, 0.3)
+    hist = np.random.default_rng(14).normal(0, 1e-5, (circ.n_dev, 4))
+    say("case newton chain100k backward Euler")
+    x, r, _ = gpu_newton(torch_dev, circ, 1e12, hist)
+    say("  ", r)
+    assert r["converged"] and r["iterations"] <= 30
+    # at the GPU's point the oracle's system satisfies A x = b up to the step size:
+    # b = A x - F(x), so the node rows of A x - b are the KCL residual F
+    rp, ci = orc.pattern(circ)
+    A, b = orc.assemble(circ, rp, ci, NC, PC, 1e12, hist, x=x)
+    import scipy.sparse as sp
+    M = sp.csr_matrix((A, ci, rp), shape=(circ.n_rows, circ.n_rows))
+    F = (M @ x - b)[:circ.n_nodes - 1]
+    assert np.abs(F).max() <= 1e-9 * np.abs(M).max()
+
+
+def test_reports_non_convergence(torch_dev):
+    circ = G.chain_dc_case(2000, 7, 0.3)
+    say("case newton max_iter=1")
+    x, r, _ = gpu_newton(torch_dev, circ, 1e12, None, max_iter=1)
+    assert r["iterations"] == 1 and not r["converged"] and r["last_step"] > 1e-9
