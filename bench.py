@@ -216,8 +216,9 @@ def bench_newton(torch, CS, G, dev):
     terms N(0, 1e-5)) of the 100,000-stage chain with its input held at 0.3 V, and of
     the 64-bit adder with every net split by its 5,696 series resistors (Table I's
     R89 shape), from the generators' start points.  Per iteration: the stamp (region
-    variant), rocSOLVER's refactorisation and solve, the update; the first call's
-    host factorisation is reported apart."""
+    variant), the refactorisation (fused with the forward substitution for the
+    level-scheduled kernels) and solve, the update, for this library's solver and
+    rocSOLVER's; the first call's host factorisation is reported apart."""
     out = {}
     for key, circ in (("chain100k_be", G.chain_dc_case(100_000, 2, 0.3)),
                       ("adder64_r89_be", G.adder_case(64, 9, "all"))):
@@ -225,24 +226,27 @@ def bench_newton(torch, CS, G, dev):
         c = CS.prepare(circ, exclude=True)
         W, L, V, x0 = device_tensors(torch, circ, dev)
         c.set_params(W, L, V)
-        x = x0.clone()
-        first = c.newton(x, AG0, hist)            # builds the factor pattern and analysis
-        x = x0.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = c.newton(x, AG0, hist)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) * 1e3
-        c.check()
-        it = max(r["iterations"], 1)
-        per = {k: round(v / it, 4) for k, v in r["ms"].items() if k != "host_factor"}
-        out[key] = dict(n_dev=circ.n_dev, n_res=circ.n_res, n_rows=c.n_rows, nnz=c.nnz,
-                        iterations=r["iterations"], converged=r["converged"], ms_per_iteration=per,
-                        wall_ms=round(wall, 3), host_factor_ms=round(first["ms"]["host_factor"], 2),
-                        solve_over_stamp=round((per["refactor"] + per["solve"]) / per["stamp"], 1))
-        log(f"  newton {key}: {r['iterations']} iterations, per iteration stamp {per['stamp']:.3f} ms, "
-            f"refactor {per['refactor']:.3f} ms, solve {per['solve']:.3f} ms, update {per['update']:.3f} ms; "
-            f"host factor {first['ms']['host_factor']:.1f} ms")
+        row = dict(n_dev=circ.n_dev, n_res=circ.n_res, n_rows=c.n_rows, nnz=c.nnz)
+        for solver in ("levels", "rocsolver"):
+            x = x0.clone()
+            first = c.newton(x, AG0, hist, solver=solver)    # factor pattern, analysis
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = c.newton(x, AG0, hist, solver=solver)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            c.check()
+            it = max(r["iterations"], 1)
+            per = {k: round(v / it, 4) for k, v in r["ms"].items() if k != "host_factor"}
+            row[solver] = dict(iterations=r["iterations"], converged=r["converged"], ms_per_iteration=per,
+                               wall_ms=round(wall, 3),
+                               solve_over_stamp=round((per["refactor"] + per["solve"]) / per["stamp"], 1))
+            row["host_factor_ms"] = round(first["ms"]["host_factor"], 2)
+            log(f"  newton {key} {solver}: {r['iterations']} iterations, per iteration stamp {per['stamp']:.3f} ms, "
+                f"refactor {per['refactor']:.3f} ms, solve {per['solve']:.3f} ms, update {per['update']:.3f} ms; "
+                f"wall {wall:.1f} ms")
+        out[key] = row
     return out
 
 

@@ -169,9 +169,10 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
  * the devices at x, stamps the linearised MNA system and solves it; the paper solves
  * with KLU, Benchmark 2).  Per iteration on `stream`: cs_eval_stamp(variant) into
  * A_val and b (caller-owned device workspace, nnz and n_rows), a sparse LU
- * refactorisation of A and its triangular solves (rocSOLVER, with the pivots of one
- * host factorisation made at the first call on this stamp map: nested-dissection
- * order, threshold partial pivoting), leaving the Newton point y in b, then
+ * refactorisation of A and its triangular solves by `solver` (cs_solver), with the
+ * pivots of one host factorisation made at the first call on this stamp map
+ * (voltage sources first as node/branch pivot pairs, then nested dissection;
+ * threshold partial pivoting), leaving the Newton point y in b, then
  * d = y - x with node rows clamped to [-vstep, vstep], x += d.  Stops when
  * max |d| <= tol or after max_iter iterations.  x: device, n_rows, the start point
  * on entry and the last iterate on return.  ag0 and hist as in cs_eval_stamp (a
@@ -181,10 +182,17 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
  * solve and update, and the one-time host factorisation.  Returns CS_OK whether or
  * not it converged; CS_EDOMAIN when a step is not finite (x then holds it) or the
  * host factorisation finds the matrix singular. */
-cs_status cs_newton(cs_circuit *c, cs_variant variant, double *x, double ag0, const double *hist,
-                    int32_t max_iter, double vstep, double tol, double *A_val, double *b,
-                    int32_t *n_iter, int32_t *converged, double *last_step, double *times_ms,
-                    void *stream);
+typedef enum {
+    CS_SOLVE_LEVELS = 0,     /* this library's kernels: rows of the factor pattern grouped by
+                                dependency level, one launch per level (refactorisation fused
+                                with the forward substitution, then the backward one) */
+    CS_SOLVE_ROCSOLVER = 1   /* rocSOLVER csrrf refactorisation and solve, same pivots */
+} cs_solver;
+
+cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x, double ag0,
+                    const double *hist, int32_t max_iter, double vstep, double tol, double *A_val,
+                    double *b, int32_t *n_iter, int32_t *converged, double *last_step,
+                    double *times_ms, void *stream);
 
 /* The host factorisation cs_newton starts from, for inspection: A_host holds nnz
  * values on the circuit's pattern.  *nnzT receives the size of T = (L - I) + U of

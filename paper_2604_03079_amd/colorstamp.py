@@ -74,7 +74,7 @@ def lib():
             "cs_set_params": [p, p, p, p, p],
             "cs_eval_stamp": [p, C.c_int, p, d, p, p, p, p],
             "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
-            "cs_newton": [p, C.c_int, p, d, p, i32, d, d, p, p, p, p, p, p, p],
+            "cs_newton": [p, C.c_int, i32, p, d, p, i32, d, d, p, p, p, p, p, p, p],
             "cs_factor_host": [p, p, p, p, p, p, p, p],
             "cs_set_launch": [p, i32, i32, i32],
             "cs_get_info": [p, p, p, p, p, p, p, p, p],
@@ -133,6 +133,7 @@ def _stream(stream):
 
 
 RT_FIELDS = 10   # fields per region in the plan's region table
+SOLVERS = {"levels": 0, "rocsolver": 1}
 ORDERS = {"natural": 0, "largest_first": 1, "dsatur": 2}   # cs_colour_order
 
 
@@ -303,9 +304,10 @@ class Circuit:
         _check(lib().cs_check(self._h, _stream(stream)), "cs_check")
 
     def newton(self, x, ag0: float = 0.0, hist=None, max_iter: int = 100, vstep: float = 0.3,
-               tol: float = 1e-9, variant="region", A=None, b=None, stream=None) -> dict:
+               tol: float = 1e-9, variant="region", solver="levels", A=None, b=None, stream=None) -> dict:
         """Newton loop on the GPU from x (device, updated in place): iterations,
-        convergence, last max |step| and the summed phase times (ms)."""
+        convergence, last max |step| and the summed phase times (ms).  solver:
+        "levels" (this library's kernels) or "rocsolver"."""
         import torch
         if A is None:
             A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
@@ -313,7 +315,8 @@ class Circuit:
             b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
         it, conv, step = C.c_int32(), C.c_int32(), C.c_double()
         t = (C.c_double * 5)()
-        _check(lib().cs_newton(self._h, VARIANTS[variant], _dev_ptr(x), float(ag0), _dev_ptr(hist), int(max_iter),
+        _check(lib().cs_newton(self._h, VARIANTS[variant], SOLVERS[solver], _dev_ptr(x), float(ag0), _dev_ptr(hist),
+                               int(max_iter),
                                float(vstep), float(tol), _dev_ptr(A), _dev_ptr(b), C.byref(it), C.byref(conv),
                                C.byref(step), t, _stream(stream)), "cs_newton")
         return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,

@@ -22,6 +22,21 @@ hipError_t launch_linear_add(int32_t n, const int32_t *idx, const double *val, d
 // Damped Newton update: d = y - x, rows below n_clamp clamped to [-vstep, vstep],
 // x += d; *step_bits = max over rows of |d| as IEEE bits (NaN above every finite),
 // which the caller clears first.
+// Level-scheduled sparse LU (solve.hip): T[t] = A[src[t]] (0 where src < 0); one
+// lower level: rows eliminated and forward-substituted (y); one upper level: rows
+// back-substituted, solution written to out at column Q(i).
+hipError_t launch_lu_load(int32_t nnzT, const int32_t *src, const double *A, double *T, hipStream_t s);
+hipError_t launch_lu_lower(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
+                           const int32_t *diag, double *T, const int32_t *P, const double *b, double *y,
+                           hipStream_t s);
+// Same as launch_lu_lower for rows of at most lu_stage_entries() entries, one wave each.
+hipError_t launch_lu_lower_wave(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
+                                const int32_t *diag, double *T, const int32_t *P, const double *b, double *y,
+                                hipStream_t s);
+int32_t lu_stage_entries();
+hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
+                           const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
+                           hipStream_t s);
 hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const double *y, double *x, double vstep,
                                 unsigned long long *step_bits, hipStream_t s);
 // cooperative: hipLaunchCooperativeKernel (the runtime checks co-residency);

@@ -4,13 +4,16 @@
 // leaves to KLU (Benchmark 2; its Conclusions name the solver as the next
 // bottleneck).
 //
-// Per iteration, on one stream: cs_eval_stamp (any variant), rocSOLVER's sparse LU
-// refactorisation of A with the pivots of one host factorisation (sparse_lu.cpp),
-// its two triangular solves (b becomes the Newton point y), then k_newton_update:
-// d = y - x, node rows clamped to [-vstep, vstep], x += d, and the largest |d|
-// read back to decide convergence (max |d| <= tol).
+// Per iteration, on one stream: cs_eval_stamp (any variant), a sparse LU
+// refactorisation of A with the pivots of one host factorisation (sparse_lu.cpp)
+// and its two triangular solves (b becomes the Newton point y), then
+// k_newton_update: d = y - x, node rows clamped to [-vstep, vstep], x += d, and the
+// largest |d| read back to decide convergence (max |d| <= tol).  The refactorisation
+// is either this library's level-scheduled kernels (solve.hip; levels analysed here
+// once) or rocSOLVER's csrrf routines with the same pivots.
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -30,7 +33,12 @@ struct NewtonState {
     DevBuf<int32_t> ptrA, indA, ptrT, indT, P, Q;
     DevBuf<double> valT;
     DevBuf<unsigned long long> step;
-    rocblas_handle handle = nullptr;
+    // level-scheduled refactorisation: T position -> A position (-1: fill), diagonal
+    // positions, rows grouped by lower and by upper dependency level
+    DevBuf<int32_t> src, diag, lrows, urows;
+    DevBuf<double> y;
+    std::vector<int32_t> lptr, uptr, lshort;   // lshort[l]: staged rows, listed first in level l
+    rocblas_handle handle = nullptr;   // rocSOLVER path, set up on its first use
     rocsolver_rfinfo rf = nullptr;
     double host_lu_ms = 0.0;
     ~NewtonState() {
@@ -109,27 +117,89 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
     NCHECK_HIP(ns->P.upload(F.P), "upload pivots");
     NCHECK_HIP(ns->Q.upload(F.Q), "upload pivots");
     NCHECK_HIP(ns->step.alloc(1), "alloc step word");
-    NCHECK_RS(rocblas_create_handle(&ns->handle), "rocblas_create_handle");
-    NCHECK_RS(rocblas_set_stream(ns->handle, s), "rocblas_set_stream");
-    NCHECK_RS(rocsolver_create_rfinfo(&ns->rf, ns->handle), "rocsolver_create_rfinfo");
-    NCHECK_RS(rocsolver_dcsrrf_analysis(ns->handle, n, 1, (rocblas_int)h.nnz, ns->ptrA.p, ns->indA.p, A_val,
-                                        (rocblas_int)ns->nnzT, ns->ptrT.p, ns->indT.p, ns->valT.p, ns->P.p,
-                                        ns->Q.p, b, n, ns->rf),
-              "rocsolver_dcsrrf_analysis");
+    // level analysis of the factor pattern
+    std::vector<int32_t> pinv((size_t)n), qinv((size_t)n), src((size_t)ns->nnzT, -1), diag((size_t)n, -1);
+    for (int32_t k = 0; k < n; ++k) {
+        pinv[(size_t)F.P[(size_t)k]] = k;
+        qinv[(size_t)F.Q[(size_t)k]] = k;
+    }
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t e = h.row_ptr[(size_t)r]; e < h.row_ptr[(size_t)r + 1]; ++e) {
+            const int32_t i = pinv[(size_t)r], k = qinv[(size_t)h.col_idx[(size_t)e]];
+            auto b0 = F.Ti.begin() + F.Tp[(size_t)i], b1 = F.Ti.begin() + F.Tp[(size_t)i + 1];
+            auto it = std::lower_bound(b0, b1, k);
+            if (it == b1 || *it != k) return nfail(CS_EINVAL, "factor pattern misses an entry of A");
+            src[(size_t)(it - F.Ti.begin())] = e;
+        }
+    std::vector<int32_t> lev((size_t)n, 0), ulev((size_t)n, 0);
+    int32_t nl = 0, nu = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t m = 0;
+        for (int32_t p = F.Tp[(size_t)i]; p < F.Tp[(size_t)i + 1]; ++p) {
+            const int32_t j = F.Ti[(size_t)p];
+            if (j < i) m = std::max(m, lev[(size_t)j] + 1);
+            else if (j == i) diag[(size_t)i] = p;
+        }
+        if (diag[(size_t)i] < 0) return nfail(CS_EINVAL, "factor pattern misses a diagonal");
+        lev[(size_t)i] = m;
+        nl = std::max(nl, m + 1);
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        int32_t m = 0;
+        for (int32_t p = diag[(size_t)i] + 1; p < F.Tp[(size_t)i + 1]; ++p)
+            m = std::max(m, ulev[(size_t)F.Ti[(size_t)p]] + 1);
+        ulev[(size_t)i] = m;
+        nu = std::max(nu, m + 1);
+    }
+    auto group = [n](const std::vector<int32_t> &lv, int32_t nlev, std::vector<int32_t> &ptr) {
+        ptr.assign((size_t)nlev + 1, 0);
+        for (int32_t i = 0; i < n; ++i) ptr[(size_t)lv[(size_t)i] + 1]++;
+        for (int32_t l = 0; l < nlev; ++l) ptr[(size_t)l + 1] += ptr[(size_t)l];
+        std::vector<int32_t> rows((size_t)n), fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i) rows[(size_t)fill[(size_t)lv[(size_t)i]]++] = i;
+        return rows;
+    };
+    std::vector<int32_t> lrows = group(lev, nl, ns->lptr);
+    // inside each lower level, rows short enough for the staged kernel first
+    ns->lshort.assign((size_t)nl, 0);
+    const int32_t cap = lu_stage_entries();
+    for (int32_t l = 0; l < nl; ++l) {
+        auto b0 = lrows.begin() + ns->lptr[(size_t)l], b1 = lrows.begin() + ns->lptr[(size_t)l + 1];
+        auto mid = std::stable_partition(b0, b1, [&](int32_t i) { return F.Tp[(size_t)i + 1] - F.Tp[(size_t)i] <= cap; });
+        ns->lshort[(size_t)l] = (int32_t)(mid - b0);
+    }
+    NCHECK_HIP(ns->lrows.upload(lrows), "upload levels");
+    NCHECK_HIP(ns->urows.upload(group(ulev, nu, ns->uptr)), "upload levels");
+    NCHECK_HIP(ns->src.upload(src), "upload load map");
+    NCHECK_HIP(ns->diag.upload(diag), "upload diagonal positions");
+    NCHECK_HIP(ns->y.alloc((size_t)n), "alloc solve vector");
     guard.p = nullptr;
     c->newton = ns;
     return CS_OK;
 }
 
+cs_status ensure_rocsolver(NewtonState &ns, const cs_circuit *c, double *A_val, double *b, hipStream_t s) {
+    if (ns.rf) return CS_OK;
+    if (!ns.handle) NCHECK_RS(rocblas_create_handle(&ns.handle), "rocblas_create_handle");
+    NCHECK_RS(rocblas_set_stream(ns.handle, s), "rocblas_set_stream");
+    NCHECK_RS(rocsolver_create_rfinfo(&ns.rf, ns.handle), "rocsolver_create_rfinfo");
+    NCHECK_RS(rocsolver_dcsrrf_analysis(ns.handle, ns.n, 1, (rocblas_int)c->h.nnz, ns.ptrA.p, ns.indA.p, A_val,
+                                        (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p, ns.valT.p, ns.P.p, ns.Q.p, b,
+                                        ns.n, ns.rf),
+              "rocsolver_dcsrrf_analysis");
+    return CS_OK;
+}
+
 }  // namespace
 
-cs_status cs_newton(cs_circuit *c, cs_variant variant, double *x, double ag0, const double *hist, int32_t max_iter,
-                    double vstep, double tol, double *A_val, double *b, int32_t *n_iter, int32_t *converged,
-                    double *last_step, double *times_ms, void *stream) {
+cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x, double ag0, const double *hist,
+                    int32_t max_iter, double vstep, double tol, double *A_val, double *b, int32_t *n_iter,
+                    int32_t *converged, double *last_step, double *times_ms, void *stream) {
     if (!c) return nfail(CS_EINVAL, "NULL circuit");
     if (!c->h.mapped) return nfail(CS_ESTATE, "cs_build_stamp_map must come first");
     if (!x || !A_val || !b) return nfail(CS_EINVAL, "NULL x, A or b");
     if (max_iter < 1 || !(vstep > 0.0) || !(tol >= 0.0)) return nfail(CS_EINVAL, "max_iter >= 1, vstep > 0, tol >= 0");
+    if (solver != CS_SOLVE_LEVELS && solver != CS_SOLVE_ROCSOLVER) return nfail(CS_EINVAL, "unknown solver");
     hipStream_t s = (hipStream_t)stream;
     if (n_iter) *n_iter = 0;
     if (converged) *converged = 0;
@@ -148,7 +218,12 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, double *x, double ag0, co
     }
     NewtonState &ns = *c->newton;
     if (times_ms) times_ms[4] = ns.host_lu_ms;
-    NCHECK_RS(rocblas_set_stream(ns.handle, s), "rocblas_set_stream");
+    const bool lib = solver == CS_SOLVE_ROCSOLVER;
+    if (lib) {
+        cs_status st = ensure_rocsolver(ns, c, A_val, b, s);
+        if (st != CS_OK) return st;
+        NCHECK_RS(rocblas_set_stream(ns.handle, s), "rocblas_set_stream");
+    }
     Events ev;
     if (times_ms) {
         for (auto &v : ev.e) NCHECK_HIP(hipEventCreate(&v), "event");
@@ -161,14 +236,33 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, double *x, double ag0, co
         cs_status st = cs_eval_stamp(c, variant, x, ag0, hist, A_val, b, stream);
         if (st != CS_OK) return st;
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[1], s), "event");
-        NCHECK_RS(rocsolver_dcsrrf_refactlu(ns.handle, n, (rocblas_int)c->h.nnz, ns.ptrA.p, ns.indA.p, A_val,
-                                            (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p, ns.valT.p, ns.P.p, ns.Q.p,
-                                            ns.rf),
-                  "rocsolver_dcsrrf_refactlu");
-        if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[2], s), "event");
-        NCHECK_RS(rocsolver_dcsrrf_solve(ns.handle, n, 1, (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p, ns.valT.p,
-                                         ns.P.p, ns.Q.p, b, n, ns.rf),
-                  "rocsolver_dcsrrf_solve");
+        if (lib) {
+            NCHECK_RS(rocsolver_dcsrrf_refactlu(ns.handle, n, (rocblas_int)c->h.nnz, ns.ptrA.p, ns.indA.p, A_val,
+                                                (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p, ns.valT.p, ns.P.p,
+                                                ns.Q.p, ns.rf),
+                      "rocsolver_dcsrrf_refactlu");
+            if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[2], s), "event");
+            NCHECK_RS(rocsolver_dcsrrf_solve(ns.handle, n, 1, (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p,
+                                             ns.valT.p, ns.P.p, ns.Q.p, b, n, ns.rf),
+                      "rocsolver_dcsrrf_solve");
+        } else {
+            // refactorisation fused with the forward substitution, level by level
+            NCHECK_HIP(launch_lu_load((int32_t)ns.nnzT, ns.src.p, A_val, ns.valT.p, s), "LU load launch");
+            for (size_t l = 0; l + 1 < ns.lptr.size(); ++l) {
+                const int32_t beg = ns.lptr[l], nsh = ns.lshort[l], cnt = ns.lptr[l + 1] - beg;
+                NCHECK_HIP(launch_lu_lower_wave(nsh, ns.lrows.p + beg, ns.ptrT.p, ns.indT.p, ns.diag.p, ns.valT.p,
+                                                ns.P.p, b, ns.y.p, s),
+                           "LU lower launch");
+                NCHECK_HIP(launch_lu_lower(cnt - nsh, ns.lrows.p + beg + nsh, ns.ptrT.p, ns.indT.p, ns.diag.p,
+                                           ns.valT.p, ns.P.p, b, ns.y.p, s),
+                           "LU lower launch");
+            }
+            if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[2], s), "event");
+            for (size_t l = 0; l + 1 < ns.uptr.size(); ++l)
+                NCHECK_HIP(launch_lu_upper(ns.uptr[l + 1] - ns.uptr[l], ns.urows.p + ns.uptr[l], ns.ptrT.p,
+                                           ns.indT.p, ns.diag.p, ns.valT.p, ns.y.p, ns.Q.p, b, s),
+                           "LU upper launch");
+        }
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[3], s), "event");
         NCHECK_HIP(hipMemsetAsync(ns.step.p, 0, sizeof(unsigned long long), s), "clear step word");
         NCHECK_HIP(launch_newton_update(n, n_clamp, b, x, vstep, ns.step.p, s), "update launch");

@@ -1,0 +1,170 @@
+// Sparse LU refactorisation and triangular solves of the Newton loop, scheduled by
+// dependency levels of the factor pattern (host analysis in newton.cpp).
+//
+// T holds (L - I) + U of P A Q in CSR over the permuted indices (columns ascending,
+// pattern closed under fill).  Row i of L depends on the rows j < i with L(i, j) != 0;
+// the rows of one lower level depend only on earlier levels, so each level is one
+// launch with one lane per row.  A lane eliminates its row left to right: for each
+// L entry (column j, ascending) it divides by U(j, j) and subtracts l * U(j, k) from
+// its own entries k > j (a merge of two sorted column lists), and it carries the
+// forward substitution y_i = b_P(i) - sum_j L(i, j) y_j along.  Rows up to
+// LU_STAGE entries go to k_lu_lower_wave instead: one wave per row, the row staged
+// in LDS, the lanes splitting U(j, :) and finding their columns in the row by
+// binary search; every entry still receives its updates in ascending j, so both
+// kernels give the same bits.  The backward
+// substitution runs over upper levels, one workgroup per row (a rail's row of U can
+// span the whole matrix), z_i = (y_i - sum_k U(i, k) z_k) / U(i, i), written to the
+// solution at column Q(i).  Every sum has a fixed order for a fixed launch shape.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "launch.hpp"
+
+namespace cs {
+
+namespace {
+
+constexpr int UPPER_BLOCK = 256;
+constexpr int32_t LU_STAGE = 2048;   // row entries a wave stages in LDS (24 KiB)
+
+__global__ void __launch_bounds__(256) k_lu_load(int32_t nnzT, const int32_t *__restrict__ src,
+                                                 const double *__restrict__ A, double *__restrict__ T) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nnzT) {
+        const int32_t e = src[t];
+        T[t] = e >= 0 ? A[e] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_lu_lower(int32_t count, const int32_t *__restrict__ rows,
+                                                  const int32_t *__restrict__ Tp, const int32_t *__restrict__ Ti,
+                                                  const int32_t *__restrict__ diag, double *T,
+                                                  const int32_t *__restrict__ P, const double *__restrict__ b,
+                                                  double *y) {
+    const int32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    const int32_t i = rows[idx];
+    const int32_t re = Tp[i + 1];
+    double yi = b[P[i]];
+    for (int32_t p = Tp[i]; p < diag[i]; ++p) {
+        const int32_t j = Ti[p];
+        const double l = T[p] / T[diag[j]];
+        T[p] = l;
+        yi = yi - l * y[j];
+        int32_t q = diag[j] + 1, r = p + 1;
+        const int32_t qe = Tp[j + 1];
+        while (q < qe && r < re) {
+            const int32_t kq = Ti[q], kr = Ti[r];
+            if (kq == kr) {
+                T[r] = T[r] - l * T[q];
+                ++q;
+                ++r;
+            } else if (kq < kr) {
+                ++q;
+            } else {
+                ++r;
+            }
+        }
+    }
+    y[i] = yi;
+}
+
+__global__ void __launch_bounds__(64) k_lu_lower_wave(const int32_t *__restrict__ rows,
+                                                      const int32_t *__restrict__ Tp,
+                                                      const int32_t *__restrict__ Ti,
+                                                      const int32_t *__restrict__ diag, double *T,
+                                                      const int32_t *__restrict__ P,
+                                                      const double *__restrict__ b, double *y) {
+    __shared__ double v[LU_STAGE];
+    __shared__ int32_t col[LU_STAGE];
+    const int32_t i = rows[blockIdx.x];
+    const int32_t lane = threadIdx.x;
+    const int32_t t0 = Tp[i], len = Tp[i + 1] - t0, nl = diag[i] - t0;
+    for (int32_t r = lane; r < len; r += 64) {
+        v[r] = T[t0 + r];
+        col[r] = Ti[t0 + r];
+    }
+    __syncthreads();
+    double yi = b[P[i]];
+    for (int32_t a = 0; a < nl; ++a) {
+        const int32_t j = col[a];
+        const double l = v[a] / T[diag[j]];
+        yi = yi - l * y[j];
+        __syncthreads();   // every lane has read v[a] before lane 0 replaces it
+        if (lane == 0) v[a] = l;
+        for (int32_t q = diag[j] + 1 + lane; q < Tp[j + 1]; q += 64) {
+            const int32_t k = Ti[q];
+            int32_t lo = a + 1, hi = len;   // columns of the row after j, ascending
+            while (lo < hi) {
+                const int32_t m = (lo + hi) >> 1;
+                if (col[m] < k) lo = m + 1;
+                else hi = m;
+            }
+            if (lo < len && col[lo] == k) v[lo] = v[lo] - l * T[q];
+        }
+        __syncthreads();
+    }
+    for (int32_t r = lane; r < len; r += 64) T[t0 + r] = v[r];
+    if (lane == 0) y[i] = yi;
+}
+
+__global__ void __launch_bounds__(UPPER_BLOCK) k_lu_upper(const int32_t *__restrict__ rows,
+                                                          const int32_t *__restrict__ Tp,
+                                                          const int32_t *__restrict__ Ti,
+                                                          const int32_t *__restrict__ diag,
+                                                          const double *__restrict__ T, double *y,
+                                                          const int32_t *__restrict__ Q, double *out) {
+    __shared__ double red[UPPER_BLOCK];
+    const int32_t i = rows[blockIdx.x];
+    double s = 0.0;
+    for (int32_t p = diag[i] + 1 + (int32_t)threadIdx.x; p < Tp[i + 1]; p += UPPER_BLOCK) s = s + T[p] * y[Ti[p]];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = UPPER_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double z = (y[i] - red[0]) / T[diag[i]];
+        y[i] = z;
+        out[Q[i]] = z;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_lu_load(int32_t nnzT, const int32_t *src, const double *A, double *T, hipStream_t s) {
+    if (nnzT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_load, dim3((nnzT + 255) / 256), dim3(256), 0, s, nnzT, src, A, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_lower(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
+                           const int32_t *diag, double *T, const int32_t *P, const double *b, double *y,
+                           hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_lower, dim3((count + 255) / 256), dim3(256), 0, s, count, rows, Tp, Ti, diag, T, P, b,
+                       y);
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_lower_wave(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
+                                const int32_t *diag, double *T, const int32_t *P, const double *b, double *y,
+                                hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_lower_wave, dim3(count), dim3(64), 0, s, rows, Tp, Ti, diag, T, P, b, y);
+    return hipGetLastError();
+}
+
+int32_t lu_stage_entries() { return LU_STAGE; }
+
+hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
+                           const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
+                           hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_upper, dim3(count), dim3(UPPER_BLOCK), 0, s, rows, Tp, Ti, diag, T, y, Q, out);
+    return hipGetLastError();
+}
+
+}  // namespace cs

@@ -8,7 +8,8 @@ the contraction of Newton's method removes: the converged points agree within
 operating points of short chains (the symmetric chain at half supply, exact),
 backward-Euler steps with history terms on chains and on a split adder with its
 series resistors, and the 100,000-stage chain, checked by the KCL residual of the
-oracle's stamp at the GPU's point."""
+oracle's stamp at the GPU's point.  Both solvers: the library's level-scheduled
+kernels and rocSOLVER's refactorisation with the same pivots."""
 import sys
 
 import numpy as np
@@ -67,14 +68,15 @@ CASES = [("chain40dc", lambda: G.chain_dc_case(40, 6, 0.0), 0.0, None),
                                                np.random.default_rng(9), G.W_CHAIN, G.L_CHAIN), 1e12, 13)]
 
 
+@pytest.mark.parametrize("solver", ["levels", "rocsolver"])
 @pytest.mark.parametrize("name,make,ag0,hseed", CASES, ids=[c[0] for c in CASES])
-def test_newton_matches_oracle(torch_dev, name, make, ag0, hseed):
+def test_newton_matches_oracle(torch_dev, name, make, ag0, hseed, solver):
     circ = make()
     hist = None if hseed is None else np.random.default_rng(hseed).normal(0, 1e-5, (circ.n_dev, 4))
     xo, ito, steps = ON.newton(circ, NC, PC, ag0=ag0, hist=hist)
     assert steps[-1] <= 1e-9, "oracle did not converge"
-    say(f"case newton {name} ag0={ag0}")
-    x, r, _ = gpu_newton(torch_dev, circ, ag0, hist)
+    say(f"case newton {name} ag0={ag0} solver={solver}")
+    x, r, _ = gpu_newton(torch_dev, circ, ag0, hist, solver=solver)
     say("  ", r)
     assert r["converged"] and abs(r["iterations"] - ito) <= 1
     assert np.abs(x - xo).max() <= 1e-9
@@ -93,11 +95,12 @@ def test_variants_give_the_same_iterates(torch_dev):
         assert it == out[0][1] and np.array_equal(x.view(np.int64), out[0][0].view(np.int64))
 
 
-def test_full_size_chain_backward_euler_step(torch_dev, orc):
+@pytest.mark.parametrize("solver", ["levels", "rocsolver"])
+def test_full_size_chain_backward_euler_step(torch_dev, orc, solver):
     circ = G.chain_dc_case(100_000, 2, 0.3)
     hist = np.random.default_rng(14).normal(0, 1e-5, (circ.n_dev, 4))
-    say("case newton chain100k backward Euler")
-    x, r, _ = gpu_newton(torch_dev, circ, 1e12, hist)
+    say(f"case newton chain100k backward Euler solver={solver}")
+    x, r, _ = gpu_newton(torch_dev, circ, 1e12, hist, solver=solver)
     say("  ", r)
     assert r["converged"] and r["iterations"] <= 30
     # at the GPU's point the oracle's system satisfies A x = b up to the step size:
@@ -115,3 +118,16 @@ def test_reports_non_convergence(torch_dev):
     say("case newton max_iter=1")
     x, r, _ = gpu_newton(torch_dev, circ, 1e12, None, max_iter=1)
     assert r["iterations"] == 1 and not r["converged"] and r["last_step"] > 1e-9
+
+
+def test_unknown_solver_is_refused(torch_dev):
+    circ = G.chain_dc_case(5, 7, 0.3)
+    c = CS.prepare(circ, True)
+    import torch
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    c.set_params(t(circ.W), t(circ.L), t(circ.VTH0))
+    x = t(circ.x)
+    A = torch.empty(c.nnz, dtype=torch.float64, device="cuda:0")
+    b = torch.empty(c.n_rows, dtype=torch.float64, device="cuda:0")
+    assert CS.lib().cs_newton(c.handle, 4, 7, CS._dev_ptr(x), 0.0, None, 10, 0.3, 1e-9, CS._dev_ptr(A),
+                              CS._dev_ptr(b), None, None, None, None, None) == -1
