@@ -13,7 +13,11 @@ safeguard of our own choosing (the paper does not state its damping):
         x    = x + d
         stop when max |d| <= tol
 
-Returns x, the number of solves and max |d| per iteration."""
+Returns x, the number of solves and max |d| per iteration.
+
+transient() chains backward-Euler steps: before each, the history term of every
+device terminal is ag0 times its charge at the present point (the charge current
+being ag0 (Q(x) - Q(x_prev)), ag0 = 1/h), then the Newton loop with that ag0."""
 from __future__ import annotations
 
 import numpy as np
@@ -43,3 +47,31 @@ def newton(circ, nmos: dict, pmos: dict, x0=None, ag0: float = 0.0, hist=None, v
         if steps[-1] <= tol:
             return x, it, steps
     return x, max_iter, steps
+
+
+def history(circ, nmos: dict, pmos: dict, x, ag0: float):
+    """ag0 * Q of every device terminal at x, (n_dev, 4)."""
+    hist = np.zeros((circ.n_dev, 4))
+    for v in range(circ.n_dev):
+        t = circ.term[v]
+        V = np.array([0.0 if n == 0 else x[n - 1] for n in t])
+        pol = int(circ.pol[v])
+        _, _, _, Q = O.device_eval(nmos if pol > 0 else pmos, pol, circ.W[v], circ.L[v], circ.VTH0[v], V, 0.0)
+        hist[v] = ag0 * Q
+    return hist
+
+
+def transient(circ, nmos: dict, pmos: dict, h: float, n_steps: int, x0=None, **kw):
+    """Backward-Euler steps of size h from x0: the iterates after every step (the
+    start first) and the Newton iteration counts."""
+    ag0 = 1.0 / h
+    x = np.array(circ.x if x0 is None else x0, dtype=np.float64, copy=True)
+    out, iters = [x.copy()], []
+    for _ in range(n_steps):
+        hist = history(circ, nmos, pmos, x, ag0)
+        x, it, steps = newton(circ, nmos, pmos, x, ag0, hist, **kw)
+        if steps[-1] > kw.get("tol", 1e-9):
+            raise FloatingPointError("Newton did not converge")
+        iters.append(it)
+        out.append(x.copy())
+    return np.array(out), iters

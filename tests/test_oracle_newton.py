@@ -12,7 +12,10 @@ Introduction: evaluate, stamp, solve, update until the step vanishes).
 * The last steps contract quadratically (Newton's rate), which fails for a wrong
   Jacobian.
 * A backward-Euler step (ag0, history terms) converges to a point where
-  I + ag0*Q - hist sums to zero at every node."""
+  I + ag0*Q - hist sums to zero at every node.
+* Backward-Euler transients (history = ag0 * Q at the previous point): an inverter
+  discharges its output monotonically toward the DC point, and a chain ends at its
+  DC operating point."""
 import numpy as np
 import pytest
 
@@ -101,3 +104,31 @@ def test_backward_euler_step(orc, seed):
     assert steps[-1] <= 1e-9
     F = kcl(orc, circ, x, 1e12, hist)
     assert np.all(np.abs(F) <= 1e-9 * max(abs(F).max(), 1e-6) + 1e-15)
+
+
+def test_transient_discharge_is_monotone_and_settles(orc):
+    # one inverter, input held at Vdd, output starting at Vdd: the NMOS discharges the
+    # output (through its own charge); backward Euler decreases it step by step toward
+    # the DC point, without overshoot
+    circ = G.drive(G.inverter_chain(1), 2, 1.0)
+    circ = G.draw_params(circ, np.random.default_rng(4), G.W_CHAIN, G.L_CHAIN)
+    x0 = np.zeros(circ.n_rows)
+    x0[0], x0[1], x0[2] = 1.0, 1.0, 1.0           # vdd, input, output
+    xdc, _, _ = N.newton(circ, NC, PC, x0)
+    wave, iters = N.transient(circ, NC, PC, 1e-13, 200, x0)
+    out = wave[:, 2]
+    above = out - xdc[2] > 1e-6
+    assert above[:20].all()                       # the decay spans many steps
+    assert np.all(np.diff(out)[above[:-1]] < 0)   # strictly falling while above the DC point
+    assert np.all(out >= xdc[2] - 1e-9)           # no overshoot
+    assert abs(out[-1] - xdc[2]) < 1e-6
+
+
+def test_transient_reaches_the_dc_point(orc):
+    circ = G.chain_dc_case(4, seed=9, vin=0.0)
+    xdc, _, steps = N.newton(circ, NC, PC)
+    assert steps[-1] <= 1e-9
+    wave, iters = N.transient(circ, NC, PC, 5e-12, 400)
+    n = circ.n_nodes - 1
+    assert np.abs(wave[-1][:n] - xdc[:n]).max() < 1e-6
+    assert max(iters) < 30
