@@ -194,6 +194,13 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
                     double *b, int32_t *n_iter, int32_t *converged, double *last_step,
                     double *times_ms, void *stream);
 
+/* History terms of the next backward-Euler step (the integration the hist argument
+ * of cs_eval_stamp and cs_newton serves: the charge current is ag0 (Q(x) - Q(x_prev))
+ * with ag0 = 1/h).  hist_out (device, n_dev*4, original device order, terminals d, g,
+ * s, b) receives ag0 * Q_t of every device at x (device, n_rows).  Model M's charges,
+ * the same values and operation order as its stamp. */
+cs_status cs_history(cs_circuit *c, const double *x, double ag0, double *hist_out, void *stream);
+
 /* The host factorisation cs_newton starts from, for inspection: A_host holds nnz
  * values on the circuit's pattern.  *nnzT receives the size of T = (L - I) + U of
  * P A Q (CSR over the permuted indices, columns ascending); P[k] is the row and Q[k]

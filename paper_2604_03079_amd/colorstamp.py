@@ -27,7 +27,7 @@ EXPORTS = (
     "cs_build_coloring_order",
     "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
-    "cs_vjp", "cs_newton", "cs_factor_host", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
+    "cs_vjp", "cs_newton", "cs_history", "cs_factor_host", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
     "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_set_plan_units", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
@@ -76,6 +76,7 @@ def lib():
             "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_newton": [p, C.c_int, i32, p, d, p, i32, d, d, p, p, p, p, p, p, p],
             "cs_factor_host": [p, p, p, p, p, p, p, p],
+            "cs_history": [p, p, d, p, p],
             "cs_set_launch": [p, i32, i32, i32],
             "cs_get_info": [p, p, p, p, p, p, p, p, p],
             "cs_plan_regions": [p, i32],
@@ -321,6 +322,36 @@ class Circuit:
                                C.byref(step), t, _stream(stream)), "cs_newton")
         return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,
                     ms=dict(stamp=t[0], refactor=t[1], solve=t[2], update=t[3], host_factor=t[4]))
+
+    def history(self, x, ag0: float, out=None, stream=None):
+        """ag0 * terminal charges of every device at x: the history terms (n_dev, 4)
+        of the next backward-Euler step."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_dev, 4), dtype=torch.float64, device=x.device)
+        _check(lib().cs_history(self._h, _dev_ptr(x), float(ag0), _dev_ptr(out), _stream(stream)), "cs_history")
+        return out
+
+    def transient(self, x, h: float, n_steps: int, nodes=None, **newton_kw):
+        """Backward-Euler transient from x (device, updated in place): per step the
+        history terms at the present point, then the Newton loop with ag0 = 1/h.
+        Returns the node voltages (rows of `nodes`, default all) after every step
+        (n_steps + 1 rows, the start first) and the Newton iteration counts."""
+        import torch
+        ag0 = 1.0 / h
+        rows = torch.arange(self.n_rows, device=x.device) if nodes is None else \
+            torch.as_tensor(np.asarray(nodes) - 1, device=x.device)
+        wave = [x[rows].clone()]
+        iters = []
+        hist = torch.empty((self.n_dev, 4), dtype=torch.float64, device=x.device)
+        for _ in range(n_steps):
+            self.history(x, ag0, hist)
+            r = self.newton(x, ag0, hist, **newton_kw)
+            if not r["converged"]:
+                raise CsError(-6, "transient", f"Newton did not converge at step {len(iters) + 1}")
+            iters.append(r["iterations"])
+            wave.append(x[rows].clone())
+        return torch.stack(wave), iters
 
     def factor_host(self, A_host):
         """The host LU the Newton loop starts from: P, Q and T = (L - I) + U (CSR)."""

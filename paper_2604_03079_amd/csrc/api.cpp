@@ -580,6 +580,18 @@ cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, doub
     return CS_OK;
 }
 
+cs_status cs_history(cs_circuit *c, const double *x, double ag0, double *hist_out, void *stream) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");
+    if (!c->models_set) return fail(CS_ESTATE, "cs_set_models must come first");
+    if (!c->params_set) return fail(CS_ESTATE, "cs_set_params must come first");
+    if (!x || !hist_out) return fail(CS_EINVAL, "NULL x or hist_out");
+    if (current_device() != c->device) return fail(CS_ESTATE, "circuit uploaded to another device");
+    const KCall call{x, ag0, nullptr, nullptr, nullptr};
+    CS_CHECK_HIP(launch_history(make_kcirc(c), call, hist_out, (hipStream_t)stream), "history launch");
+    return CS_OK;
+}
+
 cs_status cs_plan_regions(cs_circuit *c, int32_t block) {
     if (!c) return fail(CS_EINVAL, "NULL circuit");
     if (!c->h.mapped) return fail(CS_ESTATE, "cs_build_stamp_map must come first");

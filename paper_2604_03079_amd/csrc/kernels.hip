@@ -39,7 +39,7 @@ __device__ __forceinline__ double volt(const double *x, int32_t t) { return t ==
 // Evaluate the device at position pos; the card is chosen per polarity with a
 // wave-uniform index (one pass per polarity present in the wave).
 __device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, int pos,
-                                           const DevIn &d) {
+                                           const DevIn &d, double *qout = nullptr) {
     const int isP = kc.pol[pos] < 0 ? 1 : 0;
     const double W = kc.par[pos];
     const double L = kc.par[(size_t)kc.n + pos];
@@ -54,7 +54,7 @@ __device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, i
             const DevCard &cd = kc.card[p0];
             const double p = p0 ? -1.0 : 1.0;
             const SizeDep sd = size_dep(cd, p, W, L, VTH0);
-            o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist);
+            o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist, qout);
             break;
         }
     }
@@ -488,6 +488,28 @@ __global__ void __launch_bounds__(256) k_persistent_stamp(KCirc kc, KCall call, 
                                                           const double *buf, int n_part,
                                                           int n_global_chunks, KLocal kl) {
     persistent_body<2>(kc, call, ks, buf, n_part, n_global_chunks, kl);
+}
+
+// History terms of the next backward-Euler step: ag0 times each device's terminal
+// charges at x, written in original device order (4 per device: d, g, s, b).
+__global__ void __launch_bounds__(256) k_history(KCirc kc, KCall call, double *hist_out) {
+    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < kc.n; pos += gridDim.x * blockDim.x) {
+        const DevIn d = load_terms(kc, pos);
+        double q[4];
+        (void)eval_pos(kc, call, pos, d, q);
+        double *h = hist_out + 4 * (size_t)kc.perm[pos];
+        h[0] = call.ag0 * q[0];
+        h[1] = call.ag0 * q[1];
+        h[2] = call.ag0 * q[2];
+        h[3] = call.ag0 * q[3];
+    }
+}
+
+hipError_t launch_history(const KCirc &kc, const KCall &call, double *hist_out, hipStream_t s) {
+    if (kc.n == 0) return hipSuccess;
+    const int grid = std::max(1, std::min(4096, (kc.n + 255) / 256));
+    hipLaunchKernelGGL(k_history, dim3(grid), dim3(256), 0, s, kc, call, hist_out);
+    return hipGetLastError();
 }
 
 // Evaluate every device and write its merged values (buffered variant).

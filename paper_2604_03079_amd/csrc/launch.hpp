@@ -46,6 +46,8 @@ hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const double *y, dou
 hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks,
                              const double *buf, int mode, int grid, int block, bool cooperative,
                              hipStream_t s, int n_part, int n_global_chunks, const KLocal &kl);
+// hist_out[4 v + t] = ag0 * Q_t of device v at call.x (call.hist unused).
+hipError_t launch_history(const KCirc &kc, const KCall &call, double *hist_out, hipStream_t s);
 hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s);
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s);

@@ -233,11 +233,12 @@ struct DevOutT {
     S bd, bg, bs, bb;
 };
 
-// Model M at terminal voltages V = (Vd, Vg, Vs, Vb).
+// Model M at terminal voltages V = (Vd, Vg, Vs, Vb).  qout (optional): the terminal
+// charges (d, g, s, b) at V, for the history term of the next integration step.
 template <class S>
 __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, const SizeDepT<S> &sd,
                                                  double Vd, double Vg, double Vs, double Vb,
-                                                 double ag0, const double *hist) {
+                                                 double ag0, const double *hist, double *qout = nullptr) {
     using D = Dual3T<S>;
     const double vds = p * (Vd - Vs), vgs = p * (Vg - Vs), vbs = p * (Vb - Vs);
     const bool fwd = vds >= 0.0;
@@ -333,6 +334,12 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     // physical terminal currents and charges
     const S I_d = p * Idp, I_s = p * (-Idp);
     const S Q_d = p * Qdp, Q_g = p * Qg.v, Q_s = p * Qsp, Q_b = p * Qb.v;
+    if (qout) {
+        qout[0] = val(Q_d);
+        qout[1] = val(Q_g);
+        qout[2] = val(Q_s);
+        qout[3] = val(Q_b);
+    }
     const double dvd = Vd - Vs, dvg = Vg - Vs, dvb = Vb - Vs;
     o.bd = (((o.Ydd * dvd + o.Ydg * dvg) + o.Ydb * dvb) - I_d) - ag0 * Q_d;
     o.bg = (((o.Ygd * dvd + o.Ygg * dvg) + o.Ygb * dvb) - 0.0) - ag0 * Q_g;

@@ -9,7 +9,9 @@ operating points of short chains (the symmetric chain at half supply, exact),
 backward-Euler steps with history terms on chains and on a split adder with its
 series resistors, and the 100,000-stage chain, checked by the KCL residual of the
 oracle's stamp at the GPU's point.  Both solvers: the library's level-scheduled
-kernels and rocSOLVER's refactorisation with the same pivots."""
+kernels and rocSOLVER's refactorisation with the same pivots.  The history terms of
+the next backward-Euler step (ag0 * Q) are bit-exact, and a 60-step transient
+follows the oracle's waveform within 1e-7 V."""
 import sys
 
 import numpy as np
@@ -131,3 +133,37 @@ def test_unknown_solver_is_refused(torch_dev):
     b = torch.empty(c.n_rows, dtype=torch.float64, device="cuda:0")
     assert CS.lib().cs_newton(c.handle, 4, 7, CS._dev_ptr(x), 0.0, None, 10, 0.3, 1e-9, CS._dev_ptr(A),
                               CS._dev_ptr(b), None, None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("name,make", [("chain50", lambda: G.workload(0)),
+                                       ("random600x6", lambda: G.draw_params(G.random_netlist(600, 6, 21),
+                                                                             np.random.default_rng(8), G.W_CHAIN,
+                                                                             G.L_CHAIN))], ids=["chain50", "random600x6"])
+def test_history_terms_bit_exact(torch_dev, name, make):
+    # ag0 * Q of every terminal: model M's charges, bit for bit the oracle's
+    circ = make()
+    c = CS.prepare(circ, True)
+    t = lambda a: torch_dev.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    c.set_params(t(circ.W), t(circ.L), t(circ.VTH0))
+    say(f"case history {name}")
+    got = c.history(t(circ.x), 1e12).cpu().numpy()
+    ref = ON.history(circ, NC, PC, circ.x, 1e12)
+    assert np.array_equal(got.view(np.int64), ref.view(np.int64))
+
+
+@pytest.mark.parametrize("solver", ["levels", "rocsolver"])
+def test_transient_matches_oracle(torch_dev, solver):
+    # 60 backward-Euler steps of 1 ps of a 20-stage chain whose input is held at Vdd,
+    # from the generator's random start: the waveforms agree within 1e-7 V
+    circ = G.chain_dc_case(20, seed=15, vin=1.0)
+    ref, iters_o = ON.transient(circ, NC, PC, 1e-12, 60)
+    c = CS.prepare(circ, True)
+    t = lambda a: torch_dev.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    c.set_params(t(circ.W), t(circ.L), t(circ.VTH0))
+    x = t(circ.x).clone()
+    say(f"case transient chain20 solver={solver}")
+    wave, iters = c.transient(x, 1e-12, 60, solver=solver)
+    wave = wave.cpu().numpy()
+    assert wave.shape == ref.shape
+    assert np.abs(wave - ref).max() <= 1e-7
+    assert all(abs(a - b) <= 1 for a, b in zip(iters, iters_o))
