@@ -15,6 +15,8 @@
 #define S_SOFTPLUS or_csoftplus
 #define S_SIGMA or_csigma
 #define S_PCOSH or_cpcosh
+#define S_PLOG1P or_cplog1p
+#define S_RE(x) creal(x)
 #define CNT(n) ((void)0)
 #define WITH_TRACE 0
 #include "model_m.inc"

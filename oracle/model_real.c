@@ -12,6 +12,8 @@
 #define S_SOFTPLUS or_softplus
 #define S_SIGMA or_sigma
 #define S_PCOSH or_pcosh
+#define S_PLOG1P or_plog1p
+#define S_RE(x) (x)
 #define CNT(n) OR_COUNT(n)
 #define WITH_TRACE 1
 #include "model_m.inc"

@@ -21,6 +21,12 @@
 typedef struct {
     double tnom, toxe, ndep, phis, vbi, k1, k2, k3, w0, dvt0, dvt1, dsub, eta0, nfactor,
         cdsc, voff, u0, ua, ub, uc, vsat, a0, xj, delta, delta1, lambda_l, cgdo, lint, wint;
+    /* source/drain-body junctions (jmod = 1): saturation current density js (A/m^2),
+     * emission coefficient nj, zero-bias capacitance cj (F/m^2) of an abrupt
+     * junction (grading 1/2), built-in potential pb (V), forward-bias coefficient
+     * fc, diffusion length hdif (junction area = Weff * hdif), forward voltage vjmax
+     * (V, at most 40 nj VT) above which the diode is continued by its tangent */
+    double jmod, js, nj, cj, pb, fc, hdif, vjmax;
 } or_card;
 
 /* Intermediate values of one evaluation (value parts), for the model checks. */

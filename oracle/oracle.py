@@ -15,7 +15,8 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
 CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "dvt0", "dvt1",
                "dsub", "eta0", "nfactor", "cdsc", "voff", "u0", "ua", "ub", "uc", "vsat", "a0",
-               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint")
+               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint",
+               "jmod", "js", "nj", "cj", "pb", "fc", "hdif", "vjmax")
 
 
 class OrCard(C.Structure):

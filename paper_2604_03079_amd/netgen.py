@@ -74,15 +74,28 @@ def default_card(pol: int, symmetric: bool = False) -> dict:
         k3=80.0, w0=2.5e-6, dvt0=1.0, dvt1=0.53, dsub=0.56, eta0=0.08, nfactor=1.0,
         cdsc=2.4e-4, voff=-0.08, u0=0.067, ua=1e-9, ub=1e-19, uc=-4.65e-11, vsat=8e4,
         a0=1.0, xj=1.5e-7, delta=0.01, delta1=1e-3, lambda_l=4.5e-9, cgdo=3e-10,
-        lint=0.0, wint=0.0)
+        lint=0.0, wint=0.0,
+        # source/drain-body junctions, off unless jmod = 1 (BSIM4's JSS, NJS, CJS, PBS
+        # default values, abrupt grading; junction area Weff * hdif; the diode is
+        # continued by its tangent above vjmax)
+        jmod=0.0, js=1e-4, nj=1.0, cj=5e-4, pb=1.0, fc=0.5, hdif=1e-7, vjmax=0.8)
     if pol == PMOS and not symmetric:
         card["u0"] = 0.025
     return card
 
 
+def junction_card(pol: int, **over) -> dict:
+    """The default card with the source/drain-body junctions on (the second model
+    level behind the same kernels), optionally overriding junction parameters."""
+    card = default_card(pol)
+    card.update(jmod=1.0, **over)
+    return card
+
+
 CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "dvt0", "dvt1",
                "dsub", "eta0", "nfactor", "cdsc", "voff", "u0", "ua", "ub", "uc", "vsat", "a0",
-               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint")
+               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint",
+               "jmod", "js", "nj", "cj", "pb", "fc", "hdif", "vjmax")
 
 
 def _finish(name, n_nodes, devs, vdd):
