@@ -186,9 +186,13 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel, 
     plain device copy of copy_mib MiB; written to profiles/hbm_traffic.json."""
     import csv
 
+    def base(kernel_name):   # "void cs::k_region<false>(cs::KCirc, ...)" -> "void cs::k_region"
+        head = kernel_name.split("(")[0]
+        return head[:head.index("<")] if "<" in head else head
+
     def per_dispatch(path, name, counter):
         vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
-                if r["Kernel_Name"].split("(")[0].endswith(name) and r["Counter_Name"] == counter]
+                if base(r["Kernel_Name"]).endswith(name) and r["Counter_Name"] == counter]
         return sum(vals) / len(vals), len(vals)
 
     kf, nf = per_dispatch(fetch_csv, kernel, "FETCH_SIZE")
@@ -247,6 +251,24 @@ def bench_newton(torch, CS, G, dev):
                 f"refactor {per['refactor']:.3f} ms, solve {per['solve']:.3f} ms, update {per['update']:.3f} ms; "
                 f"wall {wall:.1f} ms")
         out[key] = row
+    # a backward-Euler transient of the chain: 20 steps of 1 ps (history terms from
+    # the charges at each step's start, then the Newton loop), level-scheduled solver
+    circ = G.chain_dc_case(100_000, 2, 0.3)
+    c = CS.prepare(circ, exclude=True)
+    W, L, V, x0 = device_tensors(torch, circ, dev)
+    c.set_params(W, L, V)
+    x = x0.clone()
+    c.transient(x, 1e-12, 1)                      # factor pattern and analysis
+    x = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, iters = c.transient(x, 1e-12, 20)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out["chain100k_transient_20_steps"] = dict(h_s=1e-12, steps=20, total_ms=round(ms, 2),
+                                               ms_per_step=round(ms / 20, 3), newton_iterations=iters)
+    log(f"  transient chain100k: 20 steps of 1 ps in {ms:.1f} ms ({ms / 20:.2f} ms per step), "
+        f"Newton iterations {iters}")
     return out
 
 
@@ -409,6 +431,8 @@ def main():
                     help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs and exit")
     ap.add_argument("--csweep", action="store_true",
                     help="run only the colour-count sweep and print it as one JSON line")
+    ap.add_argument("--newton", action="store_true",
+                    help="run only the Newton-loop leg (stamp, refactorisation, solve) and print its JSON")
     ap.add_argument("--pmc-kernel", default="k_region")
     ap.add_argument("--pmc-key", default="region_chain100k")
     args = ap.parse_args()
@@ -434,6 +458,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy probe: 10 copies of {args.copy_probe} MiB")
+        return
+    if args.newton:
+        print(json.dumps({"newton": bench_newton(torch, CS, G, dev), "kernel_sources": kernel_sources_hash()}),
+              flush=True)
         return
     if args.csweep:
         rows = bench_csweep(torch, CS, G, dev, steps=args.steps)

@@ -78,11 +78,19 @@ typedef enum {
                                  order of accumulation, hub entries included). */
 } cs_variant;
 
-/* Model card of the BSIM4-core subset (SI units).  One card per polarity. */
+/* Model card of the BSIM4-core subset (SI units).  One card per polarity.  The
+ * last fields select the second model level: jmod = 1 adds the source- and drain-
+ * body junctions of BSIM4 (diode current Is (e^(v/(nj VT)) - 1), Is = js Weff hdif,
+ * exponent clamped at -40 and continued by its tangent above vjmax <= 40 nj VT;
+ * abrupt-junction depletion charge, cj Weff hdif at zero bias, continued with a
+ * linear capacitance above fc pb); jmod = 0 is model M exactly.  CS_EINVAL from
+ * cs_set_models for jmod = 1 with nj <= 0, pb <= 0, fc outside [0, 1), negative
+ * js, cj or hdif, or vjmax above 40 nj VT. */
 typedef struct {
     uint32_t size;  /* = sizeof(cs_model_card) */
     double tnom, toxe, ndep, phis, vbi, k1, k2, k3, w0, dvt0, dvt1, dsub, eta0, nfactor,
         cdsc, voff, u0, ua, ub, uc, vsat, a0, xj, delta, delta1, lambda_l, cgdo, lint, wint;
+    double jmod, js, nj, cj, pb, fc, hdif, vjmax;
 } cs_model_card;
 
 /* Create a circuit.  term: n_dev*4 node ids (d, g, s, b), 0 <= id < n_nodes;

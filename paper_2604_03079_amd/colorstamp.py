@@ -19,7 +19,8 @@ STATUS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EHIP", -4: "CS_E
           -5: "CS_ENOTSUP", -6: "CS_EDOMAIN"}
 CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "dvt0", "dvt1",
                "dsub", "eta0", "nfactor", "cdsc", "voff", "u0", "ua", "ub", "uc", "vsat", "a0",
-               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint")
+               "xj", "delta", "delta1", "lambda_l", "cgdo", "lint", "wint",
+               "jmod", "js", "nj", "cj", "pb", "fc", "hdif", "vjmax")
 
 # Every entry point of include/colorstamp.h.
 EXPORTS = (

@@ -403,6 +403,13 @@ cs_status cs_set_models(cs_circuit *c, const cs_model_card *nmos, const cs_model
     if (!c || !nmos || !pmos) return fail(CS_EINVAL, "NULL argument");
     if (nmos->size != sizeof(cs_model_card) || pmos->size != sizeof(cs_model_card))
         return fail(CS_EINVAL, "model card size mismatch");
+    for (const cs_model_card *m : {nmos, pmos}) {
+        if (m->jmod == 0.0) continue;
+        const double vt = 8.617333262e-5 * m->tnom;
+        if (!(m->nj > 0.0) || !(m->pb > 0.0) || !(m->fc >= 0.0 && m->fc < 1.0) || !(m->js >= 0.0) ||
+            !(m->cj >= 0.0) || !(m->hdif >= 0.0) || !(m->vjmax <= 40.0 * (m->nj * vt)))
+            return fail(CS_EINVAL, "junction parameters out of range");
+    }
     c->card[0] = derive_card(*nmos);
     c->card[1] = derive_card(*pmos);
     c->models_set = true;

@@ -59,6 +59,10 @@ struct DevCard {
         FOUR_DELTA1_VBM, VBI_M_PHIS, K3_TOXE_PHIS, TWO_WINT, TWO_LINT, TWO_VSAT;
     double phis, k1, k2, eta0, nfactor, cdsc, voff, u0, ua, ub, uc, toxe, delta, delta1,
         dvt0, dvt1, dsub, w0, lambda_l, a0, cgdo;
+    // source/drain-body junctions (jmod != 0): card values and derived constants
+    // (all doubles: the struct has no padding, so cards compare bytewise)
+    double jmod;
+    double js, cj, pb, hdif, vjmax, NJ_VT, FCPB, FCPB2, TWO_PB, QUARTER_PB, JF1, JF2, JF3;
 };
 
 // Device view of one (possibly batched) circuit in colour-major position order.

@@ -38,6 +38,7 @@ __device__ __forceinline__ double volt(const double *x, int32_t t) { return t ==
 
 // Evaluate the device at position pos; the card is chosen per polarity with a
 // wave-uniform index (one pass per polarity present in the wave).
+template <bool J = true>
 __device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, int pos,
                                            const DevIn &d, double *qout = nullptr) {
     const int isP = kc.pol[pos] < 0 ? 1 : 0;
@@ -54,7 +55,7 @@ __device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, i
             const DevCard &cd = kc.card[p0];
             const double p = p0 ? -1.0 : 1.0;
             const SizeDep sd = size_dep(cd, p, W, L, VTH0);
-            o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist, qout);
+            o = eval_model<double, J>(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist, qout);
             break;
         }
     }
@@ -308,13 +309,14 @@ __global__ void k_gather_params(int32_t n, const int32_t *perm, const double *W,
 }
 
 // One colour per launch (the per-colour parallel-for schedule).
+template <bool J>
 __global__ void __launch_bounds__(256) k_colour_phase(KCirc kc, KCall call, int32_t c,
                                                       int32_t with_fixed) {
     const int beg = kc.cptr[c], end = kc.cptr[c + 1];
     for (int pos = beg + blockIdx.x * blockDim.x + threadIdx.x; pos < end;
          pos += gridDim.x * blockDim.x) {
         const DevIn d = load_terms(kc, pos);
-        const DevOut o = eval_pos(kc, call, pos, d);
+        const DevOut o = eval_pos<J>(kc, call, pos, d);
         stamp_colour<false>(kc, call, pos, d, o);
     }
     if (with_fixed) fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
@@ -371,6 +373,7 @@ __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
 // Circuits stamped inside one workgroup (batches): colour phases separated by
 // workgroup barriers, each device evaluated in its phase, then the circuit's own
 // hub chunks.
+template <bool J>
 __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &call, const KLocal &kl, int first,
                                int stride, double *lds) {
     for (int li = first; li < kl.n; li += stride) {
@@ -380,7 +383,7 @@ __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &cal
             const int beg = kl.cptr[cp + c], end = kl.cptr[cp + c + 1];
             for (int pos = beg + (int)threadIdx.x; pos < end; pos += blockDim.x) {
                 const DevIn d = load_terms(kc, pos);
-                const DevOut o = eval_pos(kc, call, pos, d);
+                const DevOut o = eval_pos<J>(kc, call, pos, d);
                 stamp_colour<true>(kc, call, pos, d, o);
             }
             drain_memory();
@@ -397,7 +400,7 @@ __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &cal
 // first phase and keeps the merged values in LDS (requires n_part*block >= the
 // scheduled positions; dynamic LDS of nc_max doubles per thread).  MODE 2: stamp
 // phases only, merged values read from the buffer of k_eval_buffer.
-template <int MODE, bool LOCAL = true>
+template <int MODE, bool LOCAL, bool J>
 __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &call,
                                                 const KSync &ks, const double *buf, int n_part,
                                                 int n_global_chunks, const KLocal &kl) {
@@ -406,7 +409,7 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
     if (blockIdx.x == 0) fixed_stores(kc, call, threadIdx.x, blockDim.x);
     if constexpr (LOCAL) {
         if ((int)blockIdx.x >= n_part) {
-            local_circuits(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part, lds);
+            local_circuits<J>(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part, lds);
             return;
         }
     }
@@ -427,7 +430,7 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
         for (int j = 0; j < NCODE; ++j) cdv[j] = 0xC0000000u;
         if (gtid < n_sched) {
             const DevIn d = load_terms(kc, gtid);
-            const DevOut o = eval_pos(kc, call, gtid, d);
+            const DevOut o = eval_pos<J>(kc, call, gtid, d);
             double Y[16];
             full_Y(o, Y);
             const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
@@ -449,7 +452,7 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
             for (int pos = beg + gtid; pos < end; pos += nthr) {
                 const DevIn dd = load_terms(kc, pos);
                 if constexpr (MODE == 0) {
-                    const DevOut oo = eval_pos(kc, call, pos, dd);
+                    const DevOut oo = eval_pos<J>(kc, call, pos, dd);
                     stamp_colour<true>(kc, call, pos, dd, oo);
                 } else {
                     const int k = (dd.t0 != 0) + (dd.t1 != 0 && dd.t1 != dd.t0) +
@@ -465,29 +468,33 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
     hub_chunks(kc, call, 0, n_global_chunks, blockIdx.x * (blockDim.x >> 6), n_part * (blockDim.x >> 6), lds);
 }
 
+template <bool J>
 __global__ void __launch_bounds__(256) k_persistent_phase(KCirc kc, KCall call, KSync ks,
                                                           const double *buf, int n_part,
                                                           int n_global_chunks, KLocal kl) {
-    persistent_body<0>(kc, call, ks, buf, n_part, n_global_chunks, kl);
+    persistent_body<0, true, J>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 // Evaluate-ahead keeps one device's merged values per thread across the colour
 // phases (in LDS); it needs every device resident at once, hence four waves per SIMD.
+template <bool J>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_persistent_ahead(KCirc kc, KCall call, KSync ks, const double *buf, int n_part,
                    int n_global_chunks, KLocal kl) {
-    persistent_body<1>(kc, call, ks, buf, n_part, n_global_chunks, kl);
+    persistent_body<1, true, J>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 // The same without workgroup-local circuits (single circuits): less register
 // pressure in the one path it has.
+template <bool J>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_persistent_ahead_single(KCirc kc, KCall call, KSync ks, const double *buf, int n_part,
                           int n_global_chunks, KLocal kl) {
-    persistent_body<1, false>(kc, call, ks, buf, n_part, n_global_chunks, kl);
+    persistent_body<1, false, J>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
+template <bool J>
 __global__ void __launch_bounds__(256) k_persistent_stamp(KCirc kc, KCall call, KSync ks,
                                                           const double *buf, int n_part,
                                                           int n_global_chunks, KLocal kl) {
-    persistent_body<2>(kc, call, ks, buf, n_part, n_global_chunks, kl);
+    persistent_body<2, true, J>(kc, call, ks, buf, n_part, n_global_chunks, kl);
 }
 
 // History terms of the next backward-Euler step: ag0 times each device's terminal
@@ -513,10 +520,11 @@ hipError_t launch_history(const KCirc &kc, const KCall &call, double *hist_out, 
 }
 
 // Evaluate every device and write its merged values (buffered variant).
+template <bool J>
 __global__ void __launch_bounds__(256) k_eval_buffer(KCirc kc, KCall call, double *buf) {
     for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < kc.n; pos += gridDim.x * blockDim.x) {
         const DevIn d = load_terms(kc, pos);
-        const DevOut o = eval_pos(kc, call, pos, d);
+        const DevOut o = eval_pos<J>(kc, call, pos, d);
         double Y[16];
         full_Y(o, Y);
         const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
@@ -553,11 +561,12 @@ __global__ void k_fill_zero(double *A, int64_t nA, double *b, int64_t nb) {
 }
 
 // Atomic variant: no colouring; every contribution is an FP64 atomic add.
+template <bool J>
 __global__ void __launch_bounds__(256) k_atomic(KCirc kc, KCall call) {
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     for (int pos = gtid; pos < kc.n; pos += nthr) {
         const DevIn d = load_terms(kc, pos);
-        const DevOut o = eval_pos(kc, call, pos, d);
+        const DevOut o = eval_pos<J>(kc, call, pos, d);
         double Y[16];
         full_Y(o, Y);
         const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
@@ -751,7 +760,7 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
 // written in place, level by level in colour order (first writer stores, later ones
 // load-add, coherent across XCDs), with a grid-wide barrier between levels; then the
 // hub sums.
-template <bool GRID>
+template <bool GRID, bool J>
 __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks) {
     // LDS: kr.lds_int accumulators, then kr.nc_max merged values per lane (later the
     // fold scratch, HUB_K per wave)
@@ -790,7 +799,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     int ph = -1;
     if (pos >= 0) {
         const DevIn d = load_terms(kc, pos);
-        const DevOut o = eval_pos(kc, call, pos, d);
+        const DevOut o = eval_pos<J>(kc, call, pos, d);
         const int k = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) +
                       (d.t2 != 0 && d.t2 != d.t0 && d.t2 != d.t1) +
                       (d.t3 != 0 && d.t3 != d.t0 && d.t3 != d.t1 && d.t3 != d.t2);
@@ -889,16 +898,18 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     }
 }
 
+template <bool J>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_region(KCirc kc, KCall call, KRegion kr) {
     const KSync none{nullptr, 0};
-    region_body<false>(kc, call, kr, none);
+    region_body<false, J>(kc, call, kr, none);
 }
 
 // Grid-barrier form: launched with one resident workgroup per region (cooperative
 // launch, or an ordinary one that the occupancy query says fits at once).
+template <bool J>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_region_grid(KCirc kc, KCall call, KRegion kr, KSync ks) {
-    region_body<true>(kc, call, kr, ks);
+    region_body<true, J>(kc, call, kr, ks);
 }
 
 // Follow-up kernel of the region schedule: every large shared entry, one wave each,
@@ -929,15 +940,30 @@ static hipError_t occupancy(const void *fn, int block, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
+// Kernels come in two instantiations: with the junction terms (J) and without them
+// (cards with jmod = 0: model M's code exactly, its register allocation unchanged).
+static bool junctions(const KCirc &kc) { return kc.card[0].jmod != 0.0 || kc.card[1].jmod != 0.0; }
+
+// Resident blocks per CU that both instantiations of a kernel reach.
+static hipError_t occupancy_both(const void *f0, const void *f1, int block, size_t shm, int *blocks_per_cu) {
+    int a = 0, b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f0, block, shm);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f1, block, shm);
+    *blocks_per_cu = std::min(a, b);
+    return e;
+}
+
 static size_t persistent_lds(int mode, int block, int nc_max) {
     return mode == 1 ? sizeof(double) * (size_t)nc_max * block : 0;
 }
 
 hipError_t persistent_capacity(int mode, int block, int nc_max, int *blocks_per_cu) {
-    const void *fn = mode == 1 ? (const void *)k_persistent_ahead
-                   : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block,
-                                                        persistent_lds(mode, block, nc_max));
+    const void *f0 = mode == 1 ? (const void *)k_persistent_ahead<false>
+                   : mode == 2 ? (const void *)k_persistent_stamp<false> : (const void *)k_persistent_phase<false>;
+    const void *f1 = mode == 1 ? (const void *)k_persistent_ahead<true>
+                   : mode == 2 ? (const void *)k_persistent_stamp<true> : (const void *)k_persistent_phase<true>;
+    return occupancy_both(f0, f1, block, persistent_lds(mode, block, nc_max), blocks_per_cu);
 }
 
 hipError_t launch_gather_params(int32_t n, const int32_t *perm, const double *W, const double *L,
@@ -953,7 +979,8 @@ hipError_t launch_colour_phase(const KCirc &kc, const KCall &call, int c, int co
     int grid = (count + 255) / 256;
     if (with_fixed) grid = max(grid, min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
     grid = max(grid, 1);
-    hipLaunchKernelGGL(k_colour_phase, dim3(grid), dim3(256), 0, s, kc, call, c, with_fixed);
+    if (junctions(kc)) hipLaunchKernelGGL(k_colour_phase<true>, dim3(grid), dim3(256), 0, s, kc, call, c, with_fixed);
+    else hipLaunchKernelGGL(k_colour_phase<false>, dim3(grid), dim3(256), 0, s, kc, call, c, with_fixed);
     return hipGetLastError();
 }
 
@@ -993,9 +1020,14 @@ hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks
     int np = n_part, ng = n_global_chunks;
     KLocal l = kl;
     void *args[] = {&a, &b, &c, &d, &np, &ng, &l};
-    const void *fn = mode == 1 ? (kl.n == 0 && n_part == grid ? (const void *)k_persistent_ahead_single
-                                                                 : (const void *)k_persistent_ahead)
-                   : mode == 2 ? (const void *)k_persistent_stamp : (const void *)k_persistent_phase;
+    const bool J = junctions(kc);
+    const void *fn = mode == 1 ? (kl.n == 0 && n_part == grid
+                                      ? (J ? (const void *)k_persistent_ahead_single<true>
+                                           : (const void *)k_persistent_ahead_single<false>)
+                                      : (J ? (const void *)k_persistent_ahead<true>
+                                           : (const void *)k_persistent_ahead<false>))
+                   : mode == 2 ? (J ? (const void *)k_persistent_stamp<true> : (const void *)k_persistent_stamp<false>)
+                               : (J ? (const void *)k_persistent_phase<true> : (const void *)k_persistent_phase<false>);
     const size_t shm = persistent_lds(mode, block, kc.nc_max);
     if (!cooperative) return hipLaunchKernel(fn, dim3(grid), dim3(block), args, shm, s);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, shm, s);
@@ -1004,7 +1036,8 @@ hipError_t launch_persistent(const KCirc &kc, const KCall &call, const KSync &ks
 hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, hipStream_t s) {
     if (kc.n == 0) return hipSuccess;
     const int grid = (kc.n + 255) / 256;
-    hipLaunchKernelGGL(k_eval_buffer, dim3(grid), dim3(256), 0, s, kc, call, buf);
+    if (junctions(kc)) hipLaunchKernelGGL(k_eval_buffer<true>, dim3(grid), dim3(256), 0, s, kc, call, buf);
+    else hipLaunchKernelGGL(k_eval_buffer<false>, dim3(grid), dim3(256), 0, s, kc, call, buf);
     return hipGetLastError();
 }
 
@@ -1013,14 +1046,15 @@ size_t region_lds_bytes(int lds_int, int nc_max, int block) {
 }
 
 hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_region, block,
-                                                        region_lds_bytes(lds_int, nc_max, block));
+    return occupancy_both((const void *)k_region<false>, (const void *)k_region<true>, block,
+                          region_lds_bytes(lds_int, nc_max, block), blocks_per_cu);
 }
 
 hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s) {
     const int grid = std::max(kr.n_regions, 1);
-    hipLaunchKernelGGL(k_region, dim3(grid), dim3(block), region_lds_bytes(kr.lds_int, kr.nc_max, block), s, kc,
-                       call, kr);
+    const size_t shm = region_lds_bytes(kr.lds_int, kr.nc_max, block);
+    if (junctions(kc)) hipLaunchKernelGGL(k_region<true>, dim3(grid), dim3(block), shm, s, kc, call, kr);
+    else hipLaunchKernelGGL(k_region<false>, dim3(grid), dim3(block), shm, s, kc, call, kr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || kr.n_deferred == 0) return e;
     hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
@@ -1028,8 +1062,8 @@ hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, 
 }
 
 hipError_t region_grid_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_region_grid, block,
-                                                        region_lds_bytes(lds_int, nc_max, block));
+    return occupancy_both((const void *)k_region_grid<false>, (const void *)k_region_grid<true>, block,
+                          region_lds_bytes(lds_int, nc_max, block), blocks_per_cu);
 }
 
 hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks, int block,
@@ -1041,9 +1075,9 @@ hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion 
     void *args[] = {&a, &b, &r, &k};
     const int grid = std::max(kr.n_regions, 1);
     const size_t shm = region_lds_bytes(kr.lds_int, kr.nc_max, block);
-    hipError_t e = cooperative
-        ? hipLaunchCooperativeKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s)
-        : hipLaunchKernel((const void *)k_region_grid, dim3(grid), dim3(block), args, shm, s);
+    const void *fn = junctions(kc) ? (const void *)k_region_grid<true> : (const void *)k_region_grid<false>;
+    hipError_t e = cooperative ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, shm, s)
+                               : hipLaunchKernel(fn, dim3(grid), dim3(block), args, shm, s);
     if (e != hipSuccess || kr.n_deferred == 0) return e;
     hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
     return hipGetLastError();
@@ -1077,7 +1111,8 @@ hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_
     if (e != hipSuccess) return e;
     int grid = (kc.n + 255) / 256;
     grid = std::max(grid, std::min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
-    hipLaunchKernelGGL(k_atomic, dim3(std::max(grid, 1)), dim3(256), 0, s, kc, call);
+    if (junctions(kc)) hipLaunchKernelGGL(k_atomic<true>, dim3(std::max(grid, 1)), dim3(256), 0, s, kc, call);
+    else hipLaunchKernelGGL(k_atomic<false>, dim3(std::max(grid, 1)), dim3(256), 0, s, kc, call);
     return hipGetLastError();
 }
 

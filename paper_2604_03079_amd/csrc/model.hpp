@@ -205,7 +205,7 @@ __device__ __forceinline__ Dual3T<S> dsoftplus(Dual3T<S> a) {
 // Size-dependent constants of one device (depend on W, L, VTH0 only).
 template <class S>
 struct SizeDepT {
-    S Leff, vth_s, theta_dibl, theta_sce, beta0, lambda, AbL, Cg, Cov;
+    S Leff, vth_s, theta_dibl, theta_sce, beta0, lambda, AbL, Cg, Cov, Aj;
 };
 
 template <class S>
@@ -222,7 +222,38 @@ __device__ __forceinline__ SizeDepT<S> size_dep(const DevCard &cd, double pol, S
     s.AbL = (cd.a0 * s.Leff) / (s.Leff + cd.LA);
     s.Cg = (Weff * s.Leff) * cd.COXE;
     s.Cov = cd.cgdo * Weff;
+    s.Aj = Weff * cd.hdif;   // junction area
     return s;
+}
+
+// One source/drain-body junction of forward voltage v (body above the diffusion for
+// NMOS) and area A: diode current Ij and conductance gj (exponent clamped at -40,
+// tangent continuation above vjmax), abrupt-junction depletion charge Qj and
+// capacitance Cj (linear-capacitance continuation above fc pb).  The exponentials
+// and roots depend on v only; A carries the parameter sensitivity.
+template <class S>
+__device__ __forceinline__ void junction(const DevCard &cd, S A, double v, S &Ij, S &gj, S &Qj, S &Cj) {
+    const S Is = cd.js * A;
+    if (v <= cd.vjmax) {
+        const double a = v / cd.NJ_VT;
+        const double e = pexp(a > -40.0 ? a : -40.0);
+        Ij = Is * (e - 1.0);
+        gj = (Is * e) / cd.NJ_VT;
+    } else {
+        const double el = pexp(cd.vjmax / cd.NJ_VT);
+        const S gl = (Is * el) / cd.NJ_VT;
+        Ij = Is * (el - 1.0) + gl * (v - cd.vjmax);
+        gj = gl;
+    }
+    const S Cj0 = cd.cj * A;
+    if (v < cd.FCPB) {
+        const double r = __builtin_sqrt(1.0 - v / cd.pb);
+        Qj = (Cj0 * cd.TWO_PB) * (1.0 - r);
+        Cj = Cj0 / r;
+    } else {
+        Qj = Cj0 * (cd.JF1 + ((cd.JF3 * (v - cd.FCPB)) + cd.QUARTER_PB * ((v * v) - cd.FCPB2)) / cd.JF2);
+        Cj = (Cj0 / cd.JF2) * (cd.JF3 + 0.5 * (v / cd.pb));
+    }
 }
 
 // Local outputs of one device: the 9 independent entries of Y (rows/cols d, g, b;
@@ -235,7 +266,8 @@ struct DevOutT {
 
 // Model M at terminal voltages V = (Vd, Vg, Vs, Vb).  qout (optional): the terminal
 // charges (d, g, s, b) at V, for the history term of the next integration step.
-template <class S>
+// J = false compiles the junction terms out (cards with jmod = 0 only).
+template <class S, bool J = true>
 __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, const SizeDepT<S> &sd,
                                                  double Vd, double Vg, double Vs, double Vb,
                                                  double ag0, const double *hist, double *qout = nullptr) {
@@ -323,17 +355,39 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     }
     (void)qsD; (void)qsG; (void)qsB;
 
+    // junctions (card jmod): drain-body then source-body, current and charge from
+    // the body terminal to the diffusion terminal; jy = g + ag0 C
+    const bool jon = J && cd.jmod != 0.0;
+    S jI0 = 0.0, jI1 = 0.0, jQ0 = 0.0, jQ1 = 0.0, jy0 = 0.0, jy1 = 0.0;
+    if (jon) {
+        S ij, gj, qj, cj;
+        junction(cd, sd.Aj, p * (Vb - Vd), ij, gj, qj, cj);
+        jI0 = p * ij; jQ0 = p * qj; jy0 = gj + ag0 * cj;
+        junction(cd, sd.Aj, p * (Vb - Vs), ij, gj, qj, cj);
+        jI1 = p * ij; jQ1 = p * qj; jy1 = gj + ag0 * cj;
+    }
+
     DevOutT<S> o;
     o.Ydd = iD + ag0 * qdD; o.Ydg = iG + ag0 * qdG; o.Ydb = iB + ag0 * qdB;
     o.Ygd = ag0 * qgD;      o.Ygg = ag0 * qgG;      o.Ygb = ag0 * qgB;
     o.Ybd = ag0 * qbD;      o.Ybg = ag0 * qbG;      o.Ybb = ag0 * qbB;
+    if (jon) {
+        o.Ydd = o.Ydd + jy0;
+        o.Ybd = o.Ybd - jy0;
+        o.Ydb = o.Ydb - jy0;
+        o.Ybb = (o.Ybb + jy0) + jy1;
+    }
     const S Ysd = -((o.Ydd + o.Ygd) + o.Ybd);
     const S Ysg = -((o.Ydg + o.Ygg) + o.Ybg);
     const S Ysb = -((o.Ydb + o.Ygb) + o.Ybb);
 
     // physical terminal currents and charges
-    const S I_d = p * Idp, I_s = p * (-Idp);
-    const S Q_d = p * Qdp, Q_g = p * Qg.v, Q_s = p * Qsp, Q_b = p * Qb.v;
+    S I_d = p * Idp, I_s = p * (-Idp), I_b = 0.0;
+    S Q_d = p * Qdp, Q_g = p * Qg.v, Q_s = p * Qsp, Q_b = p * Qb.v;
+    if (jon) {
+        I_d = I_d - jI0; I_s = I_s - jI1; I_b = jI0 + jI1;
+        Q_d = Q_d - jQ0; Q_s = Q_s - jQ1; Q_b = (Q_b + jQ0) + jQ1;
+    }
     if (qout) {
         qout[0] = val(Q_d);
         qout[1] = val(Q_g);
@@ -344,7 +398,7 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     o.bd = (((o.Ydd * dvd + o.Ydg * dvg) + o.Ydb * dvb) - I_d) - ag0 * Q_d;
     o.bg = (((o.Ygd * dvd + o.Ygg * dvg) + o.Ygb * dvb) - 0.0) - ag0 * Q_g;
     o.bs = (((Ysd * dvd + Ysg * dvg) + Ysb * dvb) - I_s) - ag0 * Q_s;
-    o.bb = (((o.Ybd * dvd + o.Ybg * dvg) + o.Ybb * dvb) - 0.0) - ag0 * Q_b;
+    o.bb = (((o.Ybd * dvd + o.Ybg * dvg) + o.Ybb * dvb) - I_b) - ag0 * Q_b;
     if (hist) {
         o.bd = o.bd + hist[0];
         o.bg = o.bg + hist[1];

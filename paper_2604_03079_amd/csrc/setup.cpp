@@ -9,6 +9,7 @@
 // the paper's ascending order, the vertices can be visited largest degree first
 // (Welsh and Powell) or by DSATUR (Brelaz), which often reach the clique bound.
 #include <algorithm>
+#include <cstring>
 #include <set>
 #include <tuple>
 #include <cmath>
@@ -401,6 +402,7 @@ DevCard derive_card(const cs_model_card &c) {
     // CODATA 2018 / SI exact constants
     const double EPS0 = 8.8541878128e-12, QE = 1.602176634e-19, KB_Q = 8.617333262e-5;
     DevCard d;
+    std::memset(&d, 0, sizeof(d));
     d.VT = KB_Q * c.tnom;
     const double EPSOX = 3.9 * EPS0;
     const double EPSSI = 11.7 * EPS0;
@@ -426,6 +428,18 @@ DevCard derive_card(const cs_model_card &c) {
     d.cdsc = c.cdsc; d.voff = c.voff; d.u0 = c.u0; d.ua = c.ua; d.ub = c.ub; d.uc = c.uc;
     d.toxe = c.toxe; d.delta = c.delta; d.delta1 = c.delta1; d.dvt0 = c.dvt0; d.dvt1 = c.dvt1;
     d.dsub = c.dsub; d.w0 = c.w0; d.lambda_l = c.lambda_l; d.a0 = c.a0; d.cgdo = c.cgdo;
+    // junctions: constants in the operation order of the junction equations
+    d.jmod = c.jmod != 0.0 ? 1.0 : 0.0;
+    d.js = c.js; d.cj = c.cj; d.pb = c.pb; d.hdif = c.hdif; d.vjmax = c.vjmax;
+    d.NJ_VT = c.nj * d.VT;
+    d.FCPB = c.fc * c.pb;
+    d.FCPB2 = d.FCPB * d.FCPB;
+    d.TWO_PB = 2.0 * c.pb;
+    d.QUARTER_PB = 0.25 / c.pb;
+    const double s1 = std::sqrt(1.0 - c.fc);
+    d.JF1 = (2.0 * c.pb) * (1.0 - s1);
+    d.JF2 = (1.0 - c.fc) * s1;
+    d.JF3 = 1.0 - 1.5 * c.fc;
     return d;
 }
 

@@ -189,3 +189,15 @@ def test_resistor_errors():
     p.set_resistors(np.zeros((0, 2), np.int32), np.zeros(0))
     p.colour(None)
     assert c.nnz - p.build_map()[1] == 2 * int(np.count_nonzero(circ.res.min(axis=1)))
+
+
+def test_junction_cards_are_checked():
+    c = CS.Circuit.from_netlist(G.workload(0))
+    c.colour(None)
+    c.build_map()
+    for bad in (dict(pb=0.0), dict(fc=1.0), dict(nj=-1.0), dict(vjmax=2.0), dict(js=-1e-4)):
+        with pytest.raises(CS.CsError) as e:
+            c.set_models(G.junction_card(1, **bad), G.junction_card(-1))
+        assert e.value.status == -1
+    c.set_models(G.junction_card(1), G.junction_card(-1))
+    c.set_models(G.default_card(1, ), dict(G.default_card(-1), pb=0.0))   # junctions off: not checked
