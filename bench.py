@@ -215,6 +215,27 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel, 
     print(json.dumps(entry))
 
 
+def bench_junction_level(torch, CS, G, dev):
+    """The second model level (source/drain-body junctions on every FET) on the
+    chain of 100,000 stages: the region step against model M's."""
+    circ = G.workload(1)
+    W, L, V, x = device_tensors(torch, circ, dev)
+    out = dict(n_dev=circ.n_dev)
+    for key, nm, pm in (("model_m", G.default_card(1), G.default_card(-1)),
+                        ("with_junctions", G.junction_card(1), G.junction_card(-1))):
+        c = CS.prepare(circ, exclude=True, nmos=nm, pmos=pm)
+        c.set_params(W, L, V)
+        A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+        b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+        ms, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "region"), 50, 5)
+        c.check()
+        out[key] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2))
+    out["junction_cost"] = round(out["with_junctions"]["ms_per_step"] / out["model_m"]["ms_per_step"], 3)
+    log(f"  junction level, chain100k region: {out['with_junctions']['ms_per_step'] * 1e3:.1f} us "
+        f"({out['junction_cost']} x model M's {out['model_m']['ms_per_step'] * 1e3:.1f} us, graph replay)")
+    return out
+
+
 def bench_newton(torch, CS, G, dev):
     """The Newton loop the stamp serves: one backward-Euler step (ag0 = 1e12, history
     terms N(0, 1e-5)) of the 100,000-stage chain with its input held at 0.3 V, and of
@@ -568,6 +589,7 @@ def main():
         extras["adder_64bit_28T"] = bench_adder(torch, CS, G, dev)
         extras["batch_512"] = bench_batch(torch, CS, G, dev)
         extras["adjoint"] = bench_adjoint(torch, CS, G, dev)
+        extras["junction_level"] = bench_junction_level(torch, CS, G, dev)
         extras["newton"] = bench_newton(torch, CS, G, dev)
         result["extras"] = extras
 
