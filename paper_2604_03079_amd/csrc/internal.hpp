@@ -152,8 +152,11 @@ struct HostLU {
     std::vector<double> Tx;
 };
 // Column order Q of the circuit's MNA matrix (source pairs first, then nested
-// dissection) and the preferred pivot row of each column (-1: its own row).
-void mna_order(const HostCircuit &h, std::vector<int32_t> &Q, std::vector<int32_t> &pref);
+// dissection (method 0) or minimum degree (method 1)) and the preferred pivot row
+// of each column (-1: its own row).
+void mna_order(const HostCircuit &h, std::vector<int32_t> &Q, std::vector<int32_t> &pref, int method);
+// Factor with both orders, keep the one with the lower estimated level-scheduled cost.
+Err factor_mna(const HostCircuit &h, const double *A, HostLU &F, int *method);
 // One factorisation with threshold partial pivoting (host values of A in CSR).
 Err host_lu(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx,
             const double *val, const std::vector<int32_t> &Q, const std::vector<int32_t> &pref, HostLU &F);

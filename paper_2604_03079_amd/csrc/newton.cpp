@@ -93,9 +93,7 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     HostLU F;
     try {
-        std::vector<int32_t> Q, pref;
-        mna_order(h, Q, pref);
-        Err e = host_lu(n, h.row_ptr, h.col_idx, Ah.data(), Q, pref, F);
+        Err e = factor_mna(h, Ah.data(), F, nullptr);
         if (e.st != CS_OK) return nfail(e.st, e.msg);
     } catch (const std::bad_alloc &) {
         return nfail(CS_ENOMEM, "host allocation");
@@ -295,9 +293,7 @@ cs_status cs_factor_host(const cs_circuit *c, const double *A_host, int64_t *nnz
     const HostCircuit &h = c->h;
     HostLU F;
     try {
-        std::vector<int32_t> q, pref;
-        mna_order(h, q, pref);
-        Err e = host_lu(h.n_rows, h.row_ptr, h.col_idx, A_host, q, pref, F);
+        Err e = factor_mna(h, A_host, F, nullptr);
         if (e.st != CS_OK) return nfail(e.st, e.msg);
     } catch (const std::bad_alloc &) {
         return nfail(CS_ENOMEM, "host allocation");
