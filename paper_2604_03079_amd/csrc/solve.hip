@@ -87,23 +87,45 @@ __global__ void __launch_bounds__(64) k_lu_lower_wave(const int32_t *__restrict_
     }
     __syncthreads();
     double yi = b[P[i]];
-    for (int32_t a = 0; a < nl; ++a) {
+    // rows j of the L entries are final (earlier levels): the pivot, y_j, the end of
+    // row j and this lane's first entry of U(j, :) are loaded one entry ahead
+    struct Ahead {
+        int32_t q0, qe, k0;
+        double ujj, yj, t0;
+    };
+    auto fetch = [&](int32_t a) {
+        Ahead f;
         const int32_t j = col[a];
-        const double l = v[a] / T[diag[j]];
-        yi = yi - l * y[j];
+        const int32_t dj = diag[j];
+        f.q0 = dj + 1 + lane;
+        f.qe = Tp[j + 1];
+        f.ujj = T[dj];
+        f.yj = y[j];
+        f.k0 = f.q0 < f.qe ? Ti[f.q0] : -1;
+        f.t0 = f.q0 < f.qe ? T[f.q0] : 0.0;
+        return f;
+    };
+    Ahead cur{};
+    if (nl > 0) cur = fetch(0);
+    for (int32_t a = 0; a < nl; ++a) {
+        const Ahead nxt = a + 1 < nl ? fetch(a + 1) : cur;
+        const double l = v[a] / cur.ujj;
+        yi = yi - l * cur.yj;
         __syncthreads();   // every lane has read v[a] before lane 0 replaces it
         if (lane == 0) v[a] = l;
-        for (int32_t q = diag[j] + 1 + lane; q < Tp[j + 1]; q += 64) {
-            const int32_t k = Ti[q];
+        for (int32_t q = cur.q0; q < cur.qe; q += 64) {
+            const int32_t k = q == cur.q0 ? cur.k0 : Ti[q];
+            const double t = q == cur.q0 ? cur.t0 : T[q];
             int32_t lo = a + 1, hi = len;   // columns of the row after j, ascending
             while (lo < hi) {
                 const int32_t m = (lo + hi) >> 1;
                 if (col[m] < k) lo = m + 1;
                 else hi = m;
             }
-            if (lo < len && col[lo] == k) v[lo] = v[lo] - l * T[q];
+            if (lo < len && col[lo] == k) v[lo] = v[lo] - l * t;
         }
         __syncthreads();
+        cur = nxt;
     }
     for (int32_t r = lane; r < len; r += 64) T[t0 + r] = v[r];
     if (lane == 0) y[i] = yi;
