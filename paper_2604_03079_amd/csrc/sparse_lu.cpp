@@ -47,7 +47,7 @@ struct Graph {
 
 struct Dissect {
     const Graph &g;
-    std::vector<int32_t> part, level, queue, out;
+    std::vector<int32_t> part, level, out;
     int32_t tag = 0;
     explicit Dissect(const Graph &gr) : g(gr), part((size_t)gr.n, -1), level((size_t)gr.n, -1) {}
 

@@ -76,3 +76,35 @@ def test_singular_matrix_is_refused(orc):
     with pytest.raises(CS.CsError) as e:
         c.factor_host(A)
     assert e.value.status == -6
+
+
+def _levels(n, Tp, Ti):
+    lev = np.zeros(n, np.int64)
+    for i in range(n):
+        cols = Ti[Tp[i]:Tp[i + 1]]
+        low = cols[cols < i]
+        lev[i] = lev[low].max() + 1 if len(low) else 0
+    return int(lev.max()) + 1
+
+
+def test_order_choice_chain_and_split_adder(orc):
+    # the chain keeps nested dissection (a shallow elimination, few dependency
+    # levels); the adder with every net split takes minimum degree (far less fill
+    # than the level-set separators of nested dissection give it)
+    chain = G.chain_dc_case(20_000, 2)
+    c = CS.prepare(chain, True)
+    rp, ci = orc.pattern(chain)
+    A, _ = orc.assemble(chain, rp, ci, NC, PC, 1e12)
+    _, _, Tp, Ti, _ = c.factor_host(A)
+    assert _levels(chain.n_rows, Tp, Ti) <= 80 and len(Ti) <= 2 * len(ci)
+    adder = G.adder_case(16, 9, "all")
+    c = CS.prepare(adder, True)
+    rp, ci = orc.pattern(adder)
+    A, _ = orc.assemble(adder, rp, ci, NC, PC, 1e12)
+    P, Q, Tp, Ti, Tx = c.factor_host(A)
+    assert len(Ti) <= 2 * len(ci)
+    n = adder.n_rows
+    M = sp.csr_matrix((A, ci, rp), shape=(n, n))
+    T = sp.csr_matrix((Tx, Ti, Tp), shape=(n, n))
+    L = sp.tril(T, -1) + sp.identity(n)
+    assert np.abs((L @ sp.triu(T) - M[P][:, Q]).toarray()).max() <= 1e-12 * abs(A).max()
