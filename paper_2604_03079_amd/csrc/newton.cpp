@@ -28,6 +28,7 @@
 namespace cs {
 
 struct NewtonState {
+    int device = -1;   // HIP device of the buffers below
     int32_t n = 0;
     int64_t nnzT = 0;
     DevBuf<int32_t> ptrA, indA, ptrT, indT, P, Q;
@@ -102,6 +103,7 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
     if (!ns) return nfail(CS_ENOMEM, "host allocation");
     ns->host_lu_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     ns->n = n;
+    ns->device = c->device;
     ns->nnzT = (int64_t)F.Ti.size();
     struct Guard {
         NewtonState *p;
@@ -207,6 +209,10 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
         if (converged) *converged = 1;
         if (last_step) *last_step = 0.0;
         return CS_OK;
+    }
+    if (c->newton && c->newton->device != c->device) {   // the circuit moved to another GPU
+        destroy_newton(c->newton);
+        c->newton = nullptr;
     }
     if (!c->newton) {
         cs_status st = cs_eval_stamp(c, variant, x, ag0, hist, A_val, b, stream);
