@@ -290,7 +290,58 @@ def bench_newton(torch, CS, G, dev):
                                                ms_per_step=round(ms / 20, 3), newton_iterations=iters)
     log(f"  transient chain100k: 20 steps of 1 ps in {ms:.1f} ms ({ms / 20:.2f} ms per step), "
         f"Newton iterations {iters}")
+    out["adder64_r89_sizing_batch"] = bench_batch_newton(torch, CS, G, dev)
     return out
+
+
+def bench_batch_newton(torch, CS, G, dev, n_var=32):
+    """A sizing loop's batch (the paper's motivation): n_var parameter draws of the
+    split 64-bit adder, one backward-Euler Newton solve of all of them at once
+    (cs_batch_newton, block-diagonal system) against one cs_newton per variant with
+    the faster single-circuit solver, after every factorisation is made."""
+    variants = [G.adder_case(64, 100 + k, "all") for k in range(n_var)]
+    cs = [CS.prepare(v, exclude=True) for v in variants]
+    B = CS.Batch(cs)
+    cat = lambda a: torch.from_numpy(np.concatenate([getattr(v, a) for v in variants])).to(dev)
+    W, L, V, x0 = cat("W"), cat("L"), cat("VTH0"), cat("x")
+    B.set_params(W, L, V)
+    hist = torch.from_numpy(np.random.default_rng(15).normal(0, 1e-5, (B.n_dev, 4))).to(dev)
+    row = dict(n_variants=n_var, n_dev=B.n_dev, n_rows=B.n_rows, nnz=B.nnz)
+    for solver in ("levels", "rocsolver"):
+        first = B.newton(x0.clone(), AG0, hist, solver=solver)
+        x = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = B.newton(x, AG0, hist, solver=solver)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        B.check()
+        it = max(r["iterations"], 1)
+        row["batch_" + solver] = dict(iterations=r["iterations"], converged=r["converged"], wall_ms=round(wall, 3),
+                                      ms_per_iteration={k: round(v / it, 4) for k, v in r["ms"].items()
+                                                        if k != "host_factor"},
+                                      host_factor_ms=round(first["ms"]["host_factor"], 2))
+        log(f"  sizing batch {n_var} x adder64 R89 {solver}: {r['iterations']} iterations, wall {wall:.1f} ms "
+            f"({wall / n_var:.2f} ms per variant), host factorisation {first['ms']['host_factor']:.0f} ms")
+    B.per_circuit_params(W, L, V)
+    xs, hs = [], []
+    for i, c in enumerate(cs):
+        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+        a, z = int(B.dev_off[i]), int(B.dev_off[i + 1])
+        xs.append((r0, r1))
+        hs.append(hist[a:z])
+        c.newton(x0[r0:r1].clone(), AG0, hs[-1], solver="rocsolver")   # factor pattern, analysis
+    x = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = [c.newton(x[r0:r1], AG0, h, solver="rocsolver")["iterations"] for c, (r0, r1), h in zip(cs, xs, hs)]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    row["per_variant_rocsolver"] = dict(wall_ms=round(wall, 3), iterations=its)
+    best = min(row["batch_levels"]["wall_ms"], row["batch_rocsolver"]["wall_ms"])
+    row["speedup_batch_vs_per_variant"] = round(wall / best, 2)
+    log(f"  sizing batch: one cs_newton per variant (rocSOLVER) {wall:.1f} ms; batch {wall / best:.1f} x faster")
+    return row
 
 
 def bench_batch(torch, CS, G, dev):

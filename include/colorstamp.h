@@ -335,6 +335,19 @@ cs_status cs_batch_vjp(cs_batch *b, const double *x, double ag0, const double *h
                        const double *A_bar, const double *b_bar, double *W_bar, double *L_bar,
                        double *VTH0_bar, void *stream);
 cs_status cs_batch_check(cs_batch *b, void *stream);
+/* cs_newton over every circuit of the batch at once (the paper's motivation: a
+ * sizing loop simulates many variants of a circuit, Introduction).  The batch's
+ * matrix is block diagonal: one solve of the packed system (x, b by rows, A_val by
+ * nonzeros in batch order) is one Newton step of every circuit.  Stamping is
+ * cs_batch_eval_stamp; the host factorisation (made at the first call on this batch)
+ * orders the packed pattern as cs_newton orders one circuit's, each circuit's
+ * voltage sources paired within it; node rows of every circuit are clamped.  The
+ * iteration stops when the largest step over all circuits is <= tol.  Arguments,
+ * outputs and errors as in cs_newton. */
+cs_status cs_batch_newton(cs_batch *b, int32_t solver, double *x, double ag0, const double *hist,
+                          int32_t max_iter, double vstep, double tol, double *A_val, double *b_vec,
+                          int32_t *n_iter, int32_t *converged, double *last_step, double *times_ms,
+                          void *stream);
 
 /* Message for the last non-OK status returned to the calling thread. */
 const char *cs_last_error(void);

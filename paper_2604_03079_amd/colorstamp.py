@@ -33,6 +33,7 @@ EXPORTS = (
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
     "cs_batch_get_region_plan", "cs_batch_eval_stamp", "cs_batch_vjp", "cs_batch_check",
+    "cs_batch_newton",
     "cs_last_error",
 )
 
@@ -98,6 +99,7 @@ def lib():
             "cs_batch_eval_stamp": [p, p, d, p, p, p, p],
             "cs_batch_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_batch_check": [p, p],
+            "cs_batch_newton": [p, i32, p, d, p, i32, d, d, p, p, p, p, p, p, p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -453,6 +455,56 @@ class Batch:
 
     def check(self, stream=None):
         _check(lib().cs_batch_check(self._h, _stream(stream)), "cs_batch_check")
+
+    def newton(self, x, ag0: float = 0.0, hist=None, max_iter: int = 100, vstep: float = 0.3,
+               tol: float = 1e-9, solver="levels", A=None, b=None, stream=None) -> dict:
+        """Newton loop over every circuit at once from the packed x (device, updated
+        in place); returns as Circuit.newton."""
+        import torch
+        if A is None:
+            A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
+        if b is None:
+            b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
+        it, conv, step = C.c_int32(), C.c_int32(), C.c_double()
+        t = (C.c_double * 5)()
+        _check(lib().cs_batch_newton(self._h, SOLVERS[solver], _dev_ptr(x), float(ag0), _dev_ptr(hist),
+                                     int(max_iter), float(vstep), float(tol), _dev_ptr(A), _dev_ptr(b),
+                                     C.byref(it), C.byref(conv), C.byref(step), t, _stream(stream)),
+               "cs_batch_newton")
+        return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,
+                    ms=dict(stamp=t[0], refactor=t[1], solve=t[2], update=t[3], host_factor=t[4]))
+
+    def history(self, x, ag0: float, out=None, stream=None):
+        """Packed history terms (n_dev, 4) of the next backward-Euler step: each
+        circuit's cs_history on its slice of the packed x, with the member
+        circuits' own parameters (per_circuit_params gives them the batch's)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_dev, 4), dtype=torch.float64, device=x.device)
+        for i, c in enumerate(self.circuits):
+            r0, r1 = int(self.row_off[i]), int(self.row_off[i + 1])
+            a, z = int(self.dev_off[i]), int(self.dev_off[i + 1])
+            c.history(x[r0:r1], ag0, out[a:z], stream)
+        return out
+
+    def transient(self, x, h: float, n_steps: int, **newton_kw):
+        """Backward-Euler transient of every circuit at once from the packed x
+        (device, updated in place), as Circuit.transient: the packed rows after every
+        step (n_steps + 1 rows, the start first) and the Newton iteration counts.
+        The history terms use the member circuits' parameters (per_circuit_params)."""
+        import torch
+        ag0 = 1.0 / h
+        wave = [x.clone()]
+        iters = []
+        hist = torch.empty((self.n_dev, 4), dtype=torch.float64, device=x.device)
+        for _ in range(n_steps):
+            self.history(x, ag0, hist)
+            r = self.newton(x, ag0, hist, **newton_kw)
+            if not r["converged"]:
+                raise CsError(-6, "transient", f"Newton did not converge at step {len(iters) + 1}")
+            iters.append(r["iterations"])
+            wave.append(x.clone())
+        return torch.stack(wave), iters
 
     def per_circuit_params(self, W, L, VTH0):
         """Give every member circuit its slice of the packed parameters."""

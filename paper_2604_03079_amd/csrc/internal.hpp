@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -151,15 +152,22 @@ struct HostLU {
     std::vector<int32_t> P, Q, Tp, Ti;
     std::vector<double> Tx;
 };
-// Column order Q of the circuit's MNA matrix (source pairs first, then nested
-// dissection (method 0) or minimum degree (method 1)) and the preferred pivot row
-// of each column (-1: its own row).
-void mna_order(const HostCircuit &h, std::vector<int32_t> &Q, std::vector<int32_t> &pref, int method);
+// An MNA matrix pattern for the sparse solve: n rows, CSR, and per voltage source
+// its two terminal node rows (-1 for ground) and its branch row.
+struct MnaView {
+    int32_t n = 0;
+    const int32_t *row_ptr = nullptr, *col_idx = nullptr;
+    std::vector<std::array<int32_t, 3>> src;
+};
+MnaView circuit_view(const HostCircuit &h);
+// Column order Q (source pairs first, then nested dissection (method 0) or minimum
+// degree (method 1)) and the preferred pivot row of each column (-1: its own row).
+void mna_order(const MnaView &m, std::vector<int32_t> &Q, std::vector<int32_t> &pref, int method);
 // Factor with both orders, keep the one with the lower estimated level-scheduled cost.
-Err factor_mna(const HostCircuit &h, const double *A, HostLU &F, int *method);
+Err factor_mna(const MnaView &m, const double *A, HostLU &F, int *method);
 // One factorisation with threshold partial pivoting (host values of A in CSR).
-Err host_lu(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx,
-            const double *val, const std::vector<int32_t> &Q, const std::vector<int32_t> &pref, HostLU &F);
+Err host_lu(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+            const std::vector<int32_t> &Q, const std::vector<int32_t> &pref, HostLU &F);
 
 // GPU state of the Newton loop (solver handles, factor pattern); released with the circuit.
 struct NewtonState;
@@ -237,4 +245,11 @@ struct cs_batch {
     cs_variant schedule = CS_COLOR_PERSISTENT;
     cs::RegionPlan rp;
     cs::RegionDev rd;
+    // Newton loop state (block-diagonal pattern, built by the first cs_batch_newton)
+    std::vector<int32_t> nt_row_ptr, nt_col_idx;
+    cs::NewtonState *newton = nullptr;
+    cs_batch() = default;
+    cs_batch(const cs_batch &) = delete;
+    cs_batch &operator=(const cs_batch &) = delete;
+    ~cs_batch() { cs::destroy_newton(newton); }
 };

@@ -341,15 +341,16 @@ __global__ void __launch_bounds__(256) k_linear_add(int32_t n, const int32_t *__
 // clamp compares explicitly so that a NaN step stays NaN; the largest |d| of the
 // block is reduced in LDS and merged with one 64-bit atomic max on its bits (the
 // order of non-negative doubles, NaN above infinity).
-__global__ void __launch_bounds__(256) k_newton_update(int32_t n, int32_t n_clamp, const double *__restrict__ y,
-                                                       double *__restrict__ x, double vstep,
-                                                       unsigned long long *step_bits) {
+__global__ void __launch_bounds__(256) k_newton_update(int32_t n, int32_t n_clamp,
+                                                       const uint8_t *__restrict__ clamp,
+                                                       const double *__restrict__ y, double *__restrict__ x,
+                                                       double vstep, unsigned long long *step_bits) {
     __shared__ unsigned long long red[256];
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long m = 0;
     if (i < n) {
         double d = y[i] - x[i];
-        if (i < n_clamp) {
+        if (clamp ? clamp[i] != 0 : i < n_clamp) {
             if (d > vstep) d = vstep;
             else if (d < -vstep) d = -vstep;
         }
@@ -996,10 +997,12 @@ hipError_t launch_linear_add(int32_t n, const int32_t *idx, const double *val, d
     return hipGetLastError();
 }
 
-hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const double *y, double *x, double vstep,
+hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const uint8_t *clamp, const double *y, double *x,
+                                double vstep,
                                 unsigned long long *step_bits, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_newton_update, dim3((n + 255) / 256), dim3(256), 0, s, n, n_clamp, y, x, vstep, step_bits);
+    hipLaunchKernelGGL(k_newton_update, dim3((n + 255) / 256), dim3(256), 0, s, n, n_clamp, clamp, y, x, vstep,
+                       step_bits);
     return hipGetLastError();
 }
 

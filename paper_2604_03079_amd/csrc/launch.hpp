@@ -37,7 +37,8 @@ int32_t lu_stage_entries();
 hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
                            const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
                            hipStream_t s);
-hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const double *y, double *x, double vstep,
+hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const uint8_t *clamp, const double *y, double *x,
+                                double vstep,
                                 unsigned long long *step_bits, hipStream_t s);
 // cooperative: hipLaunchCooperativeKernel (the runtime checks co-residency);
 // otherwise an ordinary launch of a grid the occupancy query says fits at once.

@@ -30,10 +30,11 @@ namespace cs {
 struct NewtonState {
     int device = -1;   // HIP device of the buffers below
     int32_t n = 0;
-    int64_t nnzT = 0;
+    int64_t nnzA = 0, nnzT = 0;
     DevBuf<int32_t> ptrA, indA, ptrT, indT, P, Q;
     DevBuf<double> valT;
     DevBuf<unsigned long long> step;
+    DevBuf<uint8_t> clamp;   // rows whose step is clamped (batches; empty: rows below n_clamp)
     // level-scheduled refactorisation: T position -> A position (-1: fill), diagonal
     // positions, rows grouped by lower and by upper dependency level
     DevBuf<int32_t> src, diag, lrows, urows;
@@ -83,18 +84,20 @@ struct Events {
     }
 };
 
-// Host factorisation at the values of A (device), upload of the factor pattern and
-// the solver's analysis.
-cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
-    const HostCircuit &h = c->h;
-    const int32_t n = h.n_rows;
-    std::vector<double> Ah((size_t)h.nnz);
+// Host factorisation of the pattern m at the values of A (device), upload of the
+// factor pattern and the level analysis.  clamp (optional, host, m.n flags): rows
+// whose Newton step is clamped.
+cs_status build_state(const MnaView &m, int device, double *A_val, const std::vector<uint8_t> *clamp,
+                      hipStream_t s, NewtonState **out) {
+    const int32_t n = m.n;
+    const int64_t nnz = m.row_ptr[n];
+    std::vector<double> Ah((size_t)nnz);
     NCHECK_HIP(hipMemcpyAsync(Ah.data(), A_val, sizeof(double) * Ah.size(), hipMemcpyDeviceToHost, s), "read A");
     NCHECK_HIP(hipStreamSynchronize(s), "stream synchronise");
     auto t0 = std::chrono::steady_clock::now();
     HostLU F;
     try {
-        Err e = factor_mna(h, Ah.data(), F, nullptr);
+        Err e = factor_mna(m, Ah.data(), F, nullptr);
         if (e.st != CS_OK) return nfail(e.st, e.msg);
     } catch (const std::bad_alloc &) {
         return nfail(CS_ENOMEM, "host allocation");
@@ -103,20 +106,22 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
     if (!ns) return nfail(CS_ENOMEM, "host allocation");
     ns->host_lu_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     ns->n = n;
-    ns->device = c->device;
+    ns->device = device;
+    ns->nnzA = nnz;
     ns->nnzT = (int64_t)F.Ti.size();
     struct Guard {
         NewtonState *p;
         ~Guard() { delete p; }
     } guard{ns};
-    NCHECK_HIP(ns->ptrA.upload(h.row_ptr), "upload pattern");
-    NCHECK_HIP(ns->indA.upload(h.col_idx), "upload pattern");
+    NCHECK_HIP(ns->ptrA.upload(std::vector<int32_t>(m.row_ptr, m.row_ptr + n + 1)), "upload pattern");
+    NCHECK_HIP(ns->indA.upload(std::vector<int32_t>(m.col_idx, m.col_idx + nnz)), "upload pattern");
     NCHECK_HIP(ns->ptrT.upload(F.Tp), "upload factor pattern");
     NCHECK_HIP(ns->indT.upload(F.Ti), "upload factor pattern");
     NCHECK_HIP(ns->valT.upload(F.Tx), "upload factors");
     NCHECK_HIP(ns->P.upload(F.P), "upload pivots");
     NCHECK_HIP(ns->Q.upload(F.Q), "upload pivots");
     NCHECK_HIP(ns->step.alloc(1), "alloc step word");
+    if (clamp) NCHECK_HIP(ns->clamp.upload(*clamp), "upload clamp flags");
     // level analysis of the factor pattern
     std::vector<int32_t> pinv((size_t)n), qinv((size_t)n), src((size_t)ns->nnzT, -1), diag((size_t)n, -1);
     for (int32_t k = 0; k < n; ++k) {
@@ -124,8 +129,8 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
         qinv[(size_t)F.Q[(size_t)k]] = k;
     }
     for (int32_t r = 0; r < n; ++r)
-        for (int32_t e = h.row_ptr[(size_t)r]; e < h.row_ptr[(size_t)r + 1]; ++e) {
-            const int32_t i = pinv[(size_t)r], k = qinv[(size_t)h.col_idx[(size_t)e]];
+        for (int32_t e = m.row_ptr[r]; e < m.row_ptr[r + 1]; ++e) {
+            const int32_t i = pinv[(size_t)r], k = qinv[(size_t)m.col_idx[e]];
             auto b0 = F.Ti.begin() + F.Tp[(size_t)i], b1 = F.Ti.begin() + F.Tp[(size_t)i + 1];
             auto it = std::lower_bound(b0, b1, k);
             if (it == b1 || *it != k) return nfail(CS_EINVAL, "factor pattern misses an entry of A");
@@ -134,22 +139,22 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
     std::vector<int32_t> lev((size_t)n, 0), ulev((size_t)n, 0);
     int32_t nl = 0, nu = 0;
     for (int32_t i = 0; i < n; ++i) {
-        int32_t m = 0;
+        int32_t mx = 0;
         for (int32_t p = F.Tp[(size_t)i]; p < F.Tp[(size_t)i + 1]; ++p) {
             const int32_t j = F.Ti[(size_t)p];
-            if (j < i) m = std::max(m, lev[(size_t)j] + 1);
+            if (j < i) mx = std::max(mx, lev[(size_t)j] + 1);
             else if (j == i) diag[(size_t)i] = p;
         }
         if (diag[(size_t)i] < 0) return nfail(CS_EINVAL, "factor pattern misses a diagonal");
-        lev[(size_t)i] = m;
-        nl = std::max(nl, m + 1);
+        lev[(size_t)i] = mx;
+        nl = std::max(nl, mx + 1);
     }
     for (int32_t i = n - 1; i >= 0; --i) {
-        int32_t m = 0;
+        int32_t mx = 0;
         for (int32_t p = diag[(size_t)i] + 1; p < F.Tp[(size_t)i + 1]; ++p)
-            m = std::max(m, ulev[(size_t)F.Ti[(size_t)p]] + 1);
-        ulev[(size_t)i] = m;
-        nu = std::max(nu, m + 1);
+            mx = std::max(mx, ulev[(size_t)F.Ti[(size_t)p]] + 1);
+        ulev[(size_t)i] = mx;
+        nu = std::max(nu, mx + 1);
     }
     auto group = [n](const std::vector<int32_t> &lv, int32_t nlev, std::vector<int32_t> &ptr) {
         ptr.assign((size_t)nlev + 1, 0);
@@ -174,57 +179,32 @@ cs_status build_state(cs_circuit *c, double *A_val, double *b, hipStream_t s) {
     NCHECK_HIP(ns->diag.upload(diag), "upload diagonal positions");
     NCHECK_HIP(ns->y.alloc((size_t)n), "alloc solve vector");
     guard.p = nullptr;
-    c->newton = ns;
+    *out = ns;
     return CS_OK;
 }
 
-cs_status ensure_rocsolver(NewtonState &ns, const cs_circuit *c, double *A_val, double *b, hipStream_t s) {
+cs_status ensure_rocsolver(NewtonState &ns, double *A_val, double *b, hipStream_t s) {
     if (ns.rf) return CS_OK;
     if (!ns.handle) NCHECK_RS(rocblas_create_handle(&ns.handle), "rocblas_create_handle");
     NCHECK_RS(rocblas_set_stream(ns.handle, s), "rocblas_set_stream");
     NCHECK_RS(rocsolver_create_rfinfo(&ns.rf, ns.handle), "rocsolver_create_rfinfo");
-    NCHECK_RS(rocsolver_dcsrrf_analysis(ns.handle, ns.n, 1, (rocblas_int)c->h.nnz, ns.ptrA.p, ns.indA.p, A_val,
+    NCHECK_RS(rocsolver_dcsrrf_analysis(ns.handle, ns.n, 1, (rocblas_int)ns.nnzA, ns.ptrA.p, ns.indA.p, A_val,
                                         (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p, ns.valT.p, ns.P.p, ns.Q.p, b,
                                         ns.n, ns.rf),
               "rocsolver_dcsrrf_analysis");
     return CS_OK;
 }
 
-}  // namespace
-
-cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x, double ag0, const double *hist,
-                    int32_t max_iter, double vstep, double tol, double *A_val, double *b, int32_t *n_iter,
-                    int32_t *converged, double *last_step, double *times_ms, void *stream) {
-    if (!c) return nfail(CS_EINVAL, "NULL circuit");
-    if (!c->h.mapped) return nfail(CS_ESTATE, "cs_build_stamp_map must come first");
-    if (!x || !A_val || !b) return nfail(CS_EINVAL, "NULL x, A or b");
-    if (max_iter < 1 || !(vstep > 0.0) || !(tol >= 0.0)) return nfail(CS_EINVAL, "max_iter >= 1, vstep > 0, tol >= 0");
-    if (solver != CS_SOLVE_LEVELS && solver != CS_SOLVE_ROCSOLVER) return nfail(CS_EINVAL, "unknown solver");
-    hipStream_t s = (hipStream_t)stream;
-    if (n_iter) *n_iter = 0;
-    if (converged) *converged = 0;
-    if (times_ms) std::memset(times_ms, 0, 5 * sizeof(double));
-    const int32_t n = c->h.n_rows;
-    if (n == 0) {
-        if (converged) *converged = 1;
-        if (last_step) *last_step = 0.0;
-        return CS_OK;
-    }
-    if (c->newton && c->newton->device != c->device) {   // the circuit moved to another GPU
-        destroy_newton(c->newton);
-        c->newton = nullptr;
-    }
-    if (!c->newton) {
-        cs_status st = cs_eval_stamp(c, variant, x, ag0, hist, A_val, b, stream);
-        if (st != CS_OK) return st;
-        st = build_state(c, A_val, b, s);
-        if (st != CS_OK) return st;
-    }
-    NewtonState &ns = *c->newton;
+// The Newton iterations on a built state: stamp() stamps A and b at x.
+template <class Stamp>
+cs_status newton_loop(NewtonState &ns, Stamp stamp, int32_t solver, double *x, int32_t n_clamp, int32_t max_iter,
+                      double vstep, double tol, double *A_val, double *b, int32_t *n_iter, int32_t *converged,
+                      double *last_step, double *times_ms, hipStream_t s) {
+    const int32_t n = ns.n;
     if (times_ms) times_ms[4] = ns.host_lu_ms;
     const bool lib = solver == CS_SOLVE_ROCSOLVER;
     if (lib) {
-        cs_status st = ensure_rocsolver(ns, c, A_val, b, s);
+        cs_status st = ensure_rocsolver(ns, A_val, b, s);
         if (st != CS_OK) return st;
         NCHECK_RS(rocblas_set_stream(ns.handle, s), "rocblas_set_stream");
     }
@@ -233,15 +213,14 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
         for (auto &v : ev.e) NCHECK_HIP(hipEventCreate(&v), "event");
         ev.on = true;
     }
-    const int32_t n_clamp = c->h.n_nodes - 1;
     double step = 0.0;
     for (int32_t it = 1; it <= max_iter; ++it) {
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[0], s), "event");
-        cs_status st = cs_eval_stamp(c, variant, x, ag0, hist, A_val, b, stream);
+        cs_status st = stamp();
         if (st != CS_OK) return st;
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[1], s), "event");
         if (lib) {
-            NCHECK_RS(rocsolver_dcsrrf_refactlu(ns.handle, n, (rocblas_int)c->h.nnz, ns.ptrA.p, ns.indA.p, A_val,
+            NCHECK_RS(rocsolver_dcsrrf_refactlu(ns.handle, n, (rocblas_int)ns.nnzA, ns.ptrA.p, ns.indA.p, A_val,
                                                 (rocblas_int)ns.nnzT, ns.ptrT.p, ns.indT.p, ns.valT.p, ns.P.p,
                                                 ns.Q.p, ns.rf),
                       "rocsolver_dcsrrf_refactlu");
@@ -269,7 +248,7 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
         }
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[3], s), "event");
         NCHECK_HIP(hipMemsetAsync(ns.step.p, 0, sizeof(unsigned long long), s), "clear step word");
-        NCHECK_HIP(launch_newton_update(n, n_clamp, b, x, vstep, ns.step.p, s), "update launch");
+        NCHECK_HIP(launch_newton_update(n, n_clamp, ns.clamp.p, b, x, vstep, ns.step.p, s), "update launch");
         unsigned long long bits = 0;
         NCHECK_HIP(hipMemcpyAsync(&bits, ns.step.p, sizeof(bits), hipMemcpyDeviceToHost, s), "read step");
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[4], s), "event");
@@ -292,6 +271,103 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
     return CS_OK;
 }
 
+cs_status check_args(double *x, double *A_val, double *b, int32_t solver, int32_t max_iter, double vstep,
+                     double tol) {
+    if (!x || !A_val || !b) return nfail(CS_EINVAL, "NULL x, A or b");
+    if (max_iter < 1 || !(vstep > 0.0) || !(tol >= 0.0)) return nfail(CS_EINVAL, "max_iter >= 1, vstep > 0, tol >= 0");
+    if (solver != CS_SOLVE_LEVELS && solver != CS_SOLVE_ROCSOLVER) return nfail(CS_EINVAL, "unknown solver");
+    return CS_OK;
+}
+
+}  // namespace
+
+cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x, double ag0, const double *hist,
+                    int32_t max_iter, double vstep, double tol, double *A_val, double *b, int32_t *n_iter,
+                    int32_t *converged, double *last_step, double *times_ms, void *stream) {
+    if (!c) return nfail(CS_EINVAL, "NULL circuit");
+    if (!c->h.mapped) return nfail(CS_ESTATE, "cs_build_stamp_map must come first");
+    cs_status st = check_args(x, A_val, b, solver, max_iter, vstep, tol);
+    if (st != CS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_iter) *n_iter = 0;
+    if (converged) *converged = 0;
+    if (times_ms) std::memset(times_ms, 0, 5 * sizeof(double));
+    if (c->h.n_rows == 0) {
+        if (converged) *converged = 1;
+        if (last_step) *last_step = 0.0;
+        return CS_OK;
+    }
+    if (c->newton && c->newton->device != c->device) {   // the circuit moved to another GPU
+        destroy_newton(c->newton);
+        c->newton = nullptr;
+    }
+    auto stamp = [&]() { return cs_eval_stamp(c, variant, x, ag0, hist, A_val, b, stream); };
+    if (!c->newton) {
+        st = stamp();
+        if (st != CS_OK) return st;
+        st = build_state(circuit_view(c->h), c->device, A_val, nullptr, s, &c->newton);
+        if (st != CS_OK) return st;
+    }
+    return newton_loop(*c->newton, stamp, solver, x, c->h.n_nodes - 1, max_iter, vstep, tol, A_val, b, n_iter,
+                       converged, last_step, times_ms, s);
+}
+
+cs_status cs_batch_newton(cs_batch *B, int32_t solver, double *x, double ag0, const double *hist, int32_t max_iter,
+                          double vstep, double tol, double *A_val, double *b, int32_t *n_iter, int32_t *converged,
+                          double *last_step, double *times_ms, void *stream) {
+    if (!B) return nfail(CS_EINVAL, "NULL batch");
+    cs_status st = check_args(x, A_val, b, solver, max_iter, vstep, tol);
+    if (st != CS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_iter) *n_iter = 0;
+    if (converged) *converged = 0;
+    if (times_ms) std::memset(times_ms, 0, 5 * sizeof(double));
+    const size_t nc = B->circ.size();
+    const int64_t n_rows = B->row_off[nc];
+    if (n_rows == 0) {
+        if (converged) *converged = 1;
+        if (last_step) *last_step = 0.0;
+        return CS_OK;
+    }
+    if (n_rows >= INDEX_LIMIT || B->nnz_off[nc] >= INDEX_LIMIT) return nfail(CS_ENOTSUP, "batch too large for the solve");
+    auto stamp = [&]() { return cs_batch_eval_stamp(B, x, ag0, hist, A_val, b, stream); };
+    if (B->newton && B->newton->device != B->device) {
+        destroy_newton(B->newton);
+        B->newton = nullptr;
+    }
+    if (!B->newton) {
+        st = stamp();   // uploads and plans the batch, then the first values of A
+        if (st != CS_OK) return st;
+        // the block-diagonal pattern of the batch, its source pairs and clamp flags
+        MnaView m;
+        std::vector<uint8_t> clamp((size_t)n_rows, 0);
+        try {
+            B->nt_row_ptr.assign(1, 0);
+            B->nt_col_idx.clear();
+            for (size_t i = 0; i < nc; ++i) {
+                const HostCircuit &h = B->circ[i]->h;
+                const int32_t ro = (int32_t)B->row_off[i], zo = (int32_t)B->nnz_off[i];
+                for (int32_t r = 0; r < h.n_rows; ++r) B->nt_row_ptr.push_back(zo + h.row_ptr[(size_t)r + 1]);
+                for (int32_t cix : h.col_idx) B->nt_col_idx.push_back(ro + cix);
+                for (int32_t r = 0; r < h.n_nodes - 1; ++r) clamp[(size_t)ro + r] = 1;
+                for (int32_t j = 0; j < h.n_vsrc; ++j) {
+                    const int32_t a = h.vsrc[2 * (size_t)j], bb = h.vsrc[2 * (size_t)j + 1];
+                    m.src.push_back({a ? ro + a - 1 : -1, bb ? ro + bb - 1 : -1, ro + h.n_nodes - 1 + j});
+                }
+            }
+        } catch (const std::bad_alloc &) {
+            return nfail(CS_ENOMEM, "host allocation");
+        }
+        m.n = (int32_t)n_rows;
+        m.row_ptr = B->nt_row_ptr.data();
+        m.col_idx = B->nt_col_idx.data();
+        st = build_state(m, B->device, A_val, &clamp, s, &B->newton);
+        if (st != CS_OK) return st;
+    }
+    return newton_loop(*B->newton, stamp, solver, x, 0, max_iter, vstep, tol, A_val, b, n_iter, converged, last_step,
+                       times_ms, s);
+}
+
 cs_status cs_factor_host(const cs_circuit *c, const double *A_host, int64_t *nnzT, int32_t *P, int32_t *Q,
                          int32_t *ptrT, int32_t *indT, double *valT) {
     if (!c || !A_host || !nnzT) return nfail(CS_EINVAL, "NULL argument");
@@ -299,7 +375,7 @@ cs_status cs_factor_host(const cs_circuit *c, const double *A_host, int64_t *nnz
     const HostCircuit &h = c->h;
     HostLU F;
     try {
-        Err e = factor_mna(h, A_host, F, nullptr);
+        Err e = factor_mna(circuit_view(h), A_host, F, nullptr);
         if (e.st != CS_OK) return nfail(e.st, e.msg);
     } catch (const std::bad_alloc &) {
         return nfail(CS_ENOMEM, "host allocation");

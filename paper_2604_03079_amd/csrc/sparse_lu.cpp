@@ -165,26 +165,38 @@ static std::vector<int32_t> md_order(const Graph &g, const std::vector<uint8_t> 
     return out;
 }
 
-void mna_order(const HostCircuit &h, std::vector<int32_t> &Q, std::vector<int32_t> &pref, int method) {
-    const int32_t n = h.n_rows, n_node = h.n_nodes - 1;
-    const std::vector<int32_t> &row_ptr = h.row_ptr, &col_idx = h.col_idx;
+MnaView circuit_view(const HostCircuit &h) {
+    MnaView m;
+    m.n = h.n_rows;
+    m.row_ptr = h.row_ptr.data();
+    m.col_idx = h.col_idx.data();
+    for (int32_t j = 0; j < h.n_vsrc; ++j) {
+        const int32_t a = h.vsrc[2 * (size_t)j], b = h.vsrc[2 * (size_t)j + 1];
+        m.src.push_back({a - 1, b - 1, h.n_nodes - 1 + j});   // ground -> -1
+    }
+    return m;
+}
+
+void mna_order(const MnaView &m, std::vector<int32_t> &Q, std::vector<int32_t> &pref, int method) {
+    const int32_t n = m.n;
+    const int32_t *row_ptr = m.row_ptr, *col_idx = m.col_idx;
     Q.clear();
     pref.assign((size_t)n, -1);
     std::vector<uint8_t> taken((size_t)n, 0);
-    for (int32_t j = 0; j < h.n_vsrc; ++j) {
-        const int32_t br = n_node + j;
-        int32_t nd = h.vsrc[2 * (size_t)j];
-        if (nd == 0 || taken[(size_t)nd - 1]) nd = h.vsrc[2 * (size_t)j + 1];
-        if (nd == 0 || taken[(size_t)nd - 1]) continue;
-        taken[(size_t)nd - 1] = taken[(size_t)br] = 1;
-        Q.push_back(nd - 1);
+    for (const auto &sr : m.src) {
+        const int32_t br = sr[2];
+        int32_t nd = sr[0];
+        if (nd < 0 || taken[(size_t)nd]) nd = sr[1];
+        if (nd < 0 || taken[(size_t)nd]) continue;
+        taken[(size_t)nd] = taken[(size_t)br] = 1;
+        Q.push_back(nd);
         Q.push_back(br);
-        pref[(size_t)nd - 1] = br;
-        pref[(size_t)br] = nd - 1;
+        pref[(size_t)nd] = br;
+        pref[(size_t)br] = nd;
     }
     // high degree: more than 32 neighbours and more than 8 times the mean
     int64_t total = 0;
-    for (int32_t i = 0; i < n; ++i) total += row_ptr[(size_t)i + 1] - row_ptr[(size_t)i];
+    for (int32_t i = 0; i < n; ++i) total += row_ptr[i + 1] - row_ptr[i];
     const double mean = n ? (double)total / n : 0.0;
     std::vector<uint8_t> heavy((size_t)n, 0);
     for (int32_t i = 0; i < n; ++i) {
@@ -263,7 +275,7 @@ double lu_cost_estimate(const HostLU &F, int32_t *n_lower, int32_t *n_upper) {
     return 4.7 * nl + 6.8 * nu + 0.94 * sum;
 }
 
-Err factor_mna(const HostCircuit &h, const double *A, HostLU &F, int *method) {
+Err factor_mna(const MnaView &h, const double *A, HostLU &F, int *method) {
     HostLU best;
     double best_cost = 0.0;
     int best_m = -1;
@@ -272,7 +284,7 @@ Err factor_mna(const HostCircuit &h, const double *A, HostLU &F, int *method) {
         std::vector<int32_t> Q, pref;
         mna_order(h, Q, pref, m);
         HostLU f;
-        last = host_lu(h.n_rows, h.row_ptr, h.col_idx, A, Q, pref, f);
+        last = host_lu(h.n, h.row_ptr, h.col_idx, A, Q, pref, f);
         if (last.st != CS_OK) continue;
         const double cost = lu_cost_estimate(f, nullptr, nullptr);
         if (best_m < 0 || cost < best_cost) {
@@ -287,8 +299,8 @@ Err factor_mna(const HostCircuit &h, const double *A, HostLU &F, int *method) {
     return {CS_OK, ""};
 }
 
-Err host_lu(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx,
-            const double *val, const std::vector<int32_t> &Q, const std::vector<int32_t> &pref, HostLU &F) {
+Err host_lu(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+            const std::vector<int32_t> &Q, const std::vector<int32_t> &pref, HostLU &F) {
     // columns of A (CSC) from its rows
     const int64_t nnz = row_ptr[(size_t)n];
     std::vector<int32_t> cp((size_t)n + 1, 0), ri((size_t)nnz);
