@@ -34,6 +34,11 @@ hipError_t launch_lu_lower_wave(int32_t count, const int32_t *rows, const int32_
                                 const int32_t *diag, double *T, const int32_t *P, const double *b, double *y,
                                 hipStream_t s);
 int32_t lu_stage_entries();
+// Caps of k_lu_lower_seq per row: entries, entries left of the diagonal, staged U
+// entries (those whose column is in the row).
+void lu_seq_caps(int32_t *row, int32_t *l, int32_t *u);
+hipError_t launch_lu_lower_seq(int32_t count, const int32_t *prow, const int32_t *plo, const int32_t *pst,
+                               double *T, const double *b, double *y, hipStream_t s);
 hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
                            const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
                            hipStream_t s);

@@ -40,6 +40,15 @@ struct NewtonState {
     DevBuf<int32_t> src, diag, lrows, urows;
     DevBuf<double> y;
     std::vector<int32_t> lptr, uptr, lshort;   // lshort[l]: staged rows, listed first in level l
+    // lower levels in launch order: [l0, l1) one level (l1 = l0 + 1) by the per-level
+    // kernels, or a run of narrow levels taken row after row by k_lu_lower_seq
+    struct LStep {
+        int32_t l0, l1;
+        bool seq;
+        int32_t r0;   // first row of the run in the sequential program
+    };
+    std::vector<LStep> lsteps;
+    DevBuf<int32_t> sq_row, sq_lo, sq_st;   // the sequential program (k_lu_lower_seq)
     rocblas_handle handle = nullptr;   // rocSOLVER path, set up on its first use
     rocsolver_rfinfo rf = nullptr;
     double host_lu_ms = 0.0;
@@ -173,6 +182,69 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
         auto mid = std::stable_partition(b0, b1, [&](int32_t i) { return F.Tp[(size_t)i + 1] - F.Tp[(size_t)i] <= cap; });
         ns->lshort[(size_t)l] = (int32_t)(mid - b0);
     }
+    // runs of narrow levels (at most SEQ_LEVEL_ROWS rows, every row within the caps of
+    // the sequential kernel) go to one launch each, with their static program: per row
+    // its header, per L entry (column j) the diagonal position of row j, j and the end
+    // of its records, per U(j, k) with k in the row the T position and the row position
+    {
+        constexpr int32_t SEQ_LEVEL_ROWS = 2;
+        int32_t crow, cl, cu;
+        lu_seq_caps(&crow, &cl, &cu);
+        std::vector<int32_t> prow, plo, pst;
+        auto program = [&](int32_t i, bool emit) {
+            const int32_t t0 = F.Tp[(size_t)i], len = F.Tp[(size_t)i + 1] - t0, nlow = diag[(size_t)i] - t0;
+            if (len > crow || nlow > cl) return false;
+            auto rb = F.Ti.begin() + t0, re = F.Ti.begin() + t0 + len;
+            int32_t ne = 0;
+            const size_t lb = plo.size() / 3, eb = pst.size() / 2;
+            for (int32_t p = t0; p < diag[(size_t)i]; ++p) {
+                const int32_t j = F.Ti[(size_t)p];
+                for (int32_t q = diag[(size_t)j] + 1; q < F.Tp[(size_t)j + 1]; ++q) {
+                    auto it = std::lower_bound(rb + (p - t0) + 1, re, F.Ti[(size_t)q]);
+                    if (it == re || *it != F.Ti[(size_t)q]) continue;
+                    if (++ne > cu) return false;
+                    if (emit) {
+                        pst.push_back(q);
+                        pst.push_back((int32_t)(it - rb));
+                    }
+                }
+                if (emit) {
+                    plo.push_back(diag[(size_t)j]);
+                    plo.push_back(j);
+                    plo.push_back(ne);
+                }
+            }
+            if (emit) {
+                const int32_t h[8] = {i, t0, len, nlow, (int32_t)lb, (int32_t)eb, ne, F.P[(size_t)i]};
+                prow.insert(prow.end(), h, h + 8);
+            }
+            return true;
+        };
+        auto narrow = [&](int32_t lv) {
+            const int32_t b0 = ns->lptr[(size_t)lv], b1 = ns->lptr[(size_t)lv + 1];
+            if (b1 - b0 > SEQ_LEVEL_ROWS) return false;
+            for (int32_t k = b0; k < b1; ++k)
+                if (!program(lrows[(size_t)k], false)) return false;
+            return true;
+        };
+        for (int32_t l = 0; l < nl;) {
+            int32_t e = l;
+            while (e < nl && narrow(e)) ++e;
+            if (e > l) {
+                ns->lsteps.push_back({l, e, true, (int32_t)(prow.size() / 8)});
+                for (int32_t k = ns->lptr[(size_t)l]; k < ns->lptr[(size_t)e]; ++k) program(lrows[(size_t)k], true);
+                l = e;
+            } else {
+                ns->lsteps.push_back({l, l + 1, false, 0});
+                ++l;
+            }
+        }
+        if (!prow.empty()) {
+            NCHECK_HIP(ns->sq_row.upload(prow), "upload sequential program");
+            if (!plo.empty()) NCHECK_HIP(ns->sq_lo.upload(plo), "upload sequential program");
+            if (!pst.empty()) NCHECK_HIP(ns->sq_st.upload(pst), "upload sequential program");
+        }
+    }
     NCHECK_HIP(ns->lrows.upload(lrows), "upload levels");
     NCHECK_HIP(ns->urows.upload(group(ulev, nu, ns->uptr)), "upload levels");
     NCHECK_HIP(ns->src.upload(src), "upload load map");
@@ -231,7 +303,15 @@ cs_status newton_loop(NewtonState &ns, Stamp stamp, int32_t solver, double *x, i
         } else {
             // refactorisation fused with the forward substitution, level by level
             NCHECK_HIP(launch_lu_load((int32_t)ns.nnzT, ns.src.p, A_val, ns.valT.p, s), "LU load launch");
-            for (size_t l = 0; l + 1 < ns.lptr.size(); ++l) {
+            for (const auto &step : ns.lsteps) {
+                if (step.seq) {
+                    NCHECK_HIP(launch_lu_lower_seq(ns.lptr[(size_t)step.l1] - ns.lptr[(size_t)step.l0],
+                                                   ns.sq_row.p + 8 * (size_t)step.r0, ns.sq_lo.p, ns.sq_st.p,
+                                                   ns.valT.p, b, ns.y.p, s),
+                               "LU lower launch");
+                    continue;
+                }
+                const size_t l = (size_t)step.l0;
                 const int32_t beg = ns.lptr[l], nsh = ns.lshort[l], cnt = ns.lptr[l + 1] - beg;
                 NCHECK_HIP(launch_lu_lower_wave(nsh, ns.lrows.p + beg, ns.ptrT.p, ns.indT.p, ns.diag.p, ns.valT.p,
                                                 ns.P.p, b, ns.y.p, s),

@@ -11,7 +11,13 @@
 // LU_STAGE entries go to k_lu_lower_wave instead: one wave per row, the row staged
 // in LDS, the lanes splitting U(j, :) and finding their columns in the row by
 // binary search; every entry still receives its updates in ascending j, so both
-// kernels give the same bits.  The backward
+// kernels give the same bits.  A run of consecutive narrow levels (a dependency chain,
+// typical of the last rows of a minimum-degree order) goes to k_lu_lower_seq: one
+// wave takes the run's rows one after another inside one launch, and per row it
+// first stages everything the row's elimination reads (the pivots, y_j and the U
+// entries of its L rows that meet the row, their positions in the row found by the
+// host), so the sequential part runs from LDS; same operations in the same order.
+// The backward
 // substitution runs over upper levels, one workgroup per row (a rail's row of U can
 // span the whole matrix), z_i = (y_i - sum_k U(i, k) z_k) / U(i, i), written to the
 // solution at column Q(i).  Every sum has a fixed order for a fixed launch shape.
@@ -27,6 +33,7 @@ namespace {
 
 constexpr int UPPER_BLOCK = 256;
 constexpr int32_t LU_STAGE = 2048;   // row entries a wave stages in LDS (24 KiB)
+constexpr int32_t SEQ_ROW = 256, SEQ_L = 64, SEQ_U = 256;   // k_lu_lower_seq caps per row
 
 __global__ void __launch_bounds__(256) k_lu_load(int32_t nnzT, const int32_t *__restrict__ src,
                                                  const double *__restrict__ A, double *__restrict__ T) {
@@ -131,6 +138,114 @@ __global__ void __launch_bounds__(64) k_lu_lower_wave(const int32_t *__restrict_
     if (lane == 0) y[i] = yi;
 }
 
+// One wave takes rows r0.. of a run in order (each row's L columns are earlier rows
+// of the run or of earlier launches), from a static program made by the host:
+// prow (8 per row: row, T offset, entries, L entries, first L record, first staged
+// record, staged records, b row P(i)), plo (3 per L entry: diagonal position of U(j, :),
+// j, end of its staged records) and pst (2 per staged record: T position of U(j, k),
+// position of column k in the row; only the k present in the row).  The program of
+// the next row is loaded while the present one is eliminated; the values of a row
+// (its entries, pivots, y_j, staged U entries) are one round of independent loads.
+// Caps: SEQ_ROW entries, SEQ_L L entries, SEQ_U staged records per row.
+struct SeqRow {
+    int32_t i, t0, len, nl, lb, eb, ne, pi;
+    int32_t dj, j, eend;
+    int32_t q[SEQ_U / 64], pos[SEQ_U / 64];
+};
+
+__device__ inline SeqRow seq_fetch(const int32_t *__restrict__ prow, const int32_t *__restrict__ plo,
+                                   const int32_t *__restrict__ pst, int32_t r, int32_t lane) {
+    SeqRow f;
+    const int32_t *h = prow + 8 * (size_t)r;
+    f.i = h[0];
+    f.t0 = h[1];
+    f.len = h[2];
+    f.nl = h[3];
+    f.lb = h[4];
+    f.eb = h[5];
+    f.ne = h[6];
+    f.pi = h[7];
+    f.dj = f.j = f.eend = 0;
+    if (lane < f.nl) {
+        const int32_t *l = plo + 3 * (size_t)(f.lb + lane);
+        f.dj = l[0];
+        f.j = l[1];
+        f.eend = l[2];
+    }
+#pragma unroll
+    for (int u = 0; u < SEQ_U / 64; ++u) {
+        const int32_t e = u * 64 + lane;
+        f.q[u] = 0;
+        f.pos[u] = 0;
+        if (e < f.ne) {
+            f.q[u] = pst[2 * (size_t)(f.eb + e)];
+            f.pos[u] = pst[2 * (size_t)(f.eb + e) + 1];
+        }
+    }
+    return f;
+}
+
+__global__ void __launch_bounds__(64) k_lu_lower_seq(int32_t count, const int32_t *__restrict__ prow,
+                                                     const int32_t *__restrict__ plo,
+                                                     const int32_t *__restrict__ pst, double *T,
+                                                     const double *__restrict__ b, double *y) {
+    __shared__ double v[SEQ_ROW];
+    __shared__ double ut[SEQ_U];
+    __shared__ int32_t upos[SEQ_U];
+    __shared__ int32_t ubeg[SEQ_L + 1];
+    __shared__ double ujj[SEQ_L], uy[SEQ_L];
+    const int32_t lane = threadIdx.x;
+    SeqRow cur = seq_fetch(prow, plo, pst, 0, lane);
+    for (int32_t r = 0; r < count; ++r) {
+        // values of this row: final except its own entries, which only it changes
+        double vr[SEQ_ROW / 64], tq[SEQ_U / 64];
+#pragma unroll
+        for (int u = 0; u < SEQ_ROW / 64; ++u) {
+            const int32_t e = u * 64 + lane;
+            vr[u] = e < cur.len ? T[cur.t0 + e] : 0.0;
+        }
+        const double pj = lane < cur.nl ? T[cur.dj] : 1.0;
+        const double yj = lane < cur.nl ? y[cur.j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < SEQ_U / 64; ++u) tq[u] = u * 64 + lane < cur.ne ? T[cur.q[u]] : 0.0;
+        double yi = b[cur.pi];
+        const SeqRow nxt = r + 1 < count ? seq_fetch(prow, plo, pst, r + 1, lane) : cur;
+#pragma unroll
+        for (int u = 0; u < SEQ_ROW / 64; ++u)
+            if (u * 64 + lane < cur.len) v[u * 64 + lane] = vr[u];
+#pragma unroll
+        for (int u = 0; u < SEQ_U / 64; ++u)
+            if (u * 64 + lane < cur.ne) {
+                ut[u * 64 + lane] = tq[u];
+                upos[u * 64 + lane] = cur.pos[u];
+            }
+        if (lane < cur.nl) {
+            ujj[lane] = pj;
+            uy[lane] = yj;
+            ubeg[lane + 1] = cur.eend;
+        }
+        if (lane == 0) ubeg[0] = 0;
+        __syncthreads();
+        for (int32_t a = 0; a < cur.nl; ++a) {
+            const double l = v[a] / ujj[a];
+            yi = yi - l * uy[a];
+            __syncthreads();   // every lane has read v[a] before lane 0 replaces it
+            if (lane == 0) v[a] = l;
+            for (int32_t e = ubeg[a] + lane; e < ubeg[a + 1]; e += 64) {
+                const int32_t pz = upos[e];
+                v[pz] = v[pz] - l * ut[e];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < SEQ_ROW / 64; ++u)
+            if (u * 64 + lane < cur.len) T[cur.t0 + u * 64 + lane] = v[u * 64 + lane];
+        if (lane == 0) y[cur.i] = yi;
+        __syncthreads();   // this row's T and y are visible to the next rows of the run
+        cur = nxt;
+    }
+}
+
 __global__ void __launch_bounds__(UPPER_BLOCK) k_lu_upper(const int32_t *__restrict__ rows,
                                                           const int32_t *__restrict__ Tp,
                                                           const int32_t *__restrict__ Ti,
@@ -180,6 +295,19 @@ hipError_t launch_lu_lower_wave(int32_t count, const int32_t *rows, const int32_
 }
 
 int32_t lu_stage_entries() { return LU_STAGE; }
+
+void lu_seq_caps(int32_t *row, int32_t *l, int32_t *u) {
+    *row = SEQ_ROW;
+    *l = SEQ_L;
+    *u = SEQ_U;
+}
+
+hipError_t launch_lu_lower_seq(int32_t count, const int32_t *prow, const int32_t *plo, const int32_t *pst,
+                               double *T, const double *b, double *y, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_lower_seq, dim3(1), dim3(64), 0, s, count, prow, plo, pst, T, b, y);
+    return hipGetLastError();
+}
 
 hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
                            const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
