@@ -302,6 +302,7 @@ def bench_batch_newton(torch, CS, G, dev, n_var=32):
     variants = [G.adder_case(64, 100 + k, "all") for k in range(n_var)]
     cs = [CS.prepare(v, exclude=True) for v in variants]
     B = CS.Batch(cs)
+    B.set_launch(block=256, schedule="region")    # the batched stamp's tuned schedule
     cat = lambda a: torch.from_numpy(np.concatenate([getattr(v, a) for v in variants])).to(dev)
     W, L, V, x0 = cat("W"), cat("L"), cat("VTH0"), cat("x")
     B.set_params(W, L, V)

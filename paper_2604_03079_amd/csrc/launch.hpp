@@ -37,11 +37,17 @@ int32_t lu_stage_entries();
 // Caps of k_lu_lower_seq per row: entries, entries left of the diagonal, staged U
 // entries (those whose column is in the row).
 void lu_seq_caps(int32_t *row, int32_t *l, int32_t *u);
-hipError_t launch_lu_lower_seq(int32_t count, const int32_t *prow, const int32_t *plo, const int32_t *pst,
-                               double *T, const double *b, double *y, hipStream_t s);
+hipError_t launch_lu_lower_seq(int32_t grid, int32_t count, const int32_t *prow, const int32_t *plo,
+                               const int32_t *pst, double *T, const double *b, double *y, hipStream_t s);
 hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
                            const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
                            hipStream_t s);
+// A run of upper levels in one workgroup (lev: nlev + 1 offsets into rows); rows
+// with at most 256 entries right of the diagonal; same bits as launch_lu_upper.
+hipError_t launch_lu_upper_seq(int32_t nlev, const int32_t *lev, const int32_t *rows, const int32_t *Tp,
+                               const int32_t *Ti, const int32_t *diag, const double *T, double *y, const int32_t *Q,
+                               double *out, hipStream_t s);
+int32_t lu_upper_seq_rows();   // widest level a run takes
 hipError_t launch_newton_update(int32_t n, int32_t n_clamp, const uint8_t *clamp, const double *y, double *x,
                                 double vstep,
                                 unsigned long long *step_bits, hipStream_t s);

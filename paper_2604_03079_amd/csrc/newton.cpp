@@ -39,16 +39,19 @@ struct NewtonState {
     // positions, rows grouped by lower and by upper dependency level
     DevBuf<int32_t> src, diag, lrows, urows;
     DevBuf<double> y;
-    std::vector<int32_t> lptr, uptr, lshort;   // lshort[l]: staged rows, listed first in level l
+    // per lower level: programmed rows (listed first), then staged rows, then the rest
+    std::vector<int32_t> lptr, uptr, lfit, lshort;
     // lower levels in launch order: [l0, l1) one level (l1 = l0 + 1) by the per-level
-    // kernels, or a run of narrow levels taken row after row by k_lu_lower_seq
+    // launches, or a run of narrow levels taken row after row by one k_lu_lower_seq wave
     struct LStep {
         int32_t l0, l1;
         bool seq;
-        int32_t r0;   // first row of the run in the sequential program
+        int32_t r0;   // first row of the step in the program
     };
     std::vector<LStep> lsteps;
     DevBuf<int32_t> sq_row, sq_lo, sq_st;   // the sequential program (k_lu_lower_seq)
+    std::vector<LStep> usteps;   // upper levels: one launch per level, or a run in one workgroup
+    DevBuf<int32_t> uptr_d;      // uptr on the device (level offsets of the upper runs)
     rocblas_handle handle = nullptr;   // rocSOLVER path, set up on its first use
     rocsolver_rfinfo rf = nullptr;
     double host_lu_ms = 0.0;
@@ -174,18 +177,14 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
         return rows;
     };
     std::vector<int32_t> lrows = group(lev, nl, ns->lptr);
-    // inside each lower level, rows short enough for the staged kernel first
-    ns->lshort.assign((size_t)nl, 0);
-    const int32_t cap = lu_stage_entries();
-    for (int32_t l = 0; l < nl; ++l) {
-        auto b0 = lrows.begin() + ns->lptr[(size_t)l], b1 = lrows.begin() + ns->lptr[(size_t)l + 1];
-        auto mid = std::stable_partition(b0, b1, [&](int32_t i) { return F.Tp[(size_t)i + 1] - F.Tp[(size_t)i] <= cap; });
-        ns->lshort[(size_t)l] = (int32_t)(mid - b0);
-    }
-    // runs of narrow levels (at most SEQ_LEVEL_ROWS rows, every row within the caps of
-    // the sequential kernel) go to one launch each, with their static program: per row
-    // its header, per L entry (column j) the diagonal position of row j, j and the end
-    // of its records, per U(j, k) with k in the row the T position and the row position
+    // The programmed kernel (k_lu_lower_seq) takes every row within its caps, from a
+    // static program: per row its header, per L entry (column j) the diagonal position
+    // of row j, j and the end of its records, per U(j, k) with k in the row the T
+    // position and the row position.  Inside each lower level the programmed rows come
+    // first, then rows short enough for the staged kernel, then the rest.  A run of
+    // consecutive narrow levels (at most SEQ_LEVEL_ROWS rows, all programmed) is one
+    // launch of one wave taking its rows in order; other levels launch one wave per
+    // programmed row.
     {
         constexpr int32_t SEQ_LEVEL_ROWS = 2;
         int32_t crow, cl, cu;
@@ -220,22 +219,34 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
             }
             return true;
         };
+        std::vector<uint8_t> fit((size_t)n);
+        for (int32_t i = 0; i < n; ++i) fit[(size_t)i] = program(i, false) ? 1 : 0;
+        ns->lfit.assign((size_t)nl, 0);
+        ns->lshort.assign((size_t)nl, 0);
+        const int32_t cap = lu_stage_entries();
+        for (int32_t l = 0; l < nl; ++l) {
+            auto b0 = lrows.begin() + ns->lptr[(size_t)l], b1 = lrows.begin() + ns->lptr[(size_t)l + 1];
+            auto m1 = std::stable_partition(b0, b1, [&](int32_t i) { return fit[(size_t)i] != 0; });
+            auto m2 = std::stable_partition(m1, b1, [&](int32_t i) { return F.Tp[(size_t)i + 1] - F.Tp[(size_t)i] <= cap; });
+            ns->lfit[(size_t)l] = (int32_t)(m1 - b0);
+            ns->lshort[(size_t)l] = (int32_t)(m2 - m1);
+        }
         auto narrow = [&](int32_t lv) {
-            const int32_t b0 = ns->lptr[(size_t)lv], b1 = ns->lptr[(size_t)lv + 1];
-            if (b1 - b0 > SEQ_LEVEL_ROWS) return false;
-            for (int32_t k = b0; k < b1; ++k)
-                if (!program(lrows[(size_t)k], false)) return false;
-            return true;
+            const int32_t rows_in = ns->lptr[(size_t)lv + 1] - ns->lptr[(size_t)lv];
+            return rows_in <= SEQ_LEVEL_ROWS && ns->lfit[(size_t)lv] == rows_in;
         };
         for (int32_t l = 0; l < nl;) {
             int32_t e = l;
             while (e < nl && narrow(e)) ++e;
+            const int32_t r0 = (int32_t)(prow.size() / 8);
             if (e > l) {
-                ns->lsteps.push_back({l, e, true, (int32_t)(prow.size() / 8)});
+                ns->lsteps.push_back({l, e, true, r0});
                 for (int32_t k = ns->lptr[(size_t)l]; k < ns->lptr[(size_t)e]; ++k) program(lrows[(size_t)k], true);
                 l = e;
             } else {
-                ns->lsteps.push_back({l, l + 1, false, 0});
+                ns->lsteps.push_back({l, l + 1, false, r0});
+                const int32_t k0 = ns->lptr[(size_t)l];
+                for (int32_t k = k0; k < k0 + ns->lfit[(size_t)l]; ++k) program(lrows[(size_t)k], true);
                 ++l;
             }
         }
@@ -245,8 +256,35 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
             if (!pst.empty()) NCHECK_HIP(ns->sq_st.upload(pst), "upload sequential program");
         }
     }
+    // runs of consecutive narrow upper levels (at most lu_upper_seq_rows() rows, each
+    // with at most 256 entries right of the diagonal): one workgroup per run
+    {
+        const int32_t wmax = lu_upper_seq_rows();
+        std::vector<int32_t> urows_h = group(ulev, nu, ns->uptr);
+        auto narrow = [&](int32_t lv) {
+            const int32_t b0 = ns->uptr[(size_t)lv], b1 = ns->uptr[(size_t)lv + 1];
+            if (b1 - b0 > wmax) return false;
+            for (int32_t k = b0; k < b1; ++k) {
+                const int32_t i = urows_h[(size_t)k];
+                if (F.Tp[(size_t)i + 1] - diag[(size_t)i] - 1 > 256) return false;
+            }
+            return true;
+        };
+        for (int32_t l = 0; l < nu;) {
+            int32_t e = l;
+            while (e < nu && narrow(e)) ++e;
+            if (e - l >= 2) {
+                ns->usteps.push_back({l, e, true, 0});
+                l = e;
+            } else {
+                ns->usteps.push_back({l, l + 1, false, 0});
+                ++l;
+            }
+        }
+        NCHECK_HIP(ns->urows.upload(urows_h), "upload levels");
+        NCHECK_HIP(ns->uptr_d.upload(ns->uptr), "upload levels");
+    }
     NCHECK_HIP(ns->lrows.upload(lrows), "upload levels");
-    NCHECK_HIP(ns->urows.upload(group(ulev, nu, ns->uptr)), "upload levels");
     NCHECK_HIP(ns->src.upload(src), "upload load map");
     NCHECK_HIP(ns->diag.upload(diag), "upload diagonal positions");
     NCHECK_HIP(ns->y.alloc((size_t)n), "alloc solve vector");
@@ -304,15 +342,18 @@ cs_status newton_loop(NewtonState &ns, Stamp stamp, int32_t solver, double *x, i
             // refactorisation fused with the forward substitution, level by level
             NCHECK_HIP(launch_lu_load((int32_t)ns.nnzT, ns.src.p, A_val, ns.valT.p, s), "LU load launch");
             for (const auto &step : ns.lsteps) {
+                const int32_t *prog = ns.sq_row.p + 8 * (size_t)step.r0;
                 if (step.seq) {
-                    NCHECK_HIP(launch_lu_lower_seq(ns.lptr[(size_t)step.l1] - ns.lptr[(size_t)step.l0],
-                                                   ns.sq_row.p + 8 * (size_t)step.r0, ns.sq_lo.p, ns.sq_st.p,
-                                                   ns.valT.p, b, ns.y.p, s),
+                    NCHECK_HIP(launch_lu_lower_seq(1, ns.lptr[(size_t)step.l1] - ns.lptr[(size_t)step.l0], prog,
+                                                   ns.sq_lo.p, ns.sq_st.p, ns.valT.p, b, ns.y.p, s),
                                "LU lower launch");
                     continue;
                 }
                 const size_t l = (size_t)step.l0;
-                const int32_t beg = ns.lptr[l], nsh = ns.lshort[l], cnt = ns.lptr[l + 1] - beg;
+                const int32_t nf = ns.lfit[l], nsh = ns.lshort[l];
+                const int32_t beg = ns.lptr[l] + nf, cnt = ns.lptr[l + 1] - beg;
+                NCHECK_HIP(launch_lu_lower_seq(nf, 1, prog, ns.sq_lo.p, ns.sq_st.p, ns.valT.p, b, ns.y.p, s),
+                           "LU lower launch");
                 NCHECK_HIP(launch_lu_lower_wave(nsh, ns.lrows.p + beg, ns.ptrT.p, ns.indT.p, ns.diag.p, ns.valT.p,
                                                 ns.P.p, b, ns.y.p, s),
                            "LU lower launch");
@@ -321,10 +362,17 @@ cs_status newton_loop(NewtonState &ns, Stamp stamp, int32_t solver, double *x, i
                            "LU lower launch");
             }
             if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[2], s), "event");
-            for (size_t l = 0; l + 1 < ns.uptr.size(); ++l)
-                NCHECK_HIP(launch_lu_upper(ns.uptr[l + 1] - ns.uptr[l], ns.urows.p + ns.uptr[l], ns.ptrT.p,
-                                           ns.indT.p, ns.diag.p, ns.valT.p, ns.y.p, ns.Q.p, b, s),
-                           "LU upper launch");
+            for (const auto &step : ns.usteps) {
+                const size_t l = (size_t)step.l0;
+                if (step.seq)
+                    NCHECK_HIP(launch_lu_upper_seq(step.l1 - step.l0, ns.uptr_d.p + l, ns.urows.p, ns.ptrT.p,
+                                                   ns.indT.p, ns.diag.p, ns.valT.p, ns.y.p, ns.Q.p, b, s),
+                               "LU upper launch");
+                else
+                    NCHECK_HIP(launch_lu_upper(ns.uptr[l + 1] - ns.uptr[l], ns.urows.p + ns.uptr[l], ns.ptrT.p,
+                                               ns.indT.p, ns.diag.p, ns.valT.p, ns.y.p, ns.Q.p, b, s),
+                               "LU upper launch");
+            }
         }
         if (ev.on) NCHECK_HIP(hipEventRecord(ev.e[3], s), "event");
         NCHECK_HIP(hipMemsetAsync(ns.step.p, 0, sizeof(unsigned long long), s), "clear step word");

@@ -11,13 +11,14 @@
 // LU_STAGE entries go to k_lu_lower_wave instead: one wave per row, the row staged
 // in LDS, the lanes splitting U(j, :) and finding their columns in the row by
 // binary search; every entry still receives its updates in ascending j, so both
-// kernels give the same bits.  A run of consecutive narrow levels (a dependency chain,
-// typical of the last rows of a minimum-degree order) goes to k_lu_lower_seq: one
-// wave takes the run's rows one after another inside one launch, and per row it
-// first stages everything the row's elimination reads (the pivots, y_j and the U
-// entries of its L rows that meet the row, their positions in the row found by the
-// host), so the sequential part runs from LDS; same operations in the same order.
-// The backward
+// kernels give the same bits.  Rows within the caps of k_lu_lower_seq (most rows of
+// circuit matrices) go to it instead: per row a wave first stages everything the
+// row's elimination reads (the pivots, y_j and the U entries of its L rows that meet
+// the row, their positions in the row found by the host), in one round of
+// independent loads, so the sequential part runs from LDS; same operations in the
+// same order.  A level launches one such wave per row; a run of consecutive narrow
+// levels (a dependency chain, typical of the last rows of a minimum-degree order) is
+// one launch of one wave that takes the run's rows one after another.  The backward
 // substitution runs over upper levels, one workgroup per row (a rail's row of U can
 // span the whole matrix), z_i = (y_i - sum_k U(i, k) z_k) / U(i, i), written to the
 // solution at column Q(i).  Every sum has a fixed order for a fixed launch shape.
@@ -138,8 +139,10 @@ __global__ void __launch_bounds__(64) k_lu_lower_wave(const int32_t *__restrict_
     if (lane == 0) y[i] = yi;
 }
 
-// One wave takes rows r0.. of a run in order (each row's L columns are earlier rows
-// of the run or of earlier launches), from a static program made by the host:
+// Workgroup b (one wave) takes rows [b count, (b + 1) count) of the program in order
+// (each row's L columns are earlier rows of its own list or rows of earlier launches:
+// a run of narrow levels is one workgroup, a level one workgroup per row), from a
+// static program made by the host:
 // prow (8 per row: row, T offset, entries, L entries, first L record, first staged
 // record, staged records, b row P(i)), plo (3 per L entry: diagonal position of U(j, :),
 // j, end of its staged records) and pst (2 per staged record: T position of U(j, k),
@@ -195,6 +198,7 @@ __global__ void __launch_bounds__(64) k_lu_lower_seq(int32_t count, const int32_
     __shared__ int32_t ubeg[SEQ_L + 1];
     __shared__ double ujj[SEQ_L], uy[SEQ_L];
     const int32_t lane = threadIdx.x;
+    prow += 8 * (size_t)blockIdx.x * count;   // workgroup b: rows [b count, (b + 1) count)
     SeqRow cur = seq_fetch(prow, plo, pst, 0, lane);
     for (int32_t r = 0; r < count; ++r) {
         // values of this row: final except its own entries, which only it changes
@@ -269,7 +273,63 @@ __global__ void __launch_bounds__(UPPER_BLOCK) k_lu_upper(const int32_t *__restr
     }
 }
 
+// A run of consecutive upper levels in one workgroup of UPS_WAVES waves: per level,
+// wave w takes the level's rows w, w + UPS_WAVES, ..., then a workgroup barrier makes
+// the new z values visible to the next level.  Every row has at most UPPER_BLOCK
+// entries right of the diagonal, and a wave forms its sum exactly as k_lu_upper's
+// UPPER_BLOCK threads do (lane l holds the partial sums of threads l, l + 64, l + 128,
+// l + 192 and the tree adds the same pairs in the same order): same bits.
+constexpr int UPS_WAVES = 16;
+__global__ void __launch_bounds__(64 * UPS_WAVES) k_lu_upper_seq(int32_t nlev, const int32_t *__restrict__ lev,
+                                                                 const int32_t *__restrict__ rows,
+                                                                 const int32_t *__restrict__ Tp,
+                                                                 const int32_t *__restrict__ Ti,
+                                                                 const int32_t *__restrict__ diag,
+                                                                 const double *__restrict__ T, double *y,
+                                                                 const int32_t *__restrict__ Q, double *out) {
+    static_assert(UPPER_BLOCK == 256, "the tree below mirrors a 256-thread k_lu_upper");
+    const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int32_t lv = 0; lv < nlev; ++lv) {
+        const int32_t r1 = lev[lv + 1];
+        for (int32_t k = lev[lv] + wave; k < r1; k += UPS_WAVES) {
+            const int32_t i = rows[k];
+            const int32_t d = diag[i], pe = Tp[i + 1];
+            double s[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int32_t p = d + 1 + lane + 64 * m;   // thread lane + 64 m of k_lu_upper
+                s[m] = 0.0;
+                if (p < pe) s[m] = s[m] + T[p] * y[Ti[p]];
+            }
+            s[0] = s[0] + s[2];   // width 128
+            s[1] = s[1] + s[3];
+            double t = s[0] + s[1];   // width 64
+            for (int w = 32; w > 0; w >>= 1) {
+                const double o = __shfl_down(t, w, 64);
+                if (lane < w) t = t + o;
+            }
+            if (lane == 0) {
+                const double z = (y[i] - t) / T[d];
+                y[i] = z;
+                out[Q[i]] = z;
+            }
+        }
+        __syncthreads();   // this level's z values are visible to the next level
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lu_upper_seq(int32_t nlev, const int32_t *lev, const int32_t *rows, const int32_t *Tp,
+                               const int32_t *Ti, const int32_t *diag, const double *T, double *y, const int32_t *Q,
+                               double *out, hipStream_t s) {
+    if (nlev <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_upper_seq, dim3(1), dim3(64 * UPS_WAVES), 0, s, nlev, lev, rows, Tp, Ti, diag, T, y, Q,
+                       out);
+    return hipGetLastError();
+}
+
+int32_t lu_upper_seq_rows() { return 4 * UPS_WAVES; }
 
 hipError_t launch_lu_load(int32_t nnzT, const int32_t *src, const double *A, double *T, hipStream_t s) {
     if (nnzT <= 0) return hipSuccess;
@@ -302,10 +362,10 @@ void lu_seq_caps(int32_t *row, int32_t *l, int32_t *u) {
     *u = SEQ_U;
 }
 
-hipError_t launch_lu_lower_seq(int32_t count, const int32_t *prow, const int32_t *plo, const int32_t *pst,
-                               double *T, const double *b, double *y, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lu_lower_seq, dim3(1), dim3(64), 0, s, count, prow, plo, pst, T, b, y);
+hipError_t launch_lu_lower_seq(int32_t grid, int32_t count, const int32_t *prow, const int32_t *plo,
+                               const int32_t *pst, double *T, const double *b, double *y, hipStream_t s) {
+    if (grid <= 0 || count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_lower_seq, dim3(grid), dim3(64), 0, s, count, prow, plo, pst, T, b, y);
     return hipGetLastError();
 }
 
