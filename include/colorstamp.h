@@ -202,6 +202,18 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
                     double *b, int32_t *n_iter, int32_t *converged, double *last_step,
                     double *times_ms, void *stream);
 
+/* Schedule options of cs_newton's level-scheduled solver (bits; 0 = default, all
+ * on).  CS_NEWTON_NO_PROGRAMMED_ROWS: every lower row by the per-level staged or
+ * per-lane kernels (no host program, no runs of narrow levels).
+ * CS_NEWTON_NO_UPPER_RUNS: every upper level in its own launch.  The options change
+ * launches only: the iterates are the same bits.  The next cs_newton plans again
+ * (its host factorisation included).  CS_EINVAL for an unknown bit. */
+enum {
+    CS_NEWTON_NO_PROGRAMMED_ROWS = 1,
+    CS_NEWTON_NO_UPPER_RUNS = 2
+};
+cs_status cs_set_newton_options(cs_circuit *c, int32_t flags);
+
 /* History terms of the next backward-Euler step (the integration the hist argument
  * of cs_eval_stamp and cs_newton serves: the charge current is ag0 (Q(x) - Q(x_prev))
  * with ag0 = 1/h).  hist_out (device, n_dev*4, original device order, terminals d, g,

@@ -28,7 +28,7 @@ EXPORTS = (
     "cs_build_coloring_order",
     "cs_build_stamp_map",
     "cs_get_pattern", "cs_get_stamp_map", "cs_set_models", "cs_set_params", "cs_eval_stamp",
-    "cs_vjp", "cs_newton", "cs_history", "cs_factor_host", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
+    "cs_vjp", "cs_newton", "cs_set_newton_options", "cs_history", "cs_factor_host", "cs_set_launch", "cs_get_info", "cs_plan_regions", "cs_get_region_info",
     "cs_get_region_plan", "cs_check", "cs_set_spin_limit", "cs_set_plan_units", "cs_batch_create", "cs_batch_destroy",
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
@@ -77,6 +77,7 @@ def lib():
             "cs_eval_stamp": [p, C.c_int, p, d, p, p, p, p],
             "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_newton": [p, C.c_int, i32, p, d, p, i32, d, d, p, p, p, p, p, p, p],
+            "cs_set_newton_options": [p, i32],
             "cs_factor_host": [p, p, p, p, p, p, p, p],
             "cs_history": [p, p, d, p, p],
             "cs_set_launch": [p, i32, i32, i32],
@@ -325,6 +326,11 @@ class Circuit:
                                C.byref(step), t, _stream(stream)), "cs_newton")
         return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,
                     ms=dict(stamp=t[0], refactor=t[1], solve=t[2], update=t[3], host_factor=t[4]))
+
+    def set_newton_options(self, programmed_rows: bool = True, upper_runs: bool = True):
+        """Launch schedule of the level-scheduled solver (same bits either way)."""
+        flags = (0 if programmed_rows else 1) | (0 if upper_runs else 2)
+        _check(lib().cs_set_newton_options(self._h, flags), "cs_set_newton_options")
 
     def history(self, x, ag0: float, out=None, stream=None):
         """ag0 * terminal charges of every device at x: the history terms (n_dev, 4)

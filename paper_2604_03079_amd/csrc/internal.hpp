@@ -204,6 +204,7 @@ struct cs_circuit {
     int32_t plan_cus = -1;   // compute units the region planner targets (-1: the current GPU's)
     int64_t rg_cap = 0;
     cs::NewtonState *newton = nullptr;   // built by the first cs_newton on this stamp map
+    int32_t newton_flags = 0;             // CS_NEWTON_NO_* bits of cs_set_newton_options
     cs_circuit() = default;
     cs_circuit(const cs_circuit &) = delete;
     cs_circuit &operator=(const cs_circuit &) = delete;

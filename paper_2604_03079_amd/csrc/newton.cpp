@@ -100,7 +100,7 @@ struct Events {
 // factor pattern and the level analysis.  clamp (optional, host, m.n flags): rows
 // whose Newton step is clamped.
 cs_status build_state(const MnaView &m, int device, double *A_val, const std::vector<uint8_t> *clamp,
-                      hipStream_t s, NewtonState **out) {
+                      int32_t flags, hipStream_t s, NewtonState **out) {
     const int32_t n = m.n;
     const int64_t nnz = m.row_ptr[n];
     std::vector<double> Ah((size_t)nnz);
@@ -220,7 +220,8 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
             return true;
         };
         std::vector<uint8_t> fit((size_t)n);
-        for (int32_t i = 0; i < n; ++i) fit[(size_t)i] = program(i, false) ? 1 : 0;
+        if (!(flags & CS_NEWTON_NO_PROGRAMMED_ROWS))
+            for (int32_t i = 0; i < n; ++i) fit[(size_t)i] = program(i, false) ? 1 : 0;
         ns->lfit.assign((size_t)nl, 0);
         ns->lshort.assign((size_t)nl, 0);
         const int32_t cap = lu_stage_entries();
@@ -273,7 +274,7 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
         for (int32_t l = 0; l < nu;) {
             int32_t e = l;
             while (e < nu && narrow(e)) ++e;
-            if (e - l >= 2) {
+            if (e - l >= 2 && !(flags & CS_NEWTON_NO_UPPER_RUNS)) {
                 ns->usteps.push_back({l, e, true, 0});
                 l = e;
             } else {
@@ -433,7 +434,7 @@ cs_status cs_newton(cs_circuit *c, cs_variant variant, int32_t solver, double *x
     if (!c->newton) {
         st = stamp();
         if (st != CS_OK) return st;
-        st = build_state(circuit_view(c->h), c->device, A_val, nullptr, s, &c->newton);
+        st = build_state(circuit_view(c->h), c->device, A_val, nullptr, c->newton_flags, s, &c->newton);
         if (st != CS_OK) return st;
     }
     return newton_loop(*c->newton, stamp, solver, x, c->h.n_nodes - 1, max_iter, vstep, tol, A_val, b, n_iter,
@@ -489,11 +490,20 @@ cs_status cs_batch_newton(cs_batch *B, int32_t solver, double *x, double ag0, co
         m.n = (int32_t)n_rows;
         m.row_ptr = B->nt_row_ptr.data();
         m.col_idx = B->nt_col_idx.data();
-        st = build_state(m, B->device, A_val, &clamp, s, &B->newton);
+        st = build_state(m, B->device, A_val, &clamp, 0, s, &B->newton);
         if (st != CS_OK) return st;
     }
     return newton_loop(*B->newton, stamp, solver, x, 0, max_iter, vstep, tol, A_val, b, n_iter, converged, last_step,
                        times_ms, s);
+}
+
+cs_status cs_set_newton_options(cs_circuit *c, int32_t flags) {
+    if (!c) return nfail(CS_EINVAL, "NULL circuit");
+    if (flags & ~(CS_NEWTON_NO_PROGRAMMED_ROWS | CS_NEWTON_NO_UPPER_RUNS)) return nfail(CS_EINVAL, "unknown flag");
+    c->newton_flags = flags;
+    destroy_newton(c->newton);   // the next cs_newton plans again
+    c->newton = nullptr;
+    return CS_OK;
 }
 
 cs_status cs_factor_host(const cs_circuit *c, const double *A_host, int64_t *nnzT, int32_t *P, int32_t *Q,

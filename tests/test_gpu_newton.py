@@ -167,3 +167,27 @@ def test_transient_matches_oracle(torch_dev, solver):
     assert wave.shape == ref.shape
     assert np.abs(wave - ref).max() <= 1e-7
     assert all(abs(a - b) <= 1 for a, b in zip(iters, iters_o))
+
+
+@pytest.mark.parametrize("name,make", [("adder8r89be", lambda: G.adder_case(8, 9, "all")),
+                                       ("chain2000be", lambda: G.chain_dc_case(2000, 7, 0.3))],
+                         ids=["adder8r89be", "chain2000be"])
+def test_solver_schedules_give_the_same_bits(torch_dev, name, make):
+    # programmed rows, runs of narrow lower levels and upper-level runs change the
+    # launches, not the arithmetic: each option set gives the same iterates bit for bit
+    circ = make()
+    hist = np.random.default_rng(16).normal(0, 1e-5, (circ.n_dev, 4))
+    t = lambda a: torch_dev.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    c = CS.prepare(circ, True, NC, PC)
+    c.set_params(t(circ.W), t(circ.L), t(circ.VTH0))
+    out = []
+    for prog, runs in ((True, True), (False, True), (True, False), (False, False)):
+        c.set_newton_options(programmed_rows=prog, upper_runs=runs)
+        x = t(circ.x).clone()
+        say(f"case newton schedule {name} programmed={prog} upper_runs={runs}")
+        r = c.newton(x, 1e12, t(hist))
+        torch_dev.cuda.synchronize()
+        assert r["converged"]
+        out.append((x.cpu().numpy(), r["iterations"]))
+    for x, it in out[1:]:
+        assert it == out[0][1] and np.array_equal(x.view(np.int64), out[0][0].view(np.int64))

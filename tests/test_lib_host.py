@@ -79,6 +79,14 @@ def test_unknown_colouring_order_is_refused():
     assert CS.lib().cs_build_coloring_order(c.handle, None, 7, None, None, None) == -1   # CS_EINVAL
 
 
+def test_newton_options_are_checked():
+    c = CS.Circuit.from_netlist(G.workload(0))
+    assert CS.lib().cs_set_newton_options(c.handle, 4) == -1   # CS_EINVAL: unknown bit
+    assert CS.lib().cs_set_newton_options(None, 0) == -1
+    c.set_newton_options(programmed_rows=False, upper_runs=False)
+    c.set_newton_options()
+
+
 @pytest.mark.parametrize("idx", [1, 2])
 def test_setup_equals_oracle_full_size(orc, idx):
     circ = G.workload(idx)
