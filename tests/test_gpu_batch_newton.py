@@ -48,15 +48,17 @@ def batch_of(torch, circs):
     return B, t
 
 
-@pytest.mark.parametrize("solver", ["levels", "rocsolver"])
-def test_batch_newton_matches_oracle_per_circuit(torch_dev, solver):
+@pytest.mark.parametrize("solver,schedule", [("levels", "persistent"), ("rocsolver", "persistent"),
+                                             ("levels", "region")])
+def test_batch_newton_matches_oracle_per_circuit(torch_dev, solver, schedule):
     circs = members()
     hists = [np.random.default_rng(40 + i).normal(0, 1e-5, (c.n_dev, 4)) for i, c in enumerate(circs)]
     ref = [ON.newton(c, NC, PC, ag0=1e12, hist=h) for c, h in zip(circs, hists)]
     assert all(r[2][-1] <= 1e-9 for r in ref), "oracle did not converge"
     B, t = batch_of(torch_dev, circs)
+    B.set_launch(block=256, schedule=schedule)
     x = t(np.concatenate([c.x for c in circs])).clone()
-    say(f"case batch newton {len(circs)} circuits, {B.n_rows} rows, solver={solver}")
+    say(f"case batch newton {len(circs)} circuits, {B.n_rows} rows, solver={solver}, stamp schedule={schedule}")
     r = B.newton(x, 1e12, t(np.concatenate(hists)), solver=solver)
     torch_dev.cuda.synchronize()
     say("  ", r)
