@@ -9,8 +9,11 @@
 // and its two triangular solves (b becomes the Newton point y), then
 // k_newton_update: d = y - x, node rows clamped to [-vstep, vstep], x += d, and the
 // largest |d| read back to decide convergence (max |d| <= tol).  The refactorisation
-// is either this library's level-scheduled kernels (solve.hip; levels analysed here
-// once) or rocSOLVER's csrrf routines with the same pivots.
+// is either this library's level-scheduled kernels (solve.hip; levels, the rows'
+// static elimination programs and the runs of narrow levels planned here once) or
+// rocSOLVER's csrrf routines with the same pivots.  cs_batch_newton runs the same
+// loop on a batch's block-diagonal system (every circuit of a sizing batch steps at
+// once), with the node rows to clamp given by a per-row mask.
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -97,8 +100,8 @@ struct Events {
 };
 
 // Host factorisation of the pattern m at the values of A (device), upload of the
-// factor pattern and the level analysis.  clamp (optional, host, m.n flags): rows
-// whose Newton step is clamped.
+// factor pattern and the level analysis and launch plan.  clamp (optional, host, m.n
+// flags): rows whose Newton step is clamped.  flags: CS_NEWTON_NO_* bits.
 cs_status build_state(const MnaView &m, int device, double *A_val, const std::vector<uint8_t> *clamp,
                       int32_t flags, hipStream_t s, NewtonState **out) {
     const int32_t n = m.n;

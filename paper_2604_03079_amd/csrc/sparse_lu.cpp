@@ -241,8 +241,11 @@ void mna_order(const MnaView &m, std::vector<int32_t> &Q, std::vector<int32_t> &
 }
 
 // Estimated time of the level-scheduled refactorisation and solves of T (microseconds,
-// fitted to measurements on MI355X): per lower level 4.7, per upper level 6.8, and 0.94
-// per L entry of the longest row of each lower level.
+// fitted to measurements on MI355X of the per-level kernels): per lower level 4.7, per
+// upper level 6.8, and 0.94 per L entry of the longest row of each lower level.  The
+// programmed rows and the runs of narrow levels make long chains of one-row levels
+// cheaper than this, so the estimate leans to nested dissection; it only ranks the
+// two orders.
 double lu_cost_estimate(const HostLU &F, int32_t *n_lower, int32_t *n_upper) {
     const int32_t n = (int32_t)F.Tp.size() - 1;
     std::vector<int32_t> lev((size_t)n, 0), ulev((size_t)n, 0), nlo((size_t)n, 0);
