@@ -37,11 +37,13 @@ int32_t lu_stage_entries();
 // Caps of k_lu_lower_seq per row: entries, entries left of the diagonal, staged U
 // entries (those whose column is in the row).
 void lu_seq_caps(int32_t *row, int32_t *l, int32_t *u);
-// grid workgroups of one wave, each taking count programmed rows in order (prow: 8
-// ints per row, workgroup b from row b * count): one level is grid = its rows and
-// count = 1, a run of narrow levels grid = 1.  Same bits as launch_lu_lower.
-hipError_t launch_lu_lower_seq(int32_t grid, int32_t count, const int32_t *prow, const int32_t *plo,
-                               const int32_t *pst, double *T, const double *b, double *y, hipStream_t s);
+// grid workgroups of one wave, each taking programmed rows in order (prow: 8 ints per
+// row): workgroup b rows [b count, (b + 1) count), or [woff[b], woff[b + 1]) when woff
+// (device, grid + 1) is given.  One level is grid = its rows and count = 1; a run of
+// narrow levels one workgroup per connected part.  Same bits as launch_lu_lower.
+hipError_t launch_lu_lower_seq(int32_t grid, int32_t count, const int32_t *woff, const int32_t *prow,
+                               const int32_t *plo, const int32_t *pst, double *T, const double *b, double *y,
+                               hipStream_t s);
 hipError_t launch_lu_upper(int32_t count, const int32_t *rows, const int32_t *Tp, const int32_t *Ti,
                            const int32_t *diag, const double *T, double *y, const int32_t *Q, double *out,
                            hipStream_t s);

@@ -49,10 +49,13 @@ struct NewtonState {
     struct LStep {
         int32_t l0, l1;
         bool seq;
-        int32_t r0;   // first row of the step in the program
+        int32_t r0;        // first row of the step in the program
+        int32_t w0 = 0;    // runs: first of grid + 1 workgroup row offsets in sq_woff
+        int32_t grid = 1;  // runs: one workgroup per connected part of the L pattern
     };
     std::vector<LStep> lsteps;
     DevBuf<int32_t> sq_row, sq_lo, sq_st;   // the sequential program (k_lu_lower_seq)
+    DevBuf<int32_t> sq_woff;                // runs: rows of each workgroup, relative to r0
     std::vector<LStep> usteps;   // upper levels: one launch per level, or a run in one workgroup
     DevBuf<int32_t> uptr_d;      // uptr on the device (level offsets of the upper runs)
     rocblas_handle handle = nullptr;   // rocSOLVER path, set up on its first use
@@ -235,17 +238,69 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
             ns->lfit[(size_t)l] = (int32_t)(m1 - b0);
             ns->lshort[(size_t)l] = (int32_t)(m2 - m1);
         }
-        auto narrow = [&](int32_t lv) {
-            const int32_t rows_in = ns->lptr[(size_t)lv + 1] - ns->lptr[(size_t)lv];
-            return rows_in <= SEQ_LEVEL_ROWS && ns->lfit[(size_t)lv] == rows_in;
+        // connected parts of the L pattern (row i joined to every j with L(i, j) != 0):
+        // rows of different parts never wait for each other in the lower solve (the
+        // circuits of a batch are such parts)
+        std::vector<int32_t> part((size_t)n);
+        for (int32_t i = 0; i < n; ++i) part[(size_t)i] = i;
+        auto root = [&](int32_t i) {
+            while (part[(size_t)i] != i) {
+                part[(size_t)i] = part[(size_t)part[(size_t)i]];
+                i = part[(size_t)i];
+            }
+            return i;
         };
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = F.Tp[(size_t)i]; p < diag[(size_t)i]; ++p) {
+                const int32_t a = root(i), c = root(F.Ti[(size_t)p]);
+                if (a != c) part[(size_t)std::max(a, c)] = std::min(a, c);
+            }
+        for (int32_t i = 0; i < n; ++i) part[(size_t)i] = root(i);
+        // a level is narrow when every part has at most SEQ_LEVEL_ROWS rows in it and
+        // every row is programmed
+        std::vector<int32_t> seen((size_t)n, -1), cnt((size_t)n, 0);
+        auto narrow = [&](int32_t lv) {
+            const int32_t b0 = ns->lptr[(size_t)lv], b1 = ns->lptr[(size_t)lv + 1];
+            if (ns->lfit[(size_t)lv] != b1 - b0) return false;
+            for (int32_t k = b0; k < b1; ++k) {
+                const int32_t pt = part[(size_t)lrows[(size_t)k]];
+                if (seen[(size_t)pt] != lv) {
+                    seen[(size_t)pt] = lv;
+                    cnt[(size_t)pt] = 0;
+                }
+                if (++cnt[(size_t)pt] > SEQ_LEVEL_ROWS) return false;
+            }
+            return true;
+        };
+        std::vector<int32_t> woff;
         for (int32_t l = 0; l < nl;) {
             int32_t e = l;
             while (e < nl && narrow(e)) ++e;
             const int32_t r0 = (int32_t)(prow.size() / 8);
             if (e > l) {
-                ns->lsteps.push_back({l, e, true, r0});
-                for (int32_t k = ns->lptr[(size_t)l]; k < ns->lptr[(size_t)e]; ++k) program(lrows[(size_t)k], true);
+                // the run's rows grouped by part (parts in order of their first row), in
+                // level order inside each part: one workgroup per part
+                const int32_t k0 = ns->lptr[(size_t)l], k1 = ns->lptr[(size_t)e];
+                std::vector<int32_t> rows_run(lrows.begin() + k0, lrows.begin() + k1);
+                std::vector<int32_t> parts;
+                for (int32_t k = 0; k < k1 - k0; ++k) {
+                    const int32_t pt = part[(size_t)rows_run[(size_t)k]];
+                    if (std::find(parts.begin(), parts.end(), pt) == parts.end()) parts.push_back(pt);
+                }
+                std::vector<int32_t> rank((size_t)n, -1);
+                for (size_t q = 0; q < parts.size(); ++q) rank[(size_t)parts[q]] = (int32_t)q;
+                std::stable_sort(rows_run.begin(), rows_run.end(), [&](int32_t x, int32_t y) {
+                    return rank[(size_t)part[(size_t)x]] < rank[(size_t)part[(size_t)y]];
+                });
+                NewtonState::LStep st{l, e, true, r0, (int32_t)woff.size(), (int32_t)parts.size()};
+                int32_t off = 0;
+                woff.push_back(0);
+                for (size_t q = 0; q < parts.size(); ++q) {
+                    while (off < k1 - k0 && part[(size_t)rows_run[(size_t)off]] == parts[q]) ++off;
+                    woff.push_back(off);
+                }
+                ns->lsteps.push_back(st);
+                for (int32_t i : rows_run) program(i, true);
                 l = e;
             } else {
                 ns->lsteps.push_back({l, l + 1, false, r0});
@@ -254,6 +309,7 @@ cs_status build_state(const MnaView &m, int device, double *A_val, const std::ve
                 ++l;
             }
         }
+        if (!woff.empty()) NCHECK_HIP(ns->sq_woff.upload(woff), "upload sequential program");
         if (!prow.empty()) {
             NCHECK_HIP(ns->sq_row.upload(prow), "upload sequential program");
             if (!plo.empty()) NCHECK_HIP(ns->sq_lo.upload(plo), "upload sequential program");
@@ -348,15 +404,15 @@ cs_status newton_loop(NewtonState &ns, Stamp stamp, int32_t solver, double *x, i
             for (const auto &step : ns.lsteps) {
                 const int32_t *prog = ns.sq_row.p + 8 * (size_t)step.r0;
                 if (step.seq) {
-                    NCHECK_HIP(launch_lu_lower_seq(1, ns.lptr[(size_t)step.l1] - ns.lptr[(size_t)step.l0], prog,
-                                                   ns.sq_lo.p, ns.sq_st.p, ns.valT.p, b, ns.y.p, s),
+                    NCHECK_HIP(launch_lu_lower_seq(step.grid, 0, ns.sq_woff.p + step.w0, prog, ns.sq_lo.p,
+                                                   ns.sq_st.p, ns.valT.p, b, ns.y.p, s),
                                "LU lower launch");
                     continue;
                 }
                 const size_t l = (size_t)step.l0;
                 const int32_t nf = ns.lfit[l], nsh = ns.lshort[l];
                 const int32_t beg = ns.lptr[l] + nf, cnt = ns.lptr[l + 1] - beg;
-                NCHECK_HIP(launch_lu_lower_seq(nf, 1, prog, ns.sq_lo.p, ns.sq_st.p, ns.valT.p, b, ns.y.p, s),
+                NCHECK_HIP(launch_lu_lower_seq(nf, 1, nullptr, prog, ns.sq_lo.p, ns.sq_st.p, ns.valT.p, b, ns.y.p, s),
                            "LU lower launch");
                 NCHECK_HIP(launch_lu_lower_wave(nsh, ns.lrows.p + beg, ns.ptrT.p, ns.indT.p, ns.diag.p, ns.valT.p,
                                                 ns.P.p, b, ns.y.p, s),

@@ -139,10 +139,11 @@ __global__ void __launch_bounds__(64) k_lu_lower_wave(const int32_t *__restrict_
     if (lane == 0) y[i] = yi;
 }
 
-// Workgroup b (one wave) takes rows [b count, (b + 1) count) of the program in order
-// (each row's L columns are earlier rows of its own list or rows of earlier launches:
-// a run of narrow levels is one workgroup, a level one workgroup per row), from a
-// static program made by the host:
+// Workgroup b (one wave) takes rows [b count, (b + 1) count) of the program in order,
+// or rows [woff[b], woff[b + 1]) (each row's L columns are earlier rows of its own
+// list or rows of earlier launches: a level is one workgroup per row, a run of narrow
+// levels one workgroup per connected part of the L pattern), from a static program
+// made by the host:
 // prow (8 per row: row, T offset, entries, L entries, first L record, first staged
 // record, staged records, b row P(i)), plo (3 per L entry: diagonal position of U(j, :),
 // j, end of its staged records) and pst (2 per staged record: T position of U(j, k),
@@ -188,7 +189,8 @@ __device__ inline SeqRow seq_fetch(const int32_t *__restrict__ prow, const int32
     return f;
 }
 
-__global__ void __launch_bounds__(64) k_lu_lower_seq(int32_t count, const int32_t *__restrict__ prow,
+__global__ void __launch_bounds__(64) k_lu_lower_seq(int32_t count, const int32_t *__restrict__ woff,
+                                                     const int32_t *__restrict__ prow,
                                                      const int32_t *__restrict__ plo,
                                                      const int32_t *__restrict__ pst, double *T,
                                                      const double *__restrict__ b, double *y) {
@@ -198,7 +200,11 @@ __global__ void __launch_bounds__(64) k_lu_lower_seq(int32_t count, const int32_
     __shared__ int32_t ubeg[SEQ_L + 1];
     __shared__ double ujj[SEQ_L], uy[SEQ_L];
     const int32_t lane = threadIdx.x;
-    prow += 8 * (size_t)blockIdx.x * count;   // workgroup b: rows [b count, (b + 1) count)
+    // workgroup b: rows [woff[b], woff[b + 1]) when woff is given, else [b count, (b + 1) count)
+    const int32_t r_beg = woff ? woff[blockIdx.x] : (int32_t)blockIdx.x * count;
+    count = woff ? woff[blockIdx.x + 1] - r_beg : count;
+    if (count <= 0) return;
+    prow += 8 * (size_t)r_beg;
     SeqRow cur = seq_fetch(prow, plo, pst, 0, lane);
     for (int32_t r = 0; r < count; ++r) {
         // values of this row: final except its own entries, which only it changes
@@ -362,10 +368,11 @@ void lu_seq_caps(int32_t *row, int32_t *l, int32_t *u) {
     *u = SEQ_U;
 }
 
-hipError_t launch_lu_lower_seq(int32_t grid, int32_t count, const int32_t *prow, const int32_t *plo,
-                               const int32_t *pst, double *T, const double *b, double *y, hipStream_t s) {
-    if (grid <= 0 || count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lu_lower_seq, dim3(grid), dim3(64), 0, s, count, prow, plo, pst, T, b, y);
+hipError_t launch_lu_lower_seq(int32_t grid, int32_t count, const int32_t *woff, const int32_t *prow,
+                               const int32_t *plo, const int32_t *pst, double *T, const double *b, double *y,
+                               hipStream_t s) {
+    if (grid <= 0 || (!woff && count <= 0)) return hipSuccess;
+    hipLaunchKernelGGL(k_lu_lower_seq, dim3(grid), dim3(64), 0, s, count, woff, prow, plo, pst, T, b, y);
     return hipGetLastError();
 }
 
