@@ -429,7 +429,17 @@ cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const d
     CS_CHECK_HIP(launch_gather_params(c->h.n_dev, c->d_perm.p, W, L, VTH0, c->d_par.p,
                                       (hipStream_t)stream), "parameter gather launch");
     c->params_set = true;
-    c->rd.par_stale = true;
+    // the region schedules read their own region-major copy: refresh it here, on the
+    // same stream, so that a captured step replayed after this call sees the new
+    // values (a replay runs no host code); without uploaded region tables the copy
+    // is made when they are uploaded
+    if (c->rd.ready) {
+        CS_CHECK_HIP(launch_permute_params(c->h.n_dev, c->rd.cm_pos.p, c->d_par.p, c->h.n_dev, c->rd.par.p,
+                                           (hipStream_t)stream), "parameter permute launch");
+        c->rd.par_stale = false;
+    } else {
+        c->rd.par_stale = true;
+    }
     return CS_OK;
 }
 

@@ -463,7 +463,14 @@ cs_status cs_batch_set_params(cs_batch *B, const double *W, const double *L, con
     CS_BCHECK(launch_gather_params(B->h.n_dev, B->d_perm.p, W, L, VTH0, B->d_par.p, (hipStream_t)stream),
               "parameter gather launch");
     B->params_set = true;
-    B->rd.par_stale = true;
+    // region-major copy refreshed on the same stream (a replayed step runs no host code)
+    if (B->rd.ready) {
+        CS_BCHECK(launch_permute_params(B->h.n_dev, B->rd.cm_pos.p, B->d_par.p, B->h.n_dev, B->rd.par.p,
+                                        (hipStream_t)stream), "parameter permute launch");
+        B->rd.par_stale = false;
+    } else {
+        B->rd.par_stale = true;
+    }
     return CS_OK;
 }
 
