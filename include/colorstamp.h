@@ -159,7 +159,10 @@ cs_status cs_get_stamp_map(const cs_circuit *c, int32_t *slot, int8_t *sflag, in
 cs_status cs_set_models(cs_circuit *c, const cs_model_card *nmos, const cs_model_card *pmos);
 
 /* Per-device parameters in original device order (device pointers, n_dev each).
- * Copied into the library's colour-major layout on `stream`. */
+ * Copied into the library's colour-major layout (and, when the region schedule's
+ * tables are on the device, its region-major copy) by kernels on `stream`, so a
+ * captured evaluate-and-stamp replayed after this call reads the new values.  The
+ * library's copies keep their addresses until the next colouring or stamp map. */
 cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const double *VTH0,
                         void *stream);
 
@@ -315,6 +318,7 @@ void cs_batch_destroy(cs_batch *b);
 /* Offsets (host arrays of n+1 entries each; any may be NULL). */
 cs_status cs_batch_layout(const cs_batch *b, int64_t *dev_off, int64_t *row_off,
                           int64_t *nnz_off);
+/* As cs_set_params, over the packed device order. */
 cs_status cs_batch_set_params(cs_batch *b, const double *W, const double *L,
                               const double *VTH0, void *stream);
 /* Launch configuration of the batched persistent kernel (see cs_set_launch) and the
@@ -340,6 +344,36 @@ cs_status cs_batch_get_region_info(const cs_batch *b, int32_t *n_regions, int32_
 cs_status cs_batch_get_region_plan(const cs_batch *b, int32_t *perm, uint16_t *phase, int32_t *code,
                                    int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item,
                                    int32_t *fold, int32_t *fold_src);
+/* A launch configuration of cs_batch_eval_stamp (see cs_batch_set_launch and
+ * cs_batch_set_schedule) and its measured time. */
+typedef struct {
+    int32_t schedule;        /* CS_COLOR_PERSISTENT or CS_COLOR_REGION */
+    int32_t block;           /* threads per workgroup */
+    int32_t eval_ahead;      /* persistent schedule: -1 choose, 0 evaluate in each phase */
+    int32_t local_max_dev;   /* persistent schedule: circuits up to this size inside one workgroup */
+    double ms;               /* mean time of one batched step, milliseconds */
+} cs_batch_config;
+
+/* Autotuner of the batched launch (a sizing loop calls the simulator repeatedly on
+ * one batch, Introduction).  Every candidate configuration (persistent schedule:
+ * block 128 or 256 x local_max_dev 0, 64, 256, 1024, 4096 x eval_ahead -1, 0;
+ * region schedule: block 128, 192, 256) is applied, its parameters gathered from
+ * W, L, VTH0 (device, packed device order), one batched step at x (device, packed
+ * rows) is captured in a HIP graph on `stream` and replayed `reps` times between two
+ * events; A and b_vec (device, packed) are the step's workspace and hold its last
+ * output.  Candidates that do not run on the device, or whose bounded barrier waits
+ * expire, are skipped.  The fastest is applied to the batch (parameters included).
+ * cache_path (host string or NULL): a text file of one line per tuned batch, keyed
+ * by the GPU architecture and the batch signature (sorted (devices, colours) pairs of
+ * its circuits); a key already in the file is applied without timing (*cached = 1),
+ * a new one is appended.  Outputs (each may be NULL): the configuration, the number
+ * of candidates timed.  Synchronises the stream.  CS_ENOTSUP if no candidate runs,
+ * CS_EINVAL for reps outside 1..100000 or an unwritable cache file. */
+cs_status cs_batch_tune(cs_batch *b, const double *W, const double *L, const double *VTH0,
+                        const double *x, double ag0, double *A, double *b_vec, int32_t reps,
+                        const char *cache_path, cs_batch_config *best, int32_t *n_tried,
+                        int32_t *cached, void *stream);
+
 /* One launch over every circuit of the batch. */
 cs_status cs_batch_eval_stamp(cs_batch *b, const double *x, double ag0, const double *hist,
                               double *A, double *b_vec, void *stream);
