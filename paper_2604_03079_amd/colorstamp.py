@@ -6,8 +6,11 @@ device memory and the current stream.  If the library is not built the import of
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -33,7 +36,7 @@ EXPORTS = (
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
     "cs_batch_get_region_plan", "cs_batch_eval_stamp", "cs_batch_vjp", "cs_batch_check",
-    "cs_batch_newton",
+    "cs_batch_newton", "cs_batch_tune",
     "cs_last_error",
 )
 
@@ -42,6 +45,12 @@ class CsError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class BatchConfig(C.Structure):
+    """cs_batch_config: a batched launch configuration and its measured time."""
+    _fields_ = [("schedule", C.c_int32), ("block", C.c_int32), ("eval_ahead", C.c_int32),
+                ("local_max_dev", C.c_int32), ("ms", C.c_double)]
 
 
 class ModelCard(C.Structure):
@@ -101,6 +110,7 @@ def lib():
             "cs_batch_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_batch_check": [p, p],
             "cs_batch_newton": [p, i32, p, d, p, i32, d, d, p, p, p, p, p, p, p],
+            "cs_batch_tune": [p, p, p, p, p, d, p, p, i32, C.c_char_p, p, p, p, p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -115,6 +125,21 @@ def lib():
     return _lib
 
 
+# Handles still open.  They are destroyed by an exit hook, which runs before the
+# interpreter tears its modules down and before the C runtime's exit handlers (where
+# the HIP runtime and any profiler attached to it finalise): a device free issued
+# from a destructor after that point would call into a runtime that is gone.
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    for o in [o for o in list(_live) if isinstance(o, Batch)] + [o for o in list(_live) if isinstance(o, Circuit)]:
+        o.close()
+
+
+atexit.register(_close_all)
+
+
 def _check(st: int, where: str):
     if st != 0:
         raise CsError(st, where, lib().cs_last_error().decode())
@@ -124,11 +149,50 @@ def _np_ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-def _dev_ptr(t):
-    if t is None:
-        return None
-    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
-    return C.c_void_p(t.data_ptr())
+def _check_layout(t, n, what):
+    """Type, dtype, element count and contiguity of one device operand."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{what}: dtype must be torch.float64, got {t.dtype}")
+    if n is not None and t.numel() != int(n):
+        raise ValueError(f"{what}: expected {int(n)} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+
+
+def _check_device(t, what, device):
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must be a CUDA tensor (the library reads and writes device memory)")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: on cuda:{t.device.index}, the handle lives on cuda:{device}")
+
+
+def _dev_ptrs(device, *specs):
+    """Device addresses of caller tensors, each spec (tensor or None, element count
+    or None, name), after checking what the kernels assume: contiguous torch.float64
+    tensors of exactly the stated size (every operand first), then CUDA tensors on
+    the handle's device.  Raises TypeError / ValueError; nothing reaches the library
+    otherwise."""
+    for t, n, what in specs:
+        if t is not None:
+            _check_layout(t, n, what)
+    for t, _, what in specs:
+        if t is not None:
+            _check_device(t, what, device)
+    return [None if t is None else C.c_void_p(t.data_ptr()) for t, _, _ in specs]
+
+
+def _dev_ptr(t, n=None, what="tensor", device=None):
+    """_dev_ptrs for one operand."""
+    return _dev_ptrs(device, (t, n, what))[0]
+
+
+def _cuda_index(t):
+    """Device index of a CUDA tensor, else None (the checks then refuse it)."""
+    import torch
+    return t.device.index if isinstance(t, torch.Tensor) and t.is_cuda else None
 
 
 def _stream(stream):
@@ -185,6 +249,7 @@ class Circuit:
                                        vsrc.shape[0], _np_ptr(vsrc), _np_ptr(vv), C.byref(h)),
                "cs_circuit_create")
         self._h = h
+        _live.add(self)
         self.n_nodes = int(n_nodes)
         self.n_dev = term.shape[0]
         self.n_rows = None
@@ -208,11 +273,18 @@ class Circuit:
         _check(lib().cs_set_resistors(self._h, nodes.shape[0], _np_ptr(nodes), _np_ptr(g)),
                "cs_set_resistors")
 
-    def __del__(self):
+    def close(self):
+        """Destroy the library handle (device memory included); idempotent."""
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.cs_circuit_destroy(h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        # during interpreter shutdown the exit hook has already closed every handle;
+        # a destructor that runs later must not call into the HIP runtime
+        if not sys.is_finalizing():
+            self.close()
 
     @property
     def handle(self):
@@ -256,8 +328,11 @@ class Circuit:
         _check(lib().cs_set_models(self._h, C.byref(cn), C.byref(cp)), "cs_set_models")
 
     def set_params(self, W, L, VTH0, stream=None):
-        _check(lib().cs_set_params(self._h, _dev_ptr(W), _dev_ptr(L), _dev_ptr(VTH0), _stream(stream)),
-               "cs_set_params")
+        dev = _cuda_index(W)
+        n = self.n_dev
+        ptrs = _dev_ptrs(dev, (W, n, "W"), (L, n, "L"), (VTH0, n, "VTH0"))
+        _check(lib().cs_set_params(self._h, *ptrs, _stream(stream)), "cs_set_params")
+        self._device = dev
 
     def set_launch(self, block: int = 0, eval_ahead: int = -1, cooperative: bool = True):
         _check(lib().cs_set_launch(self._h, int(block), int(eval_ahead), int(bool(cooperative))),
@@ -291,8 +366,10 @@ class Circuit:
             A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
         if b is None:
             b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
-        _check(lib().cs_eval_stamp(self._h, VARIANTS[variant], _dev_ptr(x), float(ag0), _dev_ptr(hist),
-                                   _dev_ptr(A), _dev_ptr(b), _stream(stream)), "cs_eval_stamp")
+        px, ph, pA, pb = _dev_ptrs(getattr(self, "_device", None), (x, self.n_rows, "x"),
+                                   (hist, 4 * self.n_dev, "hist"), (A, self.nnz, "A"), (b, self.n_rows, "b"))
+        _check(lib().cs_eval_stamp(self._h, VARIANTS[variant], px, float(ag0), ph, pA, pb, _stream(stream)),
+               "cs_eval_stamp")
         return A, b
 
     def vjp(self, x, ag0: float, A_bar, b_bar, hist=None, stream=None):
@@ -300,9 +377,11 @@ class Circuit:
         gW = torch.empty(self.n_dev, dtype=torch.float64, device=x.device)
         gL = torch.empty_like(gW)
         gV = torch.empty_like(gW)
-        _check(lib().cs_vjp(self._h, _dev_ptr(x), float(ag0), _dev_ptr(hist), _dev_ptr(A_bar),
-                            _dev_ptr(b_bar), _dev_ptr(gW), _dev_ptr(gL), _dev_ptr(gV), _stream(stream)),
-               "cs_vjp")
+        n = self.n_dev
+        px, ph, pa, pb, pw, pl, pv = _dev_ptrs(
+            getattr(self, "_device", None), (x, self.n_rows, "x"), (hist, 4 * n, "hist"), (A_bar, self.nnz, "A_bar"),
+            (b_bar, self.n_rows, "b_bar"), (gW, n, "W_bar"), (gL, n, "L_bar"), (gV, n, "VTH0_bar"))
+        _check(lib().cs_vjp(self._h, px, float(ag0), ph, pa, pb, pw, pl, pv, _stream(stream)), "cs_vjp")
         return gW, gL, gV
 
     def check(self, stream=None):
@@ -320,9 +399,10 @@ class Circuit:
             b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
         it, conv, step = C.c_int32(), C.c_int32(), C.c_double()
         t = (C.c_double * 5)()
-        _check(lib().cs_newton(self._h, VARIANTS[variant], SOLVERS[solver], _dev_ptr(x), float(ag0), _dev_ptr(hist),
-                               int(max_iter),
-                               float(vstep), float(tol), _dev_ptr(A), _dev_ptr(b), C.byref(it), C.byref(conv),
+        px, ph, pA, pb = _dev_ptrs(getattr(self, "_device", None), (x, self.n_rows, "x"),
+                                   (hist, 4 * self.n_dev, "hist"), (A, self.nnz, "A"), (b, self.n_rows, "b"))
+        _check(lib().cs_newton(self._h, VARIANTS[variant], SOLVERS[solver], px, float(ag0), ph, int(max_iter),
+                               float(vstep), float(tol), pA, pb, C.byref(it), C.byref(conv),
                                C.byref(step), t, _stream(stream)), "cs_newton")
         return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,
                     ms=dict(stamp=t[0], refactor=t[1], solve=t[2], update=t[3], host_factor=t[4]))
@@ -338,7 +418,8 @@ class Circuit:
         import torch
         if out is None:
             out = torch.empty((self.n_dev, 4), dtype=torch.float64, device=x.device)
-        _check(lib().cs_history(self._h, _dev_ptr(x), float(ag0), _dev_ptr(out), _stream(stream)), "cs_history")
+        px, po = _dev_ptrs(getattr(self, "_device", None), (x, self.n_rows, "x"), (out, 4 * self.n_dev, "hist_out"))
+        _check(lib().cs_history(self._h, px, float(ag0), po, _stream(stream)), "cs_history")
         return out
 
     def transient(self, x, h: float, n_steps: int, nodes=None, **newton_kw):
@@ -397,6 +478,7 @@ class Batch:
         h = C.c_void_p()
         _check(lib().cs_batch_create(n, arr, C.byref(h)), "cs_batch_create")
         self._h = h
+        _live.add(self)
         self.dev_off = np.zeros(n + 1, np.int64)
         self.row_off = np.zeros(n + 1, np.int64)
         self.nnz_off = np.zeros(n + 1, np.int64)
@@ -406,11 +488,16 @@ class Batch:
         self.n_rows = int(self.row_off[-1])
         self.nnz = int(self.nnz_off[-1])
 
-    def __del__(self):
+    def close(self):
+        """Destroy the batch handle (its circuits stay open); idempotent."""
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.cs_batch_destroy(h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
     def set_launch(self, block: int = 0, eval_ahead: int = -1, local_max_dev: int = 0,
                    schedule: str = "persistent"):
@@ -427,8 +514,11 @@ class Batch:
                             L.cs_batch_get_region_plan, self._h, block, self.n_dev)
 
     def set_params(self, W, L, VTH0, stream=None):
-        _check(lib().cs_batch_set_params(self._h, _dev_ptr(W), _dev_ptr(L), _dev_ptr(VTH0),
-                                         _stream(stream)), "cs_batch_set_params")
+        dev = _cuda_index(W)
+        n = self.n_dev
+        ptrs = _dev_ptrs(dev, (W, n, "W"), (L, n, "L"), (VTH0, n, "VTH0"))
+        _check(lib().cs_batch_set_params(self._h, *ptrs, _stream(stream)), "cs_batch_set_params")
+        self._device = dev
 
     def info(self) -> dict:
         nd, nr, nz = C.c_int64(), C.c_int64(), C.c_int64()
@@ -445,8 +535,9 @@ class Batch:
             A = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
         if b is None:
             b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
-        _check(lib().cs_batch_eval_stamp(self._h, _dev_ptr(x), float(ag0), _dev_ptr(hist), _dev_ptr(A),
-                                         _dev_ptr(b), _stream(stream)), "cs_batch_eval_stamp")
+        px, ph, pA, pb = _dev_ptrs(getattr(self, "_device", None), (x, self.n_rows, "x"),
+                                   (hist, 4 * self.n_dev, "hist"), (A, self.nnz, "A"), (b, self.n_rows, "b"))
+        _check(lib().cs_batch_eval_stamp(self._h, px, float(ag0), ph, pA, pb, _stream(stream)), "cs_batch_eval_stamp")
         return A, b
 
     def vjp(self, x, ag0: float, A_bar, b_bar, hist=None, stream=None):
@@ -454,13 +545,33 @@ class Batch:
         gW = torch.empty(self.n_dev, dtype=torch.float64, device=x.device)
         gL = torch.empty_like(gW)
         gV = torch.empty_like(gW)
-        _check(lib().cs_batch_vjp(self._h, _dev_ptr(x), float(ag0), _dev_ptr(hist), _dev_ptr(A_bar),
-                                  _dev_ptr(b_bar), _dev_ptr(gW), _dev_ptr(gL), _dev_ptr(gV),
-                                  _stream(stream)), "cs_batch_vjp")
+        n = self.n_dev
+        px, ph, pa, pb, pw, pl, pv = _dev_ptrs(
+            getattr(self, "_device", None), (x, self.n_rows, "x"), (hist, 4 * n, "hist"), (A_bar, self.nnz, "A_bar"),
+            (b_bar, self.n_rows, "b_bar"), (gW, n, "W_bar"), (gL, n, "L_bar"), (gV, n, "VTH0_bar"))
+        _check(lib().cs_batch_vjp(self._h, px, float(ag0), ph, pa, pb, pw, pl, pv, _stream(stream)), "cs_batch_vjp")
         return gW, gL, gV
 
     def check(self, stream=None):
         _check(lib().cs_batch_check(self._h, _stream(stream)), "cs_batch_check")
+
+    def tune(self, W, L, VTH0, x, ag0: float, A, b, reps: int = 8, cache_path: str | None = None,
+             stream=None) -> dict:
+        """cs_batch_tune: time every candidate launch configuration (graph replays)
+        and apply the fastest; returns it with its time, the number of candidates
+        timed and whether it came from the cache file."""
+        dev = _cuda_index(W)
+        n = self.n_dev
+        cfg, tried, cached = BatchConfig(), C.c_int32(), C.c_int32()
+        pw, pl, pv, px, pA, pb = _dev_ptrs(dev, (W, n, "W"), (L, n, "L"), (VTH0, n, "VTH0"), (x, self.n_rows, "x"),
+                                           (A, self.nnz, "A"), (b, self.n_rows, "b"))
+        _check(lib().cs_batch_tune(self._h, pw, pl, pv, px, float(ag0), pA, pb, int(reps),
+                                   None if cache_path is None else os.fsencode(cache_path), C.byref(cfg),
+                                   C.byref(tried), C.byref(cached), _stream(stream)), "cs_batch_tune")
+        self._device = dev
+        sched = {v: k for k, v in VARIANTS.items()}[cfg.schedule]
+        return dict(schedule=sched, block=cfg.block, eval_ahead=cfg.eval_ahead, local_max_dev=cfg.local_max_dev,
+                    ms=cfg.ms, tried=tried.value, cached=bool(cached.value))
 
     def newton(self, x, ag0: float = 0.0, hist=None, max_iter: int = 100, vstep: float = 0.3,
                tol: float = 1e-9, solver="levels", A=None, b=None, stream=None) -> dict:
@@ -473,8 +584,10 @@ class Batch:
             b = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
         it, conv, step = C.c_int32(), C.c_int32(), C.c_double()
         t = (C.c_double * 5)()
-        _check(lib().cs_batch_newton(self._h, SOLVERS[solver], _dev_ptr(x), float(ag0), _dev_ptr(hist),
-                                     int(max_iter), float(vstep), float(tol), _dev_ptr(A), _dev_ptr(b),
+        px, ph, pA, pb = _dev_ptrs(getattr(self, "_device", None), (x, self.n_rows, "x"),
+                                   (hist, 4 * self.n_dev, "hist"), (A, self.nnz, "A"), (b, self.n_rows, "b"))
+        _check(lib().cs_batch_newton(self._h, SOLVERS[solver], px, float(ag0), ph, int(max_iter), float(vstep),
+                                     float(tol), pA, pb,
                                      C.byref(it), C.byref(conv), C.byref(step), t, _stream(stream)),
                "cs_batch_newton")
         return dict(iterations=it.value, converged=bool(conv.value), last_step=step.value,

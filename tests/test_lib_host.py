@@ -209,3 +209,102 @@ def test_junction_cards_are_checked():
         assert e.value.status == -1
     c.set_models(G.junction_card(1), G.junction_card(-1))
     c.set_models(G.default_card(1, ), dict(G.default_card(-1), pb=0.0))   # junctions off: not checked
+
+
+# ---- the binding's tensor checks (they run before any library call) ------------------
+
+def _bad_tensors(n):
+    """(tensor, exception) pairs that the binding must refuse for an n-element
+    device operand, each before anything reaches the library."""
+    import torch
+    return [
+        (np.zeros(n), TypeError),                                     # not a torch tensor
+        (torch.zeros(n, dtype=torch.float32), TypeError),             # wrong dtype
+        (torch.zeros(n, dtype=torch.int64), TypeError),
+        (torch.zeros(max(n - 1, 0), dtype=torch.float64), ValueError),  # one element short
+        (torch.zeros(n + 1, dtype=torch.float64), ValueError),          # one element long
+        (torch.zeros(2 * n, dtype=torch.float64)[::2], ValueError),     # not contiguous
+        (torch.zeros(n, dtype=torch.float64), ValueError),              # host memory
+    ]
+
+
+def _prepared_chain():
+    circ = G.workload(0)
+    c = CS.prepare(circ, exclude=True)
+    return circ, c
+
+
+@pytest.mark.parametrize("k", range(7))
+def test_binding_refuses_bad_parameter_tensors(k):
+    import torch
+    circ, c = _prepared_chain()
+    n = circ.n_dev
+    good = torch.zeros(n, dtype=torch.float64)   # host memory: never reaches the library either
+    bad, exc = _bad_tensors(n)[k]
+    with pytest.raises(exc):
+        c.set_params(bad, good, good)
+    with pytest.raises((TypeError, ValueError)):
+        c.set_params(good, good, bad)
+
+
+@pytest.mark.parametrize("k", range(7))
+def test_binding_refuses_bad_step_operands(k):
+    import torch
+    circ, c = _prepared_chain()
+    for what, n in (("x", c.n_rows), ("A", c.nnz), ("b", c.n_rows), ("hist", 4 * c.n_dev)):
+        bad, exc = _bad_tensors(n)[k]
+        x = bad if what == "x" else torch.zeros(c.n_rows, dtype=torch.float64)
+        kw = {what: bad} if what != "x" else {}
+        if what == "hist":
+            kw = dict(hist=bad)
+        with pytest.raises(exc):
+            if what in ("A", "b"):
+                c.eval_stamp(torch.zeros(c.n_rows, dtype=torch.float64), 1e12, None,
+                             bad if what == "A" else torch.zeros(c.nnz, dtype=torch.float64),
+                             bad if what == "b" else torch.zeros(c.n_rows, dtype=torch.float64))
+            elif what == "hist":
+                c.eval_stamp(torch.zeros(c.n_rows, dtype=torch.float64), 1e12, bad,
+                             torch.zeros(c.nnz, dtype=torch.float64), torch.zeros(c.n_rows, dtype=torch.float64))
+            else:
+                c.eval_stamp(x, 1e12, None, torch.zeros(c.nnz, dtype=torch.float64),
+                             torch.zeros(c.n_rows, dtype=torch.float64))
+
+
+def test_binding_refuses_bad_cotangents_and_batch_operands():
+    import torch
+    circ, c = _prepared_chain()
+    z = lambda m: torch.zeros(m, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        c.vjp(z(c.n_rows), 1e12, torch.zeros(c.nnz, dtype=torch.float32), z(c.n_rows))
+    with pytest.raises(ValueError):
+        c.vjp(z(c.n_rows), 1e12, z(c.nnz - 1), z(c.n_rows))
+    with pytest.raises(ValueError):
+        c.history(z(c.n_rows + 3), 1e12, z(4 * c.n_dev))
+    with pytest.raises(ValueError):
+        c.newton(z(c.n_rows), 1e12, None, A=z(c.nnz), b=z(c.n_rows - 1))
+    B = CS.Batch([c, CS.prepare(G.workload(0), exclude=True)])
+    with pytest.raises(ValueError):
+        B.set_params(z(B.n_dev - 1), z(B.n_dev), z(B.n_dev))
+    with pytest.raises(TypeError):
+        B.set_params(torch.zeros(B.n_dev, dtype=torch.float32), z(B.n_dev), z(B.n_dev))
+    with pytest.raises(ValueError):
+        B.eval_stamp(z(B.n_rows), 1e12, None, z(B.nnz + 1), z(B.n_rows))
+    with pytest.raises(ValueError):
+        B.vjp(z(B.n_rows), 1e12, z(B.nnz), z(2 * B.n_rows))
+    with pytest.raises(ValueError):
+        B.tune(z(B.n_dev), z(B.n_dev), z(B.n_dev), z(B.n_rows), 1e12, z(B.nnz), z(B.n_rows))
+
+
+def test_handles_close_once_and_exit_hook_closes_the_rest():
+    # an explicit close and the exit hook both leave the handle closed, and neither
+    # calls the library twice for one handle
+    _, c = _prepared_chain()
+    B = CS.Batch([c])
+    c2 = CS.prepare(G.workload(0), exclude=True)
+    B.close()
+    B.close()
+    c.close()
+    assert c.handle is None and B._h is None
+    CS._close_all()
+    assert c2.handle is None
+    c2.close()
