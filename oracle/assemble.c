@@ -19,6 +19,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "oracle.h"
 #include "oracle_internal.h"
@@ -245,4 +248,148 @@ int or_assemble_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term,
                           double ag0, const double *hist, double *A, double *b) {
     return assemble_impl(n_nodes, n_dev, term, pol, n_vsrc, vsrc, vsrc_volts, n_res, res, res_g, nmos,
                          pmos, W, L, VTH0, row_ptr, col_idx, NULL, NULL, x, ag0, hist, A, b, 1);
+}
+
+/* Colour replay on every host core (the paper's ColorFused on its CPU: per-colour
+ * parallel for over the devices of the colour).  Same values as the serial colour
+ * replay, bit for bit: the compute phase is per device; within a colour no two
+ * devices share a non-hub entry, so each entry still receives its contributions in
+ * colour order (first writer stores, later writers add); hub contributions go to
+ * per-device places and are summed by or_hubsum in ascending device index, as in
+ * the serial replay.  Threads: the OpenMP default (OMP_NUM_THREADS). */
+int or_assemble_omp(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                    int32_t n_vsrc, const int32_t *vsrc, const double *vsrc_volts,
+                    int32_t n_res, const int32_t *res, const double *res_g, const or_card *nmos,
+                    const or_card *pmos, const double *W, const double *L, const double *VTH0,
+                    const int32_t *row_ptr, const int32_t *col_idx, const int32_t *colour,
+                    const uint8_t *excl, const double *x, double ag0, const double *hist, double *A,
+                    double *b) {
+    const int64_t n_rows = (int64_t)n_nodes - 1 + n_vsrc;
+    const int64_t nnz = row_ptr[n_rows];
+    double *mA = malloc(sizeof(double) * 16 * ((size_t)n_dev + 1));
+    double *mB = malloc(sizeof(double) * 4 * ((size_t)n_dev + 1));
+    int64_t *sl = malloc(sizeof(int64_t) * 16 * ((size_t)n_dev + 1));
+    int *kk = malloc(sizeof(int) * ((size_t)n_dev + 1));
+    int64_t *hoff = malloc(sizeof(int64_t) * ((size_t)n_dev + 1));
+    int bad = 0;
+    if (!mA || !mB || !sl || !kk || !hoff) { free(mA); free(mB); free(sl); free(kk); free(hoff); return -1; }
+    /* the operation counter counts serial evaluations only */
+    const int counting = or_counting_;
+    or_counting_ = 0;
+
+    /* compute phase, one device per iteration */
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int32_t v = 0; v < n_dev; ++v) {
+        const int32_t *t4 = term + 4 * (int64_t)v;
+        double V[4], Y[16], bl[4], Icur[4], Q[4];
+        gather_v(t4, x, V);
+        or_device_eval(pol[v] > 0 ? nmos : pmos, pol[v], W[v], L[v], VTH0[v], V, ag0,
+                       hist ? hist + 4 * (int64_t)v : NULL, Y, bl, Icur, Q, NULL);
+        kk[v] = merge_device(t4, Y, bl, mA + 16 * (int64_t)v, mB + 4 * (int64_t)v);
+        int32_t u[4]; int a[4];
+        or_unique_nodes(t4, u, a);
+        for (int r = 0; r < kk[v]; ++r)
+            for (int c = 0; c < kk[v]; ++c) {
+                int64_t s = or_find_slot(row_ptr, col_idx, u[r] - 1, u[c] - 1);
+                if (s < 0) bad = 1;
+                sl[16 * (int64_t)v + r * kk[v] + c] = s;
+            }
+    }
+    or_counting_ = counting;
+    if (bad) { free(mA); free(mB); free(sl); free(kk); free(hoff); return -3; }
+
+    for (int64_t i = 0; i < nnz; ++i) A[i] = 0.0;
+    for (int64_t i = 0; i < n_rows; ++i) b[i] = 0.0;
+    for (int32_t j = 0; j < n_vsrc; ++j) {
+        int32_t br = n_nodes - 1 + j;
+        for (int e = 0; e < 2; ++e) {
+            int32_t nd = vsrc[2 * j + e];
+            if (nd == 0) continue;
+            double sgn = e == 0 ? 1.0 : -1.0;
+            A[or_find_slot(row_ptr, col_idx, nd - 1, br)] = sgn;
+            A[or_find_slot(row_ptr, col_idx, br, nd - 1)] = sgn;
+        }
+        b[br] = vsrc_volts[j];
+    }
+
+    /* hub places per device: prefix over the devices in ascending index */
+    int64_t nh = 0;
+    for (int32_t v = 0; v < n_dev; ++v) {
+        hoff[v] = nh;
+        int32_t u[4]; int a[4];
+        int k = or_unique_nodes(term + 4 * (int64_t)v, u, a);
+        for (int r = 0; r < k; ++r) {
+            if (!(excl && excl[u[r]])) continue;
+            for (int c = 0; c < k; ++c) nh += excl[u[c]] ? 1 : 0;
+            nh += 1;
+        }
+    }
+    int32_t C = 0;
+    for (int32_t v = 0; v < n_dev; ++v) if (colour[v] + 1 > C) C = colour[v] + 1;
+    char *doneA = calloc((size_t)nnz + 1, 1), *doneB = calloc((size_t)n_rows + 1, 1);
+    hub_item *hubs = malloc(sizeof(hub_item) * ((size_t)nh + 1));
+    int64_t *cptr = calloc((size_t)C + 1, sizeof(int64_t));
+    int32_t *order = malloc(sizeof(int32_t) * ((size_t)n_dev + 1));
+    int64_t *fillp = malloc(sizeof(int64_t) * ((size_t)C + 1));
+    for (int32_t v = 0; v < n_dev; ++v) cptr[colour[v] + 1]++;
+    for (int32_t c = 0; c < C; ++c) cptr[c + 1] += cptr[c];
+    memcpy(fillp, cptr, sizeof(int64_t) * ((size_t)C + 1));
+    for (int32_t v = 0; v < n_dev; ++v) order[fillp[colour[v]]++] = v;
+    for (int32_t c = 0; c < C; ++c) {
+        /* the devices of one colour touch disjoint non-hub entries */
+#pragma omp parallel for schedule(static)
+        for (int64_t e = cptr[c]; e < cptr[c + 1]; ++e) {
+            int32_t v = order[e];
+            int32_t u[4]; int a[4];
+            int k = or_unique_nodes(term + 4 * (int64_t)v, u, a);
+            int64_t h = hoff[v];
+            for (int r = 0; r < k; ++r) {
+                for (int cc = 0; cc < k; ++cc) {
+                    int64_t s = sl[16 * (int64_t)v + r * k + cc];
+                    double m = mA[16 * (int64_t)v + r * k + cc];
+                    if (excl && excl[u[r]] && excl[u[cc]]) {
+                        hubs[h].key = s; hubs[h].dev = v; hubs[h].val = m; ++h;
+                    } else if (!doneA[s]) { A[s] = m; doneA[s] = 1; }
+                    else A[s] = A[s] + m;
+                }
+                int64_t row = u[r] - 1;
+                double mb = mB[4 * (int64_t)v + r];
+                if (excl && excl[u[r]]) {
+                    hubs[h].key = nnz + row; hubs[h].dev = v; hubs[h].val = mb; ++h;
+                } else if (!doneB[row]) { b[row] = mb; doneB[row] = 1; }
+                else b[row] = b[row] + mb;
+            }
+        }
+    }
+    qsort(hubs, (size_t)nh, sizeof(hub_item), cmp_hub);
+    double *vals = malloc(sizeof(double) * ((size_t)nh + 1));
+    for (int64_t i = 0; i < nh;) {
+        int64_t j = i;
+        while (j < nh && hubs[j].key == hubs[i].key) { vals[j - i] = hubs[j].val; ++j; }
+        double s = or_hubsum(vals, j - i);
+        if (hubs[i].key < nnz) A[hubs[i].key] = s; else b[hubs[i].key - nnz] = s;
+        i = j;
+    }
+    free(vals); free(doneA); free(doneB); free(hubs); free(cptr); free(order); free(fillp);
+    free(mA); free(mB); free(sl); free(kk); free(hoff);
+    if (n_res > 0) {
+        double *Lin = malloc(sizeof(double) * ((size_t)nnz + 1));
+        uint8_t *touched = malloc((size_t)nnz + 1);
+        if (!Lin || !touched) { free(Lin); free(touched); return -1; }
+        int rc = or_linear_stamp(n_nodes, n_res, res, res_g, row_ptr, col_idx, nnz, Lin, touched, 0);
+        if (rc == 0)
+            for (int64_t i = 0; i < nnz; ++i)
+                if (touched[i]) A[i] = A[i] + Lin[i];
+        free(Lin); free(touched);
+        return rc;
+    }
+    return 0;
+}
+
+int or_omp_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

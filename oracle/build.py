@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "_build", "liboracle.so")
 def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-fexcess-precision=standard", "-Wall", "-Wextra", "-Wno-unused-parameter",
+           "-fexcess-precision=standard", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
            "-o", OUT] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))

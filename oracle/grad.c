@@ -17,8 +17,14 @@
 void or_device_dparam(const or_card *card, int pol, double W, double L, double VTH0,
                       const double V[4], double ag0, const double *hist, int which,
                       double dY[16], double dbl[4]) {
+    or_device_dparam_h(card, pol, W, L, VTH0, V, ag0, hist, which, 1e-20, dY, dbl);
+}
+
+void or_device_dparam_h(const or_card *card, int pol, double W, double L, double VTH0,
+                        const double V[4], double ag0, const double *hist, int which, double rel_h,
+                        double dY[16], double dbl[4]) {
     double th = which == 0 ? W : (which == 1 ? L : VTH0);
-    double h = 1e-20 * fabs(th);
+    double h = rel_h * fabs(th);
     if (h == 0.0) h = 1e-30;
     double complex Wc = W, Lc = L, Vc = VTH0;
     if (which == 0) Wc = W + I * h;

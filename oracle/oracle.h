@@ -102,6 +102,18 @@ int or_assemble(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_
                 const int32_t *colour, const uint8_t *excl, const double *x, double ag0,
                 const double *hist, double *A, double *b);
 
+/* Colour replay (colour != NULL required) with the compute phase and each colour's
+ * devices spread over the OpenMP threads: the same bits as or_assemble's colour
+ * replay.  or_omp_threads: the number of threads it uses. */
+int or_assemble_omp(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                    int32_t n_vsrc, const int32_t *vsrc, const double *vsrc_volts,
+                    int32_t n_res, const int32_t *res, const double *res_g, const or_card *nmos,
+                    const or_card *pmos, const double *W, const double *L, const double *VTH0,
+                    const int32_t *row_ptr, const int32_t *col_idx, const int32_t *colour,
+                    const uint8_t *excl, const double *x, double ag0, const double *hist, double *A,
+                    double *b);
+int or_omp_threads(void);
+
 /* Per entry, the sum of |contribution| over devices (serial order): the scale of
  * the rounding difference between two accumulation orders. */
 int or_assemble_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term,
@@ -132,9 +144,14 @@ int or_vjp_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term, const 
                      const double *b_bar, double *W_mag, double *L_mag, double *VTH0_mag);
 
 /* Per-device local sensitivities d(Y, bl)/d(theta) by complex step, theta = 0 (W),
- * 1 (L), 2 (VTH0).  dY[16], dbl[4]. */
+ * 1 (L), 2 (VTH0).  dY[16], dbl[4].  The step is i * 1e-20 * |theta|; the _h form
+ * takes the relative step (two steps give two exact derivatives of the same rounded
+ * program, which differ only where that derivative is ill-conditioned). */
 void or_device_dparam(const or_card *card, int pol, double W, double L, double VTH0,
                       const double V[4], double ag0, const double *hist, int which,
                       double dY[16], double dbl[4]);
+void or_device_dparam_h(const or_card *card, int pol, double W, double L, double VTH0,
+                        const double V[4], double ag0, const double *hist, int which, double rel_h,
+                        double dY[16], double dbl[4]);
 
 #endif

@@ -56,11 +56,14 @@ def lib():
         _lib.or_stamp_map.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p]
         _lib.or_assemble.argtypes = [i32, i32, p, p, i32, p, p, i32, p, p, p, p, p, p, p, p, p, p, p, p,
                                      d, p, p, p]
+        _lib.or_assemble_omp.argtypes = _lib.or_assemble.argtypes
+        _lib.or_omp_threads.restype = C.c_int
         _lib.or_hubsum.restype = d
         _lib.or_hubsum.argtypes = [p, i64]
         _lib.or_vjp.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_vjp_magnitude.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_device_dparam.argtypes = [p, C.c_int, d, d, d, p, d, p, C.c_int, p, p]
+        _lib.or_device_dparam_h.argtypes = [p, C.c_int, d, d, d, p, d, p, C.c_int, d, p, p]
         _lib.or_elem_array.argtypes = [C.c_int, p, p, i64]
         _lib.or_assemble_magnitude.argtypes = [i32, i32, p, p, i32, p, p, i32, p, p, p, p, p, p, p, p,
                                                p, p, d, p, p, p]
@@ -126,13 +129,18 @@ def device_eval(cd: dict, pol: int, W: float, L: float, VTH0: float, V, ag0: flo
     return out
 
 
-def device_dparam(cd: dict, pol: int, W, L, VTH0, V, ag0=0.0, hist=None, which=0):
+def device_dparam(cd: dict, pol: int, W, L, VTH0, V, ag0=0.0, hist=None, which=0, rel_h=None):
+    """Complex-step d(Y, bl)/d(theta) of one device (relative step 1e-20 by default)."""
     c = card(cd)
     V = np.ascontiguousarray(V, dtype=np.float64)
     h = None if hist is None else np.ascontiguousarray(hist, dtype=np.float64)
     dY = np.zeros(16); dbl = np.zeros(4)
-    lib().or_device_dparam(C.byref(c), int(pol), float(W), float(L), float(VTH0), _ptr(V),
-                           float(ag0), _ptr(h), int(which), _ptr(dY), _ptr(dbl))
+    if rel_h is None:
+        lib().or_device_dparam(C.byref(c), int(pol), float(W), float(L), float(VTH0), _ptr(V),
+                               float(ag0), _ptr(h), int(which), _ptr(dY), _ptr(dbl))
+    else:
+        lib().or_device_dparam_h(C.byref(c), int(pol), float(W), float(L), float(VTH0), _ptr(V),
+                                 float(ag0), _ptr(h), int(which), float(rel_h), _ptr(dY), _ptr(dbl))
     return dY.reshape(4, 4), dbl
 
 
@@ -226,9 +234,11 @@ def stamp_map(circ, rp, ci, col, exclude: bool):
 
 
 def assemble(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=None, col=None,
-             exclude: bool = False, x=None, W=None, L=None, VTH0=None):
+             exclude: bool = False, x=None, W=None, L=None, VTH0=None, threads: bool = False):
     """A (CSR values) and b; col=None -> serial order, else colour replay; then the
-    linear part of a split netlist's series resistors, added once per entry."""
+    linear part of a split netlist's series resistors, added once per entry.
+    threads=True (colour replay only): the replay spread over the OpenMP threads
+    (or_assemble_omp), the same bits."""
     term = np.ascontiguousarray(circ.term, dtype=np.int32)
     pol = np.ascontiguousarray(circ.pol, dtype=np.int8)
     vs = np.ascontiguousarray(circ.vsrc, dtype=np.int32)
@@ -243,7 +253,10 @@ def assemble(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=None, col=No
     res, g = _resistors(circ)
     A = np.zeros(int(rp[-1])); b = np.zeros(circ.n_rows)
     cn, cp = card(nmos), card(pmos)
-    rc = lib().or_assemble(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), vs.shape[0], _ptr(vs),
+    if threads and col is None:
+        raise ValueError("the threaded assembly is a colour replay: give col")
+    fn = lib().or_assemble_omp if threads else lib().or_assemble
+    rc = fn(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), vs.shape[0], _ptr(vs),
                            _ptr(vv), res.shape[0], _ptr(res), _ptr(g), C.byref(cn), C.byref(cp),
                            _ptr(Wa), _ptr(La), _ptr(Va),
                            _ptr(rp), _ptr(ci), _ptr(colp), _ptr(excl), _ptr(xx), float(ag0),
@@ -251,6 +264,11 @@ def assemble(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=None, col=No
     if rc != 0:
         raise RuntimeError(f"or_assemble failed: {rc}")
     return A, b
+
+
+def omp_threads() -> int:
+    """Threads of the OpenMP colour replay."""
+    return int(lib().or_omp_threads())
 
 
 def assemble_magnitude(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, hist=None):

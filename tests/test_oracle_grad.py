@@ -58,3 +58,28 @@ def test_vjp_matches_directional_difference_of_assembly(orc, make):
         an = float(g @ d)
         scale = float(np.abs(g * d).sum())
         assert abs(fd - an) <= 1e-6 * scale, (name, fd, an)
+
+
+def test_random_netlist_devices_whose_gradient_rounding_decides(orc):
+    # The seeded random netlist of 600 FETs on 6 nodes holds degenerate devices.  Two
+    # of them have an L-sensitivity that exact complex-step derivatives of different
+    # step sizes disagree on beyond 1e-8 of the device's scale: device 315 (NMOS,
+    # drain and source on one node, gate and body grounded: vds = 0 exactly, so the
+    # smoothed Vdseff and Vdcv cancel to zero for every L and their L-derivatives are
+    # rounding residue) and device 383 (NMOS, only its source off ground: reverse
+    # mode with x2 = x3 = 0, deep in subthreshold, where the L-sensitivity is a
+    # difference of nearly equal terms).  Every other (device, parameter) pair agrees
+    # to 1e-9.  A second evaluation order (the GPU's tangent sweep) can only be held to
+    # this spread there, which the GPU adjoint test allows those two devices alone.
+    import gradspread
+    circ = G.draw_params(G.random_netlist(600, 6, 21), np.random.default_rng(31), G.W_CHAIN, G.L_CHAIN)
+    rp, ci = orc.pattern(circ)
+    Ab, bb = G.cotangents(len(ci), circ.n_rows, seed=50)
+    sp = gradspread.spread(orc, circ, rp, ci, Ab, bb, NC, PC)
+    bad = sorted(zip(*np.nonzero(sp > 1e-8)))
+    assert [(int(w), int(v)) for w, v in bad] == [(1, 315), (1, 383)]
+    assert list(circ.term[315]) == [5, 0, 5, 0] and circ.pol[315] == 1
+    assert list(circ.term[383]) == [0, 0, 3, 0] and circ.pol[383] == 1
+    assert sp[1, 315] > 1e-5 and sp[1, 383] > 1e-7
+    sp[1, 315] = sp[1, 383] = 0.0
+    assert sp.max() <= 1e-9

@@ -1,0 +1,163 @@
+"""Pins of the oracle's reordering scales and of its threaded colour replay (CPU).
+
+Every tolerance of the GPU parity tests outside bit-exactness is a multiple of two
+oracle scales: per entry of A and b, the sum over devices of |merged contribution|
+(the scale of the rounding difference between two accumulation orders,
+or_assemble_magnitude), and per device, the sum over its entries of
+|cotangent * d(entry)/d(parameter)| (the scale of a gradient summed in another
+order, or_vjp_magnitude).  Both are recomputed here from scratch, from one
+single-device evaluation at a time and this file's own merge and scatter, so that a
+wrong factor, a dropped term or a misplaced entry in either scale fails.  The
+threaded colour replay (the CPU baseline's all-core leg) must give the serial
+replay's bits."""
+import numpy as np
+import pytest
+
+from paper_2604_03079_amd import netgen as G
+
+NC, PC = G.default_card(1), G.default_card(-1)
+
+
+def cases():
+    rng = np.random.default_rng(61)
+    return [
+        ("chain50", G.workload(0)),
+        ("sram4x5", G.sram_case(4, 5, 3)),
+        ("opamp11", G.draw_params(G.opamp2(11), rng, G.W_OPAMP, G.L_OPAMP)),
+        ("random80x6", G.draw_params(G.random_netlist(80, 6, 21), rng, G.W_CHAIN, G.L_CHAIN)),
+        ("random60x7r", G.with_random_resistors(G.draw_params(G.random_netlist(60, 7, 5), rng, G.W_CHAIN,
+                                                              G.L_CHAIN), 30, 8)),
+        ("adder2r89", G.draw_params(G.split_nets(G.ripple_adder28(2), "all")[0], rng, G.W_CHAIN, G.L_CHAIN)),
+    ]
+
+
+CASES = cases()
+
+
+def slot_of(rp, ci, r, c):
+    lo, hi = int(rp[r]), int(rp[r + 1])
+    k = lo + int(np.searchsorted(ci[lo:hi], c))
+    assert k < hi and ci[k] == c
+    return k
+
+
+def volts(circ, v):
+    return np.array([0.0 if n == 0 else circ.x[n - 1] for n in circ.term[v]])
+
+
+@pytest.mark.parametrize("name,circ", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("ag0", [0.0, 1e12])
+def test_assemble_magnitude_is_the_sum_of_absolute_contributions(orc, name, circ, ag0):
+    rp, ci = orc.pattern(circ)
+    rng = np.random.default_rng(3)
+    hist = rng.normal(0, 1e-5, (circ.n_dev, 4)) if ag0 else None
+    mA, mb = orc.assemble_magnitude(circ, rp, ci, NC, PC, ag0, hist)
+    A = np.zeros(len(ci))
+    b = np.zeros(circ.n_rows)
+    # voltage sources: unit entries between each terminal node and the branch row,
+    # the source voltage in the branch row (exact values, counted with their size)
+    for j, ((pos, neg), volt) in enumerate(zip(circ.vsrc, circ.vsrc_volts)):
+        br = circ.n_nodes - 1 + j
+        for nd in (pos, neg):
+            if nd != 0:
+                A[slot_of(rp, ci, nd - 1, br)] = 1.0
+                A[slot_of(rp, ci, br, nd - 1)] = 1.0
+        b[br] = abs(volt)
+    for v in range(circ.n_dev):
+        Y, bl, _, _ = orc.device_eval(NC if circ.pol[v] > 0 else PC, int(circ.pol[v]), circ.W[v], circ.L[v],
+                                      circ.VTH0[v], volts(circ, v), ag0, None if hist is None else hist[v])
+        t4 = [int(n) for n in circ.term[v]]
+        # merge: per node pair, the left fold of its Y entries in (t, u) row-major order
+        mergedA, mergedB = {}, {}
+        for t in range(4):
+            if t4[t] == 0:
+                continue
+            for u in range(4):
+                if t4[u] == 0:
+                    continue
+                key = (t4[t], t4[u])
+                mergedA[key] = Y[t, u] if key not in mergedA else mergedA[key] + Y[t, u]
+            mergedB[t4[t]] = bl[t] if t4[t] not in mergedB else mergedB[t4[t]] + bl[t]
+        for (p, q), m in mergedA.items():
+            s = slot_of(rp, ci, p - 1, q - 1)
+            A[s] = A[s] + abs(m)
+        for p, m in mergedB.items():
+            b[p - 1] = b[p - 1] + abs(m)
+    # series resistors: |g| per stamp, summed per entry in resistor order, added once
+    if circ.n_res:
+        lin = np.zeros(len(ci))
+        touched = np.zeros(len(ci), bool)
+        for (p, q), g in zip(circ.res, circ.res_g):
+            for r, c in ((p, p), (p, q), (q, p), (q, q)):
+                if r == 0 or c == 0:
+                    continue
+                s = slot_of(rp, ci, r - 1, c - 1)
+                lin[s] = lin[s] + abs(g)
+                touched[s] = True
+        A[touched] = A[touched] + lin[touched]
+    assert np.array_equal(mA, A)
+    assert np.array_equal(mb, b)
+    # and it bounds the serial-vs-replay difference it is meant to scale
+    col, _, _ = orc.colour(circ, True)
+    As, bs = orc.assemble(circ, rp, ci, NC, PC, ag0, hist)
+    Ar, br = orc.assemble(circ, rp, ci, NC, PC, ag0, hist, col=col, exclude=True)
+    assert np.all(np.abs(As - Ar) <= 1e-12 * mA)
+    assert np.all(np.abs(bs - br) <= 1e-12 * mb)
+
+
+@pytest.mark.parametrize("name,circ", CASES, ids=[c[0] for c in CASES])
+def test_vjp_magnitude_is_the_sum_of_absolute_terms(orc, name, circ):
+    rp, ci = orc.pattern(circ)
+    Ab, bb = G.cotangents(len(ci), circ.n_rows, seed=50)
+    mags = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb, magnitude=True)
+    grads = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb)
+    for which in range(3):
+        m = np.zeros(circ.n_dev)
+        g = np.zeros(circ.n_dev)
+        for v in range(circ.n_dev):
+            dY, dbl = orc.device_dparam(NC if circ.pol[v] > 0 else PC, int(circ.pol[v]), circ.W[v], circ.L[v],
+                                        circ.VTH0[v], volts(circ, v), 1e12, None, which)
+            t4 = [int(n) for n in circ.term[v]]
+            acc = accm = 0.0
+            for t in range(4):
+                if t4[t] == 0:
+                    continue
+                for u in range(4):
+                    if t4[u] == 0:
+                        continue
+                    term = Ab[slot_of(rp, ci, t4[t] - 1, t4[u] - 1)] * dY[t, u]
+                    acc += term
+                    accm += abs(term)
+                term = bb[t4[t] - 1] * dbl[t]
+                acc += term
+                accm += abs(term)
+            m[v], g[v] = accm, acc
+        assert np.array_equal(mags[which], m)
+        assert np.array_equal(grads[which], g)
+        assert np.all(np.abs(grads[which]) <= mags[which])
+
+
+THREAD_CASES = [
+    ("chain50_excl", lambda: G.workload(0), True),
+    ("chain50_strict", lambda: G.workload(0), False),
+    ("chain20k", lambda: G.chain_case(10_000, 3), True),
+    ("sram24x32", lambda: G.sram_case(24, 32, 4), True),
+    ("adder8", lambda: G.adder_case(8, 9), False),
+    ("adder8r89", lambda: G.adder_case(8, 9, "all"), True),
+    ("random600x6r", lambda: G.with_random_resistors(
+        G.draw_params(G.random_netlist(600, 6, 21), np.random.default_rng(31), G.W_CHAIN, G.L_CHAIN), 300, 9), True),
+]
+
+
+@pytest.mark.parametrize("name,make,exclude", THREAD_CASES, ids=[c[0] for c in THREAD_CASES])
+def test_threaded_replay_equals_serial_replay(orc, name, make, exclude):
+    circ = make()
+    rp, ci = orc.pattern(circ)
+    col, _, _ = orc.colour(circ, exclude)
+    hist = np.random.default_rng(2).normal(0, 1e-5, (circ.n_dev, 4))
+    for h in (None, hist):
+        A0, b0 = orc.assemble(circ, rp, ci, NC, PC, 1e12, h, col=col, exclude=exclude)
+        A1, b1 = orc.assemble(circ, rp, ci, NC, PC, 1e12, h, col=col, exclude=exclude, threads=True)
+        assert np.array_equal(A0.view(np.int64), A1.view(np.int64))
+        assert np.array_equal(b0.view(np.int64), b1.view(np.int64))
+    assert orc.omp_threads() >= 1
