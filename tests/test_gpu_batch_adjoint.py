@@ -175,21 +175,22 @@ def test_vjp_matches_oracle_complex_step(torch_dev, orc, name, make):
     mag = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb, magnitude=True)
     say(f"case vjp {name}")
     got, _ = gpu_vjp(torch_dev, circ, Ab, bb)
-    # 1e-8 of the sensitivity scale.  The random netlist also holds near-singular
-    # bias points, where the oracle's complex step and the kernel's tangent sweep
-    # round differently: with drain and source on one node (vds = 0 exactly) the
-    # smoothed Vdseff and Vdcv cancel to zero for every W and L, so their L and W
-    # sensitivities are rounding residue (allowed 1e-3 of the scale), and the other
-    # devices of that netlist get 1e-6
-    tol = np.full(circ.n_dev, 1e-8)
+    # 1e-8 of the sensitivity scale for every device and parameter, except where the
+    # oracle's own derivative is decided by rounding: there (the two degenerate
+    # devices of the random netlist named by test_oracle_grad) exact complex-step
+    # derivatives of different step sizes already disagree, and the bound is ten
+    # times that spread, measured here on the CPU
+    tol = np.full((3, circ.n_dev), 1e-8)
     if name.startswith("random"):
-        tol[:] = 1e-6
-        tol[circ.term[:, 0] == circ.term[:, 2]] = 1e-3
-    for g, r, m, what in zip(got, ref, mag, ("W", "L", "VTH0")):
+        import gradspread
+        sp = gradspread.spread(orc, circ, rp, ci, Ab, bb, NC, PC)
+        tol = np.maximum(tol, 10.0 * sp)
+        assert [(int(w), int(v)) for w, v in zip(*np.nonzero(tol > 1e-8))] == [(1, 315), (1, 383)]
+    for k, (g, r, m, what) in enumerate(zip(got, ref, mag, ("W", "L", "VTH0"))):
         err = np.abs(g - r) / (m + 1e-300)
-        assert np.all(np.abs(g - r) <= tol * m + 1e-300), (what, err.max())
-        if name.startswith("random"):
-            assert np.sum(err > 1e-8) <= 2, what
+        worst = np.argsort(err)[-3:][::-1]
+        say(f"  {what}: worst devices {[(int(v), float(err[v]), float(tol[k, v])) for v in worst]}")
+        assert np.all(np.abs(g - r) <= tol[k] * m + 1e-300), (what, err.max())
 
 
 def test_vjp_full_size_chain10k(torch_dev, orc):
