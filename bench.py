@@ -54,6 +54,14 @@ def device_tensors(torch, circ, dev):
     return t(circ.W), t(circ.L), t(circ.VTH0), t(circ.x)
 
 
+def release(torch, *handles):
+    """Finish the device work, then destroy library handles now, while the HIP runtime
+    (and a profiler attached to it) is alive, instead of at interpreter exit."""
+    torch.cuda.synchronize()
+    for h in handles:
+        h.close()
+
+
 def time_graph(torch, fn, steps, warmup):
     """Capture fn() (one NR step) in a graph; replay warmup times, then time steps."""
     fn()
@@ -108,7 +116,20 @@ def time_cold(torch, fn, steps, flush_mib=512):
 
 
 def algorithmic_counts(circ, exclude=True):
-    """FP64 operations and bytes one step needs (counted on the oracle's definition)."""
+    """FP64 operations and bytes of one step of the coloured method (counted on the
+    oracle's definition of the step).
+
+    ops: the oracle's operation counter over model M (+, -, *, /, sqrt each one),
+    plus the merge adds of devices with coinciding terminals, one add per load-add
+    stamp and the hub sums' adds.
+    method_bytes: the fused coloured method's own HBM traffic per step, itemised per
+    device as the survey's measurement section lists it: W, L, VTH0 and the polarity
+    (25 B), four terminal indices (16 B), x read once (8 B per row), one 4-byte stamp
+    code per matrix slot-write, an 8-byte store per matrix slot-write, an 8-byte read
+    per load-add (slot-writes beyond the first writer of each entry), the same store
+    and read terms for the RHS writes, and every hub contribution staged and read
+    back (16 B).
+    floor_bytes: inputs once and outputs once (context only)."""
     from oracle import oracle as O
     from paper_2604_03079_amd import netgen as G
     rp, ci = O.pattern(circ)
@@ -125,8 +146,8 @@ def algorithmic_counts(circ, exclude=True):
         merges += len(nz) * len(nz) - k * k + len(nz) - k
     add_ops = int((sflag == 0).sum() + (bflag == 0).sum())
     hub_sizes = {}
-    for s in slot[sflag == 2]:
-        hub_sizes[("A", int(s))] = hub_sizes.get(("A", int(s)), 0) + 1
+    for s_ in slot[sflag == 2]:
+        hub_sizes[("A", int(s_))] = hub_sizes.get(("A", int(s_)), 0) + 1
     for r in brow[bflag == 2]:
         hub_sizes[("b", int(r))] = hub_sizes.get(("b", int(r)), 0) + 1
     hub_ops = sum(m - 1 for m in hub_sizes.values())
@@ -134,38 +155,90 @@ def algorithmic_counts(circ, exclude=True):
     n = circ.n_dev
     nslot = int((sflag >= 0).sum())
     nbrow = int((bflag >= 0).sum())
-    # bytes the step cannot avoid: per device W, L, VTH0 (24), polarity (1) and
-    # terminals (16); x read once (8 per row); one 4-byte stamp code per local entry;
-    # A and b written once (8 per nonzero and per row)
-    byts = n * (24 + 1 + 16) + 8 * circ.n_rows + 4 * (nslot + nbrow) + 8 * len(ci) + 8 * circ.n_rows
-    return dict(ops=int(ops), model_ops=int(model_ops), bytes=int(byts), n_colors=int(C))
+    slots_written = int(np.unique(slot[sflag >= 0]).size)
+    rows_written = int(np.unique(brow[bflag >= 0]).size)
+    hub_contrib = int((sflag == 2).sum() + (bflag == 2).sum())
+    items = dict(params=25 * n, terminals=16 * n, x=8 * circ.n_rows, stamp_codes=4 * nslot,
+                 A_stores=8 * nslot, A_load_add_reads=8 * (nslot - slots_written),
+                 b_stores=8 * nbrow, b_load_add_reads=8 * (nbrow - rows_written), hub_staging=16 * hub_contrib)
+    floor = n * (24 + 1 + 16) + 8 * circ.n_rows + 4 * (nslot + nbrow) + 8 * len(ci) + 8 * circ.n_rows
+    return dict(ops=int(ops), model_ops=int(model_ops), method_bytes=int(sum(items.values())),
+                method_bytes_items=items, floor_bytes=int(floor), n_colors=int(C), n_dev=int(n))
 
 
-def cpu_baseline(circ, budget_s=12.0):
-    """The oracle (serial, colour replay) on the host: devices per second."""
+def add_counts(parts):
+    """Sum of algorithmic_counts over the circuits of a batch."""
+    out = dict(ops=0, model_ops=0, method_bytes=0, floor_bytes=0, n_dev=0, n_colors=0, method_bytes_items={})
+    for p in parts:
+        for k in ("ops", "model_ops", "method_bytes", "floor_bytes", "n_dev"):
+            out[k] += p[k]
+        out["n_colors"] = max(out["n_colors"], p["n_colors"])
+        for k, v in p["method_bytes_items"].items():
+            out["method_bytes_items"][k] = out["method_bytes_items"].get(k, 0) + v
+    return out
+
+
+def roofline(counts, kernel_ms, traffic, kernel):
+    """Roofline of one step against its binding resource: t_FP64 = ops / FP64 lane-op
+    peak, t_HBM = method bytes / HBM peak; the larger is the bound, frac = that time
+    over the measured kernel time."""
+    secs = kernel_ms * 1e-3
+    t_fp64 = counts["ops"] / PEAK_FP64_OPS
+    t_hbm = counts["method_bytes"] / PEAK_HBM
+    common = dict(traffic=traffic, t_fp64_us=round(t_fp64 * 1e6, 3), t_hbm_us=round(t_hbm * 1e6, 3),
+                  kernel_avg_us=round(kernel_ms * 1e3, 3), kernel=kernel,
+                  algorithmic_ops_per_launch=counts["ops"], method_bytes_per_launch=counts["method_bytes"],
+                  method_bytes_per_device=round(counts["method_bytes"] / counts["n_dev"], 2),
+                  fp64_op_frac=round(t_fp64 / secs, 5), hbm_frac=round(t_hbm / secs, 5),
+                  floor_bytes_per_launch_context=counts["floor_bytes"])
+    if t_hbm >= t_fp64:
+        ach = counts["method_bytes"] / secs / 1e9
+        return dict(bound="hbm", achieved=round(ach, 2), peak=PEAK_HBM / 1e9, unit="GB/s",
+                    frac=round(t_hbm / secs, 5), **common)
+    ach = counts["ops"] / secs / 1e12
+    return dict(bound="alu", achieved=round(ach, 4), peak=round(PEAK_FP64_OPS / 1e12, 2),
+                unit="T FP64 op/s", frac=round(t_fp64 / secs, 5), **common)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline(circ, budget_s=10.0):
+    """The oracle on the host, same inputs: the serial colour replay on one core (the
+    paper's single-thread loadsingle form), then the colour replay spread over every
+    OpenMP thread (the paper's ColorFused on its CPU), which must give the same bits.
+    Devices per second of each; `value` is the all-core leg."""
     from oracle import oracle as O
     from paper_2604_03079_amd import netgen as G
     rp, ci = O.pattern(circ)
     col, _, _ = O.colour(circ, True)
     nc, pc = G.default_card(1), G.default_card(-1)
-    it = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        O.assemble(circ, rp, ci, nc, pc, AG0, col=col, exclude=True)
-        it += 1
-    dt = time.perf_counter() - t0
-    model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return dict(value=round(circ.n_dev * it / dt / 1e6, 4), unit="M devices/s", cores=1,
-                kind="oracle", host=f"{model}, {os.cpu_count()} logical CPUs visible",
-                sample=f"{it} NR steps of the full {circ.n_dev}-device chain, serial colour-replay "
-                       f"oracle (C, -O2), {dt:.1f} s")
+    legs = {}
+    outs = {}
+    for key, threads in (("serial_one_core", False), ("colour_replay_all_threads", True)):
+        it = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s or it < 3:
+            outs[key] = O.assemble(circ, rp, ci, nc, pc, AG0, col=col, exclude=True, threads=threads)
+            it += 1
+        dt = time.perf_counter() - t0
+        legs[key] = dict(value=round(circ.n_dev * it / dt / 1e6, 4), unit="M devices/s",
+                         cores=O.omp_threads() if threads else 1, steps=it, seconds=round(dt, 2))
+    same = all(np.array_equal(a.view(np.int64), b.view(np.int64))
+               for a, b in zip(outs["serial_one_core"], outs["colour_replay_all_threads"]))
+    main = legs["colour_replay_all_threads"]
+    return dict(value=main["value"], unit="M devices/s", cores=main["cores"], kind="oracle",
+                host=f"{cpu_model()}, {os.cpu_count()} logical CPUs visible",
+                sample=f"full {circ.n_dev}-device chain, colour replay (C, -O2): {main['steps']} steps on "
+                       f"{main['cores']} OpenMP threads; serial leg {legs['serial_one_core']['steps']} steps on 1 core",
+                legs=legs, threaded_bits_equal_serial=bool(same))
 
 
 def traffic_from_profiles(kernel_hash: str, key: str):
@@ -359,7 +432,14 @@ def bench_batch(torch, CS, G, dev):
     b = torch.empty(B.n_rows, dtype=torch.float64, device=dev)
     best = autotune.tune(B, W, L, V, x, AG0, A, b, cache_path=None, reps=5, log=log)
     ms_b, _ = time_graph(torch, lambda: B.eval_stamp(x, AG0, None, A, b), 20, 3)
+    ms_e = time_eager(torch, lambda: B.eval_stamp(x, AG0, None, A, b), 20, 3)
     B.check()
+    counts = add_counts([algorithmic_counts(c) for c in circs])
+    roof = roofline(counts, ms_e, traffic_from_profiles(kernel_sources_hash(), "batch512"),
+                    "k_region (one launch per batched step)" if best["schedule"] == "region"
+                    else "k_persistent_* (one launch per batched step)")
+    log(f"  batch 512 roofline: {roof['bound']} {roof['achieved']} {roof['unit']} = {roof['frac']:.3f} of peak "
+        f"(t_FP64 {roof['t_fp64_us']} us, t_HBM {roof['t_hbm_us']} us, kernel {roof['kernel_avg_us']} us)")
     # adjoint of the batched step: cotangents N(0,1) on every circuit's A and b
     Ab, bb = G.cotangents(B.nnz, B.n_rows, seed=50)
     Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
@@ -371,8 +451,9 @@ def bench_batch(torch, CS, G, dev):
     log(f"  batch 512: batched {ms_b:.3f} ms ({B.n_dev / ms_b / 1e3:.1f} M dev/s), "
         f"per-circuit launches {ms_p:.3f} ms ({B.n_dev / ms_p / 1e3:.1f} M dev/s), setup {setup_s:.1f} s")
     return dict(n_circuits=len(circs), n_dev=B.n_dev, n_rows=B.n_rows, nnz=B.nnz,
-                max_colors=B.info()["max_colors"], tuned=best,
-                batched=dict(ms_per_step=round(ms_b, 4), value=round(B.n_dev / ms_b / 1e3, 2)),
+                max_colors=B.info()["max_colors"], tuned=best, roofline=roof,
+                batched=dict(ms_per_step=round(ms_b, 4), value=round(B.n_dev / ms_b / 1e3, 2),
+                             stream_ms_per_step=round(ms_e, 4)),
                 per_circuit_launches=dict(ms_per_step=round(ms_p, 4), value=round(B.n_dev / ms_p / 1e3, 2)),
                 speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2),
                 adjoint=dict(ms_per_step=round(ms_a, 4), adjoint_over_forward=round(ms_a / ms_b, 3)))
@@ -548,7 +629,6 @@ def main():
     W, L, V, x = device_tensors(torch, circ, dev)
 
     variants = {}
-    graphs = []
     todo = (("persistent", True), ("persistent", False), ("per_kernel", True),
             ("buffered", True), ("region", True), ("atomic", True))
     if args.only:
@@ -563,7 +643,7 @@ def main():
         steps = args.steps if variant == args.variant and coop else max(10, args.steps // 4)
         ms, g = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, args.warmup)
         c.check()
-        graphs.append((c, g, A, b))
+        del g
         if variant == args.variant and coop:
             kernel_ms = time_eager(torch, lambda: c.eval_stamp(x, AG0, None, A, b, variant), steps, args.warmup)
             log(f"  {variant} kernel launches back to back: {kernel_ms * 1e3:.2f} us")
@@ -582,13 +662,13 @@ def main():
             variants[name]["cold_ms_per_step"] = round(cold_ms, 5)
             variants[name]["cold_value"] = round(circ.n_dev / cold_ms / 1e3, 2)
         log(f"  {name:28s} {ms * 1e3:9.2f} us/step  {circ.n_dev / ms / 1e3:9.1f} M devices/s")
+        release(torch, c)
 
     main_v = variants[args.variant]
     # a step is one launch sequence of the variant; K steps run either as K replays of
     # a captured graph or as K launches back to back on the stream: the faster counts
     launch = "graph replay" if main_v["ms_per_step"] <= kernel_ms else "stream, back to back"
     ms = min(main_v["ms_per_step"], round(kernel_ms, 5))
-    ksecs = kernel_ms * 1e-3
     result = {
         "metric": "M devices eval+stamp/s per NR iter (colored vs atomic); batched & fwd+adjoint",
         "value": round(circ.n_dev / ms / 1e3, 2),
@@ -606,19 +686,8 @@ def main():
                    "n_rows": int(main_v["info"]["n_rows"]), "nnz": int(main_v["info"]["nnz"]),
                    "n_colors": counts["n_colors"], "conflict_rule": "rails_excluded",
                    "variant": args.variant, "ag0": AG0, "launch": launch},
-        "roofline": {
-            "bound": "alu",
-            "achieved": round(counts["ops"] / ksecs / 1e12, 4),
-            "peak": round(PEAK_FP64_OPS / 1e12, 2),
-            "unit": "TFLOP/s",
-            "frac": round(counts["ops"] / ksecs / PEAK_FP64_OPS, 5),
-            "traffic": traffic_from_profiles(khash, f"{args.variant}_chain100k"),
-            "algorithmic_ops_per_launch": counts["ops"],
-            "algorithmic_bytes_per_launch": counts["bytes"],
-            "hbm_frac_at_algorithmic_bytes": round(counts["bytes"] / ksecs / PEAK_HBM, 5),
-            "kernel_avg_us": round(kernel_ms * 1e3, 3),
-            "kernel": KERNEL_OF.get(args.variant, args.variant),
-        },
+        "roofline": roofline(counts, kernel_ms, traffic_from_profiles(khash, f"{args.variant}_chain100k"),
+                             KERNEL_OF.get(args.variant, args.variant)),
         "variants": variants,
         "kernel_sources": khash,
     }
@@ -658,6 +727,11 @@ def main():
         result["cpu_baseline"] = cpu_baseline(circ)
         log(f"  cpu oracle: {result['cpu_baseline']['value']} M devices/s")
     print(json.dumps(result), flush=True)
+    # every captured graph and handle is gone before the interpreter exits
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    CS._close_all()
 
 
 if __name__ == "__main__":
