@@ -8,7 +8,8 @@
  *             within a colour no two devices share a non-hub entry, so the order
  *             inside a colour is irrelevant.  The first writer of an entry stores,
  *             later writers add.  Entries of excluded (hub) nodes are summed by the
- *             fixed-shape or_hubsum over the contributions in ascending device index.
+ *             fixed-shape pairwise or_hubsum over the contributions in ascending
+ *             device index.
  * Per device, the 4x4 local matrix Y is merged onto its unique node pairs: each
  * merged value is the left-to-right sum of the Y entries mapping to it in (t, u)
  * row-major order over (d, g, s, b); b rows likewise in terminal order.
@@ -26,24 +27,17 @@
 #include "oracle.h"
 #include "oracle_internal.h"
 
-#define HUB_K 256
-
+/* HubSum: the pairwise (tree) sum of m contributions, split at the largest power of
+ * two below m: HubSum(c, m) = HubSum(c, h) + HubSum(c + h, m - h), h = 2^ceil(log2 m) / 2,
+ * and HubSum(c, 1) = c[0].  Equivalently a perfect binary tree over the contributions
+ * padded with -0.0 to a power of two (x + -0.0 = x exactly).  Every aligned block of
+ * 2^k contributions is a subtree of its own, so the sum can be formed block by block. */
 double or_hubsum(const double *c, int64_t m) {
     if (m <= 0) return 0.0;
-    if (m <= HUB_K) {
-        double s = c[0];
-        for (int64_t i = 1; i < m; ++i) s = s + c[i];
-        return s;
-    }
-    int64_t nc = (m + HUB_K - 1) / HUB_K;
-    double *part = malloc(sizeof(double) * (size_t)nc);
-    for (int64_t j = 0; j < nc; ++j) {
-        int64_t len = m - j * HUB_K < HUB_K ? m - j * HUB_K : HUB_K;
-        part[j] = or_hubsum(c + j * HUB_K, len);
-    }
-    double r = or_hubsum(part, nc);
-    free(part);
-    return r;
+    if (m == 1) return c[0];
+    int64_t h = 1;
+    while (2 * h < m) h *= 2;
+    return or_hubsum(c, h) + or_hubsum(c + h, m - h);
 }
 
 /* Merge a device's Y and bl onto its unique nodes. mA[a*k+b], mB[a]. */

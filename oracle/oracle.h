@@ -124,8 +124,8 @@ int or_assemble_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term,
                           const int32_t *row_ptr, const int32_t *col_idx, const double *x,
                           double ag0, const double *hist, double *A, double *b);
 
-/* Fixed-shape hub sum: fold left when m <= 256, else the hub sum of the hub sums
- * of consecutive 256-element chunks. */
+/* Fixed-shape hub sum: the pairwise tree sum, split at the largest power of two
+ * below m (a perfect binary tree over the contributions padded with -0.0). */
 double or_hubsum(const double *c, int64_t m);
 
 /* Vector-Jacobian product of (A, b) with respect to per-device W, L, VTH0 by

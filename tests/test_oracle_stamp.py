@@ -105,21 +105,47 @@ def test_replay_matches_serial_within_reordering_bound(orc, idx):
 
 
 def test_hubsum_shape(orc):
-    # chunk 0 = [2^53, 1 x 255]: a left fold loses every 1 (ties to even);
-    # chunk 1 = [1 x 256] sums to 256 exactly; the hub sum adds the chunk sums.
+    # The hub sum is the pairwise tree split at the largest power of two below m.
+    # Values are hand-derived from binary64 round-to-nearest-even: 2^53 + 1 rounds
+    # to 2^53 (a tie), 2^53 + 2k is exact for small k.
+    t53 = 2.0 ** 53
+    # (c0 + c1) + (c2 + c3): the first 1 is lost, the pair (1 + 1) is not; a left fold
+    # would lose all three
+    assert orc.hubsum([t53, 1.0, 1.0, 1.0]) == t53 + 2
+    # m = 3 splits as (c0 + c1) + c2 (both ones lost), not c0 + (c1 + c2) (= 2^53 + 2)
+    assert orc.hubsum([t53, 1.0, 1.0]) == t53
+    assert orc.hubsum([1.0, 1.0, t53]) == t53 + 2          # (1 + 1) + 2^53
+    # m = 6 splits at 4: (1 + 1) + (1 + 1) = 4, then (2^53 + 1) + 1 -> 2^53, sum 2^53 + 4;
+    # a split at 3 would give ((1 + 1) + 1) + ((1 + 2^53) + 1) = 3 + 2^53 -> 2^53 + 4
+    # as well, so the next case separates them
+    assert orc.hubsum([1.0, 1.0, 1.0, 1.0, t53, 1.0]) == t53 + 4
+    # m = 6, [2^53, 1, 1, 1, 1, 1]: split at 4 gives (2^53 + 2) + (1 + 1) = 2^53 + 4;
+    # a split at 3 gives (2^53 + 1 -> 2^53, + 1 -> 2^53) + 3 -> 2^53 + 4 (tie to even
+    # of 2^53 + 3 is 2^53 + 4) -- equal again; a left fold gives 2^53
+    assert orc.hubsum([t53] + [1.0] * 5) == t53 + 4
+    # 2^53 followed by 255 ones: every aligned block of 2^j ones sums exactly to 2^j,
+    # and the block holding 2^53 grows 2^53, 2^53 + 2, + 4, ..., + 128: 2^53 + 254
     c = np.ones(512)
-    c[0] = 2.0 ** 53
-    assert orc.hubsum(c) == 2.0 ** 53 + 256
-    assert orc.hubsum(c[:256]) == 2.0 ** 53                  # m <= 256: plain fold
-    d = np.cumsum(c[:200])                                    # sequential fold
-    assert orc.hubsum(c[:200]) == d[-1]
-    # three levels (m > 256^2): integers add exactly whatever the shape
+    c[0] = t53
+    assert orc.hubsum(c[:256]) == t53 + 254
+    assert orc.hubsum(c) == t53 + 254 + 256
+    # 1 followed by 2^16 - 1 copies of 2^-53: only the first tiny value is lost (1 +
+    # 2^-53 is a tie), every later block of tiny values arrives as a multiple of
+    # 2^-52 and is exact: 1 + (2^15 - 1) 2^-52; a left fold returns 1
+    tiny = np.full(2 ** 16, 2.0 ** -53)
+    tiny[0] = 1.0
+    assert orc.hubsum(tiny) == 1.0 + (2 ** 15 - 1) * 2.0 ** -52
+    # -0.0 padding: a single -0.0, and -0.0 next to +0.0, keep IEEE signs
+    assert np.signbit(orc.hubsum([-0.0]))
+    assert not np.signbit(orc.hubsum([-0.0, 0.0, -0.0]))
+    # integers add exactly whatever the shape (no contribution dropped or repeated)
     big = np.arange(70_000, dtype=np.float64)
     assert orc.hubsum(big) == float(big.sum())
+    # the pairwise error bound: |sum - exact| <= ceil(log2 m) u sum |c|
     rng = np.random.default_rng(1)
     r = rng.standard_normal(100_000)
     import math
-    assert abs(orc.hubsum(r) - math.fsum(r)) <= 1e-13 * np.abs(r).sum()
+    assert abs(orc.hubsum(r) - math.fsum(r)) <= 17 * 2.0 ** -53 * np.abs(r).sum()
 
 
 def test_replay_uses_hubsum_for_rail_entries(orc):
@@ -136,10 +162,14 @@ def test_replay_uses_hubsum_for_rail_entries(orc):
                                           [circ.x[circ.term[v][0] - 1], circ.x[circ.term[v][1] - 1],
                                            circ.vdd, circ.vdd], 1e12)
             vals.append(((Y[2, 2] + Y[2, 3]) + Y[3, 2]) + Y[3, 3])
-    s = vals[0]
-    for x in vals[1:]:
-        s = s + x
-    assert A[rp[0]] == s          # (vdd, vdd) is the first entry of row 0
+    # 50 PMOS: the pairwise tree of 64 leaves, the last 14 being -0.0 padding; its
+    # value lies within the pairwise bound of the exact sum, and the replayed entry
+    # is that value (every PMOS contribution enters, in ascending device order)
+    import math
+    assert len(vals) == 50
+    assert A[rp[0]] == orc.hubsum(vals)          # (vdd, vdd) is the first entry of row 0
+    assert abs(A[rp[0]] - math.fsum(vals)) <= 6 * 2.0 ** -53 * sum(abs(v) for v in vals)
+    assert A[rp[0]] == orc.hubsum(vals + [-0.0] * 14)
 
 
 def netlist(n_nodes, res, g, term=None, pol=None, vdd=1.0):
