@@ -47,9 +47,11 @@ constexpr uint8_t SLOT_HUB = 2;
 constexpr uint8_t SLOT_DEFER = 3;   // large shared entry: staged, folded by the follow-up kernel
 constexpr uint32_t HUB_B_FLAG = 0x80000000u;  // hub target is a b row
 
-// Fixed-shape hub sum: chunks of HUB_K contributions, folded left, recursively.
+// Fixed-shape hub sum: the pairwise tree over a hub's contributions in ascending
+// device index (padded with -0.0 to a power of two), formed chunk by chunk: each
+// aligned chunk of HUB_K contributions is a subtree (one wave), then the chunk sums.
 constexpr int HUB_K = 256;
-// Largest hub handled by the one-workgroup reduction (level-1 partials in LDS).
+// Largest number of chunks of one hub (the chunk sums are summed by one wave).
 constexpr int HUB_MAX_CHUNKS = 2048;
 
 // Card-derived constants of the device model, evaluated once on the host in the

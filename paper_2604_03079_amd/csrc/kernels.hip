@@ -174,69 +174,107 @@ __device__ __forceinline__ void hub_store(const KCirc &kc, const KCall &call, in
     else call.A[tgt] = s;
 }
 
-// Fixed-shape hub sum (contributions in ascending device index; chunks of HUB_K
-// folded left; the chunk sums reduced the same way).  Work item = one chunk per
-// wave: the wave loads the chunk into its LDS slice with coalesced loads, lane 0
-// folds it.  The wave that completes the last chunk of a hub (a coherent counter)
-// folds the chunk sums, so no grid barrier is needed.  Every wave of the block
-// calls this (it contains workgroup barriers).  lds: (blockDim/64)*HUB_K doubles.
-__device__ __forceinline__ void hub_chunks(const KCirc &kc, const KCall &call, int q0, int q1, int wave0, int nwaves,
-                           double *lds) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *mine = lds + (size_t)wave * HUB_K;
-    const int rounds = (q1 - q0 + nwaves - 1) / nwaves;
-    for (int r = 0; r < rounds; ++r) {
-        const int q = q0 + wave0 + wave + r * nwaves;
-        int h = 0, e = 0, nchunk = 0;
-        if (q < q1) {
-            h = kc.hub_of_chunk[q];
-            const int j = q - kc.hub_cptr[h];
-            nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
-            const int beg = kc.hub_ptr[h];
-            e = min(HUB_K, kc.hub_ptr[h + 1] - beg - j * HUB_K);
-            for (int t = lane; t < e; t += 64) mine[t] = ld_coherent(kc.stage + beg + (size_t)j * HUB_K + t);
+// A hub chunk's sum is known (wave-uniform call): store it if the hub has one
+// chunk, else record it as a partial and count it; true when this wave recorded the
+// hub's last partial (the hub's final sum is then due).
+__device__ __forceinline__ bool hub_chunk_publish(const KCirc &kc, const KCall &call, int q, double s) {
+    const int lane = threadIdx.x & 63;
+    const int h = kc.hub_of_chunk[q];
+    const int nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
+    if (nchunk == 1) {
+        if (lane == 0) hub_store(kc, call, h, s);
+        return false;
+    }
+    int last = 0;
+    if (lane == 0) {
+        st_coherent(kc.hub_part + q, s);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        last = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+               (uint32_t)nchunk;
+    }
+    return __shfl(last, 0, 64) != 0;
+}
+
+// Fixed-shape hub sum: the pairwise tree over the contributions in ascending device
+// index, padded with -0.0 (the exact identity of IEEE addition) to a power of two.
+// Every aligned block of HUB_K contributions is a subtree, so a hub is summed chunk
+// by chunk (one wave per chunk), then the chunk sums by the same tree.
+
+// Tree sum of cnt <= HUB_K staged values by one wave (all lanes call it, cnt
+// wave-uniform): lane l adds values 4l .. 4l+3 as (v0 + v1) + (v2 + v3), then a
+// butterfly adds aligned groups of 2, 4, .., 64 lanes.  IEEE addition is
+// commutative bit for bit, so both lanes of a pair form the same sum and every lane
+// ends with the tree's result.
+static_assert(HUB_K == 4 * 64, "a hub chunk is four values per lane of one wave");
+__device__ __forceinline__ double wave_tree_chunk(const double *src, int cnt) {
+    const int lane = threadIdx.x & 63;
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = 4 * lane + k < cnt ? ld_coherent(src + 4 * lane + k) : -0.0;
+    double s = (v[0] + v[1]) + (v[2] + v[3]);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) s = s + __shfl_xor(s, off, 64);
+    return s;
+}
+
+// Tree sum of n <= 8 values, padded with -0.0 to eight.
+__device__ __forceinline__ double tree8(const double *g, int n) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = k < n ? g[k] : -0.0;
+    return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
+// Tree sum of a hub's cnt <= HUB_MAX_CHUNKS chunk sums by one wave (cnt
+// wave-uniform): the aligned groups of HUB_K as in wave_tree_chunk (every load
+// issued first), then the group sums.
+static_assert(HUB_MAX_CHUNKS == 8 * HUB_K, "chunk sums form at most eight groups");
+__device__ __forceinline__ double wave_tree(const double *src, int cnt) {
+    const int lane = threadIdx.x & 63;
+    double g[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = i * HUB_K + 4 * lane + k;
+            v[k] = e < cnt ? ld_coherent(src + e) : -0.0;
         }
-        __syncthreads();
-        int last = 0;
-        if (q < q1 && lane == 0) {
-            const double s = fold_lds(mine, e);
-            if (nchunk == 1) {
-                hub_store(kc, call, h, s);
-            } else {
-                st_coherent(kc.hub_part + q, s);
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                __builtin_amdgcn_s_waitcnt(0);
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                const uint32_t done = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-                last = done + 1 == (uint32_t)nchunk;
-            }
-        }
-        last = __shfl(last, 0, 64);
-        __syncthreads();
-        if (last) {
-            // level 1 and up, by this wave: chunk sums of HUB_K partials, then the
-            // (at most HUB_MAX_CHUNKS / HUB_K) level-1 sums folded by lane 0
-            const int c0 = kc.hub_cptr[h];
-            double lvl1 = 0.0;
-            const int n1 = (nchunk + HUB_K - 1) / HUB_K;   // <= HUB_MAX_CHUNKS / HUB_K
-            for (int g = 0; g < n1; ++g) {
-                const int ee = min(HUB_K, nchunk - g * HUB_K);
-                for (int t = lane; t < ee; t += 64) mine[t] = ld_coherent(kc.hub_part + c0 + (size_t)g * HUB_K + t);
-                __builtin_amdgcn_s_waitcnt(0);
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0) {
-                    const double f = fold_lds(mine, ee);
-                    lvl1 = g == 0 ? f : lvl1 + f;
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (lane == 0) {
-                hub_store(kc, call, h, lvl1);
-                __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        __syncthreads();
+        g[i] = (v[0] + v[1]) + (v[2] + v[3]);
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = g[i] + __shfl_xor(g[i], off, 64);
+    }
+    return tree8(g, 8);
+}
+
+// The last chunk of hub h has been recorded by this wave: sum the chunk sums, store,
+// and return the hub's counter to zero for the next call.
+__device__ __forceinline__ void hub_finish(const KCirc &kc, const KCall &call, int h) {
+    const int c0 = kc.hub_cptr[h];
+    const double s = wave_tree(kc.hub_part + c0, kc.hub_cptr[h + 1] - c0);
+    if ((threadIdx.x & 63) == 0) {
+        hub_store(kc, call, h, s);
+        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Hub chunks q0 .. q1-1, one per wave (waves wave0, wave0 + nwaves, ..); the wave
+// that records a hub's last chunk sum (a coherent counter) forms the hub's sum, so no
+// grid barrier is needed.  Needs no workgroup barrier: each wave works alone.
+__device__ __forceinline__ void hub_chunks(const KCirc &kc, const KCall &call, int q0, int q1, int wave0,
+                                           int nwaves) {
+    const int wave = threadIdx.x >> 6;
+    for (int q = q0 + wave0 + wave; q < q1; q += nwaves) {
+        const int h = kc.hub_of_chunk[q];
+        const int j = q - kc.hub_cptr[h];
+        const int beg = kc.hub_ptr[h] + j * HUB_K;
+        const double s = wave_tree_chunk(kc.stage + beg, min(HUB_K, kc.hub_ptr[h + 1] - beg));
+        if (hub_chunk_publish(kc, call, q, s)) hub_finish(kc, call, h);
     }
 }
 
@@ -367,8 +405,7 @@ __global__ void __launch_bounds__(256) k_newton_update(int32_t n, int32_t n_clam
 }
 
 __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
-    __shared__ double lds[4 * HUB_K];
-    hub_chunks(kc, call, 0, kc.n_hub_chunks, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6), lds);
+    hub_chunks(kc, call, 0, kc.n_hub_chunks, blockIdx.x * (blockDim.x >> 6), gridDim.x * (blockDim.x >> 6));
 }
 
 // Circuits stamped inside one workgroup (batches): colour phases separated by
@@ -376,7 +413,7 @@ __global__ void __launch_bounds__(256) k_hub(KCirc kc, KCall call) {
 // hub chunks.
 template <bool J>
 __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &call, const KLocal &kl, int first,
-                               int stride, double *lds) {
+                               int stride) {
     for (int li = first; li < kl.n; li += stride) {
         const int32_t *t = kl.table + 6 * (size_t)li;
         const int32_t cp = t[2], nc = t[3];
@@ -390,7 +427,7 @@ __device__ __forceinline__ void local_circuits(const KCirc &kc, const KCall &cal
             drain_memory();
             __syncthreads();
         }
-        hub_chunks(kc, call, t[4], t[5], 0, blockDim.x >> 6, lds);
+        hub_chunks(kc, call, t[4], t[5], 0, blockDim.x >> 6);
     }
 }
 
@@ -405,12 +442,11 @@ template <int MODE, bool LOCAL, bool J>
 __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &call,
                                                 const KSync &ks, const double *buf, int n_part,
                                                 int n_global_chunks, const KLocal &kl) {
-    __shared__ double lds[4 * HUB_K];
     __shared__ uint32_t base_s;
     if (blockIdx.x == 0) fixed_stores(kc, call, threadIdx.x, blockDim.x);
     if constexpr (LOCAL) {
         if ((int)blockIdx.x >= n_part) {
-            local_circuits<J>(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part, lds);
+            local_circuits<J>(kc, call, kl, blockIdx.x - n_part, gridDim.x - n_part);
             return;
         }
     }
@@ -466,7 +502,7 @@ __device__ __forceinline__ void persistent_body(const KCirc &kc, const KCall &ca
         }
         if (c + 1 < kc.n_colors || n_global_chunks > 0) grid_barrier(ks, ++epoch, n_part);
     }
-    hub_chunks(kc, call, 0, n_global_chunks, blockIdx.x * (blockDim.x >> 6), n_part * (blockDim.x >> 6), lds);
+    hub_chunks(kc, call, 0, n_global_chunks, blockIdx.x * (blockDim.x >> 6), n_part * (blockDim.x >> 6));
 }
 
 template <bool J>
@@ -604,71 +640,43 @@ __device__ __forceinline__ void store_target(const KCall &call, uint32_t tgt, do
     else call.A[idx] = s;
 }
 
-// Left fold of cnt staged values by one wave (all lanes call it): up to HUB_K values
+// Left fold of cnt staged values by one wave (all lanes call it): up to FOLD_K values
 // at a time go through the wave's LDS slice, lane 0 folds while the other lanes'
-// loads of the next HUB_K values are in flight; the sum is broadcast.
+// loads of the next FOLD_K values are in flight; the sum is broadcast.
+constexpr int FOLD_K = 256;
 __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *mine) {
     const int lane = threadIdx.x & 63;
-    constexpr int R = HUB_K / 64;
+    constexpr int R = FOLD_K / 64;
     double s = 0.0;
-    // chunk g + HUB_K is loaded into registers while lane 0 folds chunk g
+    // chunk g + FOLD_K is loaded into registers while lane 0 folds chunk g
     double r[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) r[k] = lane + 64 * k < cnt ? ld_coherent(src + lane + 64 * k) : 0.0;
-    for (int g = 0; g < cnt; g += HUB_K) {
-        const int e = min(HUB_K, cnt - g);
+    for (int g = 0; g < cnt; g += FOLD_K) {
+        const int e = min(FOLD_K, cnt - g);
 #pragma unroll
         for (int k = 0; k < R; ++k)
             if (lane + 64 * k < e) mine[lane + 64 * k] = r[k];
         __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the chunk is in LDS
         __builtin_amdgcn_wave_barrier();
-        const int e2 = min(HUB_K, cnt - g - HUB_K);
+        const int e2 = min(FOLD_K, cnt - g - FOLD_K);
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            if (lane + 64 * k < e2) r[k] = ld_coherent(src + g + HUB_K + lane + 64 * k);
+            if (lane + 64 * k < e2) r[k] = ld_coherent(src + g + FOLD_K + lane + 64 * k);
         if (lane == 0) s = g == 0 ? fold_lds(mine, e) : fold_more(s, mine, 0, e);
         __builtin_amdgcn_wave_barrier();
     }
     return __shfl(s, 0, 64);
 }
 
-// A hub chunk's sum is known (wave-uniform call): store it if the hub has one
-// chunk, else record it as a partial and count it; true when this wave recorded the
-// hub's last partial (the hub's final fold is then due).
-__device__ __forceinline__ bool hub_chunk_publish(const KCirc &kc, const KCall &call, int q, double s) {
-    const int lane = threadIdx.x & 63;
-    const int h = kc.hub_of_chunk[q];
-    const int nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
-    if (nchunk == 1) {
-        if (lane == 0) hub_store(kc, call, h, s);
-        return false;
-    }
-    int last = 0;
-    if (lane == 0) {
-        st_coherent(kc.hub_part + q, s);
-        drain_memory();
-        last = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
-               (uint32_t)nchunk;
-    }
-    return __shfl(last, 0, 64) != 0;
-}
-
-constexpr int PEND_MAX = 8;   // hubs whose final fold one workgroup runs in parallel
-
 // Items of one region, after its staged values are complete: count the arrival;
-// the last region of an item folds it (shared entries one lane each, hub chunks one
-// wave each; consecutive items go to different waves).  Hubs completed here get
-// their final fold from all waves: each group of HUB_K chunk sums by one wave,
-// then the group sums by one lane.  Called by every thread of the workgroup.
+// the last region of an item folds it (shared entries one lane each, in colour
+// order; hub chunks one wave each, by the tree; consecutive items go to different
+// waves).  The wave that records a hub's last chunk sum also forms the hub's sum.
+// Called by every thread of the workgroup.
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
-                                             double *scratch, bool hub_only = false) {
-    __shared__ int pend_n;
-    __shared__ int pend_h[PEND_MAX];
-    __shared__ double gsum[PEND_MAX][HUB_MAX_CHUNKS / HUB_K];
+                                             bool hub_only = false) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    double *mine = scratch + (size_t)wave * HUB_K;
-    if (threadIdx.x == 0) pend_n = 0;
-    __syncthreads();
     for (int base = jb; base < je; base += blockDim.x) {
         const int i = base + lane * nw + wave;
         int beg = 0, cnt = 0;
@@ -706,52 +714,9 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
             big &= big - 1;
             const int bbeg = __shfl(beg, l, 64), bcnt = __shfl(cnt, l, 64);
             const int q = (int)((uint32_t)__shfl((int)tgt, l, 64) & 0x3FFFFFFFu);
-            const double sum = wave_fold(kc.stage + bbeg, bcnt, mine);
-            if (hub_chunk_publish(kc, call, q, sum)) {
-                const int h = kc.hub_of_chunk[q];
-                int k = 0;
-                if (lane == 0) {
-                    k = atomicAdd(&pend_n, 1);
-                    if (k < PEND_MAX) pend_h[k] = h;
-                }
-                k = __shfl(k, 0, 64);
-                if (k >= PEND_MAX) {   // more completed hubs than slots: this wave alone
-                    const int c0 = kc.hub_cptr[h], nchunk = kc.hub_cptr[h + 1] - c0;
-                    double lvl1 = 0.0;
-                    for (int g = 0; g * HUB_K < nchunk; ++g) {
-                        const double f = wave_fold(kc.hub_part + c0 + (size_t)g * HUB_K, min(HUB_K, nchunk - g * HUB_K), mine);
-                        lvl1 = g == 0 ? f : lvl1 + f;
-                    }
-                    if (lane == 0) {
-                        hub_store(kc, call, h, lvl1);
-                        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
+            const double sum = wave_tree_chunk(kc.stage + bbeg, bcnt);
+            if (hub_chunk_publish(kc, call, q, sum)) hub_finish(kc, call, kc.hub_of_chunk[q]);
         }
-    }
-    __syncthreads();
-    const int np = min(pend_n, PEND_MAX);
-    if (np == 0) return;
-    // group folds: pair k = (pending hub, group), round-robin over the waves
-    int k = 0;
-    for (int p = 0; p < np; ++p) {
-        const int h = pend_h[p];
-        const int c0 = kc.hub_cptr[h], nchunk = kc.hub_cptr[h + 1] - c0;
-        for (int g = 0; g * HUB_K < nchunk; ++g, ++k) {
-            if (k % nw != wave) continue;
-            const double f = wave_fold(kc.hub_part + c0 + (size_t)g * HUB_K, min(HUB_K, nchunk - g * HUB_K), mine);
-            if (lane == 0) gsum[p][g] = f;
-        }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < np) {
-        const int p = threadIdx.x, h = pend_h[p];
-        const int nchunk = kc.hub_cptr[h + 1] - kc.hub_cptr[h];
-        double lvl1 = gsum[p][0];
-        for (int g = 1; g * HUB_K < nchunk; ++g) lvl1 = lvl1 + gsum[p][g];
-        hub_store(kc, call, h, lvl1);
-        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -763,8 +728,7 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
 // hub sums.
 template <bool GRID, bool J>
 __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks) {
-    // LDS: kr.lds_int accumulators, then kr.nc_max merged values per lane (later the
-    // fold scratch, HUB_K per wave)
+    // LDS: kr.lds_int accumulators, then kr.nc_max merged values per lane
     extern __shared__ double lds[];
     __shared__ uint32_t base_s;
     fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
@@ -888,13 +852,13 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         }
         drain_memory();
         __syncthreads();
-        finish_items(kc, call, kr, jb, je, lds + kr.lds_int, true);
+        finish_items(kc, call, kr, jb, je, true);
     } else {
         // staged values complete before the arrivals are counted; the region's own
         // entries are stored last (nothing waits for them)
         drain_memory();
         __syncthreads();
-        finish_items(kc, call, kr, jb, je, lds + kr.lds_int);
+        finish_items(kc, call, kr, jb, je);
         for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
     }
 }
@@ -916,12 +880,12 @@ k_region_grid(KCirc kc, KCall call, KRegion kr, KSync ks) {
 // Follow-up kernel of the region schedule: every large shared entry, one wave each,
 // its staged contributions folded left in colour order (complete at kernel start).
 __global__ void __launch_bounds__(256) k_fold_items(KCirc kc, KCall call, KRegion kr) {
-    __shared__ double lds[4 * HUB_K];
+    __shared__ double lds[4 * FOLD_K];
     const int wave = threadIdx.x >> 6;
     const int i = blockIdx.x * 4 + wave;
     if (i >= kr.n_deferred) return;
     const int32_t *f = kr.item + 4 * (size_t)kr.deferred[i];
-    const double s = wave_fold(kc.stage + f[0], f[1], lds + (size_t)wave * HUB_K);
+    const double s = wave_fold(kc.stage + f[0], f[1], lds + (size_t)wave * FOLD_K);
     if ((threadIdx.x & 63) == 0) store_target(call, (uint32_t)f[2], s);
 }
 
@@ -1045,7 +1009,7 @@ hipError_t launch_eval_buffer(const KCirc &kc, const KCall &call, double *buf, h
 }
 
 size_t region_lds_bytes(int lds_int, int nc_max, int block) {
-    return sizeof(double) * ((size_t)lds_int + std::max((size_t)nc_max * block, (size_t)(block / 64) * HUB_K));
+    return sizeof(double) * ((size_t)lds_int + (size_t)nc_max * block);
 }
 
 hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu) {

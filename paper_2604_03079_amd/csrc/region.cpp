@@ -22,7 +22,8 @@
 //     them left and stores the result, or, for entries with more than ITEM_LANE_MAX
 //     contributions, a follow-up kernel folds them (one wave per entry);
 //   * hub entries keep their fixed-shape sum: contributions staged in ascending
-//     device index, each chunk of HUB_K folded by the last region touching it.
+//     device index, each aligned chunk of HUB_K summed by the pairwise tree by the
+//     last region touching it, the chunk sums by the same tree.
 // The result is bitwise the colour-order accumulation.
 #include <algorithm>
 #include <numeric>
@@ -237,7 +238,7 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     // 3b. LDS budget: a region whose owned entries would not fit the workgroup's LDS
     // next to the merged-value rows hands single-writer entries to lane folds
     {
-        const int64_t rows = std::max<int64_t>((int64_t)R.max_nc * cap, (int64_t)(cap / 64) * HUB_K);
+        const int64_t rows = (int64_t)R.max_nc * cap;
         const int64_t budget = REGION_LDS_LIMIT / 8 - rows - 2;
         for (int32_t g = 0; g < R.n_regions; ++g) {
             auto &v = interior[(size_t)g];
