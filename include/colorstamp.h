@@ -176,6 +176,24 @@ cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const d
 cs_status cs_eval_stamp(cs_circuit *c, cs_variant variant, const double *x, double ag0,
                         const double *hist, double *A_val, double *b, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): cs_eval_stamp with the
+ * region schedule (CS_COLOR_REGION, same bits), calling no hipMalloc, hipFree or
+ * other allocating routine.  Its scratch memory (the staging array of shared-entry
+ * and hub contributions, the hub chunk sums and the arrival counters) lives in one
+ * library-wide device array of CS_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends, instead of the circuit's own buffers; its counters are cleared by a
+ * kernel at the start of every call.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race, so the caller
+ * orders them.  Requires the region tables on the device for the circuit's current
+ * block size, which one cs_eval_stamp with CS_COLOR_REGION uploads (CS_ESTATE
+ * otherwise).  CS_ENOTSUP when the circuit's scratch exceeds the array (the
+ * message gives both sizes).  Arguments, ownership and other errors as in
+ * cs_eval_stamp. */
+#define CS_NOALLOC_SCRATCH_BYTES (16u << 20)
+cs_status cs_eval_stamp_noalloc(cs_circuit *c, const double *x, double ag0, const double *hist, double *A_val,
+                                double *b, void *stream);
+
 /* Newton-Raphson loop around cs_eval_stamp (Introduction: each iteration evaluates
  * the devices at x, stamps the linearised MNA system and solves it; the paper solves
  * with KLU, Benchmark 2).  Per iteration on `stream`: cs_eval_stamp(variant) into

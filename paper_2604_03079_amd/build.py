@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_lib", "libcolorstamp.so")
 SOURCES = ["kernels.hip", "adjoint.hip", "setup.cpp", "region.cpp", "api.cpp", "batch.cpp", "sparse_lu.cpp",
-           "newton.cpp", "solve.hip", "tune.cpp"]
+           "newton.cpp", "solve.hip", "tune.cpp", "noalloc.hip"]
 # the Newton loop's sparse refactorisation and triangular solves
 LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 

@@ -36,7 +36,7 @@ EXPORTS = (
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
     "cs_batch_get_region_plan", "cs_batch_eval_stamp", "cs_batch_vjp", "cs_batch_check",
-    "cs_batch_newton", "cs_batch_tune",
+    "cs_batch_newton", "cs_batch_tune", "cs_eval_stamp_noalloc",
     "cs_last_error",
 )
 
@@ -84,6 +84,7 @@ def lib():
             "cs_set_models": [p, p, p],
             "cs_set_params": [p, p, p, p, p],
             "cs_eval_stamp": [p, C.c_int, p, d, p, p, p, p],
+            "cs_eval_stamp_noalloc": [p, p, d, p, p, p, p],
             "cs_vjp": [p, p, d, p, p, p, p, p, p, p],
             "cs_newton": [p, C.c_int, i32, p, d, p, i32, d, d, p, p, p, p, p, p, p],
             "cs_set_newton_options": [p, i32],
@@ -370,6 +371,15 @@ class Circuit:
                                    (hist, 4 * self.n_dev, "hist"), (A, self.nnz, "A"), (b, self.n_rows, "b"))
         _check(lib().cs_eval_stamp(self._h, VARIANTS[variant], px, float(ag0), ph, pA, pb, _stream(stream)),
                "cs_eval_stamp")
+        return A, b
+
+    def eval_stamp_noalloc(self, x, ag0: float, A, b, hist=None, stream=None):
+        """cs_eval_stamp_noalloc: the region schedule into the caller's A and b with the
+        library's per-GPU scratch array (no allocation, by this binding either)."""
+        px, ph, pA, pb = _dev_ptrs(getattr(self, "_device", None), (x, self.n_rows, "x"),
+                                   (hist, 4 * self.n_dev, "hist"), (A, self.nnz, "A"), (b, self.n_rows, "b"))
+        _check(lib().cs_eval_stamp_noalloc(self._h, px, float(ag0), ph, pA, pb, _stream(stream)),
+               "cs_eval_stamp_noalloc")
         return A, b
 
     def vjp(self, x, ag0: float, A_bar, b_bar, hist=None, stream=None):

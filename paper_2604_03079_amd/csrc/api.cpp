@@ -15,6 +15,39 @@ namespace cs {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
+KCirc make_kcirc(cs_circuit *c) {
+    KCirc k{};
+    const HostCircuit &h = c->h;
+    k.n = h.n_dev;
+    k.n_colors = h.n_colors;
+    k.nc_max = h.max_nc;
+    k.term = c->d_term.p;
+    k.pol = c->d_pol.p;
+    k.par = c->d_par.p;
+    k.code = c->d_code.p;
+    k.acode = c->d_acode.p;
+    k.perm = c->d_perm.p;
+    k.cptr = c->d_cptr.p;
+    k.n_fixA = (int32_t)h.fixA_idx.size();
+    k.n_fixB = (int32_t)h.fixB_idx.size();
+    k.fixA_idx = c->d_fixA_idx.p;
+    k.fixA_val = c->d_fixA_val.p;
+    k.fixB_idx = c->d_fixB_idx.p;
+    k.fixB_val = c->d_fixB_val.p;
+    k.n_hub = (int32_t)h.hub_target.size();
+    k.hub_ptr = c->d_hub_ptr.p;
+    k.hub_target = c->d_hub_target.p;
+    k.stage = c->d_stage.p;
+    k.n_hub_chunks = (int32_t)h.hub_of_chunk.size();
+    k.hub_cptr = c->d_hub_cptr.p;
+    k.hub_of_chunk = c->d_hub_of_chunk.p;
+    k.hub_part = c->d_hub_part.p;
+    k.hub_count = c->d_hub_count.p;
+    k.card[0] = c->card[0];
+    k.card[1] = c->card[1];
+    return k;
+}
+
 }  // namespace cs
 
 using namespace cs;
@@ -107,39 +140,6 @@ cs_status upload_circuit(cs_circuit *c) {
     c->grid = 0;
     c->params_set = false;
     return CS_OK;
-}
-
-KCirc make_kcirc(cs_circuit *c) {
-    KCirc k{};
-    const HostCircuit &h = c->h;
-    k.n = h.n_dev;
-    k.n_colors = h.n_colors;
-    k.nc_max = h.max_nc;
-    k.term = c->d_term.p;
-    k.pol = c->d_pol.p;
-    k.par = c->d_par.p;
-    k.code = c->d_code.p;
-    k.acode = c->d_acode.p;
-    k.perm = c->d_perm.p;
-    k.cptr = c->d_cptr.p;
-    k.n_fixA = (int32_t)h.fixA_idx.size();
-    k.n_fixB = (int32_t)h.fixB_idx.size();
-    k.fixA_idx = c->d_fixA_idx.p;
-    k.fixA_val = c->d_fixA_val.p;
-    k.fixB_idx = c->d_fixB_idx.p;
-    k.fixB_val = c->d_fixB_val.p;
-    k.n_hub = (int32_t)h.hub_target.size();
-    k.hub_ptr = c->d_hub_ptr.p;
-    k.hub_target = c->d_hub_target.p;
-    k.stage = c->d_stage.p;
-    k.n_hub_chunks = (int32_t)h.hub_of_chunk.size();
-    k.hub_cptr = c->d_hub_cptr.p;
-    k.hub_of_chunk = c->d_hub_of_chunk.p;
-    k.hub_part = c->d_hub_part.p;
-    k.hub_count = c->d_hub_count.p;
-    k.card[0] = c->card[0];
-    k.card[1] = c->card[1];
-    return k;
 }
 
 // Grid of the persistent kernel for the current configuration.  phase_only: the

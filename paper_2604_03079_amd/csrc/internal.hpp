@@ -211,6 +211,11 @@ struct cs_circuit {
     ~cs_circuit() { cs::destroy_newton(newton); }
 };
 
+namespace cs {
+// Kernel view of a single circuit's device copies (colour-major).
+KCirc make_kcirc(cs_circuit *c);
+}  // namespace cs
+
 struct cs_batch {
     std::vector<cs_circuit *> circ;
     std::vector<int64_t> dev_off, row_off, nnz_off;   // n+1 each

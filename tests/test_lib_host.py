@@ -141,6 +141,11 @@ def test_error_paths():
     st = L.cs_eval_stamp(c.handle, 0, ctypes.c_void_p(1), 0.0, None, ctypes.c_void_p(1),
                          ctypes.c_void_p(1), None)
     assert st == -4
+    # the no-allocation form checks the same state first
+    assert L.cs_eval_stamp_noalloc(c.handle, ctypes.c_void_p(1), 0.0, None, ctypes.c_void_p(1),
+                                   ctypes.c_void_p(1), None) == -4
+    assert L.cs_eval_stamp_noalloc(None, ctypes.c_void_p(1), 0.0, None, ctypes.c_void_p(1),
+                                   ctypes.c_void_p(1), None) == -1
     assert L.cs_circuit_create(3, 1, None, None, 0, None, None, ctypes.byref(ctypes.c_void_p())) == -1
     bad_card = CS.make_card(G.default_card(1))
     bad_card.size = 3
