@@ -57,7 +57,7 @@ constexpr int HUB_MAX_CHUNKS = 2048;
 // Card-derived constants of the device model, evaluated once on the host in the
 // model's operation order.
 struct DevCard {
-    double VT, COXE, LT, LA, SQPHIS, VBM, CDEP0_SQPHIS, COXE_KS, TWO_VT, FOUR_DELTA,
+    double VT, COXE, LT, LA, SQPHIS, VBM, NCDEP, INV_TOXE, COXE_KS, TWO_VT, FOUR_DELTA,
         FOUR_DELTA1_VBM, VBI_M_PHIS, K3_TOXE_PHIS, TWO_WINT, TWO_LINT, TWO_VSAT;
     double phis, k1, k2, eta0, nfactor, cdsc, voff, u0, ua, ub, uc, toxe, delta, delta1,
         dvt0, dvt1, dsub, w0, lambda_l, a0, cgdo;

@@ -12,11 +12,13 @@
 // built with -ffp-contract=off), so a serial CPU evaluation in the same order gives
 // the same bits.  Partial derivatives w.r.t. the three frame voltages travel with
 // each value ("Dual3"):
-//   a*b -> (ab, a_i b + a b_i);  a/b -> q = a/b, q_i = (a_i - q b_i)/b;
-//   c/b -> q = c/b, q_i = (-(q b_i))/b;  sqrt(a) -> s, s_i = (0.5 a_i)/s;
+//   a*b -> (ab, a_i b + a b_i);  a/b -> r = 1/b, q = a r, q_i = (a_i - q b_i) r;
+//   c/b -> r = 1/b, q = c r, q_i = (-(q b_i)) r;  sqrt(a) -> s, h = 0.5/s, s_i = a_i h;
 //   exp(a) -> e, e_i = e a_i;  softplus(a) -> sp, sp_i = sigma(a) a_i;
-//   c*a and a/c scale all four components; a +- c changes the value only;
+//   c*a scales all four components; a +- c changes the value only;
 //   c - a negates the partials.
+// One division per quotient: an FP64 division is a multi-instruction sequence on
+// gfx950 (reciprocal estimate, Newton steps, scaling and fix-up), a product is one.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -162,28 +164,27 @@ template <class S, class C>
 __device__ __forceinline__ Dual3T<S> scale(C c, Dual3T<S> a) {
     return {c * a.v, c * a.d0, c * a.d1, c * a.d2};
 }
-template <class S, class C>
-__device__ __forceinline__ Dual3T<S> over_c(Dual3T<S> a, C c) {
-    return {a.v / c, a.d0 / c, a.d1 / c, a.d2 / c};
-}
 template <class S>
 __device__ __forceinline__ Dual3T<S> operator*(Dual3T<S> a, Dual3T<S> b) {
     return {a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
 }
 template <class S>
 __device__ __forceinline__ Dual3T<S> operator/(Dual3T<S> a, Dual3T<S> b) {
-    const S q = a.v / b.v;
-    return {q, (a.d0 - q * b.d0) / b.v, (a.d1 - q * b.d1) / b.v, (a.d2 - q * b.d2) / b.v};
+    const S r = 1.0 / b.v;
+    const S q = a.v * r;
+    return {q, (a.d0 - q * b.d0) * r, (a.d1 - q * b.d1) * r, (a.d2 - q * b.d2) * r};
 }
 template <class S, class C>
 __device__ __forceinline__ Dual3T<S> c_over(C c, Dual3T<S> b) {
-    const S q = c / b.v;
-    return {q, (-(q * b.d0)) / b.v, (-(q * b.d1)) / b.v, (-(q * b.d2)) / b.v};
+    const S r = 1.0 / b.v;
+    const S q = c * r;
+    return {q, (-(q * b.d0)) * r, (-(q * b.d1)) * r, (-(q * b.d2)) * r};
 }
 template <class S>
 __device__ __forceinline__ Dual3T<S> dsqrt(Dual3T<S> a) {
     const S s = gsqrt(a.v);
-    return {s, (0.5 * a.d0) / s, (0.5 * a.d1) / s, (0.5 * a.d2) / s};
+    const S h = 0.5 / s;
+    return {s, a.d0 * h, a.d1 * h, a.d2 * h};
 }
 template <class S>
 __device__ __forceinline__ Dual3T<S> dexp(Dual3T<S> a) {
@@ -288,9 +289,8 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     const D Vth = (plus_c(scale(cd.k1, minus_c(sqPs, cd.SQPHIS)), sd.vth_s) - scale(cd.k2, Vbseff))
                   - scale(cd.eta0 * sd.theta_dibl, X1);
     // subthreshold swing factor
-    const D Cdep = c_over(cd.CDEP0_SQPHIS, sqPs);
-    const D n = plus_c(plus_c(over_c(scale(cd.nfactor, Cdep), cd.COXE), 1.0),
-                       (cd.cdsc * sd.theta_sce) / cd.COXE);
+    // (the constant factors of the Cdep term are the card constant NCDEP)
+    const D n = plus_c(plus_c(c_over(cd.NCDEP, sqPs), 1.0), (cd.cdsc * sd.theta_sce) / cd.COXE);
     const D nvt = scale(cd.VT, n);
     const D Vgst = X2 - Vth;
     // unified effective gate overdrive
@@ -300,7 +300,7 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     const D den6 = plus_c(scale(cd.COXE_KS, n) * ex6, 0.5);
     const D Vgsteff = num6 / den6;
     // mobility
-    const D Ee = over_c(Vgsteff + scale(2.0, Vth), cd.toxe);
+    const D Ee = scale(cd.INV_TOXE, Vgsteff + scale(2.0, Vth));
     const D mden = plus_c(plus_c(scale(cd.uc, Vbseff), cd.ua) * Ee, 1.0) + scale(cd.ub, Ee * Ee);
     const D mu = c_over(cd.u0, mden);
     // saturation

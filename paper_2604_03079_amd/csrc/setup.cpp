@@ -414,7 +414,8 @@ DevCard derive_card(const cs_model_card &c) {
     d.LA = 2.0 * std::sqrt(c.xj * XDEP0);
     d.SQPHIS = std::sqrt(c.phis);
     d.VBM = 0.95 * c.phis;
-    d.CDEP0_SQPHIS = CDEP0 * d.SQPHIS;
+    d.NCDEP = (c.nfactor * (CDEP0 * d.SQPHIS)) / d.COXE;
+    d.INV_TOXE = 1.0 / c.toxe;
     d.COXE_KS = d.COXE * KS;
     d.TWO_VT = 2.0 * d.VT;
     d.FOUR_DELTA = 4.0 * c.delta;
