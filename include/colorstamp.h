@@ -294,14 +294,15 @@ cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *m
  * positions p < n_dev:
  *   perm[p]      device index;               phase[p]   LDS phase of the device;
  *   code[j*n_dev + p] (j < 20): bits 31..30 = 0 LDS add, 1 LDS store, 2 staged,
- *                3 unused or read by a lane fold; bits 29..0 = LDS slot or staging
- *                index;
- *   rtab[10*r ...] first position, NMOS count, PMOS count (NMOS lanes first, then
- *                PMOS), phases, owned-entry range, item range, lane-fold range;
+ *                3 unused or read by a lane fold or a local hub chunk; bits 29..0 =
+ *                LDS slot or staging index;
+ *   rtab[12*r ...] first position, NMOS count, PMOS count (NMOS lanes first, then
+ *                PMOS), phases, owned-entry range, item range, lane-fold range,
+ *                local hub part range (cs_get_region_hubs);
  *   interior[i]  target of owned entry i (bits 31..30 = 0 A slot, 1 b row), LDS slot =
  *                i - range start;
  *   links[]      item ids per region;
- *   item[4*i ...] first staged index, count, target (kind 0 A, 1 b, 2 hub chunk),
+ *   item[4*i ...] first staged index, count, target (kind 0 A, 1 b, 2 hub part),
  *                number of contributing regions (0: an entry with more than 8
  *                contributions, folded by the follow-up kernel of the schedule);
  *   fold[3*i ...] target (as for interior), first index in fold_src, writer count;
@@ -311,6 +312,20 @@ cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *m
 cs_status cs_get_region_plan(const cs_circuit *c, int32_t *perm, uint16_t *phase, int32_t *code,
                              int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item,
                              int32_t *fold, int32_t *fold_src);
+
+/* Hub tables of the region plan (any table pointer may be NULL).  The schedule sums a
+ * hub entry (reading of the conflict rule with excluded rails, Methodology) by the
+ * pairwise tree over its contributions in ascending device index, in parts: aligned
+ * chunks of 32 contributions (subtrees of that tree), then the tree over the parts.
+ * A part whose contributions all come from one region is summed by that region: its
+ * k-th such part occupies the 32 LDS slots after the region's owned entries and
+ * 32 k before (code tag 1, slot r = contribution r of the part; unused slots keep
+ * their -0.0 start).  A part spanning regions, or one that would not fit the
+ * region's LDS, is an item (kind 2) over its staged contributions.  A follow-up
+ * kernel of the schedule sums each hub's parts.  counts[2]: local parts, hubs;
+ * hfold[i]: part index of local part i (rtab fields 10, 11 give each region's
+ * range); part_ptr[hubs + 1]: part ranges per hub. */
+cs_status cs_get_region_hubs(const cs_circuit *c, int64_t *counts, int32_t *hfold, int32_t *part_ptr);
 
 /* Read and clear the device error word of the last bounded waits (synchronises the
  * stream).  Returns CS_EDOMAIN if a barrier wait ran out of its spin budget. */
@@ -362,6 +377,7 @@ cs_status cs_batch_get_region_info(const cs_batch *b, int32_t *n_regions, int32_
 cs_status cs_batch_get_region_plan(const cs_batch *b, int32_t *perm, uint16_t *phase, int32_t *code,
                                    int32_t *rtab, int32_t *interior, int32_t *links, int32_t *item,
                                    int32_t *fold, int32_t *fold_src);
+cs_status cs_batch_get_region_hubs(const cs_batch *b, int64_t *counts, int32_t *hfold, int32_t *part_ptr);
 /* A launch configuration of cs_batch_eval_stamp (see cs_batch_set_launch and
  * cs_batch_set_schedule) and its measured time. */
 typedef struct {

@@ -36,7 +36,8 @@ EXPORTS = (
     "cs_batch_layout", "cs_batch_set_params", "cs_batch_set_launch", "cs_batch_set_schedule",
     "cs_batch_get_info", "cs_batch_plan_regions", "cs_batch_get_region_info",
     "cs_batch_get_region_plan", "cs_batch_eval_stamp", "cs_batch_vjp", "cs_batch_check",
-    "cs_batch_newton", "cs_batch_tune", "cs_eval_stamp_noalloc",
+    "cs_batch_newton", "cs_batch_tune", "cs_eval_stamp_noalloc", "cs_get_region_hubs",
+    "cs_batch_get_region_hubs",
     "cs_last_error",
 )
 
@@ -95,6 +96,8 @@ def lib():
             "cs_plan_regions": [p, i32],
             "cs_get_region_info": [p, p, p, p, p, p, p, p, p],
             "cs_get_region_plan": [p, p, p, p, p, p, p, p, p, p],
+            "cs_get_region_hubs": [p, p, p, p],
+            "cs_batch_get_region_hubs": [p, p, p, p],
             "cs_check": [p, p],
             "cs_set_spin_limit": [p, i64],
             "cs_set_plan_units": [p, i32],
@@ -202,7 +205,7 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-RT_FIELDS = 10   # fields per region in the plan's region table
+RT_FIELDS = 12   # fields per region in the plan's region table
 SOLVERS = {"levels": 0, "rocsolver": 1}
 ORDERS = {"natural": 0, "largest_first": 1, "dsatur": 2}   # cs_colour_order
 
@@ -216,7 +219,7 @@ def _region_info(fn, h) -> dict:
                 n_interior=nn.value, n_links=nl.value, n_folds=nf.value, n_fold_src=nfs.value)
 
 
-def _region_plan(plan_fn, info_fn, get_fn, h, block, n_dev) -> dict:
+def _region_plan(plan_fn, info_fn, get_fn, hubs_fn, h, block, n_dev) -> dict:
     """Host planning for `block` threads per region, and a copy of the tables."""
     _check(plan_fn(h, int(block)), "plan regions")
     inf = _region_info(info_fn, h)
@@ -229,6 +232,13 @@ def _region_plan(plan_fn, info_fn, get_fn, h, block, n_dev) -> dict:
                        for k in ("perm", "phase", "code", "rtab", "interior", "links", "item", "fold",
                                  "fold_src")]),
            "region plan")
+    # hub parts: local parts, part ranges
+    cnt = (C.c_int64 * 2)()
+    _check(hubs_fn(h, cnt, None, None), "region hubs")
+    hub = dict(hfold=np.zeros(cnt[0], np.int32), part_ptr=np.zeros(cnt[1] + 1, np.int32))
+    _check(hubs_fn(h, None, _np_ptr(hub["hfold"]) if hub["hfold"].size else None, _np_ptr(hub["part_ptr"])),
+           "region hubs")
+    t.update(hub)
     t["code"] = t["code"].reshape(20, n_dev)
     t["rtab"] = t["rtab"].reshape(-1, RT_FIELDS)
     t["item"] = t["item"].reshape(-1, 4)
@@ -358,7 +368,7 @@ class Circuit:
 
     def region_plan(self, block: int = 256) -> dict:
         L = lib()
-        return _region_plan(L.cs_plan_regions, L.cs_get_region_info, L.cs_get_region_plan, self._h,
+        return _region_plan(L.cs_plan_regions, L.cs_get_region_info, L.cs_get_region_plan, L.cs_get_region_hubs, self._h,
                             block, self.n_dev)
 
     def eval_stamp(self, x, ag0: float, hist=None, A=None, b=None, variant="persistent", stream=None):
@@ -521,7 +531,7 @@ class Batch:
     def region_plan(self, block: int = 256) -> dict:
         L = lib()
         return _region_plan(L.cs_batch_plan_regions, L.cs_batch_get_region_info,
-                            L.cs_batch_get_region_plan, self._h, block, self.n_dev)
+                            L.cs_batch_get_region_plan, L.cs_batch_get_region_hubs, self._h, block, self.n_dev)
 
     def set_params(self, W, L, VTH0, stream=None):
         dev = _cuda_index(W)

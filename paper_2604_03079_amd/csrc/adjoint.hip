@@ -94,8 +94,8 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
                 const double p = p0 ? -1.0 : 1.0;
                 const Tan Wt(W, dir == 0 ? 1.0 : 0.0), Lt(L, dir == 1 ? 1.0 : 0.0);
                 const Tan Vt(VTH0, dir == 2 ? 1.0 : 0.0);
-                const SizeDepT<Tan> sd = size_dep(cd, p, Wt, Lt, Vt);
-                const DevOutT<Tan> o = eval_model(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist);
+                const DevConstT<Tan> k = dev_const(cd, p, Wt, Lt, Vt);
+                const DevOutT<Tan> o = eval_model(cd, p, k, Vd, Vg, Vs, Vb, call.ag0, hist);
                 Tan Y[16];
                 full_Y(o, Y);
                 double acc = 0.0;

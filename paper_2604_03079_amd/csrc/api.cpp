@@ -24,6 +24,7 @@ KCirc make_kcirc(cs_circuit *c) {
     k.term = c->d_term.p;
     k.pol = c->d_pol.p;
     k.par = c->d_par.p;
+    k.sdp = c->d_sdp.p;
     k.code = c->d_code.p;
     k.acode = c->d_acode.p;
     k.perm = c->d_perm.p;
@@ -125,10 +126,11 @@ cs_status upload_circuit(cs_circuit *c) {
     CS_CHECK_HIP(c->d_hub_cptr.upload(h.hub_cptr), "upload hub chunks");
     CS_CHECK_HIP(c->d_hub_of_chunk.upload(h.hub_of_chunk), "upload hub chunks");
     CS_CHECK_HIP(c->d_hub_part.alloc(h.hub_of_chunk.size()), "alloc hub partials");
-    CS_CHECK_HIP(c->d_hub_count.alloc(h.hub_target.size()), "alloc hub counters");
+    CS_CHECK_HIP(c->d_hub_count.alloc(h.hub_target.size() * CNT_STRIDE), "alloc hub counters");
     if (!h.hub_target.empty())
-        CS_CHECK_HIP(hipMemset(c->d_hub_count.p, 0, sizeof(uint32_t) * h.hub_target.size()), "clear hub counters");
+        CS_CHECK_HIP(hipMemset(c->d_hub_count.p, 0, sizeof(uint32_t) * c->d_hub_count.n), "clear hub counters");
     CS_CHECK_HIP(c->d_par.alloc(3 * n), "alloc parameters");
+    CS_CHECK_HIP(c->d_sdp.alloc((size_t)NSD * n), "alloc model constants");
     int dev_count = 0;
     CS_CHECK_HIP(hipGetDeviceCount(&dev_count), "device count");
     hipDeviceProp_t prop;
@@ -225,6 +227,24 @@ cs_status plan_regions(cs_circuit *c, int32_t block) {
     return CS_OK;
 }
 
+// Per-device model constants from the colour-major parameters and the cards (the
+// kernels never see W, L, VTH0 themselves, except the adjoint), and their
+// region-major copy when the region tables are on the device.  Launched on the
+// caller's stream so that a captured step replayed after a parameter change reads
+// the new values (a replay runs no host code); without uploaded region tables the
+// copy is made when they are uploaded.
+cs_status refresh_consts(cs_circuit *c, hipStream_t s) {
+    CS_CHECK_HIP(launch_dev_const(make_kcirc(c), c->d_sdp.p, s), "model-constant launch");
+    if (c->rd.ready) {
+        CS_CHECK_HIP(launch_permute_rows(c->h.n_dev, c->rd.cm_pos.p, c->d_sdp.p, c->h.n_dev, NSD, c->rd.sdp.p, s),
+                     "model-constant permute launch");
+        c->rd.sdp_stale = false;
+    } else {
+        c->rd.sdp_stale = true;
+    }
+    return CS_OK;
+}
+
 // Region plan for the current block size, uploaded, and its parameter copy current.
 cs_status ensure_region(cs_circuit *c, hipStream_t s) {
     cs_status st = plan_regions(c, c->block);
@@ -236,10 +256,10 @@ cs_status ensure_region(cs_circuit *c, hipStream_t s) {
             return hip_fail(e, "upload region tables");
         }
     }
-    if (c->rd.par_stale) {
-        CS_CHECK_HIP(launch_permute_params(c->h.n_dev, c->rd.cm_pos.p, c->d_par.p, c->h.n_dev, c->rd.par.p, s),
-                     "parameter permute launch");
-        c->rd.par_stale = false;
+    if (c->rd.sdp_stale) {
+        CS_CHECK_HIP(launch_permute_rows(c->h.n_dev, c->rd.cm_pos.p, c->d_sdp.p, c->h.n_dev, NSD, c->rd.sdp.p, s),
+                     "model-constant permute launch");
+        c->rd.sdp_stale = false;
     }
     return CS_OK;
 }
@@ -413,6 +433,15 @@ cs_status cs_set_models(cs_circuit *c, const cs_model_card *nmos, const cs_model
     c->card[0] = derive_card(*nmos);
     c->card[1] = derive_card(*pmos);
     c->models_set = true;
+    // the per-device constants depend on the cards: recompute them from the set
+    // parameters (null stream), or ask for the parameters again on another device
+    if (c->params_set) {
+        if (current_device() != c->device) {
+            c->params_set = false;
+            return CS_OK;
+        }
+        return refresh_consts(c, nullptr);
+    }
     return CS_OK;
 }
 
@@ -429,18 +458,7 @@ cs_status cs_set_params(cs_circuit *c, const double *W, const double *L, const d
     CS_CHECK_HIP(launch_gather_params(c->h.n_dev, c->d_perm.p, W, L, VTH0, c->d_par.p,
                                       (hipStream_t)stream), "parameter gather launch");
     c->params_set = true;
-    // the region schedules read their own region-major copy: refresh it here, on the
-    // same stream, so that a captured step replayed after this call sees the new
-    // values (a replay runs no host code); without uploaded region tables the copy
-    // is made when they are uploaded
-    if (c->rd.ready) {
-        CS_CHECK_HIP(launch_permute_params(c->h.n_dev, c->rd.cm_pos.p, c->d_par.p, c->h.n_dev, c->rd.par.p,
-                                           (hipStream_t)stream), "parameter permute launch");
-        c->rd.par_stale = false;
-    } else {
-        c->rd.par_stale = true;
-    }
-    return CS_OK;
+    return refresh_consts(c, (hipStream_t)stream);
 }
 
 cs_status cs_set_launch(cs_circuit *c, int32_t block, int32_t eval_ahead, int32_t cooperative) {
@@ -633,6 +651,13 @@ cs_status cs_get_region_plan(const cs_circuit *c, int32_t *perm, uint16_t *phase
     return CS_OK;
 }
 
+cs_status cs_get_region_hubs(const cs_circuit *c, int64_t *counts, int32_t *hfold, int32_t *part_ptr) {
+    if (!c) return fail(CS_EINVAL, "NULL circuit");
+    if (!c->rp.built) return fail(CS_ESTATE, "no region plan yet");
+    region_hub_tables(c->rp, counts, hfold, part_ptr);
+    return CS_OK;
+}
+
 cs_status cs_check(cs_circuit *c, void *stream) {
     if (!c) return fail(CS_EINVAL, "NULL circuit");
     if (c->device < 0) return CS_OK;
@@ -643,6 +668,9 @@ cs_status cs_check(cs_circuit *c, void *stream) {
         CS_CHECK_HIP(hipMemset(c->d_sync.p + 1, 0, sizeof(uint32_t)), "clear error word");
         if (c->d_hub_count.n)
             CS_CHECK_HIP(hipMemset(c->d_hub_count.p, 0, sizeof(uint32_t) * c->d_hub_count.n), "clear hub counters");
+        // the grid-barrier form of the region schedule counts in the region tables
+        if (c->rd.item_count.n)
+            CS_CHECK_HIP(hipMemset(c->rd.item_count.p, 0, sizeof(uint32_t) * c->rd.item_count.n), "clear item counters");
         return fail(CS_EDOMAIN, "a barrier wait exceeded its spin budget");
     }
     return CS_OK;

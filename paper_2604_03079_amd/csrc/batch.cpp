@@ -204,12 +204,13 @@ cs_status upload(cs_batch *B) {
     CS_BCHECK(B->d_hub_of_chunk.upload(P.hub_of_chunk), "upload hubs");
     CS_BCHECK(B->d_stage.alloc((size_t)B->stage_total), "alloc staging");
     CS_BCHECK(B->d_hub_part.alloc(P.hub_of_chunk.size()), "alloc hub partials");
-    CS_BCHECK(B->d_hub_count.alloc(P.hub_target.size()), "alloc hub counters");
+    CS_BCHECK(B->d_hub_count.alloc(P.hub_target.size() * CNT_STRIDE), "alloc hub counters");
     if (!P.hub_target.empty())
-        CS_BCHECK(hipMemset(B->d_hub_count.p, 0, sizeof(uint32_t) * P.hub_target.size()), "clear hub counters");
+        CS_BCHECK(hipMemset(B->d_hub_count.p, 0, sizeof(uint32_t) * B->d_hub_count.n), "clear hub counters");
     CS_BCHECK(B->d_local.upload(B->local_table), "upload local table");
     CS_BCHECK(B->d_local_cptr.upload(B->local_cptr), "upload local table");
     if (B->d_par.n < 3 * (size_t)P.n_dev) CS_BCHECK(B->d_par.alloc(3 * (size_t)P.n_dev), "alloc parameters");
+    if (B->d_sdp.n < (size_t)NSD * P.n_dev) CS_BCHECK(B->d_sdp.alloc((size_t)NSD * P.n_dev), "alloc model constants");
     if (B->d_sync.n == 0) {
         hipDeviceProp_t prop;
         CS_BCHECK(hipGetDeviceProperties(&prop, cur_device()), "device properties");
@@ -231,6 +232,7 @@ KCirc make_kc(cs_batch *B) {
     k.term = B->d_term.p;
     k.pol = B->d_pol.p;
     k.par = B->d_par.p;
+    k.sdp = B->d_sdp.p;
     k.code = B->d_code.p;
     k.acode = B->d_acode.p;
     k.perm = B->d_perm.p;
@@ -342,10 +344,10 @@ cs_status ensure_region(cs_batch *B, hipStream_t s) {
             return bfail(CS_EHIP, std::string("upload region tables: ") + hipGetErrorString(e));
         }
     }
-    if (B->rd.par_stale) {
-        CS_BCHECK(launch_permute_params(B->h.n_dev, B->rd.cm_pos.p, B->d_par.p, B->h.n_dev, B->rd.par.p, s),
-                  "parameter permute launch");
-        B->rd.par_stale = false;
+    if (B->rd.sdp_stale) {
+        CS_BCHECK(launch_permute_rows(B->h.n_dev, B->rd.cm_pos.p, B->d_sdp.p, B->h.n_dev, NSD, B->rd.sdp.p, s),
+                  "model-constant permute launch");
+        B->rd.sdp_stale = false;
     }
     return CS_OK;
 }
@@ -463,13 +465,15 @@ cs_status cs_batch_set_params(cs_batch *B, const double *W, const double *L, con
     CS_BCHECK(launch_gather_params(B->h.n_dev, B->d_perm.p, W, L, VTH0, B->d_par.p, (hipStream_t)stream),
               "parameter gather launch");
     B->params_set = true;
-    // region-major copy refreshed on the same stream (a replayed step runs no host code)
+    // per-device model constants, and their region-major copy, on the same stream (a
+    // replayed step runs no host code)
+    CS_BCHECK(launch_dev_const(make_kc(B), B->d_sdp.p, (hipStream_t)stream), "model-constant launch");
     if (B->rd.ready) {
-        CS_BCHECK(launch_permute_params(B->h.n_dev, B->rd.cm_pos.p, B->d_par.p, B->h.n_dev, B->rd.par.p,
-                                        (hipStream_t)stream), "parameter permute launch");
-        B->rd.par_stale = false;
+        CS_BCHECK(launch_permute_rows(B->h.n_dev, B->rd.cm_pos.p, B->d_sdp.p, B->h.n_dev, NSD, B->rd.sdp.p,
+                                      (hipStream_t)stream), "model-constant permute launch");
+        B->rd.sdp_stale = false;
     } else {
-        B->rd.par_stale = true;
+        B->rd.sdp_stale = true;
     }
     return CS_OK;
 }
@@ -569,6 +573,13 @@ cs_status cs_batch_get_region_plan(const cs_batch *B, int32_t *perm, uint16_t *p
     return CS_OK;
 }
 
+cs_status cs_batch_get_region_hubs(const cs_batch *B, int64_t *counts, int32_t *hfold, int32_t *part_ptr) {
+    if (!B) return bfail(CS_EINVAL, "NULL batch");
+    if (!B->rp.built) return bfail(CS_ESTATE, "no region plan yet");
+    region_hub_tables(B->rp, counts, hfold, part_ptr);
+    return CS_OK;
+}
+
 cs_status cs_batch_check(cs_batch *B, void *stream) {
     if (!B) return bfail(CS_EINVAL, "NULL batch");
     if (B->device < 0) return CS_OK;
@@ -579,6 +590,8 @@ cs_status cs_batch_check(cs_batch *B, void *stream) {
         CS_BCHECK(hipMemset(B->d_sync.p + 1, 0, sizeof(uint32_t)), "clear error word");
         if (B->d_hub_count.n)
             CS_BCHECK(hipMemset(B->d_hub_count.p, 0, sizeof(uint32_t) * B->d_hub_count.n), "clear hub counters");
+        if (B->rd.item_count.n)
+            CS_BCHECK(hipMemset(B->rd.item_count.p, 0, sizeof(uint32_t) * B->rd.item_count.n), "clear item counters");
         return bfail(CS_EDOMAIN, "a barrier wait exceeded its spin budget");
     }
     return CS_OK;

@@ -111,6 +111,10 @@ struct RegionPlan {
     std::vector<int32_t> slot_tgt;     // per staged slot: target of a shared entry (-1: hub)
     std::vector<uint8_t> slot_first;   // SLOT_STORE / SLOT_ADD / SLOT_HUB / SLOT_DEFER
     std::vector<int32_t> fold, fold_src;   // lane folds (see KRegion)
+    // hub parts of the region schedule: chunks of RHUB_K contributions
+    std::vector<int32_t> hub_cptr;         // n_hub+1: part ranges per hub
+    std::vector<int32_t> hub_of_chunk;     // hub of each part
+    std::vector<int32_t> hfold;            // local hub parts (see KRegion)
 };
 
 // Device copies of a region plan.
@@ -121,10 +125,12 @@ struct RegionDev {
     DevBuf<int32_t> slot_tgt;
     DevBuf<uint8_t> slot_first;
     DevBuf<int32_t> fold, fold_src;
-    DevBuf<double> par, stage;
+    DevBuf<int32_t> hub_cptr, hub_of_chunk, hfold;
+    DevBuf<double> hub_part;
+    DevBuf<double> sdp, stage;   // sdp: per-device model constants, region-major [NSD][n]
     DevBuf<uint32_t> item_count;
     bool ready = false;      // uploaded from the current plan
-    bool par_stale = true;
+    bool sdp_stale = true;
 };
 
 Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R);
@@ -137,6 +143,7 @@ void region_info(const RegionPlan &R, int32_t *n_regions, int32_t *max_phases, i
                  int64_t *n_fold_src);
 void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t *code, int32_t *rtab,
                    int32_t *interior, int32_t *links, int32_t *item, int32_t *fold, int32_t *fold_src);
+void region_hub_tables(const RegionPlan &R, int64_t *counts, int32_t *hfold, int32_t *part_ptr);
 
 // Build the greedy colouring (ascending device order) and the colour-major order.
 // order: 0 ascending device index (the paper's), 1 largest degree first, 2 DSATUR.
@@ -186,6 +193,7 @@ struct cs_circuit {
         d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk;
     cs::DevBuf<int8_t> d_pol;
     cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_buf, d_hub_part;
+    cs::DevBuf<double> d_sdp;          // per-device model constants [NSD][n] (colour-major)
     cs::DevBuf<int32_t> d_linA_idx;
     cs::DevBuf<double> d_linA_val;
     cs::DevBuf<int32_t> d_ipos;   // device index -> position (serial stamping)
@@ -238,6 +246,7 @@ struct cs_batch {
         d_hub_ptr, d_hub_target, d_hub_cptr, d_hub_of_chunk, d_local, d_local_cptr;
     cs::DevBuf<int8_t> d_pol;
     cs::DevBuf<double> d_par, d_fixA_val, d_fixB_val, d_stage, d_hub_part;
+    cs::DevBuf<double> d_sdp;          // per-device model constants [NSD][n] (packed order)
     cs::DevBuf<int32_t> d_linA_idx;
     cs::DevBuf<double> d_linA_val;
     cs::DevBuf<uint32_t> d_sync, d_hub_count;

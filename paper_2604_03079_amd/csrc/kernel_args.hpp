@@ -26,8 +26,9 @@ constexpr uint32_t ITEM_B = 1u;     // b row
 constexpr uint32_t ITEM_HUB = 2u;   // hub chunk (index = chunk id)
 // Per-region table fields: first position, NMOS count, PMOS count (lanes: NMOS
 // first, then PMOS), phases, interior range [4], [5) in int_target,
-// item range [6], [7) in ritems, lane-fold range [8], [9) in fold.
-constexpr int RT_FIELDS = 10;
+// item range [6], [7) in ritems, lane-fold range [8], [9) in fold, local hub chunk
+// range [10], [11) in hfold.
+constexpr int RT_FIELDS = 12;
 // Shared entries with more contributions than this are folded by the follow-up
 // kernel; smaller ones by the last contributing region, one lane each.
 constexpr int ITEM_LANE_MAX = 8;
@@ -53,6 +54,19 @@ constexpr uint32_t HUB_B_FLAG = 0x80000000u;  // hub target is a b row
 constexpr int HUB_K = 256;
 // Largest number of chunks of one hub (the chunk sums are summed by one wave).
 constexpr int HUB_MAX_CHUNKS = 2048;
+// The region schedule's hub parts: aligned blocks of RHUB_K contributions (also
+// subtrees), so that a region of the usual size holds whole parts and sums them from
+// its own LDS; a follow-up kernel sums each hub's parts (HUB_K / RHUB_K times as many
+// as its chunks).
+constexpr int RHUB_K = 32;
+constexpr int HUB_MAX_PARTS = HUB_MAX_CHUNKS * (HUB_K / RHUB_K);
+// Arrival counters (hub chunks, region items) sit CNT_STRIDE words apart, one per
+// 64-byte line: atomics on different words of one line serialise like atomics on one.
+constexpr int CNT_STRIDE = 16;
+
+// Per-device constants of the model's bias-dependent part, computed from W, L, VTH0
+// and the card when the parameters are set (rows of KCirc::sdp, in DevConstT order).
+constexpr int NSD = 10;
 
 // Card-derived constants of the device model, evaluated once on the host in the
 // model's operation order.
@@ -74,7 +88,8 @@ struct KCirc {
     int32_t nc_max;          // largest number of code rows of a device (k*k + k)
     const int32_t *term;     // [4][n]: x index + 1 of d, g, s, b (0 = ground)
     const int8_t *pol;       // [n]
-    const double *par;       // [3][n]: W, L, VTH0
+    const double *par;       // [3][n]: W, L, VTH0 (the adjoint's input)
+    const double *sdp;       // [NSD][n]: per-device constants of the model (dev_const)
     const int32_t *code;     // [NCODE][n]
     const int32_t *acode;    // [NCODE][n]
     const int32_t *perm;     // [n] position -> caller's device index
@@ -92,7 +107,7 @@ struct KCirc {
     const int32_t *hub_cptr;     // [n_hub+1] chunk ranges
     const int32_t *hub_of_chunk; // [n_hub_chunks]
     double *hub_part;            // [n_hub_chunks] chunk sums
-    uint32_t *hub_count;         // [n_hub] chunks done (returns to 0 after each call)
+    uint32_t *hub_count;         // [n_hub * CNT_STRIDE] chunks done (returns to 0 after each call)
     DevCard card[2];         // 0 NMOS, 1 PMOS
 };
 
@@ -115,7 +130,7 @@ struct KRegion {
     const int32_t *ritems;      // items each region contributes to
     const int32_t *item;        // [4] per item: first staged value, count, target, regions
                                 // (0: folded by the follow-up kernel)
-    uint32_t *item_count;       // arrivals per item (returns to 0 after each call)
+    uint32_t *item_count;       // [items * CNT_STRIDE] arrivals per item (returns to 0 after each call)
     int32_t lds_int;            // LDS doubles reserved for interior entries
     int32_t nc_max;             // largest number of code rows of a device (k*k + k)
     int32_t n_deferred;         // items folded by the follow-up kernel
@@ -129,6 +144,10 @@ struct KRegion {
     // each (code row << 16) | lane of a writer in the region
     const int32_t *fold;
     const int32_t *fold_src;
+    // local hub parts: part index of each; the region's k-th local part occupies LDS
+    // slots [n_owned + RHUB_K k, n_owned + RHUB_K (k + 1)) after its owned entries,
+    // contribution r of the part at slot r
+    const int32_t *hfold;
 };
 
 // Per-call operands.

@@ -36,15 +36,32 @@ __device__ __forceinline__ DevIn load_terms(const KCirc &kc, int pos) {
 
 __device__ __forceinline__ double volt(const double *x, int32_t t) { return t == 0 ? 0.0 : x[t - 1]; }
 
+// Per-device constants of position pos (rows of kc.sdp; the junction area only
+// when the junction terms are compiled in).
+template <bool J>
+__device__ __forceinline__ DevConstT<double> load_consts(const KCirc &kc, int pos) {
+    const size_t n = (size_t)kc.n;
+    DevConstT<double> k;
+    k.vth_s = kc.sdp[pos];
+    k.dibl = kc.sdp[n + pos];
+    k.nsce = kc.sdp[2 * n + pos];
+    k.beta0 = kc.sdp[3 * n + pos];
+    k.lambda = kc.sdp[4 * n + pos];
+    k.k1AbL = kc.sdp[5 * n + pos];
+    k.esatn = kc.sdp[6 * n + pos];
+    k.Cg = kc.sdp[7 * n + pos];
+    k.Cov = kc.sdp[8 * n + pos];
+    k.Aj = J ? kc.sdp[9 * n + pos] : 0.0;
+    return k;
+}
+
 // Evaluate the device at position pos; the card is chosen per polarity with a
 // wave-uniform index (one pass per polarity present in the wave).
 template <bool J = true>
 __device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, int pos,
                                            const DevIn &d, double *qout = nullptr) {
     const int isP = kc.pol[pos] < 0 ? 1 : 0;
-    const double W = kc.par[pos];
-    const double L = kc.par[(size_t)kc.n + pos];
-    const double VTH0 = kc.par[2 * (size_t)kc.n + pos];
+    const DevConstT<double> k = load_consts<J>(kc, pos);
     const double Vd = volt(call.x, d.t0), Vg = volt(call.x, d.t1);
     const double Vs = volt(call.x, d.t2), Vb = volt(call.x, d.t3);
     const double *hist = call.hist ? call.hist + 4 * (size_t)kc.perm[pos] : nullptr;
@@ -54,8 +71,7 @@ __device__ __forceinline__ DevOut eval_pos(const KCirc &kc, const KCall &call, i
         if (isP == p0) {
             const DevCard &cd = kc.card[p0];
             const double p = p0 ? -1.0 : 1.0;
-            const SizeDep sd = size_dep(cd, p, W, L, VTH0);
-            o = eval_model<double, J>(cd, p, sd, Vd, Vg, Vs, Vb, call.ag0, hist, qout);
+            o = eval_model<double, J>(cd, p, k, Vd, Vg, Vs, Vb, call.ag0, hist, qout);
             break;
         }
     }
@@ -191,7 +207,7 @@ __device__ __forceinline__ bool hub_chunk_publish(const KCirc &kc, const KCall &
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        last = __hip_atomic_fetch_add(kc.hub_count + h, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+        last = __hip_atomic_fetch_add(kc.hub_count + (size_t)h * CNT_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
                (uint32_t)nchunk;
     }
     return __shfl(last, 0, 64) != 0;
@@ -219,37 +235,38 @@ __device__ __forceinline__ double wave_tree_chunk(const double *src, int cnt) {
     return s;
 }
 
-// Tree sum of n <= 8 values, padded with -0.0 to eight.
-__device__ __forceinline__ double tree8(const double *g, int n) {
-    double v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = k < n ? g[k] : -0.0;
-    return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-}
-
-// Tree sum of a hub's cnt <= HUB_MAX_CHUNKS chunk sums by one wave (cnt
-// wave-uniform): the aligned groups of HUB_K as in wave_tree_chunk (every load
-// issued first), then the group sums.
-static_assert(HUB_MAX_CHUNKS == 8 * HUB_K, "chunk sums form at most eight groups");
+// Tree sum of a hub's cnt <= HUB_MAX_PARTS part sums by one wave (cnt wave-uniform):
+// aligned groups of 256 as in wave_tree_chunk (four groups' loads issued at once),
+// lane g keeping group g's sum, then a butterfly over the group sums.
+static_assert(HUB_MAX_PARTS <= 64 * 256, "part sums form at most 64 groups");
 __device__ __forceinline__ double wave_tree(const double *src, int cnt) {
     const int lane = threadIdx.x & 63;
-    double g[8];
+    const int ng = (cnt + 255) / 256;
+    double mine = -0.0;
+    for (int g0 = 0; g0 < ng; g0 += 4) {
+        double gs[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        double v[4];
+        for (int i = 0; i < 4; ++i) {
+            double v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = i * HUB_K + 4 * lane + k;
-            v[k] = e < cnt ? ld_coherent(src + e) : -0.0;
+            for (int k = 0; k < 4; ++k) {
+                const int e = (g0 + i) * 256 + 4 * lane + k;
+                v[k] = e < cnt ? ld_coherent(src + e) : -0.0;
+            }
+            gs[i] = (v[0] + v[1]) + (v[2] + v[3]);
         }
-        g[i] = (v[0] + v[1]) + (v[2] + v[3]);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gs[i] = gs[i] + __shfl_xor(gs[i], off, 64);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (lane == g0 + i) mine = gs[i];
     }
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) g[i] = g[i] + __shfl_xor(g[i], off, 64);
-    }
-    return tree8(g, 8);
+    for (int off = 1; off < 64; off <<= 1) mine = mine + __shfl_xor(mine, off, 64);
+    return mine;
 }
 
 // The last chunk of hub h has been recorded by this wave: sum the chunk sums, store,
@@ -259,7 +276,7 @@ __device__ __forceinline__ void hub_finish(const KCirc &kc, const KCall &call, i
     const double s = wave_tree(kc.hub_part + c0, kc.hub_cptr[h + 1] - c0);
     if ((threadIdx.x & 63) == 0) {
         hub_store(kc, call, h, s);
-        __hip_atomic_store(kc.hub_count + h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(kc.hub_count + (size_t)h * CNT_STRIDE, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -671,9 +688,9 @@ __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *
 
 // Items of one region, after its staged values are complete: count the arrival;
 // the last region of an item folds it (shared entries one lane each, in colour
-// order; hub chunks one wave each, by the tree; consecutive items go to different
-// waves).  The wave that records a hub's last chunk sum also forms the hub's sum.
-// Called by every thread of the workgroup.
+// order; hub parts spanning regions one wave each, by the tree, stored as parts;
+// consecutive items go to different waves).  Called by every thread of the workgroup.
+// The hub sums over the parts follow in their own kernel (k_hub_parts).
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
                                              bool hub_only = false) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -692,9 +709,11 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
             if (need == 1) {
                 last = true;
             } else {
-                last = __hip_atomic_fetch_add(kr.item_count + it, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
-                       (uint32_t)need;
-                if (last) __hip_atomic_store(kr.item_count + it, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = __hip_atomic_fetch_add(kr.item_count + (size_t)it * CNT_STRIDE, 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) + 1 == (uint32_t)need;
+                if (last)
+                    __hip_atomic_store(kr.item_count + (size_t)it * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         const bool hub = (tgt >> 30) == ITEM_HUB;
@@ -715,9 +734,51 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
             const int bbeg = __shfl(beg, l, 64), bcnt = __shfl(cnt, l, 64);
             const int q = (int)((uint32_t)__shfl((int)tgt, l, 64) & 0x3FFFFFFFu);
             const double sum = wave_tree_chunk(kc.stage + bbeg, bcnt);
-            if (hub_chunk_publish(kc, call, q, sum)) hub_finish(kc, call, kc.hub_of_chunk[q]);
+            if (lane == 0) kc.hub_part[q] = sum;
         }
     }
+}
+
+// Tree sum of 16 values.
+__device__ __forceinline__ double tree16(const double *v) {
+    return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) +
+           (((v[8] + v[9]) + (v[10] + v[11])) + ((v[12] + v[13]) + (v[14] + v[15])));
+}
+
+// Follow-up kernel of the region schedule: hub h = blockIdx.x summed from its parts
+// (complete at kernel start) by the pairwise tree.  Its P parts, padded with -0.0 to
+// 256 * S (S parts per lane, a power of two), are cut into one aligned stripe of S per
+// lane, each a subtree: a lane sums its stripe in up to four blocks of 16 (every load
+// issued before the sums), a butterfly sums the stripes of a wave, thread 0 the four
+// wave sums.
+static_assert(HUB_MAX_PARTS <= 256 * 4 * 16, "a hub's parts fit four blocks of 16 per lane");
+__global__ void __launch_bounds__(256) k_hub_parts(KCirc kc, KCall call) {
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = blockIdx.x;
+    const int c0 = kc.hub_cptr[h], P = kc.hub_cptr[h + 1] - c0;
+    const double *src = kc.hub_part + c0;
+    int S = 1;
+    while (S * 256 < P) S <<= 1;
+    const int base = (int)threadIdx.x * S;
+    const int nb = S >= 16 ? S / 16 : 1;
+    double bs[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = base + b * 16 + k;
+            v[k] = (b < nb && k < S && e < P) ? src[e] : -0.0;
+        }
+        bs[b] = tree16(v);
+    }
+    double acc = (bs[0] + bs[1]) + (bs[2] + bs[3]);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc = acc + __shfl_xor(acc, off, 64);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) hub_store(kc, call, h, (red[0] + red[1]) + (red[2] + red[3]));
 }
 
 // Region schedule body.  GRID = false: the region kernel (shared entries staged and
@@ -746,12 +807,18 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         for (int k = 0; k < RT_FIELDS; ++k) f[k] = rt[k];
     }
     const int p0 = f[0], nN = f[1], nP = f[2], nph = f[3], ib = f[4], ie = f[5], jb = f[6], je = f[7];
-    const int fb = f[8], fe = f[9];
+    const int fb = f[8], fe = f[9], hb = f[10], he = f[11];
     const int t = threadIdx.x;
     const int pos = t < nN + nP ? p0 + t : -1;
     // the region's accumulators start at -0.0, the exact identity of IEEE addition, so
     // a first writer's load-add equals its store (visible after the barrier below)
-    for (int i = t; i < ie - ib; i += blockDim.x) lds[i] = -0.0;
+    for (int i = t; i < (ie - ib) + RHUB_K * (he - hb); i += blockDim.x) lds[i] = -0.0;
+    // part index of this lane's first local hub part, loaded now (used after the phases)
+    int hq0 = 0;
+    {
+        const int i0 = hb + (t >> 6) * 8 + ((t & 63) >> 3);
+        if (i0 < he) hq0 = kr.hfold[i0];
+    }
     // evaluate and merge at once (all waves in parallel); the merged values wait for
     // the device's phase in LDS, [code row][lane]
     double *mst = lds + kr.lds_int;
@@ -817,6 +884,31 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
 #pragma unroll 8
         for (int k = 1; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
         store_target(call, (uint32_t)fd[0], s);
+    }
+    // local hub parts: eight lanes per part, four of its LDS slots each (slots beyond
+    // the part's contributions hold -0.0), a butterfly over the eight lanes: the part's
+    // subtree of the hub's pairwise sum, stored as its part
+    static_assert(RHUB_K == 8 * 4, "a local hub part is eight lanes of four values");
+    {
+        const int n_owned = ie - ib;
+        int round = 0;
+        for (int base = hb + (t >> 6) * 8; base < he; base += (B >> 6) * 8, ++round) {
+            const int i = base + ((t & 63) >> 3);
+            const int r = t & 7;
+            double v[4] = {-0.0, -0.0, -0.0, -0.0};
+            int q = hq0;
+            if (i < he) {
+                if (round > 0) q = kr.hfold[i];
+                const double *src = lds + n_owned + RHUB_K * (i - hb) + 4 * r;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = src[k];
+            }
+            double sum = (v[0] + v[1]) + (v[2] + v[3]);
+            sum = sum + __shfl_xor(sum, 1, 64);
+            sum = sum + __shfl_xor(sum, 2, 64);
+            sum = sum + __shfl_xor(sum, 4, 64);
+            if (i < he && r == 0) kc.hub_part[q] = sum;
+        }
     }
     if constexpr (GRID) {
         // the region's own entries, then the shared entries level by level, then the
@@ -889,13 +981,39 @@ __global__ void __launch_bounds__(256) k_fold_items(KCirc kc, KCall call, KRegio
     if ((threadIdx.x & 63) == 0) store_target(call, (uint32_t)f[2], s);
 }
 
-__global__ void k_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
-                                 double *dst) {
+__global__ void k_permute_rows(int32_t n, const int32_t *idx, const double *src, int32_t n_src, int32_t rows,
+                               double *dst) {
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
         const int32_t q = idx[p];
-        dst[p] = src[q];
-        dst[(size_t)n + p] = src[(size_t)n_src + q];
-        dst[2 * (size_t)n + p] = src[2 * (size_t)n_src + q];
+        for (int r = 0; r < rows; ++r) dst[(size_t)r * n + p] = src[(size_t)r * n_src + q];
+    }
+}
+
+// Per-device constants of every position from W, L, VTH0 (kc.par) and the card of
+// its polarity, written to sdp[NSD][n].
+__global__ void __launch_bounds__(256) k_dev_const(KCirc kc, double *sdp) {
+    const size_t n = (size_t)kc.n;
+    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < kc.n; pos += gridDim.x * blockDim.x) {
+        const int isP = kc.pol[pos] < 0 ? 1 : 0;
+        const double W = kc.par[pos], L = kc.par[n + pos], V = kc.par[2 * n + pos];
+        DevConstT<double> k;
+        for (;;) {
+            const int p0 = __builtin_amdgcn_readfirstlane(isP);
+            if (isP == p0) {
+                k = dev_const(kc.card[p0], p0 ? -1.0 : 1.0, W, L, V);
+                break;
+            }
+        }
+        sdp[pos] = k.vth_s;
+        sdp[n + pos] = k.dibl;
+        sdp[2 * n + pos] = k.nsce;
+        sdp[3 * n + pos] = k.beta0;
+        sdp[4 * n + pos] = k.lambda;
+        sdp[5 * n + pos] = k.k1AbL;
+        sdp[6 * n + pos] = k.esatn;
+        sdp[7 * n + pos] = k.Cg;
+        sdp[8 * n + pos] = k.Cov;
+        sdp[9 * n + pos] = k.Aj;
     }
 }
 
@@ -1017,15 +1135,27 @@ hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_c
                           region_lds_bytes(lds_int, nc_max, block), blocks_per_cu);
 }
 
+// After a region launch: large shared entries, then the hub sums over their parts.
+static hipError_t launch_region_followups(const KCirc &kc, const KCall &call, const KRegion &kr, hipStream_t s) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (kr.n_deferred > 0) {
+        hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (kc.n_hub > 0) {
+        hipLaunchKernelGGL(k_hub_parts, dim3(kc.n_hub), dim3(256), 0, s, kc, call);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, int block, hipStream_t s) {
     const int grid = std::max(kr.n_regions, 1);
     const size_t shm = region_lds_bytes(kr.lds_int, kr.nc_max, block);
     if (junctions(kc)) hipLaunchKernelGGL(k_region<true>, dim3(grid), dim3(block), shm, s, kc, call, kr);
     else hipLaunchKernelGGL(k_region<false>, dim3(grid), dim3(block), shm, s, kc, call, kr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || kr.n_deferred == 0) return e;
-    hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
-    return hipGetLastError();
+    return launch_region_followups(kc, call, kr, s);
 }
 
 hipError_t region_grid_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu) {
@@ -1045,15 +1175,21 @@ hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion 
     const void *fn = junctions(kc) ? (const void *)k_region_grid<true> : (const void *)k_region_grid<false>;
     hipError_t e = cooperative ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, shm, s)
                                : hipLaunchKernel(fn, dim3(grid), dim3(block), args, shm, s);
-    if (e != hipSuccess || kr.n_deferred == 0) return e;
-    hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
+    if (e != hipSuccess) return e;
+    return launch_region_followups(kc, call, kr, s);
+}
+
+hipError_t launch_permute_rows(int32_t n, const int32_t *idx, const double *src, int32_t n_src, int32_t rows,
+                               double *dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_rows, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, src, n_src, rows, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
-                                 double *dst, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_permute_params, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, src, n_src, dst);
+hipError_t launch_dev_const(const KCirc &kc, double *sdp, hipStream_t s) {
+    if (kc.n == 0) return hipSuccess;
+    const int grid = std::max(1, std::min(8192, (kc.n + 255) / 256));
+    hipLaunchKernelGGL(k_dev_const, dim3(grid), dim3(256), 0, s, kc, sdp);
     return hipGetLastError();
 }
 

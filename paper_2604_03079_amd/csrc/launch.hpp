@@ -78,9 +78,11 @@ hipError_t launch_region(const KCirc &kc, const KCall &call, const KRegion &kr, 
 hipError_t region_grid_capacity(int block, int lds_int, int nc_max, int *blocks_per_cu);
 hipError_t launch_region_grid(const KCirc &kc, const KCall &call, const KRegion &kr, const KSync &ks, int block,
                               bool cooperative, hipStream_t s);
-// dst[j][p] = src[j][idx[p]] for the three parameter rows.
-hipError_t launch_permute_params(int32_t n, const int32_t *idx, const double *src, int32_t n_src,
-                                 double *dst, hipStream_t s);
+// dst[j][p] = src[j][idx[p]] for rows j < rows (src rows n_src long, dst rows n).
+hipError_t launch_permute_rows(int32_t n, const int32_t *idx, const double *src, int32_t n_src, int32_t rows,
+                               double *dst, hipStream_t s);
+// Per-device model constants sdp[NSD][kc.n] from kc.par (W, L, VTH0), kc.pol and kc.card.
+hipError_t launch_dev_const(const KCirc &kc, double *sdp, hipStream_t s);
 hipError_t launch_serial(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows, double *buf,
                          const int32_t *ipos, hipStream_t s);
 hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,

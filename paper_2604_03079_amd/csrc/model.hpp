@@ -227,6 +227,33 @@ __device__ __forceinline__ SizeDepT<S> size_dep(const DevCard &cd, double pol, S
     return s;
 }
 
+// The per-device constants the bias-dependent part reads, as the products it uses
+// (the same operations, in the same order, as written inline in the model): they
+// depend on W, L, VTH0 and the card only, so they are computed once per parameter
+// set, not per Newton iteration.  Field order = row order of KCirc::sdp.
+template <class S>
+struct DevConstT {
+    S vth_s, dibl, nsce, beta0, lambda, k1AbL, esatn, Cg, Cov, Aj;
+};
+static_assert(sizeof(DevConstT<double>) == NSD * sizeof(double), "one row per field");
+
+template <class S>
+__device__ __forceinline__ DevConstT<S> dev_const(const DevCard &cd, double pol, S W, S L, S VTH0) {
+    const SizeDepT<S> sd = size_dep(cd, pol, W, L, VTH0);
+    DevConstT<S> k;
+    k.vth_s = sd.vth_s;
+    k.dibl = cd.eta0 * sd.theta_dibl;                   // DIBL coefficient of M3
+    k.nsce = (cd.cdsc * sd.theta_sce) / cd.COXE;        // SCE term of M4
+    k.beta0 = sd.beta0;
+    k.lambda = sd.lambda;
+    k.k1AbL = cd.k1 * sd.AbL;                           // numerator of M8's Abulk term
+    k.esatn = cd.TWO_VSAT * sd.Leff;                    // numerator of M8's EsatL
+    k.Cg = sd.Cg;
+    k.Cov = sd.Cov;
+    k.Aj = sd.Aj;
+    return k;
+}
+
 // One source/drain-body junction of forward voltage v (body above the diffusion for
 // NMOS) and area A: diode current Ij and conductance gj (exponent clamped at -40,
 // tangent continuation above vjmax), abrupt-junction depletion charge Qj and
@@ -269,7 +296,7 @@ struct DevOutT {
 // charges (d, g, s, b) at V, for the history term of the next integration step.
 // J = false compiles the junction terms out (cards with jmod = 0 only).
 template <class S, bool J = true>
-__device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, const SizeDepT<S> &sd,
+__device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, const DevConstT<S> &sd,
                                                  double Vd, double Vg, double Vs, double Vb,
                                                  double ag0, const double *hist, double *qout = nullptr) {
     using D = Dual3T<S>;
@@ -287,10 +314,10 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     const D sqPs = dsqrt(c_minus(cd.phis, Vbseff));
     // threshold voltage
     const D Vth = (plus_c(scale(cd.k1, minus_c(sqPs, cd.SQPHIS)), sd.vth_s) - scale(cd.k2, Vbseff))
-                  - scale(cd.eta0 * sd.theta_dibl, X1);
+                  - scale(sd.dibl, X1);
     // subthreshold swing factor
     // (the constant factors of the Cdep term are the card constant NCDEP)
-    const D n = plus_c(plus_c(c_over(cd.NCDEP, sqPs), 1.0), (cd.cdsc * sd.theta_sce) / cd.COXE);
+    const D n = plus_c(plus_c(c_over(cd.NCDEP, sqPs), 1.0), sd.nsce);
     const D nvt = scale(cd.VT, n);
     const D Vgst = X2 - Vth;
     // unified effective gate overdrive
@@ -304,8 +331,8 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     const D mden = plus_c(plus_c(scale(cd.uc, Vbseff), cd.ua) * Ee, 1.0) + scale(cd.ub, Ee * Ee);
     const D mu = c_over(cd.u0, mden);
     // saturation
-    const D EsatL = c_over(cd.TWO_VSAT * sd.Leff, mu);
-    const D Abulk = plus_c(c_over(cd.k1 * sd.AbL, scale(2.0, sqPs)), 1.0);
+    const D EsatL = c_over(sd.esatn, mu);
+    const D Abulk = plus_c(c_over(sd.k1AbL, scale(2.0, sqPs)), 1.0);
     const D V2 = plus_c(Vgsteff, cd.TWO_VT);
     const D Vdsat = (EsatL * V2) / ((Abulk * EsatL) + V2);
     const D T1 = minus_c(Vdsat - X1, cd.delta);

@@ -74,14 +74,13 @@ extern "C" cs_status cs_eval_stamp_noalloc(cs_circuit *c, const double *x, doubl
         return failed(CS_ESTATE,
                       "region tables are not on the device for this block size: one cs_eval_stamp with "
                       "CS_COLOR_REGION must come first");
-    // scratch layout: staging values, hub chunk sums, hub counters, item counters
+    // scratch layout: staging values, hub part sums, item counters
     const size_t n_stage = (size_t)c->rp.stage_size;
-    const size_t n_chunks = c->h.hub_of_chunk.size();
-    const size_t n_hub = c->h.hub_target.size();
+    const size_t n_chunks = c->rp.hub_of_chunk.size();
     const size_t n_items = c->rp.item.size() / 4;
     const size_t off_part = up32(n_stage);
     const size_t off_count = off_part + up32(n_chunks);
-    const size_t n_words = n_hub + n_items;
+    const size_t n_words = n_items * CNT_STRIDE;
     const size_t need = off_count + (n_words + 1) / 2;
     if (need > SCRATCH_DOUBLES)
         return failed(CS_ENOTSUP, "the circuit needs " + std::to_string(need * sizeof(double)) +
@@ -91,18 +90,17 @@ extern "C" cs_status cs_eval_stamp_noalloc(cs_circuit *c, const double *x, doubl
     hipError_t e = scratch_address(dev, &base);
     if (e != hipSuccess) return failed(CS_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
     hipStream_t s = (hipStream_t)stream;
-    if (c->rd.par_stale) {
-        e = launch_permute_params(c->h.n_dev, c->rd.cm_pos.p, c->d_par.p, c->h.n_dev, c->rd.par.p, s);
-        if (e != hipSuccess) return failed(CS_EHIP, std::string("parameter permute launch: ") + hipGetErrorString(e));
-        c->rd.par_stale = false;
+    if (c->rd.sdp_stale) {
+        e = launch_permute_rows(c->h.n_dev, c->rd.cm_pos.p, c->d_sdp.p, c->h.n_dev, NSD, c->rd.sdp.p, s);
+        if (e != hipSuccess) return failed(CS_EHIP, std::string("model-constant permute launch: ") + hipGetErrorString(e));
+        c->rd.sdp_stale = false;
     }
     uint32_t *words = reinterpret_cast<uint32_t *>(base + off_count);
     KCirc kc = region_kcirc(make_kcirc(c), c->rp, c->rd);
     kc.stage = base;
     kc.hub_part = base + off_part;
-    kc.hub_count = words;
     KRegion kr = region_kregion(c->rp, c->rd);
-    kr.item_count = words + n_hub;
+    kr.item_count = words;
     if (n_words > 0) {
         const int grid = (int)std::min<size_t>((n_words + 255) / 256, 1024);
         hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, s, words, (int64_t)n_words);

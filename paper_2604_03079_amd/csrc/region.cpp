@@ -204,34 +204,71 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
     }
     R.stage_size = cursor;
 
-    // 3. hub contributions keep their staging index; one item per chunk
+    // 3. hub contributions, in the region schedule's parts: chunks of RHUB_K (aligned
+    // blocks of the pairwise tree, so each is a subtree).  A part whose contributions
+    // all come from one region is a candidate for that region's LDS (step 4b); a part
+    // spanning regions keeps its staging indices and is an item, summed by the last of
+    // its regions.
+    std::vector<std::vector<int32_t>> lchunk((size_t)R.n_regions);          // local parts
+    std::vector<std::vector<int32_t>> cand((size_t)R.n_regions);            // candidates
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> csrc;   // per part: (staging index, p << 5 | j)
+    // one part as an item over its staged contributions
+    auto stage_part = [&](size_t q) {
+        const auto &v = csrc[q];
+        const int32_t h = R.hub_of_chunk[q];
+        const int32_t beg = s.hub_ptr[(size_t)h] + (int32_t)(q - (size_t)R.hub_cptr[(size_t)h]) * RHUB_K;
+        std::vector<int32_t> rg;
+        for (const auto &e : v) {
+            code[(size_t)(e.second & 31) * n + (size_t)(e.second >> 5)] = (int32_t)((TAG_STAGE << 30) | (uint32_t)e.first);
+            rg.push_back(region_of[(size_t)s.perm[(size_t)(e.second >> 5)]]);
+        }
+        std::sort(rg.begin(), rg.end());
+        rg.erase(std::unique(rg.begin(), rg.end()), rg.end());
+        const int32_t it = (int32_t)(R.item.size() / 4);
+        R.item.insert(R.item.end(), {beg, (int32_t)v.size(), (int32_t)((ITEM_HUB << 30) | (uint32_t)q), (int32_t)rg.size()});
+        for (int32_t g : rg) rit[(size_t)g].push_back(it);
+    };
     {
-        std::vector<std::pair<int32_t, int32_t>> qr;   // (chunk, region)
+        const int32_t nh = s.hub_ptr.empty() ? 0 : (int32_t)s.hub_ptr.size() - 1;
+        R.hub_cptr.assign(1, 0);
+        R.hub_of_chunk.clear();
+        for (int32_t h = 0; h < nh; ++h) {
+            const int32_t m = s.hub_ptr[(size_t)h + 1] - s.hub_ptr[(size_t)h];
+            const int32_t nc = (m + RHUB_K - 1) / RHUB_K;
+            if (nc > HUB_MAX_PARTS) return {CS_ENOTSUP, "a hub entry has more contributions than the reduction supports"};
+            for (int32_t j = 0; j < nc; ++j) R.hub_of_chunk.push_back(h);
+            R.hub_cptr.push_back(R.hub_cptr.back() + nc);
+        }
+        const size_t nparts = R.hub_of_chunk.size();
+        csrc.resize(nparts);
+        std::vector<int32_t> owner(nparts, -1);   // region of the part's contributions, -2 several
         for (size_t p = 0; p < n; ++p) {
             const int k = kk[p];
             for (int j = 0; j < k * k + k; ++j) {
                 const uint32_t c = (uint32_t)s.code[(size_t)j * n + p];
                 if ((c >> 30) != TAG_HUB) continue;
                 const int32_t si = (int32_t)(c & 0x3FFFFFFFu);
-                code[(size_t)j * n + p] = (int32_t)((TAG_STAGE << 30) | (uint32_t)si);
                 const size_t h = (size_t)(std::upper_bound(s.hub_ptr.begin(), s.hub_ptr.end(), si) - s.hub_ptr.begin()) - 1;
-                const int32_t q = s.hub_cptr[h] + (si - s.hub_ptr[h]) / HUB_K;
-                qr.emplace_back(q, region_of[(size_t)s.perm[p]]);
+                const int32_t q = R.hub_cptr[h] + (si - s.hub_ptr[h]) / RHUB_K;
+                const int32_t g = region_of[(size_t)s.perm[p]];
+                owner[(size_t)q] = owner[(size_t)q] == -1 || owner[(size_t)q] == g ? g : -2;
+                csrc[(size_t)q].emplace_back(si, ((int64_t)p << 5) | j);
             }
         }
-        std::sort(qr.begin(), qr.end());
-        qr.erase(std::unique(qr.begin(), qr.end()), qr.end());
-        for (size_t a = 0; a < qr.size();) {
-            size_t b = a;
-            while (b < qr.size() && qr[b].first == qr[a].first) ++b;
-            const int32_t q = qr[a].first;
-            const size_t h = (size_t)(std::upper_bound(s.hub_cptr.begin(), s.hub_cptr.end(), q) - s.hub_cptr.begin()) - 1;
-            const int32_t beg = s.hub_ptr[h] + (q - s.hub_cptr[h]) * HUB_K;
-            const int32_t cnt = std::min<int32_t>(HUB_K, s.hub_ptr[h + 1] - beg);
-            const int32_t it = (int32_t)(R.item.size() / 4);
-            R.item.insert(R.item.end(), {beg, cnt, (int32_t)((ITEM_HUB << 30) | (uint32_t)q), (int32_t)(b - a)});
-            for (size_t e = a; e < b; ++e) rit[(size_t)qr[e].second].push_back(it);
-            a = b;
+        for (size_t q = 0; q < nparts; ++q) {
+            auto &v = csrc[q];
+            std::sort(v.begin(), v.end());
+            const int32_t h = R.hub_of_chunk[q];
+            const int32_t beg = s.hub_ptr[(size_t)h] + (int32_t)(q - (size_t)R.hub_cptr[(size_t)h]) * RHUB_K;
+            const int32_t cnt = std::min<int32_t>(RHUB_K, s.hub_ptr[(size_t)h + 1] - beg);
+            if ((int32_t)v.size() != cnt) return {CS_EINVAL, "hub contributions do not fill their staging range"};
+            if (owner[q] >= 0) {
+                // candidate: code decided in step 4b (tag 3 meanwhile: no LDS slot)
+                for (const auto &e : v) code[(size_t)(e.second & 31) * n + (size_t)(e.second >> 5)] = (int32_t)(3u << 30);
+                cand[(size_t)owner[q]].push_back((int32_t)q);
+                continue;
+            }
+            stage_part(q);
         }
     }
 
@@ -281,6 +318,34 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
             const int j = (int)(wr[(size_t)w] & 31);
             const uint32_t tag = w == kptr[(size_t)t] ? TAG_LDS_STORE : TAG_LDS_ADD;
             code[(size_t)j * n + p] = (int32_t)((tag << 30) | (uint32_t)lds_of[(size_t)t]);
+        }
+    }
+
+    // 4b. local hub parts: RHUB_K LDS slots each after the region's owned entries (the
+    // unused ones stay at their -0.0 start), one writer per slot (plain store, in the
+    // writer's phase), when they fit the workgroup's LDS next to the merged-value rows;
+    // otherwise the region's candidates are staged items of that region alone
+    {
+        const int64_t budget = REGION_LDS_LIMIT / 8 - (int64_t)R.max_nc * cap - 2;
+        for (int32_t g = 0; g < R.n_regions; ++g) {
+            auto &cv = cand[(size_t)g];
+            if (cv.empty()) continue;
+            const int64_t base = int_ptr[(size_t)g + 1] - int_ptr[(size_t)g];
+            if (base + (int64_t)RHUB_K * (int64_t)cv.size() > budget) {
+                for (int32_t q : cv) stage_part((size_t)q);
+                continue;
+            }
+            for (size_t k = 0; k < cv.size(); ++k) {
+                const int32_t q = cv[k];
+                const int32_t h = R.hub_of_chunk[(size_t)q];
+                const int32_t start = s.hub_ptr[(size_t)h] + (q - R.hub_cptr[(size_t)h]) * RHUB_K;
+                for (const auto &e : csrc[(size_t)q]) {
+                    const uint32_t slot = (uint32_t)(base + (int64_t)RHUB_K * (int64_t)k + (e.first - start));
+                    code[(size_t)(e.second & 31) * n + (size_t)(e.second >> 5)] = (int32_t)((TAG_LDS_STORE << 30) | slot);
+                }
+                lchunk[(size_t)g].push_back(q);
+            }
+            R.max_lds = std::max<int32_t>(R.max_lds, (int32_t)(base + (int64_t)RHUB_K * (int64_t)cv.size()));
         }
     }
 
@@ -439,6 +504,10 @@ Err build_regions(const RegionSource &s, int32_t cap, RegionPlan &R) {
                 }
             }
             rt[9] = (int32_t)(R.fold.size() / 3);
+            // local hub parts (LDS slots in this order after the owned entries)
+            rt[10] = (int32_t)R.hfold.size();
+            R.hfold.insert(R.hfold.end(), lchunk[(size_t)g].begin(), lchunk[(size_t)g].end());
+            rt[11] = (int32_t)R.hfold.size();
         }
     }
     R.built = true;
@@ -467,12 +536,16 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
     if ((e = D.slot_first.upload(R.slot_first)) != hipSuccess) return e;
     if ((e = D.fold.upload(R.fold)) != hipSuccess) return e;
     if ((e = D.fold_src.upload(R.fold_src)) != hipSuccess) return e;
-    if ((e = D.par.alloc(3 * R.perm.size())) != hipSuccess) return e;
+    if ((e = D.hub_cptr.upload(R.hub_cptr)) != hipSuccess) return e;
+    if ((e = D.hub_of_chunk.upload(R.hub_of_chunk)) != hipSuccess) return e;
+    if ((e = D.hfold.upload(R.hfold)) != hipSuccess) return e;
+    if ((e = D.hub_part.alloc(R.hub_of_chunk.size())) != hipSuccess) return e;
+    if ((e = D.sdp.alloc((size_t)NSD * R.perm.size())) != hipSuccess) return e;
     if ((e = D.stage.alloc((size_t)R.stage_size)) != hipSuccess) return e;
     const size_t n_items = R.item.size() / 4;
-    if ((e = D.item_count.alloc(n_items)) != hipSuccess) return e;
-    if (n_items && (e = hipMemset(D.item_count.p, 0, sizeof(uint32_t) * n_items)) != hipSuccess) return e;
-    D.par_stale = true;
+    if ((e = D.item_count.alloc(n_items * CNT_STRIDE)) != hipSuccess) return e;
+    if (n_items && (e = hipMemset(D.item_count.p, 0, sizeof(uint32_t) * D.item_count.n)) != hipSuccess) return e;
+    D.sdp_stale = true;
     D.ready = true;
     return hipSuccess;
 }
@@ -508,18 +581,34 @@ void region_tables(const RegionPlan &R, int32_t *perm, uint16_t *phase, int32_t 
     copy_out(R.item, item);
 }
 
+void region_hub_tables(const RegionPlan &R, int64_t *counts, int32_t *hfold, int32_t *part_ptr) {
+    if (counts) {
+        counts[0] = (int64_t)R.hfold.size();
+        counts[1] = R.hub_cptr.empty() ? 0 : (int64_t)R.hub_cptr.size() - 1;
+    }
+    copy_out(R.hfold, hfold);
+    copy_out(R.hub_cptr, part_ptr);
+}
+
 KCirc region_kcirc(const KCirc &base, const RegionPlan &R, const RegionDev &D) {
     KCirc k = base;
     k.n = (int32_t)R.perm.size();
     k.n_colors = 0;
     k.term = D.term.p;
     k.pol = D.pol.p;
-    k.par = D.par.p;
+    k.par = nullptr;
+    k.sdp = D.sdp.p;
     k.code = D.code.p;
     k.acode = nullptr;
     k.perm = D.perm.p;
     k.cptr = nullptr;
     k.stage = D.stage.p;
+    // hub parts in the region schedule's chunks
+    k.n_hub_chunks = (int32_t)R.hub_of_chunk.size();
+    k.hub_cptr = D.hub_cptr.p;
+    k.hub_of_chunk = D.hub_of_chunk.p;
+    k.hub_part = D.hub_part.p;
+    k.hub_count = nullptr;   // the region schedule counts no hub arrivals
     return k;
 }
 
@@ -540,6 +629,8 @@ KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
     r.slot_first = D.slot_first.p;
     r.fold = D.fold.p;
     r.fold_src = D.fold_src.p;
+    r.hfold = D.hfold.p;
+
     r.lds_int = (R.max_lds + 1) & ~1;
     r.nc_max = R.max_nc;
     return r;

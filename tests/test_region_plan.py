@@ -1,13 +1,15 @@
 """CPU checks of the region schedule's host planner.
 
 The library's plan tables (regions, LDS phases, stamp codes, shared-entry items) are
-replayed here on the host exactly as the region kernel uses them, with every device's
+replayed here on the host exactly as the region kernels use them, with every device's
 local values taken from the oracle; the replayed matrix entries and RHS rows must
 equal the oracle's colour-order replay bit for bit.  Structural checks cover the
 region layout (NMOS lanes first, then PMOS lanes, capacity), the code
 rows, the item bookkeeping and, for batches, that a circuit fitting one region is
-never split.  Hub entries keep their staging indices; their fixed-shape sum is a
-kernel step, checked on the GPU."""
+never split.  Hub entries are summed in parts of 32 contributions: a part held by one
+region from its parked values, a part spanning regions from its staged
+contributions; the replay forms every hub's pairwise tree from those parts and
+compares it with the oracle's hub entries too."""
 import numpy as np
 import pytest
 
@@ -47,23 +49,34 @@ def merged_values(orc, circ, v):
     return m
 
 
+def tree(vals, size):
+    """Perfect binary tree sum of vals padded with -0.0 to size (a power of two)."""
+    v = [float(x) for x in vals] + [-0.0] * (size - len(vals))
+    while len(v) > 1:
+        v = [v[2 * i] + v[2 * i + 1] for i in range(len(v) // 2)]
+    return v[0]
+
+
 def replay(plan, vals, pol, block, nnz, n_rows):
     """Host replay of the region kernel: returns {('A'|'b', index): value} for every
-    entry the plan owns or shares, and the staging array."""
+    non-hub entry the plan owns or shares, and per hub its sum formed from the plan's
+    parts ({hub index: value})."""
     code, rtab, phase, perm = plan["code"], plan["rtab"], plan["phase"], plan["perm"]
     n = len(perm)
     stage = np.full(plan["n_staged"], np.nan)
     out = {}
+    parts = {}
     seen = np.zeros(n, bool)
     nxt = 0
     for r in range(plan["n_regions"]):
-        p0, nN, nP, nph, ib, ie, jb, je, fb, fe = (int(v) for v in rtab[r])
+        p0, nN, nP, nph, ib, ie, jb, je, fb, fe, hb, he = (int(v) for v in rtab[r])
         assert p0 == nxt and nN + nP > 0
         nxt = p0 + nN + nP
         assert nN + nP <= block
         pos = list(range(p0, p0 + nN + nP))
         assert all(pol[perm[p]] > 0 for p in pos[:nN]) and all(pol[perm[p]] < 0 for p in pos[nN:])
-        lds = np.full(ie - ib, np.nan)
+        # owned entries, then 32 slots per local hub part
+        lds = np.full(ie - ib + 32 * (he - hb), np.nan)
         folded = set()
         for i in range(fb, fe):
             _, sb, cnt = (int(v) for v in plan["fold"][i])
@@ -88,7 +101,7 @@ def replay(plan, vals, pol, block, nnz, n_rows):
         # as the kernel: accumulators start at -0.0 and every writer load-adds in its
         # phase; two writers of one entry never share a phase
         lds[:] = -0.0
-        written = [set() for _ in range(ie - ib)]
+        written = [set() for _ in range(len(lds))]
         for q in range(nph):
             for p in pos:
                 if phase[p] != q:
@@ -100,7 +113,14 @@ def replay(plan, vals, pol, block, nnz, n_rows):
                         assert q not in written[idx], "two writers of an entry in one phase"
                         written[idx].add(q)
                         lds[idx] = lds[idx] + mv
-        assert all(written)
+        assert all(written[:ie - ib])
+        assert all(len(w) <= 1 for w in written[ie - ib:])   # one writer per hub slot
+        # local hub parts: slot r of part k holds contribution r (-0.0 beyond the
+        # part's contributions), summed by the 32-leaf tree
+        for k in range(he - hb):
+            q = int(plan["hfold"][hb + k])
+            assert q not in parts
+            parts[q] = tree(lds[ie - ib + 32 * k: ie - ib + 32 * (k + 1)], 32)
         # lane folds: the writers' merged values, left to right in colour order
         for i in range(fb, fe):
             tg, sb, cnt = (int(v) for v in plan["fold"][i])
@@ -128,8 +148,11 @@ def replay(plan, vals, pol, block, nnz, n_rows):
         tgt = int(tgt) & 0xFFFFFFFF
         assert not np.isnan(stage[beg:beg + cnt]).any()
         if tgt >> 30 == 2:
-            assert len(links.get(it, [])) == need >= 1
-            assert cnt <= 256
+            # a hub part spanning regions: its staged contributions by the tree
+            q = tgt & 0x3FFFFFFF
+            assert len(links.get(it, [])) == need >= 2
+            assert 1 <= cnt <= 32 and q not in parts
+            parts[q] = tree(stage[beg:beg + cnt], 32)
             continue
         if need == 0:     # large shared entry: folded by the follow-up kernel
             assert it not in links and cnt > 8
@@ -141,8 +164,18 @@ def replay(plan, vals, pol, block, nnz, n_rows):
         key = ("b" if tgt >> 30 == 1 else "A", tgt & 0x3FFFFFFF)
         assert key not in out
         out[key] = s
-    assert not np.isnan(stage).any()
-    return out
+    # hub staging slots of local parts are never written; every other slot is
+    hubs = {}
+    pp = plan["part_ptr"]
+    for h in range(len(pp) - 1):
+        q0, q1 = int(pp[h]), int(pp[h + 1])
+        assert all(q in parts for q in range(q0, q1))
+        size = 1
+        while size < q1 - q0:
+            size *= 2
+        hubs[h] = tree([parts[q] for q in range(q0, q1)], size)
+    assert len(parts) == (int(pp[-1]) if len(pp) else 0)
+    return out, hubs
 
 
 def check_against_oracle(orc, circ, c, exclude, block):
@@ -151,7 +184,16 @@ def check_against_oracle(orc, circ, c, exclude, block):
     A0, b0 = orc.assemble(circ, rp, ci, NC, PC, AG0, col=col, exclude=exclude)
     plan = c.region_plan(block)
     vals = [merged_values(orc, circ, v) for v in range(circ.n_dev)]
-    out = replay(plan, vals, circ.pol, block, len(ci), circ.n_rows)
+    out, hubs = replay(plan, vals, circ.pol, block, len(ci), circ.n_rows)
+    # hub entries in ascending target order (A slots, then b rows), as the library
+    # numbers them; each equals the oracle's entry bit for bit
+    slot, sflag, brow, bflag = orc.stamp_map(circ, rp, ci, col, exclude)
+    targets = sorted({int(s) for s, f in zip(slot.ravel(), sflag.ravel()) if f == 2} |
+                     {len(ci) + int(r) for r, f in zip(brow.ravel(), bflag.ravel()) if f == 2})
+    assert len(targets) == len(hubs)
+    for h, tg in enumerate(targets):
+        ref = A0[tg] if tg < len(ci) else b0[tg - len(ci)]
+        assert np.float64(hubs[h]).view(np.int64) == np.float64(ref).view(np.int64), ("hub", h, hubs[h], ref)
     # a split netlist's series resistors: their linear part follows the schedule
     Lin, touched = orc.linear_stamp(circ, rp, ci)
     for (kind, idx), v in out.items():
@@ -235,7 +277,7 @@ def test_batch_plan_keeps_small_circuits_whole_and_replays(orc):
     vals, pol = [], np.concatenate([cc.pol for cc in circs])
     for cc in circs:
         vals += [merged_values(orc, cc, v) for v in range(cc.n_dev)]
-    out = replay(plan, vals, pol, 128, B.nnz, B.n_rows)
+    out, _ = replay(plan, vals, pol, 128, B.nnz, B.n_rows)
     for i, cc in enumerate(circs):
         col, _, _ = orc.colour(cc, True)
         rp, ci = orc.pattern(cc)
@@ -310,3 +352,22 @@ def test_lds_budget_moves_single_writer_entries_to_lane_folds(orc):
     assert plan["n_regions"] == 1 and plan["n_folds"] > 0 and (plan["fold"][:, 2] == 1).all()
     # slots left in LDS: at most 64 KiB - 1 KiB with the 20 x 256 merged-value rows
     assert plan["n_interior"] + 20 * 256 + 2 <= (65536 - 1024) // 8
+
+
+def test_chain_hub_parts_are_summed_inside_regions(orc):
+    # regions of 256 devices hold 128 PMOS, i.e. four whole parts of 32 contributions
+    # of each rail hub (the vdd diagonal and the vdd RHS row): no hub part is staged
+    circ = G.chain_case(5000, seed=12)
+    c = CS.prepare(circ, True)
+    c.set_plan_units(0)
+    plan = c.region_plan(256)
+    kinds = (plan["item"][:, 2].astype(np.int64) & 0xFFFFFFFF) >> 30
+    assert (kinds != 2).all()
+    assert len(plan["part_ptr"]) == 3 and int(plan["part_ptr"][-1]) == 2 * ((5000 + 31) // 32)
+    assert len(plan["hfold"]) == int(plan["part_ptr"][-1])
+    # the same chain cut for 32 compute units: the one-wave regions of the last round
+    # hold 32 PMOS each, still whole parts
+    c.set_plan_units(32)
+    plan = c.region_plan(256)
+    kinds = (plan["item"][:, 2].astype(np.int64) & 0xFFFFFFFF) >> 30
+    assert (kinds != 2).all()
