@@ -27,10 +27,11 @@ import numpy as np  # noqa: E402
 
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x FP64 lanes x clock: one op per lane-cycle
 KERNEL_OF = {"persistent": "k_persistent_* (one launch per step)",
-             "region": "k_region (one launch per step)",
+             "region": "k_region + k_hub_parts (one launch each per step)",
              "per_kernel": "k_colour_phase x colours + k_hub",
              "buffered": "k_eval_buffer + k_persistent_stamp",
              "atomic": "k_fill_zero + k_atomic",
+             "atomic_wave": "k_fill_zero + k_atomic_wave (hub entries summed per wave)",
              "serial": "k_fill_zero + k_eval_buffer + k_serial_stamp (one lane)"}
 PEAK_HBM = 8.0e12
 AG0 = 1e12
@@ -119,16 +120,17 @@ def algorithmic_counts(circ, exclude=True):
     """FP64 operations and bytes of one step of the coloured method (counted on the
     oracle's definition of the step).
 
-    ops: the oracle's operation counter over model M (+, -, *, /, sqrt each one),
-    plus the merge adds of devices with coinciding terminals, one add per load-add
-    stamp and the hub sums' adds.
+    ops: the oracle's operation counter over model M (+, -, *, /, sqrt each one)
+    less its size-dependent constants (computed once per parameter set, when the
+    parameters are set, not per step), plus the merge adds of devices with coinciding
+    terminals, one add per load-add stamp and the hub sums' adds.
     method_bytes: the fused coloured method's own HBM traffic per step, itemised per
-    device as the survey's measurement section lists it: W, L, VTH0 and the polarity
-    (25 B), four terminal indices (16 B), x read once (8 B per row), one 4-byte stamp
-    code per matrix slot-write, an 8-byte store per matrix slot-write, an 8-byte read
-    per load-add (slot-writes beyond the first writer of each entry), the same store
-    and read terms for the RHS writes, and every hub contribution staged and read
-    back (16 B).
+    device: the nine per-device model constants and the polarity (73 B), four terminal
+    indices (16 B), x read once (8 B per row), one 4-byte stamp code per matrix
+    slot-write, an 8-byte store per matrix slot-write, an 8-byte read per load-add
+    (slot-writes beyond the first writer of each entry), the same store and read terms
+    for the RHS writes, and for the hub entries one part per 32 contributions (summed
+    on chip), written and read back (16 B per part).
     floor_bytes: inputs once and outputs once (context only)."""
     from oracle import oracle as O
     from paper_2604_03079_amd import netgen as G
@@ -138,6 +140,9 @@ def algorithmic_counts(circ, exclude=True):
     O.assemble(circ, rp, ci, G.default_card(1), G.default_card(-1), AG0, col=col, exclude=exclude)
     model_ops = O.lib().or_ops()
     O.lib().or_count_ops(0)
+    # the size-dependent share is the same for every device (no branches)
+    sizedep = O.model_sizedep_opcount(G.default_card(1), 1, 1e-6, 45e-9, 0.4, [0.5, 0.5, 0.0, 0.0])
+    model_ops -= sizedep * circ.n_dev
     slot, sflag, brow, bflag = O.stamp_map(circ, rp, ci, col, exclude)
     merges = 0
     for t4 in circ.term:
@@ -157,10 +162,10 @@ def algorithmic_counts(circ, exclude=True):
     nbrow = int((bflag >= 0).sum())
     slots_written = int(np.unique(slot[sflag >= 0]).size)
     rows_written = int(np.unique(brow[bflag >= 0]).size)
-    hub_contrib = int((sflag == 2).sum() + (bflag == 2).sum())
-    items = dict(params=25 * n, terminals=16 * n, x=8 * circ.n_rows, stamp_codes=4 * nslot,
+    hub_parts = sum((m + 31) // 32 for m in hub_sizes.values())
+    items = dict(device_constants=73 * n, terminals=16 * n, x=8 * circ.n_rows, stamp_codes=4 * nslot,
                  A_stores=8 * nslot, A_load_add_reads=8 * (nslot - slots_written),
-                 b_stores=8 * nbrow, b_load_add_reads=8 * (nbrow - rows_written), hub_staging=16 * hub_contrib)
+                 b_stores=8 * nbrow, b_load_add_reads=8 * (nbrow - rows_written), hub_parts=16 * hub_parts)
     floor = n * (24 + 1 + 16) + 8 * circ.n_rows + 4 * (nslot + nbrow) + 8 * len(ci) + 8 * circ.n_rows
     return dict(ops=int(ops), model_ops=int(model_ops), method_bytes=int(sum(items.values())),
                 method_bytes_items=items, floor_bytes=int(floor), n_colors=int(C), n_dev=int(n))
@@ -470,7 +475,7 @@ def bench_adder(torch, CS, G, dev):
         circ = G.adder_case(64, seed=9, split=split)
         W, L, V, x = device_tensors(torch, circ, dev)
         row = {}
-        for variant in ("region", "persistent", "per_kernel", "buffered", "atomic", "serial"):
+        for variant in ("region", "persistent", "per_kernel", "buffered", "atomic", "atomic_wave", "serial"):
             c = CS.prepare(circ, exclude=excl)
             c.set_params(W, L, V)
             A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
@@ -483,7 +488,7 @@ def bench_adder(torch, CS, G, dev):
         out[key] = row
         log(f"  adder 64x28T {key:20s} C {row['n_colors']:4d}: " +
             ", ".join(f"{v} {row[v]['ms_per_step'] * 1e3:.1f} us" for v in
-                      ("region", "persistent", "per_kernel", "buffered", "atomic", "serial")))
+                      ("region", "persistent", "per_kernel", "buffered", "atomic", "atomic_wave", "serial")))
     return out
 
 
@@ -630,7 +635,7 @@ def main():
 
     variants = {}
     todo = (("persistent", True), ("persistent", False), ("per_kernel", True),
-            ("buffered", True), ("region", True), ("atomic", True))
+            ("buffered", True), ("region", True), ("atomic", True), ("atomic_wave", True))
     if args.only:
         todo = ((args.variant, True),)
     coop_main = not (args.only and args.ordinary)
@@ -697,7 +702,7 @@ def main():
         sram = G.workload(2)
         Ws, Ls, Vs, xs = device_tensors(torch, sram, dev)
         ex = {}
-        for variant in ("persistent", "per_kernel", "region", "atomic"):
+        for variant in ("persistent", "per_kernel", "region", "atomic", "atomic_wave"):
             c = CS.prepare(sram, exclude=True)
             c.set_params(Ws, Ls, Vs)
             A = torch.empty(c.nnz, dtype=torch.float64, device=dev)

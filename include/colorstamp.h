@@ -72,10 +72,15 @@ typedef enum {
                                  folded in colour order by the last contributing
                                  region.  Same bits as CS_COLOR_PERSISTENT; no
                                  grid-wide barrier. */
-    CS_SERIAL_STAMP = 5       /* loadomp: evaluate every device into a buffer in
+    CS_SERIAL_STAMP = 5,      /* loadomp: evaluate every device into a buffer in
                                  parallel, then one lane adds every device's values in
                                  ascending device index onto zeroed A and b (the serial
                                  order of accumulation, hub entries included). */
+    CS_ATOMIC_WAVE = 6        /* comparison: CS_ATOMIC with each wave's contributions to
+                                 a hub (rail) entry summed over the wave first and added
+                                 with one atomic, so that the comparison measures
+                                 lock-free stamping rather than contention on the
+                                 rails (without excluded rails it equals CS_ATOMIC) */
 } cs_variant;
 
 /* Model card of the BSIM4-core subset (SI units).  One card per polarity.  The

@@ -47,6 +47,8 @@ long long or_opcount_ = 0;
 int or_counting_ = 0;
 void or_count_ops(int on) { or_counting_ = on; or_opcount_ = 0; }
 long long or_ops(void) { return or_opcount_; }
+long long or_sizedep_ops_ = 0;
+long long or_sizedep_ops(void) { return or_sizedep_ops_; }
 
 double or_pexp(double a) {
     double k = rint(a * INV_LN2);

@@ -18,6 +18,8 @@
 #define S_PLOG1P or_cplog1p
 #define S_RE(x) creal(x)
 #define CNT(n) ((void)0)
+#define SIZEDEP_BEGIN ((void)0)
+#define SIZEDEP_END ((void)0)
 #define WITH_TRACE 0
 #include "model_m.inc"
 

@@ -15,6 +15,8 @@
 #define S_PLOG1P or_plog1p
 #define S_RE(x) (x)
 #define CNT(n) OR_COUNT(n)
+#define SIZEDEP_BEGIN const long long sizedep0_ = or_opcount_
+#define SIZEDEP_END or_sizedep_ops_ = or_opcount_ - sizedep0_
 #define WITH_TRACE 1
 #include "model_m.inc"
 

@@ -50,6 +50,9 @@ void or_elem_array(int kind, const double *x, double *y, int64_t n);
 /* FP64 operation counter for model M (+, -, *, /, sqrt each count 1). */
 void or_count_ops(int on);
 long long or_ops(void);
+/* Operations of the size-dependent constants (W, L, VTH0 only) in the last counted
+ * device evaluation: work done once per parameter set, not per Newton iteration. */
+long long or_sizedep_ops(void);
 
 /* One device: V = terminal voltages (d, g, s, b).  Outputs Y[4][4] row-major
  * (rows/cols d, g, s, b), bl[4], physical terminal currents I[4] and charges Q[4].

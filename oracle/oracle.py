@@ -47,6 +47,7 @@ def lib():
             getattr(_lib, name).restype = d
             getattr(_lib, name).argtypes = [d]
         _lib.or_ops.restype = C.c_longlong
+        _lib.or_sizedep_ops.restype = C.c_longlong
         _lib.or_count_ops.argtypes = [C.c_int]
         _lib.or_device_eval.argtypes = [p, C.c_int, d, d, d, p, d, p, p, p, p, p, p]
         _lib.or_colour.argtypes = [i32, i32, p, p, p, p, p]
@@ -149,6 +150,16 @@ def model_opcount(cd: dict, pol: int, W, L, VTH0, V, ag0=1e12, hist=None) -> int
     lib().or_count_ops(1)
     device_eval(cd, pol, W, L, VTH0, V, ag0, hist)
     n = lib().or_ops()
+    lib().or_count_ops(0)
+    return int(n)
+
+
+def model_sizedep_opcount(cd: dict, pol: int, W, L, VTH0, V, ag0=1e12, hist=None) -> int:
+    """The share of model_opcount spent on the size-dependent constants (W, L, VTH0
+    only), which a simulator computes once per parameter set."""
+    lib().or_count_ops(1)
+    device_eval(cd, pol, W, L, VTH0, V, ag0, hist)
+    n = lib().or_sizedep_ops()
     lib().or_count_ops(0)
     return int(n)
 

@@ -8,6 +8,7 @@
 #include "oracle.h"
 
 extern long long or_opcount_;
+extern long long or_sizedep_ops_;
 extern int or_counting_;
 #define OR_COUNT(n) do { if (or_counting_) or_opcount_ += (n); } while (0)
 

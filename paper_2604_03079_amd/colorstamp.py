@@ -17,7 +17,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libcolorstamp.so")
 
-VARIANTS = {"persistent": 0, "per_kernel": 1, "atomic": 2, "buffered": 3, "region": 4, "serial": 5}
+VARIANTS = {"persistent": 0, "per_kernel": 1, "atomic": 2, "buffered": 3, "region": 4, "serial": 5,
+            "atomic_wave": 6}
 STATUS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EHIP", -4: "CS_ESTATE",
           -5: "CS_ENOTSUP", -6: "CS_EDOMAIN"}
 CARD_FIELDS = ("tnom", "toxe", "ndep", "phis", "vbi", "k1", "k2", "k3", "w0", "dvt0", "dvt1",

@@ -573,6 +573,9 @@ static cs_status eval_devices(cs_circuit *c, cs_variant variant, const KCall &ca
         case CS_ATOMIC:
             CS_CHECK_HIP(launch_atomic(kc, call, c->h.nnz, c->h.n_rows, s), "atomic launch");
             return CS_OK;
+        case CS_ATOMIC_WAVE:
+            CS_CHECK_HIP(launch_atomic_wave(kc, call, c->h.nnz, c->h.n_rows, s), "atomic launch");
+            return CS_OK;
         case CS_SERIAL_STAMP: {
             const HostCircuit &h = c->h;
             if (c->d_buf.n < (size_t)NCODE * h.n_dev)

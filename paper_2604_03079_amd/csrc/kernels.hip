@@ -630,6 +630,49 @@ __global__ void __launch_bounds__(256) k_atomic(KCirc kc, KCall call) {
     fixed_stores(kc, call, gtid, nthr);
 }
 
+// Atomic variant with wave-level pre-reduction of the hub (rail) entries: every
+// other contribution is an FP64 atomic add as in k_atomic; a wave's contributions to
+// one hub target are summed over the wave (a butterfly) and added by one lane.
+template <bool J>
+__global__ void __launch_bounds__(256) k_atomic_wave(KCirc kc, KCall call) {
+    constexpr int HS = 4;
+    const int lane = threadIdx.x & 63;
+    const int nthr = gridDim.x * blockDim.x;
+    // wave-uniform trip count: every lane of a wave takes part in the reductions
+    for (int base = blockIdx.x * blockDim.x + ((int)threadIdx.x & ~63); base < kc.n; base += nthr) {
+        const int pos = base + lane;
+        AtomicHubSink<HS> sink{kc.acode, kc.code, kc.n, pos, call.A, call.b};
+        if (pos < kc.n) {
+            const DevIn d = load_terms(kc, pos);
+            const DevOut o = eval_pos<J>(kc, call, pos, d);
+            double Y[16];
+            full_Y(o, Y);
+            const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
+            emit_merged(d.key, Y, bl, sink);
+        }
+#pragma unroll
+        for (int s = 0; s < HS; ++s) {
+            int32_t t = s < sink.nh ? sink.tgt[s] : -1;
+            const double v = s < sink.nh ? sink.val[s] : -0.0;
+            uint64_t act = __ballot(t != -1);
+            while (act) {
+                const int leader = __builtin_ctzll(act);
+                const int32_t t0 = __shfl(t, leader, 64);
+                double x = t == t0 ? v : -0.0;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) x = x + __shfl_xor(x, off, 64);
+                if (lane == leader) {
+                    const uint32_t u = (uint32_t)t0;
+                    (void)unsafeAtomicAdd((u & HUB_B_FLAG ? call.b : call.A) + (u & ~HUB_B_FLAG), x);
+                }
+                if (t == t0) t = -1;
+                act = __ballot(t != -1);
+            }
+        }
+    }
+    fixed_stores(kc, call, blockIdx.x * blockDim.x + threadIdx.x, nthr);
+}
+
 // ---- region schedule ------------------------------------------------------------
 // One workgroup per region.  The region's devices are evaluated at once (NMOS lanes
 // first, then PMOS lanes) and their merged values parked in LDS rows.  An entry
@@ -1202,6 +1245,19 @@ hipError_t launch_serial(const KCirc &kc, const KCall &call, int64_t nnz, int64_
     if (e != hipSuccess) return e;
     if ((e = launch_eval_buffer(kc, call, buf, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_serial_stamp, dim3(1), dim3(64), 0, s, kc, call, buf, ipos);
+    return hipGetLastError();
+}
+
+hipError_t launch_atomic_wave(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows, hipStream_t s) {
+    const int64_t tot = nnz + n_rows;
+    const int gz = (int)std::min<int64_t>((tot + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_zero, dim3(std::max(gz, 1)), dim3(256), 0, s, call.A, nnz, call.b, n_rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int grid = (kc.n + 255) / 256;
+    grid = std::max(grid, std::min(1024, (kc.n_fixA + kc.n_fixB + 255) / 256));
+    if (junctions(kc)) hipLaunchKernelGGL(k_atomic_wave<true>, dim3(std::max(grid, 1)), dim3(256), 0, s, kc, call);
+    else hipLaunchKernelGGL(k_atomic_wave<false>, dim3(std::max(grid, 1)), dim3(256), 0, s, kc, call);
     return hipGetLastError();
 }
 

@@ -87,5 +87,7 @@ hipError_t launch_serial(const KCirc &kc, const KCall &call, int64_t nnz, int64_
                          const int32_t *ipos, hipStream_t s);
 hipError_t launch_atomic(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows,
                          hipStream_t s);
+// The atomic variant with each wave's hub-entry contributions summed before its atomic.
+hipError_t launch_atomic_wave(const KCirc &kc, const KCall &call, int64_t nnz, int64_t n_rows, hipStream_t s);
 
 }  // namespace cs

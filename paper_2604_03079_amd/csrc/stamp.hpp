@@ -231,6 +231,43 @@ struct AtomicSink {
     }
 };
 
+// Atomic stamping with hub entries held back: an entry whose colour code marks it a
+// hub (a rail entry every device on that rail writes) is recorded in the lane (up to
+// HS of them, the rest added at once); the kernel then sums each hub target over the
+// wave and adds the sum with one atomic, so the rails take one atomic per wave
+// instead of one per device.
+template <int HS>
+struct AtomicHubSink {
+    static constexpr bool kStreaming = false;
+    const int32_t *acode;
+    const int32_t *code;
+    int32_t n, pos;
+    double *A, *b;
+    int nh = 0;
+    int32_t tgt[HS];   // A index, or b row | HUB_B_FLAG
+    double val[HS];
+    template <int NA, int NB>
+    __device__ __forceinline__ void stamp(const double *m) {
+#pragma unroll
+        for (int j = 0; j < NA + NB; ++j) {
+            const int32_t idx = acode[(size_t)j * n + pos];
+            const bool hub = ((uint32_t)code[(size_t)j * n + pos] >> 30) == TAG_HUB;
+            if (hub && nh < HS) {
+                const int32_t t = j >= NA ? (int32_t)((uint32_t)idx | HUB_B_FLAG) : idx;
+#pragma unroll
+                for (int s = 0; s < HS; ++s)
+                    if (s == nh) {
+                        tgt[s] = t;
+                        val[s] = m[j];
+                    }
+                ++nh;
+            } else {
+                (void)unsafeAtomicAdd((j >= NA ? b : A) + idx, m[j]);
+            }
+        }
+    }
+};
+
 // LDS row sink (region schedule): merged value j of a lane goes to p[j * stride].
 struct LdsRowSink {
     static constexpr bool kStreaming = true;

@@ -116,10 +116,12 @@ def test_atomic_within_reordering_bound(torch_dev, orc, name, circ):
     rp, ci = orc.pattern(circ)
     As, bs = orc.assemble(circ, rp, ci, NC, PC, 1e12)
     mA, mb = orc.assemble_magnitude(circ, rp, ci, NC, PC, 1e12)
-    say(f"case {name} variant=atomic")
-    A, b, _ = gpu_stamp(torch_dev, circ, True, "atomic")
-    assert np.all(np.abs(A - As) <= 1e-12 * mA)
-    assert np.all(np.abs(b - bs) <= 1e-12 * mb)
+    for exclude in (True, False):
+        for variant in ("atomic", "atomic_wave"):
+            say(f"case {name} exclude={exclude} variant={variant}")
+            A, b, _ = gpu_stamp(torch_dev, circ, exclude, variant)
+            assert np.all(np.abs(A - As) <= 1e-12 * mA), variant
+            assert np.all(np.abs(b - bs) <= 1e-12 * mb), variant
 
 
 SERIAL = SMALL[:9] + [s for s in SMALL if s[0] in ("adder8r89", "adder8r14", "random600x6r")]
@@ -203,10 +205,11 @@ def test_full_size_workloads(torch_dev, orc, idx):
     rp, ci = orc.pattern(circ)
     As, bs = orc.assemble(circ, rp, ci, NC, PC, 1e12)
     mA, mb = orc.assemble_magnitude(circ, rp, ci, NC, PC, 1e12)
-    say(f"case workload{idx} variant=atomic")
-    A, b, _ = gpu_stamp(torch_dev, circ, True, "atomic")
-    assert np.all(np.abs(A - As) <= 1e-12 * mA)
-    assert np.all(np.abs(b - bs) <= 1e-12 * mb)
+    for variant in ("atomic", "atomic_wave"):
+        say(f"case workload{idx} variant={variant}")
+        A, b, _ = gpu_stamp(torch_dev, circ, True, variant)
+        assert np.all(np.abs(A - As) <= 1e-12 * mA), variant
+        assert np.all(np.abs(b - bs) <= 1e-12 * mb), variant
 
 
 def test_full_size_strict_chain(torch_dev, orc):

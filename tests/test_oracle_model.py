@@ -245,3 +245,13 @@ def test_inverter_transfer_point(orc):
 def test_operation_count(orc):
     n = orc.model_opcount(NC, 1, 1e-6, 45e-9, 0.4, [0.7, 0.9, 0.1, 0.0], 1e12)
     assert 700 < n < 1000
+    # the size-dependent constants, counted by hand from their formulas (products of
+    # card values alone, such as 2 WINT or (K3 TOXE) PHIS, are card constants, not
+    # per-device work): Weff, Leff, VTH0i (3); theta_sce and theta_dibl: a product, a
+    # quotient, pcosh, a difference and a quotient each (4 + pcosh), pcosh = pexp (the
+    # argument's product, rint-free Cody-Waite reduction 4 ops, 13 Horner steps of 2)
+    # + 3; vth_s: DVT0 theta_sce, its product with (VBI - PHIS), the difference, Weff +
+    # W0, the quotient, the sum (6); beta0, lambda, AbL, Cg, Cov (2 + 1 + 3 + 2 + 1)
+    pexp = 5 + 2 * 13
+    assert orc.model_sizedep_opcount(NC, 1, 1e-6, 45e-9, 0.4, [0.7, 0.9, 0.1, 0.0], 1e12) == \
+        3 + 2 * (4 + pexp + 3) + 6 + (2 + 1 + 3 + 2 + 1)
