@@ -273,8 +273,13 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel, 
                 if base(r["Kernel_Name"]).endswith(name) and r["Counter_Name"] == counter]
         return sum(vals) / len(vals), len(vals)
 
-    kf, nf = per_dispatch(fetch_csv, kernel, "FETCH_SIZE")
-    kw, nw = per_dispatch(write_csv, kernel, "WRITE_SIZE")
+    # the kernels of one step: their per-dispatch averages add up
+    kf = kw = 0.0
+    nf = nw = 0
+    for name in kernel.split(","):
+        f_, n_ = per_dispatch(fetch_csv, name, "FETCH_SIZE")
+        w_, m_ = per_dispatch(write_csv, name, "WRITE_SIZE")
+        kf, kw, nf, nw = kf + f_, kw + w_, max(nf, n_), max(nw, m_)
     cf, _ = per_dispatch(copy_fetch_csv, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
     cw, _ = per_dispatch(copy_write_csv, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
     copy_bytes = copy_mib * (1 << 20)
@@ -592,7 +597,10 @@ def main():
                     help="run only the colour-count sweep and print it as one JSON line")
     ap.add_argument("--newton", action="store_true",
                     help="run only the Newton-loop leg (stamp, refactorisation, solve) and print its JSON")
-    ap.add_argument("--pmc-kernel", default="k_region")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the 512-circuit batched step, region schedule, block 256 (profiling runs)")
+    ap.add_argument("--pmc-kernel", default="k_region,k_hub_parts",
+                    help="kernels of one step (comma-separated) whose counters --summarize-pmc sums")
     ap.add_argument("--pmc-key", default="region_chain100k")
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -621,6 +629,20 @@ def main():
     if args.newton:
         print(json.dumps({"newton": bench_newton(torch, CS, G, dev), "kernel_sources": kernel_sources_hash()}),
               flush=True)
+        return
+    if args.batch_only:
+        circs = G.workload(3)
+        B = CS.Batch([CS.prepare(c, exclude=True) for c in circs])
+        B.set_launch(256, -1, 0, schedule="region")
+        cat = lambda a: torch.from_numpy(np.concatenate([getattr(c, a) for c in circs])).to(dev)
+        W, L, V, x = cat("W"), cat("L"), cat("VTH0"), cat("x")
+        B.set_params(W, L, V)
+        A = torch.empty(B.nnz, dtype=torch.float64, device=dev)
+        b = torch.empty(B.n_rows, dtype=torch.float64, device=dev)
+        ms = time_eager(torch, lambda: B.eval_stamp(x, AG0, None, A, b), args.steps, args.warmup)
+        B.check()
+        log(f"batch 512 region block 256: {ms * 1e3:.1f} us per step ({args.steps} steps)")
+        release(torch, B)
         return
     if args.csweep:
         rows = bench_csweep(torch, CS, G, dev, steps=args.steps)

@@ -96,9 +96,12 @@ __device__ __forceinline__ Tan operator+(Tan a, Tan b) { return {a.v + b.v, a.t 
 __device__ __forceinline__ Tan operator-(Tan a, Tan b) { return {a.v - b.v, a.t - b.t}; }
 __device__ __forceinline__ Tan operator-(Tan a) { return {-a.v, -a.t}; }
 __device__ __forceinline__ Tan operator*(Tan a, Tan b) { return {a.v * b.v, a.t * b.v + a.v * b.t}; }
+// Quotients take one reciprocal (the adjoint's tangents are checked against the
+// complex-step gradient to a relative tolerance, not bit for bit).
 __device__ __forceinline__ Tan operator/(Tan a, Tan b) {
-    const double q = a.v / b.v;
-    return {q, (a.t - q * b.t) / b.v};
+    const double r = 1.0 / b.v;
+    const double q = a.v * r;
+    return {q, (a.t - q * b.t) * r};
 }
 __device__ __forceinline__ Tan operator+(Tan a, double b) { return {a.v + b, a.t}; }
 __device__ __forceinline__ Tan operator+(double a, Tan b) { return {a + b.v, b.t}; }
@@ -108,8 +111,9 @@ __device__ __forceinline__ Tan operator*(double a, Tan b) { return {a * b.v, a *
 __device__ __forceinline__ Tan operator*(Tan a, double b) { return {a.v * b, a.t * b}; }
 __device__ __forceinline__ Tan operator/(Tan a, double b) { return {a.v / b, a.t / b}; }
 __device__ __forceinline__ Tan operator/(double a, Tan b) {
-    const double q = a / b.v;
-    return {q, (-(q * b.t)) / b.v};
+    const double r = 1.0 / b.v;
+    const double q = a * r;
+    return {q, (-(q * b.t)) * r};
 }
 
 __device__ __forceinline__ double val(double x) { return x; }
