@@ -446,7 +446,7 @@ def bench_batch(torch, CS, G, dev):
     B.check()
     counts = add_counts([algorithmic_counts(c) for c in circs])
     roof = roofline(counts, ms_e, traffic_from_profiles(kernel_sources_hash(), "batch512"),
-                    "k_region (one launch per batched step)" if best["schedule"] == "region"
+                    "k_region + k_hub_parts (one launch each per batched step)" if best["schedule"] == "region"
                     else "k_persistent_* (one launch per batched step)")
     log(f"  batch 512 roofline: {roof['bound']} {roof['achieved']} {roof['unit']} = {roof['frac']:.3f} of peak "
         f"(t_FP64 {roof['t_fp64_us']} us, t_HBM {roof['t_hbm_us']} us, kernel {roof['kernel_avg_us']} us)")
@@ -520,7 +520,7 @@ def bench_csweep(torch, CS, G, dev, steps=20):
         circ = make()
         W, L, V, x = device_tensors(torch, circ, dev)
         row = dict(case=name, n_dev=circ.n_dev, rails_excluded=excl)
-        for variant in ("region", "persistent", "per_kernel", "atomic"):
+        for variant in ("region", "persistent", "per_kernel", "atomic", "atomic_wave"):
             c = CS.prepare(circ, exclude=excl)
             row["n_colors"] = c.info()["n_colors"]
             many = row["n_colors"] > SWEEP_MAX_PHASES
