@@ -36,12 +36,15 @@ void or_device_dparam_h(const or_card *card, int pol, double W, double L, double
     for (int j = 0; j < 4; ++j) dbl[j] = cimag(bl[j]) / h;
 }
 
+/* mode 0: the gradient; 1: sum of |cotangent * sensitivity| over the device's
+ * stamped entries; 2: the largest |cotangent| of the device times the sum of |d/dtheta|
+ * over all 16 local entries and 4 local RHS values (ground terminals included). */
 static int vjp_impl(int32_t n_dev, const int32_t *term, const int8_t *pol,
                     const or_card *nmos, const or_card *pmos, const double *W, const double *L,
                     const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
                     const double *x, double ag0, const double *hist, const double *A_bar,
                     const double *b_bar, double *W_bar, double *L_bar, double *VTH0_bar,
-                    int magnitude) {
+                    int mode) {
     for (int32_t v = 0; v < n_dev; ++v) {
         const int32_t *t4 = term + 4 * (int64_t)v;
         double V[4];
@@ -51,16 +54,26 @@ static int vjp_impl(int32_t n_dev, const int32_t *term, const int8_t *pol,
             double dY[16], dbl[4];
             or_device_dparam(pol[v] > 0 ? nmos : pmos, pol[v], W[v], L[v], VTH0[v], V, ag0,
                              hist ? hist + 4 * (int64_t)v : NULL, which, dY, dbl);
-            double g = 0.0;
+            double g = 0.0, cmax = 0.0;
             for (int t = 0; t < 4; ++t) {
                 if (t4[t] == 0) continue;
                 for (int s = 0; s < 4; ++s) {
                     if (t4[s] == 0) continue;
                     int64_t sl = or_find_slot(row_ptr, col_idx, t4[t] - 1, t4[s] - 1);
                     if (sl < 0) return -3;
-                    g += magnitude ? fabs(A_bar[sl] * dY[t * 4 + s]) : A_bar[sl] * dY[t * 4 + s];
+                    const double term_ts = A_bar[sl] * dY[t * 4 + s];
+                    g += mode == 0 ? term_ts : fabs(term_ts);
+                    if (fabs(A_bar[sl]) > cmax) cmax = fabs(A_bar[sl]);
                 }
-                g += magnitude ? fabs(b_bar[t4[t] - 1] * dbl[t]) : b_bar[t4[t] - 1] * dbl[t];
+                const double term_t = b_bar[t4[t] - 1] * dbl[t];
+                g += mode == 0 ? term_t : fabs(term_t);
+                if (fabs(b_bar[t4[t] - 1]) > cmax) cmax = fabs(b_bar[t4[t] - 1]);
+            }
+            if (mode == 2) {
+                double sum = 0.0;
+                for (int j = 0; j < 16; ++j) sum += fabs(dY[j]);
+                for (int j = 0; j < 4; ++j) sum += fabs(dbl[j]);
+                g = cmax * sum;
             }
             *out[which] = g;
         }
@@ -88,4 +101,21 @@ int or_vjp_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term, const 
     (void)n_nodes;
     return vjp_impl(n_dev, term, pol, nmos, pmos, W, L, VTH0, row_ptr, col_idx, x, ag0, hist, A_bar,
                     b_bar, W_mag, L_mag, VTH0_mag, 1);
+}
+
+/* Per device, the largest |cotangent| over its stamped entries and rows times the
+ * sum of |d/dtheta| over all its local outputs: the scale of the numbers its
+ * sensitivities are formed from.  Entries of the source row and column are negated
+ * sums of the others (conservation), and the RHS adds Y (V - V_s) to the currents
+ * and charges, so where those cancel (a sensitivity at rounding level beside large
+ * ones, e.g. beside an unstamped ground-terminal entry) the oracle's own value is
+ * decided by rounding at this scale. */
+int or_vjp_round_scale(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                       const or_card *nmos, const or_card *pmos, const double *W, const double *L,
+                       const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+                       const double *x, double ag0, const double *hist, const double *A_bar,
+                       const double *b_bar, double *W_s, double *L_s, double *VTH0_s) {
+    (void)n_nodes;
+    return vjp_impl(n_dev, term, pol, nmos, pmos, W, L, VTH0, row_ptr, col_idx, x, ag0, hist, A_bar,
+                    b_bar, W_s, L_s, VTH0_s, 2);
 }

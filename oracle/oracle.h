@@ -146,6 +146,15 @@ int or_vjp_magnitude(int32_t n_nodes, int32_t n_dev, const int32_t *term, const 
                      const double *x, double ag0, const double *hist, const double *A_bar,
                      const double *b_bar, double *W_mag, double *L_mag, double *VTH0_mag);
 
+/* Per device, max |cotangent| over its stamped entries and rows times the sum of
+ * |d(local output)/d(theta)| over all 16 local entries and 4 RHS values: the rounding
+ * scale of its sensitivities where conservation sums cancel. */
+int or_vjp_round_scale(int32_t n_nodes, int32_t n_dev, const int32_t *term, const int8_t *pol,
+                       const or_card *nmos, const or_card *pmos, const double *W, const double *L,
+                       const double *VTH0, const int32_t *row_ptr, const int32_t *col_idx,
+                       const double *x, double ag0, const double *hist, const double *A_bar,
+                       const double *b_bar, double *W_s, double *L_s, double *VTH0_s);
+
 /* Per-device local sensitivities d(Y, bl)/d(theta) by complex step, theta = 0 (W),
  * 1 (L), 2 (VTH0).  dY[16], dbl[4].  The step is i * 1e-20 * |theta|; the _h form
  * takes the relative step (two steps give two exact derivatives of the same rounded

@@ -63,6 +63,7 @@ def lib():
         _lib.or_hubsum.argtypes = [p, i64]
         _lib.or_vjp.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_vjp_magnitude.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
+        _lib.or_vjp_round_scale.argtypes = [i32, i32, p, p, p, p, p, p, p, p, p, p, d, p, p, p, p, p, p]
         _lib.or_device_dparam.argtypes = [p, C.c_int, d, d, d, p, d, p, C.c_int, p, p]
         _lib.or_device_dparam_h.argtypes = [p, C.c_int, d, d, d, p, d, p, C.c_int, d, p, p]
         _lib.or_elem_array.argtypes = [C.c_int, p, p, i64]
@@ -310,6 +311,9 @@ def hubsum(c) -> float:
 
 def vjp(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, A_bar, b_bar, hist=None,
         x=None, W=None, L=None, VTH0=None, magnitude=False):
+    """Per-device gradient of <A_bar, A> + <b_bar, b> w.r.t. (W, L, VTH0); with
+    magnitude=True the sum of |cotangent * sensitivity| over each device's entries,
+    with magnitude="round" the device's rounding scale (or_vjp_round_scale)."""
     term = np.ascontiguousarray(circ.term, dtype=np.int32)
     pol = np.ascontiguousarray(circ.pol, dtype=np.int8)
     xx = np.ascontiguousarray(circ.x if x is None else x, dtype=np.float64)
@@ -321,7 +325,7 @@ def vjp(circ, rp, ci, nmos: dict, pmos: dict, ag0: float, A_bar, b_bar, hist=Non
     bb = np.ascontiguousarray(b_bar, dtype=np.float64)
     gW = np.zeros(circ.n_dev); gL = np.zeros(circ.n_dev); gV = np.zeros(circ.n_dev)
     cn, cp = card(nmos), card(pmos)
-    fn = lib().or_vjp_magnitude if magnitude else lib().or_vjp
+    fn = {False: lib().or_vjp, True: lib().or_vjp_magnitude, "round": lib().or_vjp_round_scale}[magnitude]
     rc = fn(circ.n_nodes, circ.n_dev, _ptr(term), _ptr(pol), C.byref(cn), C.byref(cp),
                       _ptr(Wa), _ptr(La), _ptr(Va), _ptr(rp), _ptr(ci), _ptr(xx), float(ag0),
                       _ptr(h), _ptr(Ab), _ptr(bb), _ptr(gW), _ptr(gL), _ptr(gV))

@@ -5,9 +5,11 @@ oracle scales: per entry of A and b, the sum over devices of |merged contributio
 (the scale of the rounding difference between two accumulation orders,
 or_assemble_magnitude), and per device, the sum over its entries of
 |cotangent * d(entry)/d(parameter)| (the scale of a gradient summed in another
-order, or_vjp_magnitude).  Both are recomputed here from scratch, from one
-single-device evaluation at a time and this file's own merge and scatter, so that a
-wrong factor, a dropped term or a misplaced entry in either scale fails.  The
+order, or_vjp_magnitude), with a floor at the device's rounding scale (its largest
+|cotangent| times the sum of |sensitivity| over all its local outputs,
+or_vjp_round_scale).  All are recomputed here from scratch, from one single-device
+evaluation at a time and this file's own merge and scatter, so that a wrong factor,
+a dropped term or a misplaced entry in any scale fails.  The
 threaded colour replay (the CPU baseline's all-core leg) must give the serial
 replay's bits."""
 import numpy as np
@@ -135,6 +137,29 @@ def test_vjp_magnitude_is_the_sum_of_absolute_terms(orc, name, circ):
         assert np.array_equal(mags[which], m)
         assert np.array_equal(grads[which], g)
         assert np.all(np.abs(grads[which]) <= mags[which])
+
+
+@pytest.mark.parametrize("name,circ", CASES, ids=[c[0] for c in CASES])
+def test_vjp_round_scale_is_max_cotangent_times_all_local_sensitivities(orc, name, circ):
+    rp, ci = orc.pattern(circ)
+    Ab, bb = G.cotangents(len(ci), circ.n_rows, seed=50)
+    scales = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb, magnitude="round")
+    mags = orc.vjp(circ, rp, ci, NC, PC, 1e12, Ab, bb, magnitude=True)
+    for which in range(3):
+        s = np.zeros(circ.n_dev)
+        for v in range(circ.n_dev):
+            dY, dbl = orc.device_dparam(NC if circ.pol[v] > 0 else PC, int(circ.pol[v]), circ.W[v], circ.L[v],
+                                        circ.VTH0[v], volts(circ, v), 1e12, None, which)
+            t4 = [int(n) for n in circ.term[v]]
+            cots = [abs(Ab[slot_of(rp, ci, t4[t] - 1, t4[u] - 1)]) for t in range(4) for u in range(4)
+                    if t4[t] and t4[u]] + [abs(bb[t4[t] - 1]) for t in range(4) if t4[t]]
+            # every local output counts, those of ground terminals too
+            s[v] = max(cots, default=0.0) * (float(np.abs(dY).sum()) + float(np.abs(dbl).sum()))
+        np.testing.assert_allclose(scales[which], s, rtol=1e-14, atol=0.0)
+        # it bounds the sum of |cotangent * sensitivity| over the stamped entries
+        assert np.all(mags[which] <= scales[which] * (1 + 1e-12))
+    # a device with every terminal on ground has no cotangent and no scale
+    assert np.all(scales[0][np.all(circ.term == 0, axis=1)] == 0.0)
 
 
 THREAD_CASES = [
