@@ -2,13 +2,28 @@
 // device's W, L and VTH0.
 //
 // A and b are sums of per-device contributions, each depending on its own device's
-// parameters only, so the gradient of <A_bar, A> + <b_bar, b> w.r.t. theta_k is
-//   sum_{(t,u)} A_bar[slot(t,u)] dY_k[t][u]/dtheta_k + sum_t b_bar[row(t)] dbl_k[t]/dtheta_k
-// over the device's non-ground terminals.  The cotangents are gathered through the
-// device's slot map (no colouring, no atomics: every gradient entry has one writer),
-// and a forward-mode sweep of the model per parameter (the tangent of W, L or VTH0
-// carried alongside every value and partial) recomputes the intermediates instead
-// of storing them.
+// parameters only, so the gradient of S = <A_bar, A> + <b_bar, b> w.r.t. theta is,
+// per device, the derivative of
+//   S_dev = sum_{t,u} A_bar[t][u] Y[t][u] + sum_t b_bar[t] b_loc[t]
+// over its terminals t, u (cotangents gathered through the device's slot map: no
+// colouring, no atomics, every gradient entry has one writer).  With G_t = I_t +
+// ag0 Q_t the terminal's current, Y[t][u] = dG_t/dV_u and b_loc[t] = sum_u Y[t][u]
+// (V_u - V_s) - G_t + hist_t, so
+//   S_dev = sum_t ( D_{U_t} G_t - b_bar[t] G_t ) + const,
+//   U_t[u] = A_bar[t][u] + b_bar[t] (V_u - V_s)   (V_s - V_s = 0),
+// where D_U is the derivative along the voltage direction U.  Written out over the
+// channel's functions, S_dev needs only
+//   * Ids and its derivative along U_d - U_s,
+//   * hQ (half the inversion charge) and its derivative along U_d + U_s - 2 U_g,
+//   * Qb, the overlap charges and the junctions, which depend on the parameters
+//     through one per-device constant each (Cg, Cov, Aj) linearly.
+// So the adjoint evaluates the channel with two directional partials instead of the
+// three voltage partials, and differentiates w.r.t. the parameters in forward mode:
+// W and VTH0 act on the nonlinear part only through the threshold constant vth_s,
+// L through several constants, so two sweeps cover the three parameters:
+//   sweep 0: tangent d/d vth_s; dS/dVTH0 = pol dS/dvth_s, and dS/dW adds the
+//            linear terms of beta0 (Ids is proportional to it), Cg, Cov and Aj;
+//   sweep 1: tangent d/dL through every per-device constant.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,17 +77,154 @@ __device__ __forceinline__ void gather_cotangents(int key, const int32_t *acode,
     }
 }
 
-// One (device, parameter) pair per thread: thread i takes parameter dir = i / n of
-// device position i % n, so the three forward-mode sweeps of a device run in three
-// lanes at once (a wave holds one parameter and consecutive devices).
+// dS/dAj: the junctions of unit area (their currents, charges and conductances are
+// proportional to the area).  The drain-body junction adds J0 = I + ag0 Q at v0 =
+// p (V_b - V_d) to G_b and subtracts it from G_d, and dJ0/dV = jy (e_b - e_d).
+__device__ __forceinline__ double vjp_junction(const DevCard &cd, double p, const double V[4], double ag0,
+                                               const double Yb[16], const double bb[4]) {
+    double s = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int t = side == 0 ? 0 : 2;   // the diffusion terminal
+        double ij, gj, qj, cj;
+        junction(cd, 1.0, p * (V[3] - V[t]), ij, gj, qj, cj);
+        const double J = p * ij + ag0 * (p * qj);
+        const double jy = gj + ag0 * cj;
+        const double db = V[3] - V[2], dt = V[t] - V[2];
+        // (U_b - U_t)[b] - (U_b - U_t)[t], U_x[u] = A_bar[x][u] + b_bar[x] (V_u - V_s)
+        const double Ubb = Yb[12 + 3] + bb[3] * db, Ubt = Yb[12 + t] + bb[3] * dt;
+        const double Utb = Yb[t * 4 + 3] + bb[t] * db, Utt = Yb[t * 4 + t] + bb[t] * dt;
+        s += jy * ((Ubb - Utb) - (Ubt - Utt)) - (bb[3] - bb[t]) * J;
+    }
+    return s;
+}
+
+// Sensitivities of one device's S_dev: g w.r.t. the tangent the constants k carry,
+// and the value-level factors of the constants that enter linearly (W_TERMS: those
+// W moves; otherwise only s_qb, since L moves Cg but neither Cov nor Aj).
+struct VjpParts {
+    double g;       // dS/dtheta through the channel (the tangent of k)
+    double s_beta;  // dS/dbeta0
+    double s_hq;    // dS/dCg through hQ
+    double s_qb;    // dS/dCg through Qb
+    double s_cov;   // dS/dCov
+    double s_aj;    // dS/dAj (with_junction only)
+};
+
+template <bool W_TERMS>
+__device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const DevConstT<Tan> &k,
+                                              const double V[4], double ag0, const double Yb[16],
+                                              const double bb[4], bool with_junction) {
+    VjpParts r;
+    r.s_aj = (W_TERMS && with_junction) ? vjp_junction(cd, p, V, ag0, Yb, bb) : 0.0;
+    const double vds = p * (V[0] - V[2]), vgs = p * (V[1] - V[2]), vbs = p * (V[3] - V[2]);
+    const bool fwd = vds >= 0.0;
+    const double x1 = fwd ? vds : -vds;
+    const double x2 = fwd ? vgs : vgs - vds;
+    const double x3 = fwd ? vbs : vbs - vds;
+    // frame: (x1, x2, x3) = p (V_dr - V_rf, V_g - V_rf, V_b - V_rf), (dr, rf) = (d, s)
+    // forward, (s, d) reversed; every index below is static (selects, no arrays
+    // indexed by the frame)
+    const double dv[4] = {V[0] - V[2], V[1] - V[2], 0.0, V[3] - V[2]};
+    double U[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) U[t][u] = Yb[t * 4 + u] + bb[t] * dv[u];
+    // the frame components of a direction Wv (a 4-vector over d, g, s, b)
+    auto frame = [&](const double Wv[4], double out[3]) {
+        const double wdr = fwd ? Wv[0] : Wv[2], wrf = fwd ? Wv[2] : Wv[0];
+        out[0] = p * (wdr - wrf);
+        out[1] = p * (Wv[1] - wrf);
+        out[2] = p * (Wv[3] - wrf);
+    };
+    // U_d - U_s, U_d + U_s - 2 U_g, U_b - U_g, U_dr - U_g, U_rf - U_g
+    double UI[4], UQ[4], UB[4], UA[4], US[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        UI[u] = U[0][u] - U[2][u];
+        UQ[u] = (U[0][u] + U[2][u]) - 2.0 * U[1][u];
+        UB[u] = U[3][u] - U[1][u];
+        UA[u] = (fwd ? U[0][u] : U[2][u]) - U[1][u];
+        US[u] = (fwd ? U[2][u] : U[0][u]) - U[1][u];
+    }
+    double wI[3], wQ[3], wB[3], wA[3], wS[3];
+    frame(UI, wI);
+    frame(UQ, wQ);
+    frame(UB, wB);
+    frame(UA, wA);
+    frame(US, wS);
+    const double bdr = fwd ? bb[0] : bb[2], brf = fwd ? bb[2] : bb[0];
+    const double cI = bb[0] - bb[2];
+    const double cQ = (bb[0] + bb[2]) - 2.0 * bb[1];
+    const double cB = bb[3] - bb[1];
+    const double sI = fwd ? p : -p, sQ = ag0 * p;   // terminal d carries sI * Ids
+
+    // body bias along x3 (no parameter dependence)
+    using D1 = DualN<double, 1>;
+    const BodyT<D1> bo = body_bias(cd, D1{x3, {1.0}});
+    // Qb = -(Cg k1) sqPs, a function of x3
+    r.s_qb = sQ * (-cd.k1) * (bo.sqPs.d[0] * wB[2] - cB * bo.sqPs.v);
+    if (W_TERMS) {
+        // overlap parts: -Cov (x2 - x1) in the frame's Qd (terminal dr), -Cov x2 in its
+        // Qs (terminal rf), both also in Qg = -(Qd + Qs + Qb)
+        r.s_cov = -sQ * (((wA[1] - wA[0]) - (bdr - bb[1]) * (x2 - x1)) + (wS[1] - (brf - bb[1]) * x2));
+    } else {
+        r.s_cov = 0.0;
+    }
+    // Gate part with the partials along x2 and x3.  x1 enters the gate only through
+    // the DIBL term -dibl x1 of Vth, next to x2 in Vgst = x2 - Vth, so the gate's
+    // x1 partials are dVth/dx1 = -dibl and dVgsteff/dx1 = dibl dVgsteff/dx2.
+    using G2 = DualN<Tan, 2>;
+    const G2 X1g{Tan(x1), {Tan(0.0), Tan(0.0)}};
+    const G2 X2g{Tan(x2), {Tan(1.0), Tan(0.0)}};
+    const G2 Vbg{Tan(bo.Vbseff.v), {Tan(0.0), Tan(bo.Vbseff.d[0])}};
+    const G2 sqg{Tan(bo.sqPs.v), {Tan(0.0), Tan(bo.sqPs.d[0])}};
+    const GateT<G2> gt = gate(cd, k, X1g, X2g, sqg, Vbg);
+    const Tan vth_x1 = -k.dibl, vg_x1 = k.dibl * gt.Vgsteff.d[0];
+    // drain current along U_d - U_s
+    using C1 = DualN<Tan, 1>;
+    const C1 X1i{Tan(x1), {Tan(wI[0])}};
+    const C1 Vthi{gt.Vth.v, {(wI[0] * vth_x1 + wI[1] * gt.Vth.d[0]) + wI[2] * gt.Vth.d[1]}};
+    const C1 Vgi{gt.Vgsteff.v, {(wI[0] * vg_x1 + wI[1] * gt.Vgsteff.d[0]) + wI[2] * gt.Vgsteff.d[1]}};
+    const C1 Vbi{Tan(bo.Vbseff.v), {Tan(wI[2] * bo.Vbseff.d[0])}};
+    const C1 sqi{Tan(bo.sqPs.v), {Tan(wI[2] * bo.sqPs.d[0])}};
+    const C1 Ids = drain_current(cd, k, X1i, Vthi, Vgi, Vbi, bulk_factor(k, sqi));
+    // half the inversion charge with d/dx1 on its own (seed 1, as in the stamped
+    // model: where the charge smoothing cancels to rounding level in x1 this keeps the
+    // rounding of the stamped values' own partials) and the x2-x3 part of
+    // U_d + U_s - 2 U_g
+    using C2 = DualN<Tan, 2>;
+    const C2 X1q{Tan(x1), {Tan(1.0), Tan(0.0)}};
+    const C2 Vgq{gt.Vgsteff.v, {vg_x1, wQ[1] * gt.Vgsteff.d[0] + wQ[2] * gt.Vgsteff.d[1]}};
+    const C2 sqq{Tan(bo.sqPs.v), {Tan(0.0), Tan(wQ[2] * bo.sqPs.d[0])}};
+    const C2 hQ = half_inversion_charge(cd, k, X1q, Vgq, bulk_factor(k, sqq));
+    const Tan dI = Ids.d[0];
+    const Tan dQ = wQ[0] * hQ.d[0] + hQ.d[1];
+
+    r.g = sI * (dI.t - cI * Ids.v.t) + sQ * (dQ.t - cQ * hQ.v.t);
+    if (W_TERMS) {
+        r.s_beta = (sI * (dI.v - cI * Ids.v.v)) / k.beta0.v;
+        r.s_hq = (sQ * (dQ.v - cQ * hQ.v.v)) / k.Cg.v;
+    } else {
+        r.s_beta = r.s_hq = 0.0;
+    }
+    return r;
+}
+
+// Two sweeps per device.  Workgroup b takes devices [b H, b H + H), H = half the
+// workgroup: its first half runs sweep 0 and its second half sweep 1 over the same
+// devices, so a wave holds one sweep and the two sweeps' gathers of a device meet in
+// the same CU's caches.
 __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double *A_bar,
                                              const double *b_bar, double *gW, double *gL,
                                              double *gV) {
-    const int64_t total = 3 * (int64_t)kc.n;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int dir = (int)(i / kc.n);
-        const int pos = (int)(i - (int64_t)dir * kc.n);
+    const int H = (int)blockDim.x / 2;
+    const int sweep = (int)threadIdx.x < H ? 0 : 1;
+    const int lane = (int)threadIdx.x - sweep * H;
+    for (int64_t base = (int64_t)blockIdx.x * H; base < kc.n; base += (int64_t)gridDim.x * H) {
+        if (base + lane >= kc.n) continue;
+        const int pos = (int)(base + lane);
         const int32_t t0 = kc.term[pos], t1 = kc.term[(size_t)kc.n + pos];
         const int32_t t2 = kc.term[2 * (size_t)kc.n + pos], t3 = kc.term[3 * (size_t)kc.n + pos];
         const int key = pattern_key(t0, t1, t2, t3);
@@ -81,40 +233,44 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
         const double W = kc.par[pos];
         const double L = kc.par[(size_t)kc.n + pos];
         const double VTH0 = kc.par[2 * (size_t)kc.n + pos];
-        const double Vd = t0 ? call.x[t0 - 1] : 0.0, Vg = t1 ? call.x[t1 - 1] : 0.0;
-        const double Vs = t2 ? call.x[t2 - 1] : 0.0, Vb = t3 ? call.x[t3 - 1] : 0.0;
+        const double V[4] = {t0 ? call.x[t0 - 1] : 0.0, t1 ? call.x[t1 - 1] : 0.0,
+                             t2 ? call.x[t2 - 1] : 0.0, t3 ? call.x[t3 - 1] : 0.0};
         const int32_t v = kc.perm[pos];
-        const double *hist = call.hist ? call.hist + 4 * (size_t)v : nullptr;
         const int isP = kc.pol[pos] < 0 ? 1 : 0;
-        double g = 0.0;
         for (;;) {
             const int p0 = __builtin_amdgcn_readfirstlane(isP);
             if (isP == p0) {
                 const DevCard &cd = kc.card[p0];
                 const double p = p0 ? -1.0 : 1.0;
-                const Tan Wt(W, dir == 0 ? 1.0 : 0.0), Lt(L, dir == 1 ? 1.0 : 0.0);
-                const Tan Vt(VTH0, dir == 2 ? 1.0 : 0.0);
-                const DevConstT<Tan> k = dev_const(cd, p, Wt, Lt, Vt);
-                const DevOutT<Tan> o = eval_model(cd, p, k, Vd, Vg, Vs, Vb, call.ag0, hist);
-                Tan Y[16];
-                full_Y(o, Y);
-                double acc = 0.0;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc += Yb[k] * Y[k].t;
-                acc += bb[0] * o.bd.t + bb[1] * o.bg.t + bb[2] * o.bs.t + bb[3] * o.bb.t;
-                g = acc;
+                if (sweep == 0) {
+                    // the channel sweep carries d/dvth_s; W moves vth_s, beta0, Cg, Cov, Aj
+                    const DevConstT<double> kv = dev_const(cd, p, W, L, VTH0);
+                    const DevConstW kw = dev_const_dW(cd, W, L);
+                    const DevConstT<Tan> k{Tan(kv.vth_s, 1.0), Tan(kv.dibl), Tan(kv.nsce), Tan(kv.beta0),
+                                           Tan(kv.lambda), Tan(kv.k1AbL), Tan(kv.esatn), Tan(kv.Cg),
+                                           Tan(kv.Cov), Tan(kv.Aj)};
+                    const VjpParts r = vjp_parts<true>(cd, p, k, V, call.ag0, Yb, bb, cd.jmod != 0.0);
+                    double w = kw.vth_s * r.g + kw.beta0 * r.s_beta;
+                    w += kw.Cg * (r.s_hq + r.s_qb) + kw.Cov * r.s_cov;
+                    w += kw.Aj * r.s_aj;
+                    gW[v] = w;
+                    gV[v] = p * r.g;
+                } else {
+                    // L moves every constant except Cov and Aj (both W hdif-like products)
+                    const DevConstT<Tan> k = dev_const(cd, p, Tan(W), Tan(L, 1.0), Tan(VTH0));
+                    const VjpParts r = vjp_parts<false>(cd, p, k, V, call.ag0, Yb, bb, false);
+                    gL[v] = r.g + k.Cg.t * r.s_qb;
+                }
                 break;
             }
         }
-        (dir == 0 ? gW : dir == 1 ? gL : gV)[v] = g;
     }
 }
 
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s) {
     if (kc.n == 0) return hipSuccess;
-    const int64_t total = 3 * (int64_t)kc.n;
-    const int grid = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
+    const int grid = (int)std::min<int64_t>(((int64_t)kc.n + 127) / 128, 1 << 20);
     hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
     return hipGetLastError();
 }

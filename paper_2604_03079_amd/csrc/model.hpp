@@ -207,6 +207,121 @@ __device__ __forceinline__ Dual3T<S> dsoftplus(Dual3T<S> a) {
     return {sp, sg * a.d0, sg * a.d1, sg * a.d2};
 }
 
+// ---- values with N directional partials --------------------------------------------
+// The same rules as Dual3 for N partials, each along a direction chosen by the caller
+// (the adjoint carries the partials along the cotangent directions it contracts with).
+template <class S, int N>
+struct DualN {
+    S v;
+    S d[N];
+};
+
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> operator+(const DualN<S, N> &a, const DualN<S, N> &b) {
+    DualN<S, N> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> operator-(const DualN<S, N> &a, const DualN<S, N> &b) {
+    DualN<S, N> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> operator-(const DualN<S, N> &a) {
+    DualN<S, N> r;
+    r.v = -a.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+    return r;
+}
+template <class S, int N, class C>
+__device__ __forceinline__ DualN<S, N> plus_c(DualN<S, N> a, C c) {
+    a.v = a.v + c;
+    return a;
+}
+template <class S, int N, class C>
+__device__ __forceinline__ DualN<S, N> minus_c(DualN<S, N> a, C c) {
+    a.v = a.v - c;
+    return a;
+}
+template <class S, int N, class C>
+__device__ __forceinline__ DualN<S, N> c_minus(C c, const DualN<S, N> &a) {
+    DualN<S, N> r;
+    r.v = c - a.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+    return r;
+}
+template <class S, int N, class C>
+__device__ __forceinline__ DualN<S, N> scale(C c, const DualN<S, N> &a) {
+    DualN<S, N> r;
+    r.v = c * a.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = c * a.d[i];
+    return r;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> operator*(const DualN<S, N> &a, const DualN<S, N> &b) {
+    DualN<S, N> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> operator/(const DualN<S, N> &a, const DualN<S, N> &b) {
+    const S r = 1.0 / b.v;
+    DualN<S, N> o;
+    o.v = a.v * r;
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.d[i] = (a.d[i] - o.v * b.d[i]) * r;
+    return o;
+}
+template <class S, int N, class C>
+__device__ __forceinline__ DualN<S, N> c_over(C c, const DualN<S, N> &b) {
+    const S r = 1.0 / b.v;
+    DualN<S, N> o;
+    o.v = c * r;
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.d[i] = (-(o.v * b.d[i])) * r;
+    return o;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> dsqrt(const DualN<S, N> &a) {
+    DualN<S, N> o;
+    o.v = gsqrt(a.v);
+    const S h = 0.5 / o.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.d[i] = a.d[i] * h;
+    return o;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> dexp(const DualN<S, N> &a) {
+    DualN<S, N> o;
+    o.v = gexp(a.v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.d[i] = o.v * a.d[i];
+    return o;
+}
+template <class S, int N>
+__device__ __forceinline__ DualN<S, N> dsoftplus(const DualN<S, N> &a) {
+    const S t = a.v;
+    const S e = gexp(-gabs(t));
+    DualN<S, N> o;
+    o.v = (val(t) > 0.0 ? t : S(0.0)) + glog1p(e);
+    const S dn = 1.0 + e;
+    const S sg = val(t) >= 0.0 ? 1.0 / dn : e / dn;
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.d[i] = sg * a.d[i];
+    return o;
+}
+
 // Size-dependent constants of one device (depend on W, L, VTH0 only).
 template <class S>
 struct SizeDepT {
@@ -258,6 +373,18 @@ __device__ __forceinline__ DevConstT<S> dev_const(const DevCard &cd, double pol,
     return k;
 }
 
+// d/dW of the per-device constants that depend on W (vth_s through the narrow-width
+// term, beta0, Cg, Cov, Aj); the others depend on L and the card only.
+struct DevConstW {
+    double vth_s, beta0, Cg, Cov, Aj;
+};
+__device__ __forceinline__ DevConstW dev_const_dW(const DevCard &cd, double W, double L) {
+    const double Weff = W - cd.TWO_WINT;
+    const double Leff = L - cd.TWO_LINT;
+    const double ww = Weff + cd.w0;
+    return {-cd.K3_TOXE_PHIS / (ww * ww), cd.COXE / Leff, Leff * cd.COXE, cd.cgdo, cd.hdif};
+}
+
 // One source/drain-body junction of forward voltage v (body above the diffusion for
 // NMOS) and area A: diode current Ij and conductance gj (exponent clamped at -40,
 // tangent continuation above vjmax), abrupt-junction depletion charge Qj and
@@ -288,6 +415,103 @@ __device__ __forceinline__ void junction(const DevCard &cd, S A, double v, S &Ij
     }
 }
 
+// Effective body bias and sqrt(phis - Vbseff): functions of the frame's x3 alone.
+template <class D>
+struct BodyT {
+    D Vbseff, sqPs;
+};
+template <class D>
+__device__ __forceinline__ BodyT<D> body_bias(const DevCard &cd, const D &X3) {
+    const D T0 = minus_c(c_minus(cd.VBM, X3), cd.delta1);
+    const D sq0 = dsqrt(plus_c(T0 * T0, cd.FOUR_DELTA1_VBM));
+    const D Vbseff = c_minus(cd.VBM, scale(0.5, T0 + sq0));
+    const D sqPs = dsqrt(c_minus(cd.phis, Vbseff));
+    return {Vbseff, sqPs};
+}
+
+// The channel of model M in the frame (x1, x2, x3) = (|vds|, gate, body voltages
+// from the source side), in four parts, each generic over the number type D (value
+// with partials) and the per-device constants K (fields of one scalar type): the
+// gate part (threshold and effective overdrive), the bulk-charge factor, the drain
+// current and half the inversion charge (the 50/50 partition).
+template <class D>
+struct GateT {
+    D Vth, Vgsteff;
+};
+template <class D, class K>
+__device__ __forceinline__ GateT<D> gate(const DevCard &cd, const K &sd, const D &X1, const D &X2,
+                                         const D &sqPs, const D &Vbseff) {
+    // threshold voltage
+    const D Vth = (plus_c(scale(cd.k1, minus_c(sqPs, cd.SQPHIS)), sd.vth_s) - scale(cd.k2, Vbseff))
+                  - scale(sd.dibl, X1);
+    // subthreshold swing factor
+    // (the constant factors of the Cdep term are the card constant NCDEP)
+    const D n = plus_c(plus_c(c_over(cd.NCDEP, sqPs), 1.0), sd.nsce);
+    const D nvt = scale(cd.VT, n);
+    const D Vgst = X2 - Vth;
+    // unified effective gate overdrive
+    const D h = scale(0.5, Vgst);
+    const D num6 = nvt * dsoftplus(h / nvt);
+    const D ex6 = dexp((-minus_c(h, cd.voff)) / nvt);
+    const D den6 = plus_c(scale(cd.COXE_KS, n) * ex6, 0.5);
+    const D Vgsteff = num6 / den6;
+    return {Vth, Vgsteff};
+}
+template <class D, class K>
+__device__ __forceinline__ D bulk_factor(const K &sd, const D &sqPs) {
+    return plus_c(c_over(sd.k1AbL, scale(2.0, sqPs)), 1.0);
+}
+template <class D, class K>
+__device__ __forceinline__ D drain_current(const DevCard &cd, const K &sd, const D &X1, const D &Vth,
+                                           const D &Vgsteff, const D &Vbseff, const D &Abulk) {
+    // mobility
+    const D Ee = scale(cd.INV_TOXE, Vgsteff + scale(2.0, Vth));
+    const D mden = plus_c(plus_c(scale(cd.uc, Vbseff), cd.ua) * Ee, 1.0) + scale(cd.ub, Ee * Ee);
+    const D mu = c_over(cd.u0, mden);
+    // saturation
+    const D EsatL = c_over(sd.esatn, mu);
+    const D V2 = plus_c(Vgsteff, cd.TWO_VT);
+    const D Vdsat = (EsatL * V2) / ((Abulk * EsatL) + V2);
+    const D T1 = minus_c(Vdsat - X1, cd.delta);
+    const D sq1 = dsqrt((T1 * T1) + scale(cd.FOUR_DELTA, Vdsat));
+    const D Vdseff = Vdsat - scale(0.5, T1 + sq1);
+    // drain current with channel-length modulation
+    const D c11 = (scale(sd.beta0, mu) * Vgsteff) * Vdseff;
+    const D f11 = c_minus(1.0, (Abulk * Vdseff) / scale(2.0, V2));
+    const D g11 = plus_c(Vdseff / EsatL, 1.0);
+    const D Ids0 = (c11 * f11) / g11;
+    return Ids0 * plus_c(scale(sd.lambda, X1 - Vdseff), 1.0);
+}
+template <class D, class K>
+__device__ __forceinline__ D half_inversion_charge(const DevCard &cd, const K &sd, const D &X1,
+                                                   const D &Vgsteff, const D &Abulk) {
+    const D Vdc = Vgsteff / Abulk;
+    const D T2 = minus_c(Vdc - X1, cd.delta);
+    const D sq2 = dsqrt((T2 * T2) + scale(cd.FOUR_DELTA, Vdc));
+    const D Vdcv = Vdc - scale(0.5, T2 + sq2);
+    const D AV = Abulk * Vdcv;
+    const D Tq = Vgsteff - scale(0.5, AV);
+    const D Qinv = scale(-sd.Cg, Tq + (AV * AV) / scale(12.0, Tq));
+    return scale(0.5, Qinv);
+}
+
+// The whole channel with one number type: drain current Ids, half the inversion
+// charge hQ and the depletion charge Qb.
+template <class D>
+struct ChannelT {
+    D Ids, hQ, Qb;
+};
+template <class D, class K>
+__device__ __forceinline__ ChannelT<D> channel(const DevCard &cd, const K &sd, const D &X1, const D &X2,
+                                               const D &Vbseff, const D &sqPs) {
+    const GateT<D> g = gate(cd, sd, X1, X2, sqPs, Vbseff);
+    const D Abulk = bulk_factor(sd, sqPs);
+    const D Ids = drain_current(cd, sd, X1, g.Vth, g.Vgsteff, Vbseff, Abulk);
+    const D hQ = half_inversion_charge(cd, sd, X1, g.Vgsteff, Abulk);
+    const D Qb = scale(-(sd.Cg * cd.k1), sqPs);
+    return {Ids, hQ, Qb};
+}
+
 // Local outputs of one device: the 9 independent entries of Y (rows/cols d, g, b;
 // the s row and column follow from conservation) and the local RHS.
 template <class S>
@@ -311,53 +535,11 @@ __device__ __forceinline__ DevOutT<S> eval_model(const DevCard &cd, double p, co
     const double x3 = fwd ? vbs : vbs - vds;
     const D X1 = seed<S>(x1, 0), X2 = seed<S>(x2, 1), X3 = seed<S>(x3, 2);
 
-    // effective body bias and body factor
-    const D T0 = minus_c(c_minus(cd.VBM, X3), cd.delta1);
-    const D sq0 = dsqrt(plus_c(T0 * T0, cd.FOUR_DELTA1_VBM));
-    const D Vbseff = c_minus(cd.VBM, scale(0.5, T0 + sq0));
-    const D sqPs = dsqrt(c_minus(cd.phis, Vbseff));
-    // threshold voltage
-    const D Vth = (plus_c(scale(cd.k1, minus_c(sqPs, cd.SQPHIS)), sd.vth_s) - scale(cd.k2, Vbseff))
-                  - scale(sd.dibl, X1);
-    // subthreshold swing factor
-    // (the constant factors of the Cdep term are the card constant NCDEP)
-    const D n = plus_c(plus_c(c_over(cd.NCDEP, sqPs), 1.0), sd.nsce);
-    const D nvt = scale(cd.VT, n);
-    const D Vgst = X2 - Vth;
-    // unified effective gate overdrive
-    const D h = scale(0.5, Vgst);
-    const D num6 = nvt * dsoftplus(h / nvt);
-    const D ex6 = dexp((-minus_c(h, cd.voff)) / nvt);
-    const D den6 = plus_c(scale(cd.COXE_KS, n) * ex6, 0.5);
-    const D Vgsteff = num6 / den6;
-    // mobility
-    const D Ee = scale(cd.INV_TOXE, Vgsteff + scale(2.0, Vth));
-    const D mden = plus_c(plus_c(scale(cd.uc, Vbseff), cd.ua) * Ee, 1.0) + scale(cd.ub, Ee * Ee);
-    const D mu = c_over(cd.u0, mden);
-    // saturation
-    const D EsatL = c_over(sd.esatn, mu);
-    const D Abulk = plus_c(c_over(sd.k1AbL, scale(2.0, sqPs)), 1.0);
-    const D V2 = plus_c(Vgsteff, cd.TWO_VT);
-    const D Vdsat = (EsatL * V2) / ((Abulk * EsatL) + V2);
-    const D T1 = minus_c(Vdsat - X1, cd.delta);
-    const D sq1 = dsqrt((T1 * T1) + scale(cd.FOUR_DELTA, Vdsat));
-    const D Vdseff = Vdsat - scale(0.5, T1 + sq1);
-    // drain current with channel-length modulation
-    const D c11 = (scale(sd.beta0, mu) * Vgsteff) * Vdseff;
-    const D f11 = c_minus(1.0, (Abulk * Vdseff) / scale(2.0, V2));
-    const D g11 = plus_c(Vdseff / EsatL, 1.0);
-    const D Ids0 = (c11 * f11) / g11;
-    const D Ids = Ids0 * plus_c(scale(sd.lambda, X1 - Vdseff), 1.0);
-    // charges
-    const D Vdc = Vgsteff / Abulk;
-    const D T2 = minus_c(Vdc - X1, cd.delta);
-    const D sq2 = dsqrt((T2 * T2) + scale(cd.FOUR_DELTA, Vdc));
-    const D Vdcv = Vdc - scale(0.5, T2 + sq2);
-    const D AV = Abulk * Vdcv;
-    const D Tq = Vgsteff - scale(0.5, AV);
-    const D Qinv = scale(-sd.Cg, Tq + (AV * AV) / scale(12.0, Tq));
-    const D Qb = scale(-(sd.Cg * cd.k1), sqPs);
-    const D hQ = scale(0.5, Qinv);
+    const BodyT<D> bo = body_bias(cd, X3);
+    const ChannelT<D> ch = channel(cd, sd, X1, X2, bo.Vbseff, bo.sqPs);
+    const D &Ids = ch.Ids;
+    const D &hQ = ch.hQ;
+    const D &Qb = ch.Qb;
     const D Qd = hQ - scale(sd.Cov, X2 - X1);
     const D Qs = hQ - scale(sd.Cov, X2);
     const D Qg = -((Qd + Qs) + Qb);

@@ -4,7 +4,7 @@ Complex steps of different sizes are each an exact derivative of the same rounde
 program up to O(h^2); where two of them disagree, the derivative itself is decided
 by rounding (a sensitivity formed by cancellation), and no evaluation order can be
 expected to agree with another beyond that spread.  Used by the CPU test that names
-such devices and by the GPU adjoint test that allows them their spread."""
+such devices."""
 import numpy as np
 
 STEPS = (1e-20, 3.7e-23, 1.3e-17)
