@@ -733,9 +733,10 @@ __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *
 // the last region of an item folds it (shared entries one lane each, in colour
 // order; hub parts spanning regions one wave each, by the tree, stored as parts;
 // consecutive items go to different waves).  Called by every thread of the workgroup.
-// The hub sums over the parts follow in their own kernel (k_hub_parts).
+// The hub sums over the parts follow in their own kernel (k_hub_parts).  it_first:
+// this thread's item of the first round, when the caller has loaded it already.
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
-                                             bool hub_only = false) {
+                                             bool hub_only = false, int it_first = -1) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int base = jb; base < je; base += blockDim.x) {
         const int i = base + lane * nw + wave;
@@ -743,7 +744,7 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
         uint32_t tgt = 0;
         bool last = false;
         if (i < je && !(hub_only && ((uint32_t)kr.item[4 * (size_t)kr.ritems[i] + 2] >> 30) != ITEM_HUB)) {
-            const int it = kr.ritems[i];
+            const int it = (base == jb && it_first >= 0) ? it_first : kr.ritems[i];
             const int32_t *f = kr.item + 4 * (size_t)it;
             beg = f[0];
             cnt = f[1];
@@ -888,6 +889,23 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         LdsRowSink sink{mst + t, B};
         emit_merged(d.key, Y, bl, sink);
     }
+    // tables the tail needs, first loads issued now (their latency overlaps the staging
+    // and the phases): this lane's lane fold, its first item, its owned-entry targets
+    constexpr int OWN_PF = 4;
+    const int fi = fb + t;
+    int fd_t = 0, fd_s = 0, fd_c = 0;
+    if (fi < fe) {
+        const int32_t *fd = kr.fold + 3 * (size_t)fi;
+        fd_t = fd[0];
+        fd_s = fd[1];
+        fd_c = fd[2];
+    }
+    const int nw0 = blockDim.x >> 6;
+    const int ii0 = jb + (t & 63) * nw0 + (t >> 6);
+    int it0 = ii0 < je ? kr.ritems[ii0] : 0;
+    uint32_t own_t[OWN_PF];
+#pragma unroll
+    for (int k = 0; k < OWN_PF; ++k) own_t[k] = t + k * B < ie - ib ? (uint32_t)kr.int_target[ib + t + k * B] : 0u;
     // values of shared entries and hubs: staged at once (no order among them); the grid
     // form stages only the hub values
 #pragma unroll
@@ -898,6 +916,11 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         st_coherent(kc.stage + sl, mst[j * B + t]);
     }
     lds_barrier();
+    // this lane's fold sources (the descriptor has arrived by now), used after the phases
+    constexpr int FSRC_PF = 4;
+    int32_t fsrc[FSRC_PF];
+#pragma unroll
+    for (int k = 0; k < FSRC_PF; ++k) fsrc[k] = (fi < fe && k < fd_c) ? kr.fold_src[fd_s + k] : 0;
     // phases: in its own phase each device loads its entries, adds its values and
     // stores them back (plain LDS loads and stores: no other lane of the phase touches
     // those entries; a device's entries are distinct, so all loads go first), a
@@ -920,13 +943,27 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     // lane folds: entries of the region with many writers, one lane each, the
     // writers' merged values read from LDS in colour order (no phase per writer)
     for (int i = fb + t; i < fe; i += B) {
-        const int32_t *fd = kr.fold + 3 * (size_t)i;
-        const int32_t *src = kr.fold_src + fd[1];
-        const int cnt = fd[2];
-        double s = mst[(src[0] >> 16) * B + (src[0] & 0xFFFF)];
+        int tg = fd_t, sb = fd_s, cnt = fd_c;
+        if (i != fi) {
+            const int32_t *fd = kr.fold + 3 * (size_t)i;
+            tg = fd[0];
+            sb = fd[1];
+            cnt = fd[2];
+        }
+        const int32_t *src = kr.fold_src + sb;
+        double s;
+        if (i == fi) {
+            s = mst[(fsrc[0] >> 16) * B + (fsrc[0] & 0xFFFF)];
+#pragma unroll
+            for (int k = 1; k < FSRC_PF; ++k)
+                if (k < cnt) s = s + mst[(fsrc[k] >> 16) * B + (fsrc[k] & 0xFFFF)];
+            for (int k = FSRC_PF; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
+        } else {
+            s = mst[(src[0] >> 16) * B + (src[0] & 0xFFFF)];
 #pragma unroll 8
-        for (int k = 1; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
-        store_target(call, (uint32_t)fd[0], s);
+            for (int k = 1; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
+        }
+        store_target(call, (uint32_t)tg, s);
     }
     // local hub parts: eight lanes per part, four of its LDS slots each (slots beyond
     // the part's contributions hold -0.0), a butterfly over the eight lanes: the part's
@@ -993,8 +1030,12 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         // entries are stored last (nothing waits for them)
         drain_memory();
         __syncthreads();
-        finish_items(kc, call, kr, jb, je);
-        for (int i = t; i < ie - ib; i += blockDim.x) store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
+        finish_items(kc, call, kr, jb, je, false, it0);
+#pragma unroll
+        for (int k = 0; k < OWN_PF; ++k)
+            if (t + k * B < ie - ib) store_target(call, own_t[k], lds[t + k * B]);
+        for (int i = t + OWN_PF * B; i < ie - ib; i += blockDim.x)
+            store_target(call, (uint32_t)kr.int_target[ib + i], lds[i]);
     }
 }
 
