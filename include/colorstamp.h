@@ -66,7 +66,8 @@ typedef enum {
     CS_COLOR_REGION = 4,      /* ColorFused at workgroup scope: devices are cut (in
                                  index order) into regions of one workgroup; an entry
                                  written by one or two devices of a region accumulates
-                                 in LDS in phases, one written by more devices of a
+                                 in LDS by LDS atomic adds (exact for two writers),
+                                 one written by more devices of a
                                  region is folded by one lane in colour order, and
                                  entries written from several regions are staged and
                                  folded in colour order by the last contributing
@@ -297,7 +298,10 @@ cs_status cs_get_region_info(const cs_circuit *c, int32_t *n_regions, int32_t *m
 
 /* Host copies of the region plan tables (any pointer may be NULL), region-major
  * positions p < n_dev:
- *   perm[p]      device index;               phase[p]   LDS phase of the device;
+ *   perm[p]      device index;               phase[p]   phase of the device (an order
+ *                                            in which plain LDS loads and stores
+ *                                            would accumulate; the kernel adds with
+ *                                            LDS atomics instead);
  *   code[j*n_dev + p] (j < 20): bits 31..30 = 0 LDS add, 1 LDS store, 2 staged,
  *                3 unused or read by a lane fold or a local hub chunk; bits 29..0 =
  *                LDS slot or staging index;

@@ -676,9 +676,9 @@ __global__ void __launch_bounds__(256) k_atomic_wave(KCirc kc, KCall call) {
 // ---- region schedule ------------------------------------------------------------
 // One workgroup per region.  The region's devices are evaluated at once (NMOS lanes
 // first, then PMOS lanes) and their merged values parked in LDS rows.  An entry
-// written by one or two devices of the region accumulates in an LDS slot phase by
-// phase (a workgroup barrier between phases); an entry written by more devices of
-// the region is folded by one lane from the parked values in colour order;
+// written by one or two devices of the region accumulates in an LDS slot by LDS
+// atomic adds (exact in any order for two writers); an entry written by more devices
+// of the region is folded by one lane from the parked values in colour order;
 // contributions to entries shared with other regions and to hub entries are staged
 // in global memory, and every shared entry or hub chunk is folded by the last region
 // that contributes to it (an arrival counter), large shared entries by a follow-up
@@ -850,7 +850,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
 #pragma unroll
         for (int k = 0; k < RT_FIELDS; ++k) f[k] = rt[k];
     }
-    const int p0 = f[0], nN = f[1], nP = f[2], nph = f[3], ib = f[4], ie = f[5], jb = f[6], je = f[7];
+    const int p0 = f[0], nN = f[1], nP = f[2], ib = f[4], ie = f[5], jb = f[6], je = f[7];
     const int fb = f[8], fe = f[9], hb = f[10], he = f[11];
     const int t = threadIdx.x;
     const int pos = t < nN + nP ? p0 + t : -1;
@@ -872,7 +872,6 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     uint32_t cd[NCODE];
 #pragma unroll
     for (int j = 0; j < NCODE; ++j) cd[j] = 0xC0000000u;
-    int ph = -1;
     if (pos >= 0) {
         const DevIn d = load_terms(kc, pos);
         const DevOut o = eval_pos<J>(kc, call, pos, d);
@@ -882,7 +881,6 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         const int nc = k * k + k;
 #pragma unroll
         for (int j = 0; j < NCODE; ++j) cd[j] = j < nc ? (uint32_t)kc.code[(size_t)j * kc.n + pos] : 0xC0000000u;
-        ph = kr.phase[pos];
         double Y[16];
         full_Y(o, Y);
         const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
@@ -921,25 +919,17 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     int32_t fsrc[FSRC_PF];
 #pragma unroll
     for (int k = 0; k < FSRC_PF; ++k) fsrc[k] = (fi < fe && k < fd_c) ? kr.fold_src[fd_s + k] : 0;
-    // phases: in its own phase each device loads its entries, adds its values and
-    // stores them back (plain LDS loads and stores: no other lane of the phase touches
-    // those entries; a device's entries are distinct, so all loads go first), a
-    // workgroup barrier between phases
-    for (int q = 0; q < max(nph, 1); ++q) {
-        if (ph == q) {
-            double v[NCODE], cur[NCODE];
+    // entries of the region with one or two writers: every device adds its merged
+    // values to their LDS slots with LDS atomic adds, all devices at once (the slots
+    // start at -0.0, the identity, and two writers commute exactly: a + b = b + a, so
+    // the sum is the colour order's whichever add lands first)
 #pragma unroll
-            for (int j = 0; j < NCODE; ++j) {
-                const bool mine = (cd[j] >> 30) <= TAG_LDS_STORE;
-                v[j] = mine ? mst[j * B + t] : 0.0;
-                cur[j] = mine ? lds[cd[j] & 0x3FFFFFFFu] : 0.0;
-            }
-#pragma unroll
-            for (int j = 0; j < NCODE; ++j)
-                if ((cd[j] >> 30) <= TAG_LDS_STORE) lds[cd[j] & 0x3FFFFFFFu] = cur[j] + v[j];
-        }
-        lds_barrier();
+    for (int j = 0; j < NCODE; ++j) {
+        if ((cd[j] >> 30) <= TAG_LDS_STORE)
+            (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), mst[j * B + t], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    lds_barrier();
     // lane folds: entries of the region with many writers, one lane each, the
     // writers' merged values read from LDS in colour order (no phase per writer)
     for (int i = fb + t; i < fe; i += B) {

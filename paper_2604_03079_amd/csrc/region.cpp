@@ -8,10 +8,11 @@
 //   * devices are cut, in ascending device index, into regions of at most one
 //     workgroup (a circuit that fits one region is never split);
 //   * an entry whose writers all lie in one region and are at most LDS_WRITERS_MAX
-//     (one or two) is accumulated in that workgroup's LDS, in phases separated by
-//     workgroup barriers; two writers of an entry take distinct phases (two values
-//     added to the -0.0 start give the same bits in either order), so a handful of
-//     phases serve any number of colours;
+//     (one or two) is accumulated in that workgroup's LDS by LDS atomic adds, all
+//     writers at once (two values added to the -0.0 start give the same bits in
+//     either order); the plan also gives each device a phase, two writers of an
+//     entry in distinct phases: an order in which plain loads and stores would do,
+//     which the host replay of the plan follows;
 //   * an entry whose writers all lie in one region and are more is a lane fold: one
 //     lane folds the writers' merged values, read from LDS in colour order, and
 //     stores the result (no phase per writer); so are single-writer entries of a

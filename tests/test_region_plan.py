@@ -1,6 +1,6 @@
 """CPU checks of the region schedule's host planner.
 
-The library's plan tables (regions, LDS phases, stamp codes, shared-entry items) are
+The library's plan tables (regions, phases, stamp codes, shared-entry items) are
 replayed here on the host exactly as the region kernels use them, with every device's
 local values taken from the oracle; the replayed matrix entries and RHS rows must
 equal the oracle's colour-order replay bit for bit.  Structural checks cover the
@@ -98,23 +98,29 @@ def replay(plan, vals, pol, block, nnz, n_rows):
             for j in range(len(vals[perm[p]]), 20):
                 assert (int(code[j, p]) & 0xFFFFFFFF) >> 30 == 3
             assert phase[p] < max(nph, 1)
-        # as the kernel: accumulators start at -0.0 and every writer load-adds in its
-        # phase; two writers of one entry never share a phase
-        lds[:] = -0.0
+        # the plan's phases: two writers of one entry never share a phase
         written = [set() for _ in range(len(lds))]
-        for q in range(nph):
-            for p in pos:
-                if phase[p] != q:
-                    continue
-                for j, mv in enumerate(vals[perm[p]]):
-                    c = int(code[j, p]) & 0xFFFFFFFF
-                    tag, idx = c >> 30, c & 0x3FFFFFFF
-                    if tag in (0, 1):
-                        assert q not in written[idx], "two writers of an entry in one phase"
-                        written[idx].add(q)
-                        lds[idx] = lds[idx] + mv
+        for p in pos:
+            for j, mv in enumerate(vals[perm[p]]):
+                c = int(code[j, p]) & 0xFFFFFFFF
+                tag, idx = c >> 30, c & 0x3FFFFFFF
+                if tag in (0, 1):
+                    assert phase[p] not in written[idx], "two writers of an entry in one phase"
+                    written[idx].add(int(phase[p]))
         assert all(written[:ie - ib])
+        # as the kernel: accumulators start at -0.0 and the writers add in whatever
+        # order their LDS atomics land (here a seeded shuffle), exact because an
+        # entry has at most two writers: -0.0 + a = a and a + b = b + a
+        assert all(len(w) <= 2 for w in written[:ie - ib])
         assert all(len(w) <= 1 for w in written[ie - ib:])   # one writer per hub slot
+        lds[:] = -0.0
+        adds = [(p, j) for p in pos for j in range(len(vals[perm[p]]))]
+        for k in np.random.default_rng(r).permutation(len(adds)):
+            p, j = adds[k]
+            c = int(code[j, p]) & 0xFFFFFFFF
+            tag, idx = c >> 30, c & 0x3FFFFFFF
+            if tag in (0, 1):
+                lds[idx] = lds[idx] + vals[perm[p]][j]
         # local hub parts: slot r of part k holds contribution r (-0.0 beyond the
         # part's contributions), summed by the 32-leaf tree
         for k in range(he - hb):
