@@ -213,30 +213,54 @@ __device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const
 }
 
 // Two sweeps per device.  Workgroup b takes devices [b H, b H + H), H = half the
-// workgroup: its first half runs sweep 0 and its second half sweep 1 over the same
-// devices, so a wave holds one sweep and the two sweeps' gathers of a device meet in
-// the same CU's caches.
+// workgroup, then every gridDim-th such range (the grid is what stays resident): its
+// first half runs sweep 0 and its second half sweep 1 over the same devices, so a wave
+// holds one sweep and the two sweeps' gathers of a device meet in the same CU's
+// caches.
 __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double *A_bar,
                                              const double *b_bar, double *gW, double *gL,
                                              double *gV) {
     const int H = (int)blockDim.x / 2;
     const int sweep = (int)threadIdx.x < H ? 0 : 1;
     const int lane = (int)threadIdx.x - sweep * H;
-    for (int64_t base = (int64_t)blockIdx.x * H; base < kc.n; base += (int64_t)gridDim.x * H) {
+    const int64_t stride = (int64_t)gridDim.x * H;
+    // the next device's terminals and parameters are loaded while this one is computed
+    struct Pre {
+        int32_t t0, t1, t2, t3, v, isP;
+        double W, L, VTH0;
+    };
+    auto fetch = [&](int64_t b) {
+        Pre q{0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
+        if (b + lane < kc.n) {
+            const int ps = (int)(b + lane);
+            const size_t n = (size_t)kc.n;
+            q.t0 = kc.term[ps];
+            q.t1 = kc.term[n + ps];
+            q.t2 = kc.term[2 * n + ps];
+            q.t3 = kc.term[3 * n + ps];
+            q.v = kc.perm[ps];
+            q.isP = kc.pol[ps] < 0 ? 1 : 0;
+            q.W = kc.par[ps];
+            q.L = kc.par[n + ps];
+            q.VTH0 = kc.par[2 * n + ps];
+        }
+        return q;
+    };
+    Pre nx = fetch((int64_t)blockIdx.x * H);
+    for (int64_t base = (int64_t)blockIdx.x * H; base < kc.n; base += stride) {
+        const Pre cu = nx;
+        nx = fetch(base + stride);
         if (base + lane >= kc.n) continue;
         const int pos = (int)(base + lane);
-        const int32_t t0 = kc.term[pos], t1 = kc.term[(size_t)kc.n + pos];
-        const int32_t t2 = kc.term[2 * (size_t)kc.n + pos], t3 = kc.term[3 * (size_t)kc.n + pos];
+        const int32_t t0 = cu.t0, t1 = cu.t1, t2 = cu.t2, t3 = cu.t3;
         const int key = pattern_key(t0, t1, t2, t3);
         double Yb[16], bb[4];
         gather_cotangents(key, kc.acode, kc.n, pos, A_bar, b_bar, Yb, bb);
-        const double W = kc.par[pos];
-        const double L = kc.par[(size_t)kc.n + pos];
-        const double VTH0 = kc.par[2 * (size_t)kc.n + pos];
+        const double W = cu.W, L = cu.L, VTH0 = cu.VTH0;
         const double V[4] = {t0 ? call.x[t0 - 1] : 0.0, t1 ? call.x[t1 - 1] : 0.0,
                              t2 ? call.x[t2 - 1] : 0.0, t3 ? call.x[t3 - 1] : 0.0};
-        const int32_t v = kc.perm[pos];
-        const int isP = kc.pol[pos] < 0 ? 1 : 0;
+        const int32_t v = cu.v;
+        const int isP = cu.isP;
         for (;;) {
             const int p0 = __builtin_amdgcn_readfirstlane(isP);
             if (isP == p0) {
@@ -270,7 +294,13 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s) {
     if (kc.n == 0) return hipSuccess;
-    const int grid = (int)std::min<int64_t>(((int64_t)kc.n + 127) / 128, 1 << 20);
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_vjp, 256, 0);
+    if (e != hipSuccess) return e;
+    const int64_t resident = std::max<int64_t>(1, (int64_t)cus * per);
+    const int grid = (int)std::min<int64_t>(((int64_t)kc.n + 127) / 128, resident);
     hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
     return hipGetLastError();
 }

@@ -96,10 +96,28 @@ __device__ __forceinline__ Tan operator+(Tan a, Tan b) { return {a.v + b.v, a.t 
 __device__ __forceinline__ Tan operator-(Tan a, Tan b) { return {a.v - b.v, a.t - b.t}; }
 __device__ __forceinline__ Tan operator-(Tan a) { return {-a.v, -a.t}; }
 __device__ __forceinline__ Tan operator*(Tan a, Tan b) { return {a.v * b.v, a.t * b.v + a.v * b.t}; }
-// Quotients take one reciprocal (the adjoint's tangents are checked against the
-// complex-step gradient to a relative tolerance, not bit for bit).
+// Reciprocal and square root for Tan numbers: the hardware estimate refined by two
+// Newton steps, within a few ulps of the correctly rounded result (the adjoint's
+// values and tangents are checked against the complex-step gradient to a relative
+// tolerance, not bit for bit, and never reach the stamped outputs).  The divisors
+// and radicands of model M are positive and normal.
+__device__ __forceinline__ double rcp_tan(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ double sqrt_tan(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * y;
+    double s = x * y;
+    s = __builtin_fma(__builtin_fma(-s, s, x), h, s);
+    s = __builtin_fma(__builtin_fma(-s, s, x), h, s);
+    return x > 0.0 ? s : 0.0;
+}
+// Quotients take one reciprocal.
 __device__ __forceinline__ Tan operator/(Tan a, Tan b) {
-    const double r = 1.0 / b.v;
+    const double r = rcp_tan(b.v);
     const double q = a.v * r;
     return {q, (a.t - q * b.t) * r};
 }
@@ -109,9 +127,12 @@ __device__ __forceinline__ Tan operator-(Tan a, double b) { return {a.v - b, a.t
 __device__ __forceinline__ Tan operator-(double a, Tan b) { return {a - b.v, -b.t}; }
 __device__ __forceinline__ Tan operator*(double a, Tan b) { return {a * b.v, a * b.t}; }
 __device__ __forceinline__ Tan operator*(Tan a, double b) { return {a.v * b, a.t * b}; }
-__device__ __forceinline__ Tan operator/(Tan a, double b) { return {a.v / b, a.t / b}; }
+__device__ __forceinline__ Tan operator/(Tan a, double b) {
+    const double r = rcp_tan(b);
+    return {a.v * r, a.t * r};
+}
 __device__ __forceinline__ Tan operator/(double a, Tan b) {
-    const double r = 1.0 / b.v;
+    const double r = rcp_tan(b.v);
     const double q = a * r;
     return {q, (-(q * b.t)) * r};
 }
@@ -120,8 +141,8 @@ __device__ __forceinline__ double val(double x) { return x; }
 __device__ __forceinline__ double val(const Tan &x) { return x.v; }
 __device__ __forceinline__ double gsqrt(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ Tan gsqrt(Tan x) {
-    const double s = __builtin_sqrt(x.v);
-    return {s, (0.5 * x.t) / s};
+    const double s = sqrt_tan(x.v);
+    return {s, (0.5 * x.t) * rcp_tan(s)};
 }
 __device__ __forceinline__ double gabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ Tan gabs(Tan x) { return x.v >= 0.0 ? x : -x; }
@@ -131,7 +152,7 @@ __device__ __forceinline__ Tan gexp(Tan a) {
     return {e, e * a.t};
 }
 __device__ __forceinline__ double glog1p(double y) { return plog1p(y); }
-__device__ __forceinline__ Tan glog1p(Tan y) { return {plog1p(y.v), y.t / (1.0 + y.v)}; }
+__device__ __forceinline__ Tan glog1p(Tan y) { return {plog1p(y.v), y.t * rcp_tan(1.0 + y.v)}; }
 template <class S>
 __device__ __forceinline__ S gcosh(S u) {
     const S e = gexp(u);
