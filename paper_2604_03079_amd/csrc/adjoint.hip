@@ -20,10 +20,11 @@
 // So the adjoint evaluates the channel with two directional partials instead of the
 // three voltage partials, and differentiates w.r.t. the parameters in forward mode:
 // W and VTH0 act on the nonlinear part only through the threshold constant vth_s,
-// L through several constants, so two sweeps cover the three parameters:
-//   sweep 0: tangent d/d vth_s; dS/dVTH0 = pol dS/dvth_s, and dS/dW adds the
-//            linear terms of beta0 (Ids is proportional to it), Cg, Cov and Aj;
-//   sweep 1: tangent d/dL through every per-device constant.
+// L through several constants, so two tangents cover the three parameters, carried
+// together in one pass per device (Tan2: the values are computed once):
+//   tangent 0: d/dvth_s; dS/dVTH0 = pol dS/dvth_s, and dS/dW adds the linear terms
+//              of beta0 (Ids is proportional to it), Cg, Cov and Aj;
+//   tangent 1: d/dL through every per-device constant.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,11 +100,10 @@ __device__ __forceinline__ double vjp_junction(const DevCard &cd, double p, cons
     return s;
 }
 
-// Sensitivities of one device's S_dev: g w.r.t. the tangent the constants k carry,
-// and the value-level factors of the constants that enter linearly (W_TERMS: those
-// W moves; otherwise only s_qb, since L moves Cg but neither Cov nor Aj).
+// Sensitivities of one device's S_dev: g0, g1 along the two tangents the constants
+// k carry, and the value-level factors of the constants that enter linearly.
 struct VjpParts {
-    double g;       // dS/dtheta through the channel (the tangent of k)
+    double g0, g1;  // dS/dtheta through the channel, per tangent
     double s_beta;  // dS/dbeta0
     double s_hq;    // dS/dCg through hQ
     double s_qb;    // dS/dCg through Qb
@@ -111,12 +111,12 @@ struct VjpParts {
     double s_aj;    // dS/dAj (with_junction only)
 };
 
-template <bool W_TERMS>
-__device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const DevConstT<Tan> &k,
+__device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const DevConstT<Tan2> &k,
                                               const double V[4], double ag0, const double Yb[16],
                                               const double bb[4], bool with_junction) {
+    using T = Tan2;
     VjpParts r;
-    r.s_aj = (W_TERMS && with_junction) ? vjp_junction(cd, p, V, ag0, Yb, bb) : 0.0;
+    r.s_aj = with_junction ? vjp_junction(cd, p, V, ag0, Yb, bb) : 0.0;
     const double vds = p * (V[0] - V[2]), vgs = p * (V[1] - V[2]), vbs = p * (V[3] - V[2]);
     const bool fwd = vds >= 0.0;
     const double x1 = fwd ? vds : -vds;
@@ -165,74 +165,61 @@ __device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const
     const BodyT<D1> bo = body_bias(cd, D1{x3, {1.0}});
     // Qb = -(Cg k1) sqPs, a function of x3
     r.s_qb = sQ * (-cd.k1) * (bo.sqPs.d[0] * wB[2] - cB * bo.sqPs.v);
-    if (W_TERMS) {
-        // overlap parts: -Cov (x2 - x1) in the frame's Qd (terminal dr), -Cov x2 in its
-        // Qs (terminal rf), both also in Qg = -(Qd + Qs + Qb)
-        r.s_cov = -sQ * (((wA[1] - wA[0]) - (bdr - bb[1]) * (x2 - x1)) + (wS[1] - (brf - bb[1]) * x2));
-    } else {
-        r.s_cov = 0.0;
-    }
+    // overlap parts: -Cov (x2 - x1) in the frame's Qd (terminal dr), -Cov x2 in its Qs
+    // (terminal rf), both also in Qg = -(Qd + Qs + Qb)
+    r.s_cov = -sQ * (((wA[1] - wA[0]) - (bdr - bb[1]) * (x2 - x1)) + (wS[1] - (brf - bb[1]) * x2));
     // Gate part with the partials along x2 and x3.  x1 enters the gate only through
     // the DIBL term -dibl x1 of Vth, next to x2 in Vgst = x2 - Vth, so the gate's
     // x1 partials are dVth/dx1 = -dibl and dVgsteff/dx1 = dibl dVgsteff/dx2.
-    using G2 = DualN<Tan, 2>;
-    const G2 X1g{Tan(x1), {Tan(0.0), Tan(0.0)}};
-    const G2 X2g{Tan(x2), {Tan(1.0), Tan(0.0)}};
-    const G2 Vbg{Tan(bo.Vbseff.v), {Tan(0.0), Tan(bo.Vbseff.d[0])}};
-    const G2 sqg{Tan(bo.sqPs.v), {Tan(0.0), Tan(bo.sqPs.d[0])}};
+    using G2 = DualN<T, 2>;
+    const G2 X1g{T(x1), {T(0.0), T(0.0)}};
+    const G2 X2g{T(x2), {T(1.0), T(0.0)}};
+    const G2 Vbg{T(bo.Vbseff.v), {T(0.0), T(bo.Vbseff.d[0])}};
+    const G2 sqg{T(bo.sqPs.v), {T(0.0), T(bo.sqPs.d[0])}};
     const GateT<G2> gt = gate(cd, k, X1g, X2g, sqg, Vbg);
-    const Tan vth_x1 = -k.dibl, vg_x1 = k.dibl * gt.Vgsteff.d[0];
+    const T vth_x1 = -k.dibl, vg_x1 = k.dibl * gt.Vgsteff.d[0];
     // drain current along U_d - U_s
-    using C1 = DualN<Tan, 1>;
-    const C1 X1i{Tan(x1), {Tan(wI[0])}};
+    using C1 = DualN<T, 1>;
+    const C1 X1i{T(x1), {T(wI[0])}};
     const C1 Vthi{gt.Vth.v, {(wI[0] * vth_x1 + wI[1] * gt.Vth.d[0]) + wI[2] * gt.Vth.d[1]}};
     const C1 Vgi{gt.Vgsteff.v, {(wI[0] * vg_x1 + wI[1] * gt.Vgsteff.d[0]) + wI[2] * gt.Vgsteff.d[1]}};
-    const C1 Vbi{Tan(bo.Vbseff.v), {Tan(wI[2] * bo.Vbseff.d[0])}};
-    const C1 sqi{Tan(bo.sqPs.v), {Tan(wI[2] * bo.sqPs.d[0])}};
+    const C1 Vbi{T(bo.Vbseff.v), {T(wI[2] * bo.Vbseff.d[0])}};
+    const C1 sqi{T(bo.sqPs.v), {T(wI[2] * bo.sqPs.d[0])}};
     const C1 Ids = drain_current(cd, k, X1i, Vthi, Vgi, Vbi, bulk_factor(k, sqi));
     // half the inversion charge with d/dx1 on its own (seed 1, as in the stamped
     // model: where the charge smoothing cancels to rounding level in x1 this keeps the
     // rounding of the stamped values' own partials) and the x2-x3 part of
     // U_d + U_s - 2 U_g
-    using C2 = DualN<Tan, 2>;
-    const C2 X1q{Tan(x1), {Tan(1.0), Tan(0.0)}};
+    using C2 = DualN<T, 2>;
+    const C2 X1q{T(x1), {T(1.0), T(0.0)}};
     const C2 Vgq{gt.Vgsteff.v, {vg_x1, wQ[1] * gt.Vgsteff.d[0] + wQ[2] * gt.Vgsteff.d[1]}};
-    const C2 sqq{Tan(bo.sqPs.v), {Tan(0.0), Tan(wQ[2] * bo.sqPs.d[0])}};
+    const C2 sqq{T(bo.sqPs.v), {T(0.0), T(wQ[2] * bo.sqPs.d[0])}};
     const C2 hQ = half_inversion_charge(cd, k, X1q, Vgq, bulk_factor(k, sqq));
-    const Tan dI = Ids.d[0];
-    const Tan dQ = wQ[0] * hQ.d[0] + hQ.d[1];
+    const T dI = Ids.d[0];
+    const T dQ = wQ[0] * hQ.d[0] + hQ.d[1];
 
-    r.g = sI * (dI.t - cI * Ids.v.t) + sQ * (dQ.t - cQ * hQ.v.t);
-    if (W_TERMS) {
-        r.s_beta = (sI * (dI.v - cI * Ids.v.v)) / k.beta0.v;
-        r.s_hq = (sQ * (dQ.v - cQ * hQ.v.v)) / k.Cg.v;
-    } else {
-        r.s_beta = r.s_hq = 0.0;
-    }
+    r.g0 = sI * (dI.t0 - cI * Ids.v.t0) + sQ * (dQ.t0 - cQ * hQ.v.t0);
+    r.g1 = sI * (dI.t1 - cI * Ids.v.t1) + sQ * (dQ.t1 - cQ * hQ.v.t1);
+    r.s_beta = (sI * (dI.v - cI * Ids.v.v)) / k.beta0.v;
+    r.s_hq = (sQ * (dQ.v - cQ * hQ.v.v)) / k.Cg.v;
     return r;
 }
 
-// Two sweeps per device.  Workgroup b takes devices [b H, b H + H), H = half the
-// workgroup, then every gridDim-th such range (the grid is what stays resident): its
-// first half runs sweep 0 and its second half sweep 1 over the same devices, so a wave
-// holds one sweep and the two sweeps' gathers of a device meet in the same CU's
-// caches.
+// One pass per device, both tangents at once.  The grid is what stays resident: a
+// thread takes every (gridDim x blockDim)-th device and loads the next one's
+// terminals and parameters while it computes the current one.
 __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double *A_bar,
                                              const double *b_bar, double *gW, double *gL,
                                              double *gV) {
-    const int H = (int)blockDim.x / 2;
-    const int sweep = (int)threadIdx.x < H ? 0 : 1;
-    const int lane = (int)threadIdx.x - sweep * H;
-    const int64_t stride = (int64_t)gridDim.x * H;
-    // the next device's terminals and parameters are loaded while this one is computed
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     struct Pre {
         int32_t t0, t1, t2, t3, v, isP;
         double W, L, VTH0;
     };
-    auto fetch = [&](int64_t b) {
+    auto fetch = [&](int64_t ps64) {
         Pre q{0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
-        if (b + lane < kc.n) {
-            const int ps = (int)(b + lane);
+        if (ps64 < kc.n) {
+            const int ps = (int)ps64;
             const size_t n = (size_t)kc.n;
             q.t0 = kc.term[ps];
             q.t1 = kc.term[n + ps];
@@ -246,45 +233,39 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
         }
         return q;
     };
-    Pre nx = fetch((int64_t)blockIdx.x * H);
-    for (int64_t base = (int64_t)blockIdx.x * H; base < kc.n; base += stride) {
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Pre nx = fetch(first);
+    for (int64_t i = first; i < kc.n; i += stride) {
         const Pre cu = nx;
-        nx = fetch(base + stride);
-        if (base + lane >= kc.n) continue;
-        const int pos = (int)(base + lane);
+        nx = fetch(i + stride);
+        const int pos = (int)i;
         const int32_t t0 = cu.t0, t1 = cu.t1, t2 = cu.t2, t3 = cu.t3;
         const int key = pattern_key(t0, t1, t2, t3);
         double Yb[16], bb[4];
         gather_cotangents(key, kc.acode, kc.n, pos, A_bar, b_bar, Yb, bb);
-        const double W = cu.W, L = cu.L, VTH0 = cu.VTH0;
         const double V[4] = {t0 ? call.x[t0 - 1] : 0.0, t1 ? call.x[t1 - 1] : 0.0,
                              t2 ? call.x[t2 - 1] : 0.0, t3 ? call.x[t3 - 1] : 0.0};
-        const int32_t v = cu.v;
-        const int isP = cu.isP;
         for (;;) {
-            const int p0 = __builtin_amdgcn_readfirstlane(isP);
-            if (isP == p0) {
+            const int p0 = __builtin_amdgcn_readfirstlane(cu.isP);
+            if (cu.isP == p0) {
                 const DevCard &cd = kc.card[p0];
                 const double p = p0 ? -1.0 : 1.0;
-                if (sweep == 0) {
-                    // the channel sweep carries d/dvth_s; W moves vth_s, beta0, Cg, Cov, Aj
-                    const DevConstT<double> kv = dev_const(cd, p, W, L, VTH0);
-                    const DevConstW kw = dev_const_dW(cd, W, L);
-                    const DevConstT<Tan> k{Tan(kv.vth_s, 1.0), Tan(kv.dibl), Tan(kv.nsce), Tan(kv.beta0),
-                                           Tan(kv.lambda), Tan(kv.k1AbL), Tan(kv.esatn), Tan(kv.Cg),
-                                           Tan(kv.Cov), Tan(kv.Aj)};
-                    const VjpParts r = vjp_parts<true>(cd, p, k, V, call.ag0, Yb, bb, cd.jmod != 0.0);
-                    double w = kw.vth_s * r.g + kw.beta0 * r.s_beta;
-                    w += kw.Cg * (r.s_hq + r.s_qb) + kw.Cov * r.s_cov;
-                    w += kw.Aj * r.s_aj;
-                    gW[v] = w;
-                    gV[v] = p * r.g;
-                } else {
-                    // L moves every constant except Cov and Aj (both W hdif-like products)
-                    const DevConstT<Tan> k = dev_const(cd, p, Tan(W), Tan(L, 1.0), Tan(VTH0));
-                    const VjpParts r = vjp_parts<false>(cd, p, k, V, call.ag0, Yb, bb, false);
-                    gL[v] = r.g + k.Cg.t * r.s_qb;
-                }
+                // tangent 0: d/dvth_s; tangent 1: d/dL through every constant (W moves
+                // vth_s, beta0, Cg, Cov, Aj; L every constant but Cov and Aj)
+                const DevConstT<Tan> kl = dev_const(cd, p, Tan(cu.W), Tan(cu.L, 1.0), Tan(cu.VTH0));
+                const DevConstW kw = dev_const_dW(cd, cu.W, cu.L);
+                const DevConstT<Tan2> k{Tan2(kl.vth_s.v, 1.0, kl.vth_s.t), Tan2(kl.dibl.v, 0.0, kl.dibl.t),
+                                        Tan2(kl.nsce.v, 0.0, kl.nsce.t), Tan2(kl.beta0.v, 0.0, kl.beta0.t),
+                                        Tan2(kl.lambda.v, 0.0, kl.lambda.t), Tan2(kl.k1AbL.v, 0.0, kl.k1AbL.t),
+                                        Tan2(kl.esatn.v, 0.0, kl.esatn.t), Tan2(kl.Cg.v, 0.0, kl.Cg.t),
+                                        Tan2(kl.Cov.v, 0.0, kl.Cov.t), Tan2(kl.Aj.v, 0.0, kl.Aj.t)};
+                const VjpParts r = vjp_parts(cd, p, k, V, call.ag0, Yb, bb, cd.jmod != 0.0);
+                double w = kw.vth_s * r.g0 + kw.beta0 * r.s_beta;
+                w += kw.Cg * (r.s_hq + r.s_qb) + kw.Cov * r.s_cov;
+                w += kw.Aj * r.s_aj;
+                gW[cu.v] = w;
+                gV[cu.v] = p * r.g0;
+                gL[cu.v] = r.g1 + kl.Cg.t * r.s_qb;
                 break;
             }
         }
@@ -300,7 +281,7 @@ hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, c
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_vjp, 256, 0);
     if (e != hipSuccess) return e;
     const int64_t resident = std::max<int64_t>(1, (int64_t)cus * per);
-    const int grid = (int)std::min<int64_t>(((int64_t)kc.n + 127) / 128, resident);
+    const int grid = (int)std::min<int64_t>(((int64_t)kc.n + 255) / 256, resident);
     hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
     return hipGetLastError();
 }

@@ -84,8 +84,9 @@ __device__ __forceinline__ double pcosh(double u) {
 
 // ---- scalar types ------------------------------------------------------------------
 // The model is written once for a scalar type S: plain double (the stamped values,
-// bit-exact) or Tan, a value with one tangent w.r.t. a device parameter (the
-// adjoint's forward-mode sweeps).  Branches are decided on values.
+// bit-exact), Tan, a value with one tangent w.r.t. a device parameter (the
+// per-device constants' L-derivatives), or Tan2, a value with two tangents (the
+// adjoint's forward-mode pass).  Branches are decided on values.
 struct Tan {
     double v, t;
     Tan() = default;
@@ -153,6 +154,55 @@ __device__ __forceinline__ Tan gexp(Tan a) {
 }
 __device__ __forceinline__ double glog1p(double y) { return plog1p(y); }
 __device__ __forceinline__ Tan glog1p(Tan y) { return {plog1p(y.v), y.t * rcp_tan(1.0 + y.v)}; }
+// Value with two tangents (the adjoint carries d/dvth_s and d/dL in one pass); the
+// same rules as Tan, each tangent on its own.
+struct Tan2 {
+    double v, t0, t1;
+    Tan2() = default;
+    __device__ __forceinline__ Tan2(double x) : v(x), t0(0.0), t1(0.0) {}
+    __device__ __forceinline__ Tan2(double x, double a, double b) : v(x), t0(a), t1(b) {}
+};
+__device__ __forceinline__ Tan2 operator+(Tan2 a, Tan2 b) { return {a.v + b.v, a.t0 + b.t0, a.t1 + b.t1}; }
+__device__ __forceinline__ Tan2 operator-(Tan2 a, Tan2 b) { return {a.v - b.v, a.t0 - b.t0, a.t1 - b.t1}; }
+__device__ __forceinline__ Tan2 operator-(Tan2 a) { return {-a.v, -a.t0, -a.t1}; }
+__device__ __forceinline__ Tan2 operator*(Tan2 a, Tan2 b) {
+    return {a.v * b.v, a.t0 * b.v + a.v * b.t0, a.t1 * b.v + a.v * b.t1};
+}
+__device__ __forceinline__ Tan2 operator/(Tan2 a, Tan2 b) {
+    const double r = rcp_tan(b.v);
+    const double q = a.v * r;
+    return {q, (a.t0 - q * b.t0) * r, (a.t1 - q * b.t1) * r};
+}
+__device__ __forceinline__ Tan2 operator+(Tan2 a, double b) { return {a.v + b, a.t0, a.t1}; }
+__device__ __forceinline__ Tan2 operator+(double a, Tan2 b) { return {a + b.v, b.t0, b.t1}; }
+__device__ __forceinline__ Tan2 operator-(Tan2 a, double b) { return {a.v - b, a.t0, a.t1}; }
+__device__ __forceinline__ Tan2 operator-(double a, Tan2 b) { return {a - b.v, -b.t0, -b.t1}; }
+__device__ __forceinline__ Tan2 operator*(double a, Tan2 b) { return {a * b.v, a * b.t0, a * b.t1}; }
+__device__ __forceinline__ Tan2 operator*(Tan2 a, double b) { return {a.v * b, a.t0 * b, a.t1 * b}; }
+__device__ __forceinline__ Tan2 operator/(Tan2 a, double b) {
+    const double r = rcp_tan(b);
+    return {a.v * r, a.t0 * r, a.t1 * r};
+}
+__device__ __forceinline__ Tan2 operator/(double a, Tan2 b) {
+    const double r = rcp_tan(b.v);
+    const double q = a * r;
+    return {q, (-(q * b.t0)) * r, (-(q * b.t1)) * r};
+}
+__device__ __forceinline__ double val(const Tan2 &x) { return x.v; }
+__device__ __forceinline__ Tan2 gsqrt(Tan2 x) {
+    const double s = sqrt_tan(x.v);
+    const double h = 0.5 * rcp_tan(s);
+    return {s, x.t0 * h, x.t1 * h};
+}
+__device__ __forceinline__ Tan2 gabs(Tan2 x) { return x.v >= 0.0 ? x : -x; }
+__device__ __forceinline__ Tan2 gexp(Tan2 a) {
+    const double e = pexp(a.v);
+    return {e, e * a.t0, e * a.t1};
+}
+__device__ __forceinline__ Tan2 glog1p(Tan2 y) {
+    const double r = rcp_tan(1.0 + y.v);
+    return {plog1p(y.v), y.t0 * r, y.t1 * r};
+}
 template <class S>
 __device__ __forceinline__ S gcosh(S u) {
     const S e = gexp(u);
