@@ -125,6 +125,7 @@ struct RegionDev {
     DevBuf<int32_t> slot_tgt;
     DevBuf<uint8_t> slot_first;
     DevBuf<int32_t> fold, fold_src;
+    DevBuf<int32_t> fold_head;   // per fold its first FOLD_HEAD sources (0 beyond its count)
     DevBuf<int32_t> hub_cptr, hub_of_chunk, hfold;
     DevBuf<double> hub_part;
     DevBuf<double> sdp, stage;   // sdp: per-device model constants, region-major [NSD][n]

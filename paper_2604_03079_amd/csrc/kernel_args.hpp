@@ -28,6 +28,7 @@ constexpr uint32_t ITEM_HUB = 2u;   // hub chunk (index = chunk id)
 // first, then PMOS), phases, interior range [4], [5) in int_target,
 // item range [6], [7) in ritems, lane-fold range [8], [9) in fold, local hub chunk
 // range [10], [11) in hfold.
+constexpr int FOLD_HEAD = 4;
 constexpr int RT_FIELDS = 12;
 // Shared entries with more contributions than this are folded by the follow-up
 // kernel; smaller ones by the last contributing region, one lane each.
@@ -144,6 +145,9 @@ struct KRegion {
     // each (code row << 16) | lane of a writer in the region
     const int32_t *fold;
     const int32_t *fold_src;
+    // per fold its first FOLD_HEAD sources (0 beyond its count), so that a lane's fold
+    // and the start of its sources arrive in one round trip
+    const int32_t *fold_head;
     // local hub parts: part index of each; the region's k-th local part occupies LDS
     // slots [n_owned + RHUB_K k, n_owned + RHUB_K (k + 1)) after its owned entries,
     // contribution r of the part at slot r

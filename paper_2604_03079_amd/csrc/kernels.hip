@@ -887,16 +887,24 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         LdsRowSink sink{mst + t, B};
         emit_merged(d.key, Y, bl, sink);
     }
-    // tables the tail needs, first loads issued now (their latency overlaps the staging
-    // and the phases): this lane's lane fold, its first item, its owned-entry targets
+    // tables the tail needs, loaded now (their latency overlaps the staging and the LDS
+    // adds): this lane's lane fold and its first sources, its first item, its
+    // owned-entry targets
     constexpr int OWN_PF = 4;
     const int fi = fb + t;
     int fd_t = 0, fd_s = 0, fd_c = 0;
+    int32_t fsrc[FOLD_HEAD] = {};
     if (fi < fe) {
         const int32_t *fd = kr.fold + 3 * (size_t)fi;
         fd_t = fd[0];
         fd_s = fd[1];
         fd_c = fd[2];
+        static_assert(FOLD_HEAD == 4, "one 16-byte load per fold head");
+        const int4 h = *reinterpret_cast<const int4 *>(kr.fold_head + FOLD_HEAD * (size_t)fi);
+        fsrc[0] = h.x;
+        fsrc[1] = h.y;
+        fsrc[2] = h.z;
+        fsrc[3] = h.w;
     }
     const int nw0 = blockDim.x >> 6;
     const int ii0 = jb + (t & 63) * nw0 + (t >> 6);
@@ -914,11 +922,6 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         st_coherent(kc.stage + sl, mst[j * B + t]);
     }
     lds_barrier();
-    // this lane's fold sources (the descriptor has arrived by now), used after the phases
-    constexpr int FSRC_PF = 4;
-    int32_t fsrc[FSRC_PF];
-#pragma unroll
-    for (int k = 0; k < FSRC_PF; ++k) fsrc[k] = (fi < fe && k < fd_c) ? kr.fold_src[fd_s + k] : 0;
     // entries of the region with one or two writers: every device adds its merged
     // values to their LDS slots with LDS atomic adds, all devices at once (the slots
     // start at -0.0, the identity, and two writers commute exactly: a + b = b + a, so
@@ -945,9 +948,9 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         if (i == fi) {
             s = mst[(fsrc[0] >> 16) * B + (fsrc[0] & 0xFFFF)];
 #pragma unroll
-            for (int k = 1; k < FSRC_PF; ++k)
+            for (int k = 1; k < FOLD_HEAD; ++k)
                 if (k < cnt) s = s + mst[(fsrc[k] >> 16) * B + (fsrc[k] & 0xFFFF)];
-            for (int k = FSRC_PF; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
+            for (int k = FOLD_HEAD; k < cnt; ++k) s = s + mst[(src[k] >> 16) * B + (src[k] & 0xFFFF)];
         } else {
             s = mst[(src[0] >> 16) * B + (src[0] & 0xFFFF)];
 #pragma unroll 8

@@ -537,6 +537,15 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
     if ((e = D.slot_first.upload(R.slot_first)) != hipSuccess) return e;
     if ((e = D.fold.upload(R.fold)) != hipSuccess) return e;
     if ((e = D.fold_src.upload(R.fold_src)) != hipSuccess) return e;
+    {
+        const size_t nf = R.fold.size() / 3;
+        std::vector<int32_t> head(FOLD_HEAD * nf, 0);
+        for (size_t i = 0; i < nf; ++i) {
+            const int32_t s0 = R.fold[3 * i + 1], cnt = R.fold[3 * i + 2];
+            for (int k = 0; k < FOLD_HEAD && k < cnt; ++k) head[FOLD_HEAD * i + (size_t)k] = R.fold_src[(size_t)s0 + (size_t)k];
+        }
+        if ((e = D.fold_head.upload(head)) != hipSuccess) return e;
+    }
     if ((e = D.hub_cptr.upload(R.hub_cptr)) != hipSuccess) return e;
     if ((e = D.hub_of_chunk.upload(R.hub_of_chunk)) != hipSuccess) return e;
     if ((e = D.hfold.upload(R.hfold)) != hipSuccess) return e;
@@ -630,6 +639,7 @@ KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
     r.slot_first = D.slot_first.p;
     r.fold = D.fold.p;
     r.fold_src = D.fold_src.p;
+    r.fold_head = D.fold_head.p;
     r.hfold = D.hfold.p;
 
     r.lds_int = (R.max_lds + 1) & ~1;
