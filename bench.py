@@ -598,7 +598,7 @@ def main():
     ap.add_argument("--newton", action="store_true",
                     help="run only the Newton-loop leg (stamp, refactorisation, solve) and print its JSON")
     ap.add_argument("--batch-only", action="store_true",
-                    help="time only the 512-circuit batched step, region schedule, block 256 (profiling runs)")
+                    help="time only the 512-circuit batched step (region schedule, block 256) and its adjoint (profiling runs)")
     ap.add_argument("--pmc-kernel", default="k_region,k_hub_parts",
                     help="kernels of one step (comma-separated) whose counters --summarize-pmc sums")
     ap.add_argument("--pmc-key", default="region_chain100k")
@@ -642,6 +642,11 @@ def main():
         ms = time_eager(torch, lambda: B.eval_stamp(x, AG0, None, A, b), args.steps, args.warmup)
         B.check()
         log(f"batch 512 region block 256: {ms * 1e3:.1f} us per step ({args.steps} steps)")
+        Ab, bb = G.cotangents(B.nnz, B.n_rows, seed=50)
+        Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
+        ms_a = time_eager(torch, lambda: B.vjp(x, AG0, Ab, bb), args.steps, args.warmup)
+        B.check()
+        log(f"batch 512 adjoint: {ms_a * 1e3:.1f} us per step ({ms_a / ms:.2f} x the forward)")
         release(torch, B)
         return
     if args.csweep:
