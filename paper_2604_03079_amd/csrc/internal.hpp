@@ -126,6 +126,7 @@ struct RegionDev {
     DevBuf<uint8_t> slot_first;
     DevBuf<int32_t> fold, fold_src;
     DevBuf<int32_t> fold_head;   // per fold its first FOLD_HEAD sources (0 beyond its count)
+    DevBuf<int32_t> ritem_head;  // per link its item's fields (KRegion::ritem_head)
     DevBuf<int32_t> hub_cptr, hub_of_chunk, hfold;
     DevBuf<double> hub_part;
     DevBuf<double> sdp, stage;   // sdp: per-device model constants, region-major [NSD][n]

@@ -30,6 +30,10 @@ constexpr uint32_t ITEM_HUB = 2u;   // hub chunk (index = chunk id)
 // range [10], [11) in hfold.
 constexpr int FOLD_HEAD = 4;
 constexpr int RT_FIELDS = 12;
+// A region's items, one int4 per link (ritems entry): item, first staged value,
+// target, count | regions << ITEM_NEED_SHIFT, so that a thread's item arrives in one
+// round trip.
+constexpr int ITEM_NEED_SHIFT = 16;
 // Shared entries with more contributions than this are folded by the follow-up
 // kernel; smaller ones by the last contributing region, one lane each.
 constexpr int ITEM_LANE_MAX = 8;
@@ -131,6 +135,8 @@ struct KRegion {
     const int32_t *ritems;      // items each region contributes to
     const int32_t *item;        // [4] per item: first staged value, count, target, regions
                                 // (0: folded by the follow-up kernel)
+    const int32_t *ritem_head;  // [4] per link: item, first staged value, target,
+                                // count | regions << ITEM_NEED_SHIFT
     uint32_t *item_count;       // [items * CNT_STRIDE] arrivals per item (returns to 0 after each call)
     int32_t lds_int;            // LDS doubles reserved for interior entries
     int32_t nc_max;             // largest number of code rows of a device (k*k + k)

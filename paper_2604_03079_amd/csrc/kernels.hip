@@ -729,14 +729,46 @@ __device__ __forceinline__ double wave_fold(const double *src, int cnt, double *
     return __shfl(s, 0, 64);
 }
 
-// Items of one region, after its staged values are complete: count the arrival;
-// the last region of an item folds it (shared entries one lane each, in colour
-// order; hub parts spanning regions one wave each, by the tree, stored as parts;
-// consecutive items go to different waves).  Called by every thread of the workgroup.
-// The hub sums over the parts follow in their own kernel (k_hub_parts).  it_first:
-// this thread's item of the first round, when the caller has loaded it already.
+// Fold of the items this thread's region was the last to reach (last: that region;
+// shared entries one lane each, in colour order; hub parts spanning regions one wave
+// each, by the tree, stored as parts).  Called by every lane of the wave.
+__device__ __forceinline__ void fold_item(const KCirc &kc, const KCall &call, bool last, int beg, int cnt,
+                                          uint32_t tgt) {
+    const int lane = threadIdx.x & 63;
+    const bool hub = (tgt >> 30) == ITEM_HUB;
+    if (last && !hub) {   // shared entry, at most ITEM_LANE_MAX contributions
+        double v[ITEM_LANE_MAX];
+#pragma unroll
+        for (int k = 0; k < ITEM_LANE_MAX; ++k) v[k] = k < cnt ? ld_coherent(kc.stage + beg + k) : 0.0;
+        double sum = v[0];
+#pragma unroll
+        for (int k = 1; k < ITEM_LANE_MAX; ++k)
+            if (k < cnt) sum = sum + v[k];
+        store_target(call, tgt, sum);
+    }
+    uint64_t big = __ballot(last && hub);
+    while (big) {
+        const int l = __builtin_ctzll(big);
+        big &= big - 1;
+        const int bbeg = __shfl(beg, l, 64), bcnt = __shfl(cnt, l, 64);
+        const int q = (int)((uint32_t)__shfl((int)tgt, l, 64) & 0x3FFFFFFFu);
+        const double sum = wave_tree_chunk(kc.stage + bbeg, bcnt);
+        if (lane == 0) kc.hub_part[q] = sum;
+    }
+}
+
+// An item's arrival counter after the last of its regions has counted: back to 0 for
+// the next call.
+__device__ __forceinline__ void reset_count(const KRegion &kr, int it) {
+    __hip_atomic_store(kr.item_count + (size_t)it * CNT_STRIDE, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Items of one region in [jb, je) of its links, after its staged values are complete:
+// count the arrival; the last region of an item folds it (fold_item; consecutive
+// items go to different waves).  Called by every thread of the workgroup.  The hub
+// sums over the parts follow in their own kernel (k_hub_parts).
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
-                                             bool hub_only = false, int it_first = -1) {
+                                             bool hub_only = false) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int base = jb; base < je; base += blockDim.x) {
         const int i = base + lane * nw + wave;
@@ -744,7 +776,7 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
         uint32_t tgt = 0;
         bool last = false;
         if (i < je && !(hub_only && ((uint32_t)kr.item[4 * (size_t)kr.ritems[i] + 2] >> 30) != ITEM_HUB)) {
-            const int it = (base == jb && it_first >= 0) ? it_first : kr.ritems[i];
+            const int it = kr.ritems[i];
             const int32_t *f = kr.item + 4 * (size_t)it;
             beg = f[0];
             cnt = f[1];
@@ -755,31 +787,10 @@ __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call,
             } else {
                 last = __hip_atomic_fetch_add(kr.item_count + (size_t)it * CNT_STRIDE, 1u, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT) + 1 == (uint32_t)need;
-                if (last)
-                    __hip_atomic_store(kr.item_count + (size_t)it * CNT_STRIDE, 0u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (last) reset_count(kr, it);
             }
         }
-        const bool hub = (tgt >> 30) == ITEM_HUB;
-        if (last && !hub) {   // shared entry, at most ITEM_LANE_MAX contributions
-            double v[ITEM_LANE_MAX];
-#pragma unroll
-            for (int k = 0; k < ITEM_LANE_MAX; ++k) v[k] = k < cnt ? ld_coherent(kc.stage + beg + k) : 0.0;
-            double sum = v[0];
-#pragma unroll
-            for (int k = 1; k < ITEM_LANE_MAX; ++k)
-                if (k < cnt) sum = sum + v[k];
-            store_target(call, tgt, sum);
-        }
-        uint64_t big = __ballot(last && hub);
-        while (big) {
-            const int l = __builtin_ctzll(big);
-            big &= big - 1;
-            const int bbeg = __shfl(beg, l, 64), bcnt = __shfl(cnt, l, 64);
-            const int q = (int)((uint32_t)__shfl((int)tgt, l, 64) & 0x3FFFFFFFu);
-            const double sum = wave_tree_chunk(kc.stage + bbeg, bcnt);
-            if (lane == 0) kc.hub_part[q] = sum;
-        }
+        fold_item(kc, call, last, beg, cnt, tgt);
     }
 }
 
@@ -908,7 +919,8 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     }
     const int nw0 = blockDim.x >> 6;
     const int ii0 = jb + (t & 63) * nw0 + (t >> 6);
-    int it0 = ii0 < je ? kr.ritems[ii0] : 0;
+    int4 ih = make_int4(0, 0, 0, 0);   // this thread's item of the first round (KRegion::ritem_head)
+    if (!GRID && ii0 < je) ih = *reinterpret_cast<const int4 *>(kr.ritem_head + 4 * (size_t)ii0);
     uint32_t own_t[OWN_PF];
 #pragma unroll
     for (int k = 0; k < OWN_PF; ++k) own_t[k] = t + k * B < ie - ib ? (uint32_t)kr.int_target[ib + t + k * B] : 0u;
@@ -932,7 +944,17 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
             (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), mst[j * B + t], __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    // the region form counts its arrivals right after this barrier, so each wave's
+    // staged values must be complete before it
+    if constexpr (!GRID) drain_memory();
     lds_barrier();
+    // arrivals at the items of the first round, counted now: their round trip overlaps
+    // the lane folds and the local hub parts
+    const int need0 = ih.w >> ITEM_NEED_SHIFT;
+    uint32_t arr0 = 0;
+    if (!GRID && ii0 < je && need0 > 1)
+        arr0 = __hip_atomic_fetch_add(kr.item_count + (size_t)ih.x * CNT_STRIDE, 1u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
     // lane folds: entries of the region with many writers, one lane each, the
     // writers' merged values read from LDS in colour order (no phase per writer)
     for (int i = fb + t; i < fe; i += B) {
@@ -1019,11 +1041,12 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         __syncthreads();
         finish_items(kc, call, kr, jb, je, true);
     } else {
-        // staged values complete before the arrivals are counted; the region's own
-        // entries are stored last (nothing waits for them)
-        drain_memory();
-        __syncthreads();
-        finish_items(kc, call, kr, jb, je, false, it0);
+        // the items of the first round (arrivals counted above), then any later rounds;
+        // the region's own entries are stored last (nothing waits for them)
+        const bool last0 = ii0 < je && (need0 == 1 || arr0 + 1 == (uint32_t)need0);
+        if (last0 && need0 > 1) reset_count(kr, ih.x);
+        fold_item(kc, call, last0, ih.y, ih.w & ((1 << ITEM_NEED_SHIFT) - 1), (uint32_t)ih.z);
+        if (jb + B < je) finish_items(kc, call, kr, jb + B, je);
 #pragma unroll
         for (int k = 0; k < OWN_PF; ++k)
             if (t + k * B < ie - ib) store_target(call, own_t[k], lds[t + k * B]);

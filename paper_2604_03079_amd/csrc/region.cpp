@@ -546,6 +546,21 @@ hipError_t upload_regions(const RegionPlan &R, RegionDev &D) {
         }
         if ((e = D.fold_head.upload(head)) != hipSuccess) return e;
     }
+    {
+        // an item's count is at most RHUB_K (a hub part) or ITEM_LANE_MAX (a shared
+        // entry), and so is the number of regions contributing to it
+        static_assert(RHUB_K < (1 << ITEM_NEED_SHIFT) && ITEM_LANE_MAX < (1 << ITEM_NEED_SHIFT) &&
+                          RHUB_K < (1 << (31 - ITEM_NEED_SHIFT)), "count and regions share one word");
+        std::vector<int32_t> ih(4 * R.ritems.size());
+        for (size_t i = 0; i < R.ritems.size(); ++i) {
+            const int32_t *f = R.item.data() + 4 * (size_t)R.ritems[i];
+            ih[4 * i] = R.ritems[i];
+            ih[4 * i + 1] = f[0];
+            ih[4 * i + 2] = f[2];
+            ih[4 * i + 3] = f[1] | (f[3] << ITEM_NEED_SHIFT);
+        }
+        if ((e = D.ritem_head.upload(ih)) != hipSuccess) return e;
+    }
     if ((e = D.hub_cptr.upload(R.hub_cptr)) != hipSuccess) return e;
     if ((e = D.hub_of_chunk.upload(R.hub_of_chunk)) != hipSuccess) return e;
     if ((e = D.hfold.upload(R.hfold)) != hipSuccess) return e;
@@ -630,6 +645,7 @@ KRegion region_kregion(const RegionPlan &R, const RegionDev &D) {
     r.int_target = D.int_target.p;
     r.ritems = D.ritems.p;
     r.item = D.item.p;
+    r.ritem_head = D.ritem_head.p;
     r.item_count = D.item_count.p;
     r.n_deferred = (int32_t)R.deferred.size();
     r.deferred = D.deferred.p;
