@@ -1042,7 +1042,10 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         finish_items(kc, call, kr, jb, je, true);
     } else {
         // the items of the first round (arrivals counted above), then any later rounds;
-        // the region's own entries are stored last (nothing waits for them)
+        // the region's own entries are stored last (nothing waits for them).  The empty
+        // asm is the first use of the counted value, so that its wait stays here and is
+        // not pulled up to the atomic
+        asm volatile("" : "+v"(arr0));
         const bool last0 = ii0 < je && (need0 == 1 || arr0 + 1 == (uint32_t)need0);
         if (last0 && need0 > 1) reset_count(kr, ih.x);
         fold_item(kc, call, last0, ih.y, ih.w & ((1 << ITEM_NEED_SHIFT) - 1), (uint32_t)ih.z);
