@@ -24,12 +24,24 @@ struct DevIn {
     int key;
 };
 
+// Element pos of a per-position table row that starts at row (the same address on
+// every lane): a uniform base plus a 32-bit byte offset, the form the global loads
+// take directly, so a row costs no per-lane 64-bit address arithmetic.  Positions
+// are below 2^31 / NCODE (checked when a circuit or batch is created), so the
+// offset of an 8-byte element fits 32 bits.
+static_assert(NCODE >= 8, "a position's byte offset in an 8-byte row fits 32 bits");
+template <class T>
+__device__ __forceinline__ T ld_row(const T *row, int pos) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + (uint32_t)pos * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ DevIn load_terms(const KCirc &kc, int pos) {
     DevIn d;
-    d.t0 = kc.term[pos];
-    d.t1 = kc.term[(size_t)kc.n + pos];
-    d.t2 = kc.term[2 * (size_t)kc.n + pos];
-    d.t3 = kc.term[3 * (size_t)kc.n + pos];
+    const size_t n = (size_t)kc.n;
+    d.t0 = ld_row(kc.term, pos);
+    d.t1 = ld_row(kc.term + n, pos);
+    d.t2 = ld_row(kc.term + 2 * n, pos);
+    d.t3 = ld_row(kc.term + 3 * n, pos);
     d.key = pattern_key(d.t0, d.t1, d.t2, d.t3);
     return d;
 }
@@ -42,16 +54,16 @@ template <bool J>
 __device__ __forceinline__ DevConstT<double> load_consts(const KCirc &kc, int pos) {
     const size_t n = (size_t)kc.n;
     DevConstT<double> k;
-    k.vth_s = kc.sdp[pos];
-    k.dibl = kc.sdp[n + pos];
-    k.nsce = kc.sdp[2 * n + pos];
-    k.beta0 = kc.sdp[3 * n + pos];
-    k.lambda = kc.sdp[4 * n + pos];
-    k.k1AbL = kc.sdp[5 * n + pos];
-    k.esatn = kc.sdp[6 * n + pos];
-    k.Cg = kc.sdp[7 * n + pos];
-    k.Cov = kc.sdp[8 * n + pos];
-    k.Aj = J ? kc.sdp[9 * n + pos] : 0.0;
+    k.vth_s = ld_row(kc.sdp, pos);
+    k.dibl = ld_row(kc.sdp + n, pos);
+    k.nsce = ld_row(kc.sdp + 2 * n, pos);
+    k.beta0 = ld_row(kc.sdp + 3 * n, pos);
+    k.lambda = ld_row(kc.sdp + 4 * n, pos);
+    k.k1AbL = ld_row(kc.sdp + 5 * n, pos);
+    k.esatn = ld_row(kc.sdp + 6 * n, pos);
+    k.Cg = ld_row(kc.sdp + 7 * n, pos);
+    k.Cov = ld_row(kc.sdp + 8 * n, pos);
+    k.Aj = J ? ld_row(kc.sdp + 9 * n, pos) : 0.0;
     return k;
 }
 
@@ -878,20 +890,18 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     // the device's phase in LDS, [code row][lane]
     double *mst = lds + kr.lds_int;
     const int B = blockDim.x;
-    // code words: tag 3 (unused) on every lane, loaded for the lanes holding a device
-    // right after the evaluation, so that the loads overlap the merge
+    // code words, loaded right after the evaluation (the loads overlap the merge) on
+    // the lanes holding a device.  Only rows j < ncm are read (ncm, the largest row
+    // count of any device, is the same on every lane; the rows of a device beyond its
+    // own count hold tag 3, unused); the loads of the rows beyond ncm repeat row
+    // ncm - 1, so that every load is unconditional.
+    const int ncm = kr.nc_max;
     uint32_t cd[NCODE];
-#pragma unroll
-    for (int j = 0; j < NCODE; ++j) cd[j] = 0xC0000000u;
     if (pos >= 0) {
         const DevIn d = load_terms(kc, pos);
         const DevOut o = eval_pos<J>(kc, call, pos, d);
-        const int k = (d.t0 != 0) + (d.t1 != 0 && d.t1 != d.t0) +
-                      (d.t2 != 0 && d.t2 != d.t0 && d.t2 != d.t1) +
-                      (d.t3 != 0 && d.t3 != d.t0 && d.t3 != d.t1 && d.t3 != d.t2);
-        const int nc = k * k + k;
 #pragma unroll
-        for (int j = 0; j < NCODE; ++j) cd[j] = j < nc ? (uint32_t)kc.code[(size_t)j * kc.n + pos] : 0xC0000000u;
+        for (int j = 0; j < NCODE; ++j) cd[j] = (uint32_t)ld_row(kc.code + (size_t)min(j, ncm - 1) * kc.n, pos);
         double Y[16];
         full_Y(o, Y);
         const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
@@ -926,23 +936,27 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     for (int k = 0; k < OWN_PF; ++k) own_t[k] = t + k * B < ie - ib ? (uint32_t)kr.int_target[ib + t + k * B] : 0u;
     // values of shared entries and hubs: staged at once (no order among them); the grid
     // form stages only the hub values
+    if (pos >= 0) {
 #pragma unroll
-    for (int j = 0; j < NCODE; ++j) {
-        if ((cd[j] >> 30) != TAG_STAGE) continue;
-        const uint32_t sl = cd[j] & 0x3FFFFFFFu;
-        if (GRID && kr.slot_first[sl] < SLOT_HUB) continue;
-        st_coherent(kc.stage + sl, mst[j * B + t]);
+        for (int j = 0; j < NCODE; ++j) {
+            if (j >= ncm || (cd[j] >> 30) != TAG_STAGE) continue;
+            const uint32_t sl = cd[j] & 0x3FFFFFFFu;
+            if (GRID && kr.slot_first[sl] < SLOT_HUB) continue;
+            st_coherent(kc.stage + sl, mst[j * B + t]);
+        }
     }
     lds_barrier();
     // entries of the region with one or two writers: every device adds its merged
     // values to their LDS slots with LDS atomic adds, all devices at once (the slots
     // start at -0.0, the identity, and two writers commute exactly: a + b = b + a, so
     // the sum is the colour order's whichever add lands first)
+    if (pos >= 0) {
 #pragma unroll
-    for (int j = 0; j < NCODE; ++j) {
-        if ((cd[j] >> 30) <= TAG_LDS_STORE)
-            (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), mst[j * B + t], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int j = 0; j < NCODE; ++j) {
+            if (j < ncm && (cd[j] >> 30) <= TAG_LDS_STORE)
+                (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), mst[j * B + t], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
     // the region form counts its arrivals right after this barrier, so each wave's
     // staged values must be complete before it
@@ -1019,7 +1033,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
 #pragma unroll
                 for (int j = 0; j < NCODE; ++j) {
                     old[j] = -0.0;
-                    if ((cd[j] >> 30) != TAG_STAGE) continue;
+                    if (j >= ncm || (cd[j] >> 30) != TAG_STAGE) continue;
                     const uint32_t sl = cd[j] & 0x3FFFFFFFu;
                     if (kr.slot_first[sl] == SLOT_ADD) {
                         const uint32_t tg = (uint32_t)kr.slot_tgt[sl];
@@ -1028,7 +1042,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
                 }
 #pragma unroll
                 for (int j = 0; j < NCODE; ++j) {
-                    if ((cd[j] >> 30) != TAG_STAGE) continue;
+                    if (j >= ncm || (cd[j] >> 30) != TAG_STAGE) continue;
                     const uint32_t sl = cd[j] & 0x3FFFFFFFu;
                     if (kr.slot_first[sl] >= SLOT_HUB) continue;
                     const uint32_t tg = (uint32_t)kr.slot_tgt[sl];
