@@ -897,6 +897,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     // ncm - 1, so that every load is unconditional.
     const int ncm = kr.nc_max;
     uint32_t cd[NCODE];
+    double mv[NCODE];   // the merged values, also kept in registers for the region form
     if (pos >= 0) {
         const DevIn d = load_terms(kc, pos);
         const DevOut o = eval_pos<J>(kc, call, pos, d);
@@ -905,8 +906,13 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
         double Y[16];
         full_Y(o, Y);
         const double bl[4] = {o.bd, o.bg, o.bs, o.bb};
-        LdsRowSink sink{mst + t, B};
-        emit_merged(d.key, Y, bl, sink);
+        if constexpr (GRID) {
+            LdsRowSink sink{mst + t, B};
+            emit_merged(d.key, Y, bl, sink);
+        } else {
+            LdsRowRegSink sink{mst + t, B, mv};
+            emit_merged(d.key, Y, bl, sink);
+        }
     }
     // tables the tail needs, loaded now (their latency overlaps the staging and the LDS
     // adds): this lane's lane fold and its first sources, its first item, its
@@ -942,7 +948,7 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
             if (j >= ncm || (cd[j] >> 30) != TAG_STAGE) continue;
             const uint32_t sl = cd[j] & 0x3FFFFFFFu;
             if (GRID && kr.slot_first[sl] < SLOT_HUB) continue;
-            st_coherent(kc.stage + sl, mst[j * B + t]);
+            st_coherent(kc.stage + sl, GRID ? mst[j * B + t] : mv[j]);
         }
     }
     lds_barrier();
@@ -954,8 +960,8 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
 #pragma unroll
         for (int j = 0; j < NCODE; ++j) {
             if (j < ncm && (cd[j] >> 30) <= TAG_LDS_STORE)
-                (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), mst[j * B + t], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+                (void)__hip_atomic_fetch_add(lds + (cd[j] & 0x3FFFFFFFu), GRID ? mst[j * B + t] : mv[j],
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     // the region form counts its arrivals right after this barrier, so each wave's

@@ -279,6 +279,20 @@ struct LdsRowSink {
     }
 };
 
+// The same, keeping a copy of each merged value in r[J] (a local array the caller
+// indexes with constants only, so that it lives in registers).
+struct LdsRowRegSink {
+    static constexpr bool kStreaming = true;
+    double *p;
+    int stride;
+    double *r;
+    template <int J>
+    __device__ __forceinline__ void put(double v) {
+        p[J * stride] = v;
+        r[J] = v;
+    }
+};
+
 // Buffer sink: merged values into a [NCODE][n] buffer (the buffered variant).
 struct BufferSink {
     static constexpr bool kStreaming = false;
