@@ -92,6 +92,11 @@ def small_cases():
     ]
     for k in range(8, 15):
         out.append((f"opamp{k}", G.draw_params(G.opamp2(k, 0.9), rng, G.W_OPAMP, G.L_OPAMP)))
+    # regions with more items (entries shared with other regions) than threads: the
+    # region schedule counts their arrivals in several rounds (tests/test_region_plan.py
+    # checks that the plans have such regions)
+    out.append(("random2000x800", G.draw_params(G.random_netlist(2000, 800, 31), np.random.default_rng(78),
+                                                G.W_CHAIN, G.L_CHAIN)))
     return out
 
 

@@ -330,6 +330,19 @@ def test_lane_folds_take_many_writer_entries(orc):
     assert int(plan["fold"][:, 2].max()) == 80
 
 
+def test_regions_with_more_items_than_threads(orc):
+    # a random netlist of 2,000 FETs on 800 nodes: few writers per entry, spread over
+    # many regions, so a region contributes to more shared entries than it has
+    # threads and the region kernel counts its arrivals in several rounds (the GPU
+    # parity cases include this netlist at blocks 64, 192 and 256)
+    circ = G.draw_params(G.random_netlist(2000, 800, 31), np.random.default_rng(78), G.W_CHAIN, G.L_CHAIN)
+    c = CS.prepare(circ, True)
+    for block in (64, 192, 256):
+        rt = c.region_plan(block)["rtab"]
+        assert ((rt[:, 7] - rt[:, 6]) > block).sum() >= rt.shape[0] // 2, block
+    check_against_oracle(orc, circ, c, True, 64)
+
+
 def test_last_round_cut_into_one_wave_regions(orc):
     # 5,000 stages at 256 devices per region: 40 regions; planned for 32 compute
     # units the last round (8 regions, 1,808 devices) becomes 29 regions of at most
