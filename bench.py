@@ -454,8 +454,10 @@ def bench_batch(torch, CS, G, dev):
     Ab, bb = G.cotangents(B.nnz, B.n_rows, seed=50)
     Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
     ms_a, _ = time_graph(torch, lambda: B.vjp(x, AG0, Ab, bb), 20, 3)
+    ms_as = time_eager(torch, lambda: B.vjp(x, AG0, Ab, bb), 20, 3)
     B.check()
-    log(f"  batch 512: adjoint {ms_a:.3f} ms ({ms_a / ms_b:.2f} x the batched forward)")
+    log(f"  batch 512: adjoint {ms_a:.3f} ms ({ms_a / ms_b:.2f} x the batched forward; stream {ms_as:.3f} ms, "
+        f"{ms_as / ms_e:.2f} x)")
     B.per_circuit_params(W, L, V)
     ms_p, _ = time_graph(torch, lambda: B.per_circuit_eval(x, AG0, A, b), 5, 1)
     log(f"  batch 512: batched {ms_b:.3f} ms ({B.n_dev / ms_b / 1e3:.1f} M dev/s), "
@@ -466,7 +468,8 @@ def bench_batch(torch, CS, G, dev):
                              stream_ms_per_step=round(ms_e, 4)),
                 per_circuit_launches=dict(ms_per_step=round(ms_p, 4), value=round(B.n_dev / ms_p / 1e3, 2)),
                 speedup_batched_vs_per_circuit=round(ms_p / ms_b, 2), host_setup_s=round(setup_s, 2),
-                adjoint=dict(ms_per_step=round(ms_a, 4), adjoint_over_forward=round(ms_a / ms_b, 3)))
+                adjoint=dict(ms_per_step=round(ms_a, 4), adjoint_over_forward=round(ms_a / ms_b, 3),
+                             stream_ms_per_step=round(ms_as, 4), stream_adjoint_over_forward=round(ms_as / ms_e, 3)))
 
 
 def bench_adder(torch, CS, G, dev):
@@ -560,9 +563,17 @@ def bench_adjoint(torch, CS, G, dev):
     Ab, bb = torch.from_numpy(Ab).to(dev), torch.from_numpy(bb).to(dev)
     A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
     b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
-    ms_f, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "region"), 50, 5)
-    ms_a, _ = time_graph(torch, lambda: c.vjp(x, AG0, Ab, bb), 50, 5)
-    log(f"  adjoint chain10k: forward {ms_f * 1e3:.1f} us, adjoint {ms_a * 1e3:.1f} us, ratio {ms_a / ms_f:.2f}")
+    # both legs timed as graph replays and as stream launches; each takes the faster
+    # (at 20,000 devices a kernel lasts about as long as a launch)
+    fwd = lambda: c.eval_stamp(x, AG0, None, A, b, "region")
+    adj = lambda: c.vjp(x, AG0, Ab, bb)
+    ms_fg, _ = time_graph(torch, fwd, 50, 5)
+    ms_ag, _ = time_graph(torch, adj, 50, 5)
+    ms_fs = time_eager(torch, fwd, 50, 5)
+    ms_as = time_eager(torch, adj, 50, 5)
+    ms_f, ms_a = min(ms_fg, ms_fs), min(ms_ag, ms_as)
+    log(f"  adjoint chain10k: forward {ms_f * 1e3:.1f} us, adjoint {ms_a * 1e3:.1f} us, ratio {ms_a / ms_f:.2f} "
+        f"(graph {ms_fg * 1e3:.1f} / {ms_ag * 1e3:.1f} us, stream {ms_fs * 1e3:.1f} / {ms_as * 1e3:.1f} us)")
     # the paper's four evaluation-kernel variants on the same step: serial stamping
     # after a parallel evaluation (loadomp), buffered evaluation then colour phases
     # (Color), and the fused coloured schedule (ColorFused: region)
@@ -574,6 +585,9 @@ def bench_adjoint(torch, CS, G, dev):
     return dict(workload="inverter_chain_10k_stages", n_dev=circ.n_dev,
                 forward_ms=round(ms_f, 5), adjoint_ms=round(ms_a, 5),
                 adjoint_over_forward=round(ms_a / ms_f, 3),
+                launch="faster of graph replay and stream launches, per leg",
+                graph=dict(forward_ms=round(ms_fg, 5), adjoint_ms=round(ms_ag, 5)),
+                stream=dict(forward_ms=round(ms_fs, 5), adjoint_ms=round(ms_as, 5)),
                 forward_plus_adjoint_value=round(circ.n_dev / (ms_f + ms_a) / 1e3, 2),
                 variants_ms=dict(serial_stamp=round(ms_s, 5), buffered=round(ms_b, 5), region=round(ms_f, 5)))
 

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "kernel_args.hpp"
 #include "launch.hpp"
@@ -101,7 +102,8 @@ __device__ __forceinline__ double vjp_junction(const DevCard &cd, double p, cons
 }
 
 // Sensitivities of one device's S_dev: g0, g1 along the two tangents the constants
-// k carry, and the value-level factors of the constants that enter linearly.
+// k carry (a Tan carries one: g0 = g1), and the value-level factors of the constants
+// that enter linearly.
 struct VjpParts {
     double g0, g1;  // dS/dtheta through the channel, per tangent
     double s_beta;  // dS/dbeta0
@@ -111,10 +113,13 @@ struct VjpParts {
     double s_aj;    // dS/dAj (with_junction only)
 };
 
-__device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const DevConstT<Tan2> &k,
+__device__ __forceinline__ double tangent(const Tan2 &x, int i) { return i == 0 ? x.t0 : x.t1; }
+__device__ __forceinline__ double tangent(const Tan &x, int) { return x.t; }
+
+template <class T>
+__device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const DevConstT<T> &k,
                                               const double V[4], double ag0, const double Yb[16],
                                               const double bb[4], bool with_junction) {
-    using T = Tan2;
     VjpParts r;
     r.s_aj = with_junction ? vjp_junction(cd, p, V, ag0, Yb, bb) : 0.0;
     const double vds = p * (V[0] - V[2]), vgs = p * (V[1] - V[2]), vbs = p * (V[3] - V[2]);
@@ -198,28 +203,35 @@ __device__ __forceinline__ VjpParts vjp_parts(const DevCard &cd, double p, const
     const T dI = Ids.d[0];
     const T dQ = wQ[0] * hQ.d[0] + hQ.d[1];
 
-    r.g0 = sI * (dI.t0 - cI * Ids.v.t0) + sQ * (dQ.t0 - cQ * hQ.v.t0);
-    r.g1 = sI * (dI.t1 - cI * Ids.v.t1) + sQ * (dQ.t1 - cQ * hQ.v.t1);
+    r.g0 = sI * (tangent(dI, 0) - cI * tangent(Ids.v, 0)) + sQ * (tangent(dQ, 0) - cQ * tangent(hQ.v, 0));
+    r.g1 = sI * (tangent(dI, 1) - cI * tangent(Ids.v, 1)) + sQ * (tangent(dQ, 1) - cQ * tangent(hQ.v, 1));
     r.s_beta = (sI * (dI.v - cI * Ids.v.v)) / k.beta0.v;
     r.s_hq = (sQ * (dQ.v - cQ * hQ.v.v)) / k.Cg.v;
     return r;
 }
 
-// One pass per device, both tangents at once.  The grid is what stays resident: a
-// thread takes every (gridDim x blockDim)-th device and loads the next one's
-// terminals and parameters while it computes the current one.
+// One pass per device, both tangents at once (SPLIT = false), or, for inputs too
+// small to give every SIMD several waves, two adjacent lanes per device with one
+// tangent each (SPLIT = true: lane 0 of the pair d/dvth_s and the W and VTH0
+// gradients, lane 1 d/dL and the L gradient; the same arithmetic per tangent, so the
+// same results, with the latency of a lane's chain cut).  The grid is what stays
+// resident: a thread takes every (gridDim x blockDim)-th item and loads the next
+// one's terminals and parameters while it computes the current one.
+template <bool SPLIT>
 __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double *A_bar,
                                              const double *b_bar, double *gW, double *gL,
                                              double *gV) {
+    constexpr int SH = SPLIT ? 1 : 0;   // items per device: 1 << SH
+    const int64_t n_items = (int64_t)kc.n << SH;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     struct Pre {
         int32_t t0, t1, t2, t3, v, isP;
         double W, L, VTH0;
     };
-    auto fetch = [&](int64_t ps64) {
+    auto fetch = [&](int64_t item) {
         Pre q{0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
-        if (ps64 < kc.n) {
-            const int ps = (int)ps64;
+        if (item < n_items) {
+            const int ps = (int)(item >> SH);
             const size_t n = (size_t)kc.n;
             q.t0 = kc.term[ps];
             q.t1 = kc.term[n + ps];
@@ -235,10 +247,10 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
     };
     const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Pre nx = fetch(first);
-    for (int64_t i = first; i < kc.n; i += stride) {
+    for (int64_t i = first; i < n_items; i += stride) {
         const Pre cu = nx;
         nx = fetch(i + stride);
-        const int pos = (int)i;
+        const int pos = (int)(i >> SH);
         const int32_t t0 = cu.t0, t1 = cu.t1, t2 = cu.t2, t3 = cu.t3;
         const int key = pattern_key(t0, t1, t2, t3);
         double Yb[16], bb[4];
@@ -254,35 +266,82 @@ __global__ void __launch_bounds__(256) k_vjp(KCirc kc, KCall call, const double 
                 // vth_s, beta0, Cg, Cov, Aj; L every constant but Cov and Aj)
                 const DevConstT<Tan> kl = dev_const(cd, p, Tan(cu.W), Tan(cu.L, 1.0), Tan(cu.VTH0));
                 const DevConstW kw = dev_const_dW(cd, cu.W, cu.L);
-                const DevConstT<Tan2> k{Tan2(kl.vth_s.v, 1.0, kl.vth_s.t), Tan2(kl.dibl.v, 0.0, kl.dibl.t),
-                                        Tan2(kl.nsce.v, 0.0, kl.nsce.t), Tan2(kl.beta0.v, 0.0, kl.beta0.t),
-                                        Tan2(kl.lambda.v, 0.0, kl.lambda.t), Tan2(kl.k1AbL.v, 0.0, kl.k1AbL.t),
-                                        Tan2(kl.esatn.v, 0.0, kl.esatn.t), Tan2(kl.Cg.v, 0.0, kl.Cg.t),
-                                        Tan2(kl.Cov.v, 0.0, kl.Cov.t), Tan2(kl.Aj.v, 0.0, kl.Aj.t)};
-                const VjpParts r = vjp_parts(cd, p, k, V, call.ag0, Yb, bb, cd.jmod != 0.0);
-                double w = kw.vth_s * r.g0 + kw.beta0 * r.s_beta;
-                w += kw.Cg * (r.s_hq + r.s_qb) + kw.Cov * r.s_cov;
-                w += kw.Aj * r.s_aj;
-                gW[cu.v] = w;
-                gV[cu.v] = p * r.g0;
-                gL[cu.v] = r.g1 + kl.Cg.t * r.s_qb;
+                // lane of the pair (SPLIT): 0 carries d/dvth_s, 1 carries d/dL
+                const bool lt = SPLIT && (i & 1) != 0;
+                auto gradW = [&](const VjpParts &r) {
+                    double w = kw.vth_s * r.g0 + kw.beta0 * r.s_beta;
+                    w += kw.Cg * (r.s_hq + r.s_qb) + kw.Cov * r.s_cov;
+                    w += kw.Aj * r.s_aj;
+                    gW[cu.v] = w;
+                    gV[cu.v] = p * r.g0;
+                };
+                if constexpr (SPLIT) {
+                    auto seed = [&](const Tan &c, double vth) { return Tan(c.v, lt ? c.t : vth); };
+                    const DevConstT<Tan> k{seed(kl.vth_s, 1.0), seed(kl.dibl, 0.0), seed(kl.nsce, 0.0),
+                                           seed(kl.beta0, 0.0), seed(kl.lambda, 0.0), seed(kl.k1AbL, 0.0),
+                                           seed(kl.esatn, 0.0), seed(kl.Cg, 0.0), seed(kl.Cov, 0.0),
+                                           seed(kl.Aj, 0.0)};
+                    const VjpParts r = vjp_parts(cd, p, k, V, call.ag0, Yb, bb, cd.jmod != 0.0);
+                    if (lt) gL[cu.v] = r.g0 + kl.Cg.t * r.s_qb;
+                    else gradW(r);
+                } else {
+                    const DevConstT<Tan2> k{Tan2(kl.vth_s.v, 1.0, kl.vth_s.t), Tan2(kl.dibl.v, 0.0, kl.dibl.t),
+                                            Tan2(kl.nsce.v, 0.0, kl.nsce.t), Tan2(kl.beta0.v, 0.0, kl.beta0.t),
+                                            Tan2(kl.lambda.v, 0.0, kl.lambda.t), Tan2(kl.k1AbL.v, 0.0, kl.k1AbL.t),
+                                            Tan2(kl.esatn.v, 0.0, kl.esatn.t), Tan2(kl.Cg.v, 0.0, kl.Cg.t),
+                                            Tan2(kl.Cov.v, 0.0, kl.Cov.t), Tan2(kl.Aj.v, 0.0, kl.Aj.t)};
+                    const VjpParts r = vjp_parts(cd, p, k, V, call.ag0, Yb, bb, cd.jmod != 0.0);
+                    gradW(r);
+                    gL[cu.v] = r.g1 + kl.Cg.t * r.s_qb;
+                }
                 break;
             }
         }
     }
 }
 
+// Compute units and resident blocks per compute unit of the two forms, per device,
+// queried on a device's first call (the queries cost host time comparable to the
+// kernel on small inputs).  Concurrent first calls store the same values.
+namespace {
+constexpr int VJP_MAX_DEVICES = 64;
+std::atomic<int> g_vjp_cus[VJP_MAX_DEVICES];
+std::atomic<int> g_vjp_per[VJP_MAX_DEVICES][2];
+
+hipError_t vjp_launch_facts(int dev, bool split, int *cus, int *per) {
+    if (dev >= 0 && dev < VJP_MAX_DEVICES) {
+        *cus = g_vjp_cus[dev].load(std::memory_order_relaxed);
+        *per = g_vjp_per[dev][split].load(std::memory_order_relaxed);
+        if (*cus > 0 && *per > 0) return hipSuccess;
+    }
+    hipError_t e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn = split ? (const void *)k_vjp<true> : (const void *)k_vjp<false>;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, fn, 256, 0);
+    if (e == hipSuccess && dev >= 0 && dev < VJP_MAX_DEVICES) {
+        g_vjp_cus[dev].store(*cus, std::memory_order_relaxed);
+        g_vjp_per[dev][split].store(*per, std::memory_order_relaxed);
+    }
+    return e;
+}
+}  // namespace
+
 hipError_t launch_vjp(const KCirc &kc, const KCall &call, const double *A_bar, const double *b_bar,
                       double *gW, double *gL, double *gV, hipStream_t s) {
     if (kc.n == 0) return hipSuccess;
     int dev = 0, cus = 0, per = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_vjp, 256, 0);
     if (e != hipSuccess) return e;
+    // two lanes per device while the devices fill fewer than one 256-thread block per
+    // compute unit, one lane per device beyond (the compute-unit count does not depend
+    // on the form: ask with the wider one first)
+    if ((e = vjp_launch_facts(dev, false, &cus, &per)) != hipSuccess) return e;
+    const bool split = (int64_t)kc.n < (int64_t)cus * 256;
+    if (split && (e = vjp_launch_facts(dev, true, &cus, &per)) != hipSuccess) return e;
     const int64_t resident = std::max<int64_t>(1, (int64_t)cus * per);
-    const int grid = (int)std::min<int64_t>(((int64_t)kc.n + 255) / 256, resident);
-    hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
+    const int64_t items = (int64_t)kc.n << (split ? 1 : 0);
+    const int grid = (int)std::min<int64_t>((items + 255) / 256, resident);
+    if (split) hipLaunchKernelGGL(k_vjp<true>, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
+    else hipLaunchKernelGGL(k_vjp<false>, dim3(grid), dim3(256), 0, s, kc, call, A_bar, b_bar, gW, gL, gV);
     return hipGetLastError();
 }
 
