@@ -257,3 +257,29 @@ def test_batch_vjp_equals_per_circuit(torch_dev, batch_oracle, orc):
         bbi = bb[B.row_off[i]:B.row_off[i + 1]]
         vjpbound.check(orc, [g.cpu().numpy()[d0:d1] for g in (gW, gL, gV)], c, rp, ci, NC, PC, 1e12, Abi, bbi,
                        label=f"batch circuit {i}")
+
+
+def test_two_lane_adjoint_equals_one_lane(torch_dev):
+    # Below one 256-thread block per compute unit of devices the adjoint gives each
+    # device two lanes with one tangent each; above, one lane carries both.  Chains of
+    # 1,000 stages alone take the two-lane form, their batch the one-lane form: the
+    # same arithmetic per tangent gives the same bits.
+    torch = torch_dev
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n_chain = (cus * 256) // 2000 + 2
+    circs = [G.chain_case(1000, seed=200 + i) for i in range(n_chain)]
+    assert circs[0].n_dev < cus * 256 <= sum(c.n_dev for c in circs)
+    B = CS.Batch([CS.prepare(c, True) for c in circs])
+    W, L, V, x = (packed(torch, circs, a) for a in ("W", "L", "VTH0", "x"))
+    B.set_params(W, L, V)
+    Ab, bb = G.cotangents(B.nnz, B.n_rows, seed=51)
+    say(f"case two-lane vs one-lane adjoint: {n_chain} chains, {B.n_dev} devices")
+    gB = [g.cpu().numpy() for g in B.vjp(x, 1e12, torch.from_numpy(Ab).to("cuda:0"),
+                                         torch.from_numpy(bb).to("cuda:0"))]
+    for i, c in enumerate(circs):
+        d0, d1 = B.dev_off[i], B.dev_off[i + 1]
+        g, h = gpu_vjp(torch, c, Ab[B.nnz_off[i]:B.nnz_off[i + 1]], bb[B.row_off[i]:B.row_off[i + 1]])
+        h.close()
+        for k, name in enumerate(("W", "L", "VTH0")):
+            assert np.array_equal(bits(g[k]), bits(gB[k][d0:d1])), f"chain {i} d/d{name}"
+    B.close()
