@@ -690,11 +690,14 @@ __global__ void __launch_bounds__(256) k_atomic_wave(KCirc kc, KCall call) {
 // first, then PMOS lanes) and their merged values parked in LDS rows.  An entry
 // written by one or two devices of the region accumulates in an LDS slot by LDS
 // atomic adds (exact in any order for two writers); an entry written by more devices
-// of the region is folded by one lane from the parked values in colour order;
-// contributions to entries shared with other regions and to hub entries are staged
-// in global memory, and every shared entry or hub chunk is folded by the last region
-// that contributes to it (an arrival counter), large shared entries by a follow-up
-// kernel.  No wave ever waits for another workgroup.
+// of the region is folded by one lane from the parked values in colour order; a hub
+// part whose contributions all come from the region is summed from LDS.
+// Contributions to entries shared with other regions and to hub parts spanning
+// regions are staged in global memory, and each such entry or part is folded by the
+// last region that contributes to it (an arrival counter, counted right after the
+// LDS adds so that its round trip overlaps the lane folds).  Follow-up kernels fold
+// the large shared entries and sum each hub's parts.  No wave ever waits for another
+// workgroup.
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
 // (lgkmcnt 0), not for its global stores, which a full __syncthreads would drain.
@@ -880,14 +883,15 @@ __device__ __forceinline__ void region_body(const KCirc &kc, const KCall &call, 
     // the region's accumulators start at -0.0, the exact identity of IEEE addition, so
     // a first writer's load-add equals its store (visible after the barrier below)
     for (int i = t; i < (ie - ib) + RHUB_K * (he - hb); i += blockDim.x) lds[i] = -0.0;
-    // part index of this lane's first local hub part, loaded now (used after the phases)
+    // part index of this lane's first local hub part, loaded now (used after the LDS adds)
     int hq0 = 0;
     {
         const int i0 = hb + (t >> 6) * 8 + ((t & 63) >> 3);
         if (i0 < he) hq0 = kr.hfold[i0];
     }
-    // evaluate and merge at once (all waves in parallel); the merged values wait for
-    // the device's phase in LDS, [code row][lane]
+    // evaluate and merge at once (all waves in parallel); the merged values go to LDS
+    // rows [code row][lane], where the lane folds read them, and in the region form
+    // also stay in registers for the staging stores and the LDS adds
     double *mst = lds + kr.lds_int;
     const int B = blockDim.x;
     // code words, loaded right after the evaluation (the loads overlap the merge) on
