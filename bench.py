@@ -310,12 +310,21 @@ def bench_junction_level(torch, CS, G, dev):
         c.set_params(W, L, V)
         A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
         b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
-        ms, _ = time_graph(torch, lambda: c.eval_stamp(x, AG0, None, A, b, "region"), 50, 5)
+        step = lambda: c.eval_stamp(x, AG0, None, A, b, "region")
+        ms_g, g = time_graph(torch, step, 50, 5)
+        ms_s = time_eager(torch, step, 50, 5)
+        ms = min(ms_g, ms_s)
         c.check()
-        out[key] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2))
+        out[key] = dict(ms_per_step=round(ms, 5), value=round(circ.n_dev / ms / 1e3, 2),
+                        graph_ms_per_step=round(ms_g, 5), stream_ms_per_step=round(ms_s, 5))
+        del g
+        release(torch, c)
     out["junction_cost"] = round(out["with_junctions"]["ms_per_step"] / out["model_m"]["ms_per_step"], 3)
+    out["launch"] = "faster of graph replay and stream launches, per model"
     log(f"  junction level, chain100k region: {out['with_junctions']['ms_per_step'] * 1e3:.1f} us "
-        f"({out['junction_cost']} x model M's {out['model_m']['ms_per_step'] * 1e3:.1f} us, graph replay)")
+        f"({out['junction_cost']} x model M's {out['model_m']['ms_per_step'] * 1e3:.1f} us; graph "
+        f"{out['model_m']['graph_ms_per_step'] * 1e3:.1f} / {out['with_junctions']['graph_ms_per_step'] * 1e3:.1f} us, "
+        f"stream {out['model_m']['stream_ms_per_step'] * 1e3:.1f} / {out['with_junctions']['stream_ms_per_step'] * 1e3:.1f} us)")
     return out
 
 
