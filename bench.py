@@ -620,6 +620,8 @@ def main():
                     help="run only the colour-count sweep and print it as one JSON line")
     ap.add_argument("--newton", action="store_true",
                     help="run only the Newton-loop leg (stamp, refactorisation, solve) and print its JSON")
+    ap.add_argument("--sram-only", action="store_true",
+                    help="time only the 256 x 256 SRAM's region step (profiling runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the 512-circuit batched step (region schedule, block 256) and its adjoint (profiling runs)")
     ap.add_argument("--pmc-kernel", default="k_region,k_hub_parts",
@@ -652,6 +654,18 @@ def main():
     if args.newton:
         print(json.dumps({"newton": bench_newton(torch, CS, G, dev), "kernel_sources": kernel_sources_hash()}),
               flush=True)
+        return
+    if args.sram_only:
+        sram = G.workload(2)
+        c = CS.prepare(sram, exclude=True)
+        Ws, Ls, Vs, xs = device_tensors(torch, sram, dev)
+        c.set_params(Ws, Ls, Vs)
+        A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
+        b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
+        ms = time_eager(torch, lambda: c.eval_stamp(xs, AG0, None, A, b, "region"), args.steps, args.warmup)
+        c.check()
+        log(f"sram 256x256 region block 256: {ms * 1e3:.1f} us per step ({args.steps} steps)")
+        release(torch, c)
         return
     if args.batch_only:
         circs = G.workload(3)
@@ -757,9 +771,13 @@ def main():
             c.set_params(Ws, Ls, Vs)
             A = torch.empty(c.nnz, dtype=torch.float64, device=dev)
             b = torch.empty(c.n_rows, dtype=torch.float64, device=dev)
-            msv, _ = time_graph(torch, lambda: c.eval_stamp(xs, AG0, None, A, b, variant), 5, 2)
+            step = lambda: c.eval_stamp(xs, AG0, None, A, b, variant)
+            msg, _ = time_graph(torch, step, 5, 2)
+            mss = time_eager(torch, step, 5, 2)
+            msv = min(msg, mss)   # the faster of graph replay and stream launches
             c.check()
-            ex[variant] = dict(ms_per_step=round(msv, 4), value=round(sram.n_dev / msv / 1e3, 2))
+            ex[variant] = dict(ms_per_step=round(msv, 4), value=round(sram.n_dev / msv / 1e3, 2),
+                               graph_ms_per_step=round(msg, 4), stream_ms_per_step=round(mss, 4))
             log(f"  sram {variant:12s} {msv:8.3f} ms/step {sram.n_dev / msv / 1e3:9.1f} M devices/s")
         extras["sram_256x256"] = dict(n_dev=sram.n_dev, n_colors=c.info()["n_colors"], **ex)
         extras["adder_64bit_28T"] = bench_adder(torch, CS, G, dev)
