@@ -715,35 +715,6 @@ __device__ __forceinline__ void store_target(const KCall &call, uint32_t tgt, do
     else call.A[idx] = s;
 }
 
-// Left fold of cnt staged values by one wave (all lanes call it): up to FOLD_K values
-// at a time go through the wave's LDS slice, lane 0 folds while the other lanes'
-// loads of the next FOLD_K values are in flight; the sum is broadcast.
-constexpr int FOLD_K = 256;
-__device__ __forceinline__ double wave_fold(const double *src, int cnt, double *mine) {
-    const int lane = threadIdx.x & 63;
-    constexpr int R = FOLD_K / 64;
-    double s = 0.0;
-    // chunk g + FOLD_K is loaded into registers while lane 0 folds chunk g
-    double r[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) r[k] = lane + 64 * k < cnt ? ld_coherent(src + lane + 64 * k) : 0.0;
-    for (int g = 0; g < cnt; g += FOLD_K) {
-        const int e = min(FOLD_K, cnt - g);
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (lane + 64 * k < e) mine[lane + 64 * k] = r[k];
-        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the chunk is in LDS
-        __builtin_amdgcn_wave_barrier();
-        const int e2 = min(FOLD_K, cnt - g - FOLD_K);
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (lane + 64 * k < e2) r[k] = ld_coherent(src + g + FOLD_K + lane + 64 * k);
-        if (lane == 0) s = g == 0 ? fold_lds(mine, e) : fold_more(s, mine, 0, e);
-        __builtin_amdgcn_wave_barrier();
-    }
-    return __shfl(s, 0, 64);
-}
-
 // Fold of the items this thread's region was the last to reach (last: that region;
 // shared entries one lane each, in colour order; hub parts spanning regions one wave
 // each, by the tree, stored as parts).  Called by every lane of the wave.
@@ -1096,16 +1067,63 @@ k_region_grid(KCirc kc, KCall call, KRegion kr, KSync ks) {
     region_body<true, J>(kc, call, kr, ks);
 }
 
-// Follow-up kernel of the region schedule: every large shared entry, one wave each,
-// its staged contributions folded left in colour order (complete at kernel start).
-__global__ void __launch_bounds__(256) k_fold_items(KCirc kc, KCall call, KRegion kr) {
-    __shared__ double lds[4 * FOLD_K];
-    const int wave = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + wave;
-    if (i >= kr.n_deferred) return;
-    const int32_t *f = kr.item + 4 * (size_t)kr.deferred[i];
-    const double s = wave_fold(kc.stage + f[0], f[1], lds + (size_t)wave * FOLD_K);
-    if ((threadIdx.x & 63) == 0) store_target(call, (uint32_t)f[2], s);
+// Follow-up kernel of the region schedule: the large shared entries, FOLD_E per
+// workgroup of one wave, their staged contributions folded left in colour order
+// (complete at kernel start).  In each round the wave loads up to FOLD_CAP
+// contributions of each of its entries at once (one memory round trip for all of
+// them) into one LDS row per entry, and lane e folds row e, continuing from the
+// previous round for entries longer than FOLD_CAP.  The rows are padded by one value
+// so that the folding lanes read from different banks.
+constexpr int FOLD_E = 8;
+constexpr int FOLD_CAP = 512;
+constexpr int FOLD_ROW = FOLD_CAP + 1;
+static_assert(FOLD_CAP % 64 == 0, "a row is loaded in whole waves");
+__global__ void __launch_bounds__(64) k_fold_items(KCirc kc, KCall call, KRegion kr) {
+    __shared__ double rows[FOLD_E * FOLD_ROW];
+    const int lane = threadIdx.x;
+    const int i0 = blockIdx.x * FOLD_E;
+    // the entries of this workgroup (the same on every lane) and the folding lane's own
+    int beg[FOLD_E], cnt[FOLD_E];
+    int maxc = 0;
+#pragma unroll
+    for (int e = 0; e < FOLD_E; ++e) {
+        beg[e] = 0;
+        cnt[e] = 0;
+        if (i0 + e < kr.n_deferred) {
+            const int32_t *f = kr.item + 4 * (size_t)kr.deferred[i0 + e];
+            beg[e] = f[0];
+            cnt[e] = f[1];
+        }
+        maxc = max(maxc, cnt[e]);
+    }
+    int my_cnt = 0;
+    uint32_t my_tgt = 0;
+    if (lane < FOLD_E && i0 + lane < kr.n_deferred) {
+        const int32_t *f = kr.item + 4 * (size_t)kr.deferred[i0 + lane];
+        my_cnt = f[1];
+        my_tgt = (uint32_t)f[2];
+    }
+    double s = 0.0;
+    for (int p = 0; p < maxc; p += FOLD_CAP) {
+        constexpr int K = FOLD_CAP / 64;
+        double v[FOLD_E][K];
+#pragma unroll
+        for (int e = 0; e < FOLD_E; ++e)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int idx = p + k * 64 + lane;
+                v[e][k] = idx < cnt[e] ? kc.stage[(size_t)beg[e] + idx] : 0.0;
+            }
+        if (p > 0) __syncthreads();   // the previous round's rows are folded
+#pragma unroll
+        for (int e = 0; e < FOLD_E; ++e)
+#pragma unroll
+            for (int k = 0; k < K; ++k) rows[e * FOLD_ROW + k * 64 + lane] = v[e][k];
+        __syncthreads();
+        const int n = min(FOLD_CAP, my_cnt - p);
+        if (n > 0) s = p == 0 ? fold_lds(rows + lane * FOLD_ROW, n) : fold_more(s, rows + lane * FOLD_ROW, 0, n);
+    }
+    if (my_cnt > 0) store_target(call, my_tgt, s);
 }
 
 __global__ void k_permute_rows(int32_t n, const int32_t *idx, const double *src, int32_t n_src, int32_t rows,
@@ -1267,7 +1285,7 @@ static hipError_t launch_region_followups(const KCirc &kc, const KCall &call, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (kr.n_deferred > 0) {
-        hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + 3) / 4), dim3(256), 0, s, kc, call, kr);
+        hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + FOLD_E - 1) / FOLD_E), dim3(64), 0, s, kc, call, kr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (kc.n_hub > 0) {
