@@ -752,7 +752,7 @@ __device__ __forceinline__ void reset_count(const KRegion &kr, int it) {
 // Items of one region in [jb, je) of its links, after its staged values are complete:
 // count the arrival; the last region of an item folds it (fold_item; consecutive
 // items go to different waves).  Called by every thread of the workgroup.  The hub
-// sums over the parts follow in their own kernel (k_hub_parts).
+// sums over the parts follow in the follow-up kernel (k_region_tail).
 __device__ __forceinline__ void finish_items(const KCirc &kc, const KCall &call, const KRegion &kr, int jb, int je,
                                              bool hub_only = false) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -786,17 +786,16 @@ __device__ __forceinline__ double tree16(const double *v) {
            (((v[8] + v[9]) + (v[10] + v[11])) + ((v[12] + v[13]) + (v[14] + v[15])));
 }
 
-// Follow-up kernel of the region schedule: hub h = blockIdx.x summed from its parts
-// (complete at kernel start) by the pairwise tree.  Its P parts, padded with -0.0 to
-// 256 * S (S parts per lane, a power of two), are cut into one aligned stripe of S per
-// lane, each a subtree: a lane sums its stripe in up to four blocks of 16 (every load
-// issued before the sums), a butterfly sums the stripes of a wave, thread 0 the four
-// wave sums.
+// Follow-up of the region schedule, one workgroup of 256 threads: hub h summed from
+// its parts (complete at kernel start) by the pairwise tree.  Its P parts, padded
+// with -0.0 to 256 * S (S parts per lane, a power of two), are cut into one aligned
+// stripe of S per lane, each a subtree: a lane sums its stripe in up to four blocks
+// of 16 (every load issued before the sums), a butterfly sums the stripes of a wave,
+// thread 0 the four wave sums.
 static_assert(HUB_MAX_PARTS <= 256 * 4 * 16, "a hub's parts fit four blocks of 16 per lane");
-__global__ void __launch_bounds__(256) k_hub_parts(KCirc kc, KCall call) {
+__device__ __forceinline__ void hub_parts_block(const KCirc &kc, const KCall &call, int h) {
     __shared__ double red[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int h = blockIdx.x;
     const int c0 = kc.hub_cptr[h], P = kc.hub_cptr[h + 1] - c0;
     const double *src = kc.hub_part + c0;
     int S = 1;
@@ -1067,21 +1066,20 @@ k_region_grid(KCirc kc, KCall call, KRegion kr, KSync ks) {
     region_body<true, J>(kc, call, kr, ks);
 }
 
-// Follow-up kernel of the region schedule: the large shared entries, FOLD_E per
-// workgroup of one wave, their staged contributions folded left in colour order
-// (complete at kernel start).  In each round the wave loads up to FOLD_CAP
+// Follow-up of the region schedule, one workgroup of 256 threads: large shared
+// entries i0 .. i0 + FOLD_E - 1, their staged contributions folded left in colour
+// order (complete at kernel start).  In each round the workgroup loads up to FOLD_CAP
 // contributions of each of its entries at once (one memory round trip for all of
-// them) into one LDS row per entry, and lane e folds row e, continuing from the
+// them) into one LDS row per entry, and thread e folds row e, continuing from the
 // previous round for entries longer than FOLD_CAP.  The rows are padded by one value
-// so that the folding lanes read from different banks.
+// so that the folding threads read from different banks.
 constexpr int FOLD_E = 8;
 constexpr int FOLD_CAP = 512;
 constexpr int FOLD_ROW = FOLD_CAP + 1;
-static_assert(FOLD_CAP % 64 == 0, "a row is loaded in whole waves");
-__global__ void __launch_bounds__(64) k_fold_items(KCirc kc, KCall call, KRegion kr) {
+static_assert(FOLD_CAP % 256 == 0, "a row is loaded in whole workgroups");
+__device__ __forceinline__ void fold_items_block(const KCirc &kc, const KCall &call, const KRegion &kr, int i0) {
     __shared__ double rows[FOLD_E * FOLD_ROW];
     const int lane = threadIdx.x;
-    const int i0 = blockIdx.x * FOLD_E;
     // the entries of this workgroup (the same on every lane) and the folding lane's own
     int beg[FOLD_E], cnt[FOLD_E];
     int maxc = 0;
@@ -1105,25 +1103,33 @@ __global__ void __launch_bounds__(64) k_fold_items(KCirc kc, KCall call, KRegion
     }
     double s = 0.0;
     for (int p = 0; p < maxc; p += FOLD_CAP) {
-        constexpr int K = FOLD_CAP / 64;
+        constexpr int K = FOLD_CAP / 256;
         double v[FOLD_E][K];
 #pragma unroll
         for (int e = 0; e < FOLD_E; ++e)
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int idx = p + k * 64 + lane;
+                const int idx = p + k * 256 + lane;
                 v[e][k] = idx < cnt[e] ? kc.stage[(size_t)beg[e] + idx] : 0.0;
             }
         if (p > 0) __syncthreads();   // the previous round's rows are folded
 #pragma unroll
         for (int e = 0; e < FOLD_E; ++e)
 #pragma unroll
-            for (int k = 0; k < K; ++k) rows[e * FOLD_ROW + k * 64 + lane] = v[e][k];
+            for (int k = 0; k < K; ++k) rows[e * FOLD_ROW + k * 256 + lane] = v[e][k];
         __syncthreads();
         const int n = min(FOLD_CAP, my_cnt - p);
         if (n > 0) s = p == 0 ? fold_lds(rows + lane * FOLD_ROW, n) : fold_more(s, rows + lane * FOLD_ROW, 0, n);
     }
     if (my_cnt > 0) store_target(call, my_tgt, s);
+}
+
+// The follow-ups of a region launch in one kernel: workgroups [0, n_fold) fold the
+// large shared entries (FOLD_E each), the next n_hub sum one hub each.  The two sets
+// touch different entries and read only what the region kernel completed.
+__global__ void __launch_bounds__(256) k_region_tail(KCirc kc, KCall call, KRegion kr, int32_t n_fold) {
+    if ((int)blockIdx.x < n_fold) fold_items_block(kc, call, kr, (int)blockIdx.x * FOLD_E);
+    else hub_parts_block(kc, call, (int)blockIdx.x - n_fold);
 }
 
 __global__ void k_permute_rows(int32_t n, const int32_t *idx, const double *src, int32_t n_src, int32_t rows,
@@ -1284,12 +1290,9 @@ hipError_t region_capacity(int block, int lds_int, int nc_max, int *blocks_per_c
 static hipError_t launch_region_followups(const KCirc &kc, const KCall &call, const KRegion &kr, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (kr.n_deferred > 0) {
-        hipLaunchKernelGGL(k_fold_items, dim3((kr.n_deferred + FOLD_E - 1) / FOLD_E), dim3(64), 0, s, kc, call, kr);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (kc.n_hub > 0) {
-        hipLaunchKernelGGL(k_hub_parts, dim3(kc.n_hub), dim3(256), 0, s, kc, call);
+    const int32_t n_fold = (kr.n_deferred + FOLD_E - 1) / FOLD_E;
+    if (n_fold + kc.n_hub > 0) {
+        hipLaunchKernelGGL(k_region_tail, dim3(n_fold + kc.n_hub), dim3(256), 0, s, kc, call, kr, n_fold);
         e = hipGetLastError();
     }
     return e;
