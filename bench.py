@@ -27,7 +27,7 @@ import numpy as np  # noqa: E402
 
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x FP64 lanes x clock: one op per lane-cycle
 KERNEL_OF = {"persistent": "k_persistent_* (one launch per step)",
-             "region": "k_region + k_hub_parts (one launch each per step)",
+             "region": "k_region + k_region_tail (one launch each per step)",
              "per_kernel": "k_colour_phase x colours + k_hub",
              "buffered": "k_eval_buffer + k_persistent_stamp",
              "atomic": "k_fill_zero + k_atomic",
@@ -455,7 +455,7 @@ def bench_batch(torch, CS, G, dev):
     B.check()
     counts = add_counts([algorithmic_counts(c) for c in circs])
     roof = roofline(counts, ms_e, traffic_from_profiles(kernel_sources_hash(), "batch512"),
-                    "k_region + k_hub_parts (one launch each per batched step)" if best["schedule"] == "region"
+                    "k_region + k_region_tail (one launch each per batched step)" if best["schedule"] == "region"
                     else "k_persistent_* (one launch per batched step)")
     log(f"  batch 512 roofline: {roof['bound']} {roof['achieved']} {roof['unit']} = {roof['frac']:.3f} of peak "
         f"(t_FP64 {roof['t_fp64_us']} us, t_HBM {roof['t_hbm_us']} us, kernel {roof['kernel_avg_us']} us)")
@@ -624,7 +624,7 @@ def main():
                     help="time only the 256 x 256 SRAM's region step (profiling runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the 512-circuit batched step (region schedule, block 256) and its adjoint (profiling runs)")
-    ap.add_argument("--pmc-kernel", default="k_region,k_hub_parts",
+    ap.add_argument("--pmc-kernel", default="k_region,k_region_tail",
                     help="kernels of one step (comma-separated) whose counters --summarize-pmc sums")
     ap.add_argument("--pmc-key", default="region_chain100k")
     args = ap.parse_args()
